@@ -1,0 +1,167 @@
+/*
+ * mfft: complex DFTs over I/O tensors on AMD Instinct MI355X (gfx950).
+ *
+ * The problem statement is the one of Johnson & Frigo, "Implementing FFTs in
+ * Practice", Section 4.1 ("The problem to be solved"): a DFT problem
+ * dft(N, V, I, O) is a rank-r transform size N and a vector size V, both
+ * I/O tensors -- sets of I/O dimensions (n, is, os) with a non-negative length n
+ * and integer input/output strides -- plus an input pointer I and an output
+ * pointer O.  Every I/O dimension of V is a loop of independent transforms,
+ * every I/O dimension of N one dimension of the (separable) transform.  I = O
+ * is the in-place case.
+ *
+ * Conventions fixed by this library where the paper leaves a choice:
+ *   - strides count complex elements of the plan's precision; data is
+ *     interleaved (re, im);
+ *   - sign -1 is the forward DFT of eq. (dft), Section 2,
+ *     Y[k] = sum_l X[l] exp(-2 pi i l k / n); sign +1 conjugates the exponent;
+ *     neither direction is normalized (forward then inverse = n * identity);
+ *   - a problem with any n = 0 is a valid no-op; rank 0 is a copy;
+ *   - the input is read as it was before the call, also when I = O with
+ *     different input and output strides (scratch memory is used then);
+ *   - two different (vector, frequency) indices writing one output address is
+ *     an error (MFFT_EINVAL).
+ *
+ * All functions return a status code (0 = success, < 0 = error) and never
+ * throw; mfft_last_error() holds a thread-local message for the last failure.
+ * Device pointers are plain HIP device addresses; streams are hipStream_t
+ * passed as void* (NULL = the default stream).
+ */
+#ifndef MFFT_H
+#define MFFT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ status */
+#define MFFT_OK        0
+#define MFFT_EINVAL   (-1)  /* malformed problem or argument                    */
+#define MFFT_ENOTSUP  (-2)  /* well-formed problem this build cannot plan       */
+#define MFFT_ENOMEM   (-3)  /* device or host allocation failed                 */
+#define MFFT_EHIP     (-4)  /* a HIP runtime call failed (text in last_error)   */
+#define MFFT_EALIGN   (-5)  /* execute pointers contradict what the plan assumed */
+#define MFFT_EBUDGET  (-6)  /* request can never fit the server's HBM budget    */
+#define MFFT_ESTATE   (-7)  /* object in the wrong state (stopped, unknown id)  */
+#define MFFT_ETIMEOUT (-8)  /* wait expired before completion                   */
+#define MFFT_ECANCELED (-9) /* request was cancelled                            */
+#define MFFT_ENOWISDOM (-10) /* MFFT_WISDOM_ONLY and no stored plan matches      */
+
+/* ------------------------------------------------------------------ problem */
+/* One I/O dimension (Section 4.1): length n >= 0, input stride is, output
+ * stride os, both in complex elements, either sign. */
+typedef struct {
+    int64_t n, is, os;
+} mfft_iodim;
+
+/* Precision of data and arithmetic: interleaved single or double complex. */
+typedef enum { MFFT_C32 = 0, MFFT_C64 = 1 } mfft_prec;
+
+/* Planner rigor (Section 4.3, "The FFTW planner"). */
+#define MFFT_ESTIMATE    0u  /* heuristic cost model, no timing                 */
+#define MFFT_MEASURE     1u  /* time candidate plans on the stream, keep fastest */
+#define MFFT_WISDOM_ONLY 2u  /* only a stored plan; else MFFT_ENOWISDOM          */
+#define MFFT_NO_WISDOM   4u  /* neither consult nor record stored plans          */
+
+/* Optional device allocator (e.g. a framework's caching allocator).  alloc
+ * returns NULL on failure.  NULL allocator = hipMalloc / hipFree. */
+typedef struct {
+    void *(*alloc)(size_t bytes, void *stream, void *ctx);
+    void (*free)(void *ptr, void *stream, void *ctx);
+    void *ctx;
+} mfft_allocator;
+
+typedef struct mfft_plan_s *mfft_plan;
+
+/* Description of a plan (for reports and tests). */
+typedef struct {
+    int prec;                 /* mfft_prec                                     */
+    int sign;                 /* -1 or +1                                      */
+    int rank, howmany_rank;   /* after canonicalization                        */
+    int inplace;              /* plan expects in == out                        */
+    int n_passes;             /* kernel launches per execute                   */
+    int64_t n_total;          /* product of transform lengths                  */
+    int64_t howmany;          /* product of vector lengths                     */
+    double flops;             /* nominal 5 N log2 N per transform, x howmany   */
+    double bytes_compulsory;  /* read input once + write output once           */
+    double bytes_passes;      /* bytes the passes move to and from HBM         */
+    size_t scratch_bytes;     /* device scratch owned by the plan              */
+    size_t table_bytes;       /* device twiddle / chirp / index tables         */
+    char desc[1024];          /* human-readable pass list                      */
+} mfft_plan_info_t;
+
+/*
+ * Validate a problem without touching the GPU (host-only).
+ *   rank, dims:                 transform size N (rank <= 8); dims may be NULL
+ *                               when rank == 0.
+ *   howmany_rank, howmany_dims: vector size V (rank <= 8).
+ *   inplace:                    1 if the caller will pass in == out.
+ *   sign:                       -1 or +1.   prec: MFFT_C32 or MFFT_C64.
+ * Returns MFFT_OK, MFFT_EINVAL (bad lengths, strides that overflow, outputs
+ * that alias, bad sign/prec) or MFFT_ENOTSUP.
+ */
+int mfft_problem_check(int rank, const mfft_iodim *dims, int howmany_rank,
+                       const mfft_iodim *howmany_dims, int inplace, int sign, mfft_prec prec);
+
+/*
+ * Plan dft(N, V, I, O) (Section 4: a plan is a composition of algorithmic
+ * steps chosen by the planner; here each step is one GPU pass).
+ * Arguments as for mfft_problem_check, plus
+ *   flags:      MFFT_ESTIMATE / MFFT_MEASURE / MFFT_WISDOM_ONLY | MFFT_NO_WISDOM;
+ *   alloc:      allocator for the plan's tables and scratch (NULL = hipMalloc);
+ *   hip_stream: stream for table generation and measurement.
+ * On success *out receives a plan that owns its device tables and scratch.
+ * Table generation is enqueued on hip_stream; executing on another stream
+ * requires the caller to order the two streams.  Planning is serialized by an
+ * internal lock.  Errors: EINVAL, ENOTSUP, ENOMEM, EHIP, ENOWISDOM.
+ */
+int mfft_plan_dft(mfft_plan *out, int rank, const mfft_iodim *dims, int howmany_rank,
+                  const mfft_iodim *howmany_dims, int inplace, int sign, mfft_prec prec,
+                  unsigned flags, const mfft_allocator *alloc, void *hip_stream);
+
+/*
+ * Enqueue the transform on hip_stream (asynchronous; no allocation, no
+ * synchronization, so it can be captured in a HIP graph).  `in` and `out` point
+ * at element (0,...,0) of the input and output tensors.  An out-of-place plan
+ * (inplace = 0) never writes the input; in == out is rejected with
+ * MFFT_EALIGN for it, as is in != out for an in-place plan or a pointer not
+ * aligned to the complex element size.  Calls on one plan must not overlap
+ * in time (they share the plan's scratch); use mfft_execute_scratch with
+ * distinct scratch buffers for concurrent executions.
+ */
+int mfft_execute(mfft_plan plan, const void *in, void *out, void *hip_stream);
+
+/* As mfft_execute, with caller-owned scratch of at least info.scratch_bytes
+ * (NULL allowed when that size is 0). */
+int mfft_execute_scratch(mfft_plan plan, const void *in, void *out, void *scratch,
+                         void *hip_stream);
+
+/* Fill *info for a plan. */
+int mfft_plan_info(mfft_plan plan, mfft_plan_info_t *info);
+
+/* Free the plan's device memory (stream-ordered on the plan's stream). */
+int mfft_plan_destroy(mfft_plan plan);
+
+/* ------------------------------------------------------------------ wisdom */
+/* Stored plans (Section 4.3: plans can be precomputed and loaded later).  The
+ * text records, per canonical problem, precision, device architecture and
+ * library version, the choices the planner made.  export allocates *buf with
+ * malloc-compatible memory released by mfft_free. */
+int mfft_wisdom_export(char **buf, size_t *len);
+int mfft_wisdom_import(const char *buf, size_t len);
+int mfft_wisdom_forget(void);
+void mfft_free(void *p);
+
+/* ------------------------------------------------------------------ misc */
+/* Thread-local text of the last error on this thread ("" if none). */
+const char *mfft_last_error(void);
+/* Library version string. */
+const char *mfft_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MFFT_H */

@@ -1,0 +1,280 @@
+"""Python binding of libmfft (ctypes): argument marshalling only.
+
+Every step of a transform runs in the HIP kernels of libmfft.so; PyTorch is
+used only to hold device memory and to name streams.  If the library has not
+been built, loading fails loudly -- there is no fallback.
+
+The functions keep the C names (``mfft_plan_dft``, ``mfft_execute``, ...) and
+a small ``Plan`` class wraps them for tensors.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+__all__ = [
+    "lib", "IoDim", "PlanInfo", "MfftError", "Plan", "mfft_problem_check", "mfft_plan_dft",
+    "mfft_execute", "mfft_execute_scratch", "mfft_plan_info", "mfft_plan_destroy",
+    "mfft_wisdom_export", "mfft_wisdom_import", "mfft_wisdom_forget", "mfft_last_error",
+    "mfft_version", "C32", "C64", "ESTIMATE", "MEASURE", "WISDOM_ONLY", "NO_WISDOM",
+    "header_functions", "LIB_PATH", "HEADER_PATH",
+]
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmfft.so")
+HEADER_PATH = os.path.join(os.path.dirname(HERE), "include", "mfft.h")
+
+C32, C64 = 0, 1
+ESTIMATE, MEASURE, WISDOM_ONLY, NO_WISDOM = 0, 1, 2, 4
+
+STATUS = {0: "MFFT_OK", -1: "MFFT_EINVAL", -2: "MFFT_ENOTSUP", -3: "MFFT_ENOMEM",
+          -4: "MFFT_EHIP", -5: "MFFT_EALIGN", -6: "MFFT_EBUDGET", -7: "MFFT_ESTATE",
+          -8: "MFFT_ETIMEOUT", -9: "MFFT_ECANCELED", -10: "MFFT_ENOWISDOM"}
+
+
+class MfftError(RuntimeError):
+    def __init__(self, code: int, where: str, msg: str):
+        super().__init__(f"{where}: {STATUS.get(code, code)} ({msg})")
+        self.code = code
+
+
+class IoDim(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("is_", ctypes.c_int64), ("os", ctypes.c_int64)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("prec", ctypes.c_int), ("sign", ctypes.c_int), ("rank", ctypes.c_int),
+                ("howmany_rank", ctypes.c_int), ("inplace", ctypes.c_int),
+                ("n_passes", ctypes.c_int), ("n_total", ctypes.c_int64),
+                ("howmany", ctypes.c_int64), ("flops", ctypes.c_double),
+                ("bytes_compulsory", ctypes.c_double), ("bytes_passes", ctypes.c_double),
+                ("scratch_bytes", ctypes.c_size_t), ("table_bytes", ctypes.c_size_t),
+                ("desc", ctypes.c_char * 1024)]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class Allocator(ctypes.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", ctypes.c_void_p)]
+
+
+_LIB = None
+
+
+def lib():
+    """Load libmfft.so (after torch, so both share one HIP runtime)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"libmfft.so is not built ({LIB_PATH}); run __graft_entry__.build()")
+    try:
+        import torch  # noqa: F401  (loads the HIP runtime first)
+    except ImportError:  # pragma: no cover
+        pass
+    L = ctypes.CDLL(LIB_PATH, mode=ctypes.RTLD_GLOBAL)
+    p = ctypes.c_void_p
+    i64 = ctypes.c_int64
+    dims_p = ctypes.POINTER(IoDim)
+    L.mfft_problem_check.argtypes = [ctypes.c_int, dims_p, ctypes.c_int, dims_p, ctypes.c_int,
+                                     ctypes.c_int, ctypes.c_int]
+    L.mfft_plan_dft.argtypes = [ctypes.POINTER(p), ctypes.c_int, dims_p, ctypes.c_int, dims_p,
+                                ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint,
+                                ctypes.POINTER(Allocator), p]
+    L.mfft_execute.argtypes = [p, p, p, p]
+    L.mfft_execute_scratch.argtypes = [p, p, p, p, p]
+    L.mfft_plan_info.argtypes = [p, ctypes.POINTER(PlanInfo)]
+    L.mfft_plan_destroy.argtypes = [p]
+    L.mfft_wisdom_export.argtypes = [ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_size_t)]
+    L.mfft_wisdom_import.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
+    L.mfft_wisdom_forget.argtypes = []
+    L.mfft_free.argtypes = [p]
+    L.mfft_last_error.restype = ctypes.c_char_p
+    L.mfft_version.restype = ctypes.c_char_p
+    for name in ("mfft_problem_check", "mfft_plan_dft", "mfft_execute", "mfft_execute_scratch",
+                 "mfft_plan_info", "mfft_plan_destroy", "mfft_wisdom_export",
+                 "mfft_wisdom_import", "mfft_wisdom_forget"):
+        getattr(L, name).restype = ctypes.c_int
+    _LIB = L
+    del i64
+    return L
+
+
+def header_functions(path: str = HEADER_PATH) -> list[str]:
+    """Names of the functions include/mfft.h declares."""
+    text = open(path).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mfft_[a-z0-9_]+)\s*\(", text)))
+
+
+def mfft_last_error() -> str:
+    return lib().mfft_last_error().decode()
+
+
+def mfft_version() -> str:
+    return lib().mfft_version().decode()
+
+
+def _check(rc: int, where: str):
+    if rc != 0:
+        raise MfftError(rc, where, mfft_last_error())
+
+
+def _dims(dims):
+    dims = [tuple(int(v) for v in d) for d in (dims or [])]
+    arr = (IoDim * max(1, len(dims)))(*[IoDim(*d) for d in dims])
+    return len(dims), arr
+
+
+def _ptr(x) -> int:
+    if x is None:
+        return 0
+    if isinstance(x, int):
+        return x
+    return int(x.data_ptr())
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        import torch
+        return int(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)
+
+
+def mfft_problem_check(dims, howmany_dims=(), inplace=0, sign=-1, prec=C32) -> int:
+    """Host-only validation; returns the status code (0 = valid)."""
+    nr, nd = _dims(dims)
+    vr, vd = _dims(howmany_dims)
+    return lib().mfft_problem_check(nr, nd, vr, vd, int(inplace), int(sign), int(prec))
+
+
+def mfft_plan_dft(dims, howmany_dims=(), inplace=0, sign=-1, prec=C32, flags=ESTIMATE,
+                  allocator=None, stream=None) -> int:
+    """Returns a plan handle (int); raises MfftError on failure."""
+    nr, nd = _dims(dims)
+    vr, vd = _dims(howmany_dims)
+    h = ctypes.c_void_p()
+    rc = lib().mfft_plan_dft(ctypes.byref(h), nr, nd, vr, vd, int(inplace), int(sign),
+                             int(prec), int(flags), allocator, _stream(stream))
+    _check(rc, "mfft_plan_dft")
+    return h.value
+
+
+def mfft_execute(plan: int, x, y, stream=None):
+    _check(lib().mfft_execute(plan, _ptr(x), _ptr(y), _stream(stream)), "mfft_execute")
+
+
+def mfft_execute_scratch(plan: int, x, y, scratch, stream=None):
+    _check(lib().mfft_execute_scratch(plan, _ptr(x), _ptr(y), _ptr(scratch), _stream(stream)),
+           "mfft_execute_scratch")
+
+
+def mfft_plan_info(plan: int) -> dict:
+    info = PlanInfo()
+    _check(lib().mfft_plan_info(plan, ctypes.byref(info)), "mfft_plan_info")
+    d = {k: getattr(info, k) for k, _ in PlanInfo._fields_ if k != "desc"}
+    d["desc"] = info.desc.decode(errors="replace")
+    return d
+
+
+def mfft_plan_destroy(plan: int):
+    _check(lib().mfft_plan_destroy(plan), "mfft_plan_destroy")
+
+
+def mfft_wisdom_export() -> str:
+    buf = ctypes.c_char_p()
+    n = ctypes.c_size_t()
+    _check(lib().mfft_wisdom_export(ctypes.byref(buf), ctypes.byref(n)), "mfft_wisdom_export")
+    s = ctypes.string_at(buf, n.value).decode()
+    lib().mfft_free(ctypes.cast(buf, ctypes.c_void_p))
+    return s
+
+
+def mfft_wisdom_import(text: str):
+    b = text.encode()
+    _check(lib().mfft_wisdom_import(b, len(b)), "mfft_wisdom_import")
+
+
+def mfft_wisdom_forget():
+    _check(lib().mfft_wisdom_forget(), "mfft_wisdom_forget")
+
+
+def torch_allocator(device=None):
+    """An mfft_allocator backed by torch's caching allocator (keeps the
+    callbacks alive as attributes of the returned structure)."""
+    import torch
+    dev = torch.cuda.current_device() if device is None else device
+
+    @ALLOC_FN
+    def _alloc(nbytes, stream, ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), dev, stream or 0)
+        except Exception:  # pragma: no cover
+            return None
+
+    @FREE_FN
+    def _free(ptr, stream, ctx):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    a = Allocator(_alloc, _free, None)
+    a._keep = (_alloc, _free)
+    return a
+
+
+class Plan:
+    """A planned dft(N, V, I, O); strides in complex elements."""
+
+    def __init__(self, dims, howmany_dims=(), inplace=False, sign=-1, prec=C32,
+                 flags=ESTIMATE, stream=None, allocator=None):
+        self.dims = [tuple(d) for d in dims]
+        self.howmany_dims = [tuple(d) for d in howmany_dims]
+        self.inplace = bool(inplace)
+        self.sign = sign
+        self.prec = prec
+        self._alloc = allocator
+        self.handle = mfft_plan_dft(dims, howmany_dims, int(inplace), sign, prec, flags,
+                                    ctypes.byref(allocator) if allocator is not None else None,
+                                    stream)
+
+    def execute(self, x, y=None, stream=None):
+        y = x if y is None else y
+        mfft_execute(self.handle, x, y, stream)
+        return y
+
+    def execute_scratch(self, x, y, scratch, stream=None):
+        mfft_execute_scratch(self.handle, x, y, scratch, stream)
+        return y
+
+    def info(self) -> dict:
+        return mfft_plan_info(self.handle)
+
+    def destroy(self):
+        if self.handle:
+            mfft_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def fft_plan_for(x_shape, axes=None, batch_axes=None, sign=-1, prec=C32, inplace=False,
+                 out_strides=None):
+    """Plan the DFT of a contiguous tensor of shape `x_shape` over `axes` (default:
+    all), looping over the remaining axes.  Output strides default to the input's."""
+    nd = len(x_shape)
+    axes = list(range(nd)) if axes is None else [a % nd for a in axes]
+    strides = [1] * nd
+    for i in range(nd - 2, -1, -1):
+        strides[i] = strides[i + 1] * x_shape[i + 1]
+    ostr = strides if out_strides is None else out_strides
+    dims = [(x_shape[a], strides[a], ostr[a]) for a in axes]
+    hdims = [(x_shape[a], strides[a], ostr[a]) for a in range(nd) if a not in axes]
+    return Plan(dims, hdims, inplace=inplace, sign=sign, prec=prec)

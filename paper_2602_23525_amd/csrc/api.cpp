@@ -1,0 +1,246 @@
+// C ABI: plan / execute / destroy, plan info, wisdom, errors.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <string>
+
+#include "plan.h"
+
+struct mfft_plan_s {
+    mfft::PlanImpl impl;
+};
+
+namespace mfft {
+
+const char *last_error_text();
+extern size_t g_lds_budget;
+
+static std::mutex g_plan_mutex;
+static bool g_inited = false;
+static std::string g_arch = "unknown";
+
+static int init_device()
+{
+    if (g_inited) return MFFT_OK;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(MFFT_EHIP, std::string("no HIP device: ") + hipGetErrorString(e));
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, dev);
+    if (e != hipSuccess) return fail(MFFT_EHIP, hipGetErrorString(e));
+    g_arch = prop.gcnArchName;
+    size_t lds = prop.sharedMemPerBlock;
+    if (const char *env = getenv("MFFT_LDS_BUDGET")) lds = std::min(lds, (size_t)atol(env));
+    g_lds_budget = std::min<size_t>(lds, 65536);
+    g_inited = true;
+    return MFFT_OK;
+}
+
+const std::string &device_arch() { return g_arch; }
+
+// ------------------------------------------------------------ wisdom store
+
+static std::mutex g_wisdom_mutex;
+static std::map<std::string, std::string> g_wisdom;
+
+bool wisdom_lookup(const std::string &key, std::string *val)
+{
+    std::lock_guard<std::mutex> lk(g_wisdom_mutex);
+    auto it = g_wisdom.find(key);
+    if (it == g_wisdom.end()) return false;
+    *val = it->second;
+    return true;
+}
+
+void wisdom_record(const std::string &key, const std::string &val)
+{
+    std::lock_guard<std::mutex> lk(g_wisdom_mutex);
+    g_wisdom[key] = val;
+}
+
+static void destroy_impl(PlanImpl *p)
+{
+    for (DeviceAlloc &d : p->tables) dev_free(p, d.ptr, d.bytes);
+    p->tables.clear();
+    if (p->scratch) dev_free(p, p->scratch, p->scratch_bytes);
+    p->scratch = nullptr;
+}
+
+// Plan without the global lock (used for the FP64 sub-transforms that build
+// Rader and Bluestein spectra while another plan is being made).
+int plan_internal(mfft_plan *out, int rank, const mfft_iodim *dims, int howmany_rank,
+                  const mfft_iodim *hdims, int inplace, int sign, int prec, hipStream_t stream,
+                  unsigned flags, const mfft_allocator *alloc)
+{
+    *out = nullptr;
+    int rc = init_device();
+    if (rc) return rc;
+    mfft_plan pl = new (std::nothrow) mfft_plan_s();
+    if (!pl) return fail(MFFT_ENOMEM, "host allocation failed");
+    PlanImpl *p = &pl->impl;
+    rc = canonicalize(rank, dims, howmany_rank, hdims, inplace, sign, prec, &p->prob);
+    if (rc) {
+        delete pl;
+        return rc;
+    }
+    p->flags = flags;
+    p->stream = stream;
+    if (alloc) {
+        p->alloc = *alloc;
+        p->has_alloc = true;
+    }
+    (void)hipGetDevice(&p->device);
+    rc = build_plan(p);
+    if (rc == MFFT_OK && p->scratch_bytes) {
+        p->scratch = dev_alloc(p, p->scratch_bytes);
+        if (!p->scratch) rc = fail(MFFT_ENOMEM, "scratch allocation failed");
+    }
+    if (rc == MFFT_OK) {
+        hipError_t e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) rc = fail(MFFT_EHIP, std::string("table generation: ") + hipGetErrorString(e));
+    }
+    if (rc) {
+        destroy_impl(p);
+        delete pl;
+        return rc;
+    }
+    std::ostringstream d;
+    d << problem_key(p->prob) << "\n";
+    p->bytes_passes = 0;
+    for (const Pass &ps : p->passes) {
+        d << "  " << ps.desc << "\n";
+        p->bytes_passes += ps.bytes;
+    }
+    p->desc = d.str();
+    *out = pl;
+    return MFFT_OK;
+}
+
+}  // namespace mfft
+
+using namespace mfft;
+
+extern "C" {
+
+const char *mfft_last_error(void) { return last_error_text(); }
+
+const char *mfft_version(void) { return "mfft 0.1.0 (gfx950)"; }
+
+int mfft_plan_dft(mfft_plan *out, int rank, const mfft_iodim *dims, int howmany_rank,
+                  const mfft_iodim *howmany_dims, int inplace, int sign, mfft_prec prec,
+                  unsigned flags, const mfft_allocator *alloc, void *hip_stream)
+{
+    if (!out) return fail(MFFT_EINVAL, "out is NULL");
+    *out = nullptr;
+    std::lock_guard<std::mutex> lk(g_plan_mutex);
+    return plan_internal(out, rank, dims, howmany_rank, howmany_dims, inplace, sign, (int)prec,
+                         (hipStream_t)hip_stream, flags, alloc);
+}
+
+int mfft_execute_scratch(mfft_plan plan, const void *in, void *out, void *scratch,
+                         void *hip_stream)
+{
+    if (!plan) return fail(MFFT_EINVAL, "plan is NULL");
+    const PlanImpl *p = &plan->impl;
+    if (p->prob.empty) return MFFT_OK;
+    const size_t eb = p->prob.prec ? 16 : 8;
+    if (!in || !out) return fail(MFFT_EINVAL, "NULL data pointer");
+    if (((uintptr_t)in % eb) || ((uintptr_t)out % eb))
+        return fail(MFFT_EALIGN, "data pointers must be aligned to the complex element size");
+    if (p->prob.inplace && in != out)
+        return fail(MFFT_EALIGN, "in-place plan executed with in != out");
+    if (!p->prob.inplace && in == out)
+        return fail(MFFT_EALIGN, "out-of-place plan executed with in == out");
+    if (p->scratch_bytes && !scratch) return fail(MFFT_EINVAL, "plan needs scratch memory");
+    return run_plan(p, in, out, scratch, (hipStream_t)hip_stream);
+}
+
+int mfft_execute(mfft_plan plan, const void *in, void *out, void *hip_stream)
+{
+    if (!plan) return fail(MFFT_EINVAL, "plan is NULL");
+    return mfft_execute_scratch(plan, in, out, plan->impl.scratch, hip_stream);
+}
+
+int mfft_plan_info(mfft_plan plan, mfft_plan_info_t *info)
+{
+    if (!plan || !info) return fail(MFFT_EINVAL, "NULL argument");
+    const PlanImpl *p = &plan->impl;
+    std::memset(info, 0, sizeof(*info));
+    info->prec = p->prob.prec;
+    info->sign = p->prob.sign;
+    info->rank = (int)p->prob.N.size();
+    info->howmany_rank = (int)p->prob.V.size();
+    info->inplace = p->prob.inplace;
+    info->n_passes = (int)p->passes.size();
+    info->n_total = p->prob.empty ? 0 : p->prob.n_total;
+    info->howmany = p->prob.empty ? 0 : p->prob.howmany;
+    const double N = (double)info->n_total;
+    info->flops = N > 1 ? 5.0 * N * std::log2(N) * (double)info->howmany : 0.0;
+    info->bytes_compulsory = 2.0 * (p->prob.prec ? 16.0 : 8.0) * N * (double)info->howmany;
+    info->bytes_passes = p->bytes_passes;
+    info->scratch_bytes = p->scratch_bytes;
+    info->table_bytes = p->table_bytes;
+    std::strncpy(info->desc, p->desc.c_str(), sizeof(info->desc) - 1);
+    return MFFT_OK;
+}
+
+int mfft_plan_destroy(mfft_plan plan)
+{
+    if (!plan) return MFFT_OK;
+    destroy_impl(&plan->impl);
+    delete plan;
+    return MFFT_OK;
+}
+
+int mfft_wisdom_export(char **buf, size_t *len)
+{
+    if (!buf || !len) return fail(MFFT_EINVAL, "NULL argument");
+    std::ostringstream s;
+    s << "mfft-wisdom 1 " << mfft_version() << "\n";
+    {
+        std::lock_guard<std::mutex> lk(g_wisdom_mutex);
+        for (auto &kv : g_wisdom) s << kv.first << " => " << kv.second << "\n";
+    }
+    const std::string t = s.str();
+    char *m = (char *)std::malloc(t.size() + 1);
+    if (!m) return fail(MFFT_ENOMEM, "host allocation failed");
+    std::memcpy(m, t.c_str(), t.size() + 1);
+    *buf = m;
+    *len = t.size();
+    return MFFT_OK;
+}
+
+int mfft_wisdom_import(const char *buf, size_t len)
+{
+    if (!buf) return fail(MFFT_EINVAL, "NULL buffer");
+    std::istringstream s(std::string(buf, len));
+    std::string line;
+    if (!std::getline(s, line) || line.rfind("mfft-wisdom 1 ", 0) != 0)
+        return fail(MFFT_EINVAL, "not mfft wisdom text");
+    std::map<std::string, std::string> add;
+    while (std::getline(s, line)) {
+        if (line.empty()) continue;
+        const size_t k = line.find(" => ");
+        if (k == std::string::npos) return fail(MFFT_EINVAL, "malformed wisdom line");
+        add[line.substr(0, k)] = line.substr(k + 4);
+    }
+    std::lock_guard<std::mutex> lk(g_wisdom_mutex);
+    for (auto &kv : add) g_wisdom[kv.first] = kv.second;
+    return MFFT_OK;
+}
+
+int mfft_wisdom_forget(void)
+{
+    std::lock_guard<std::mutex> lk(g_wisdom_mutex);
+    g_wisdom.clear();
+    return MFFT_OK;
+}
+
+void mfft_free(void *p) { std::free(p); }
+
+}  // extern "C"

@@ -1,0 +1,23 @@
+// Tile-kernel variant: float complex, kernel kind 0 (see tile.h), up to 16
+// elements per thread.
+#include "tile.h"
+
+namespace mfft {
+
+hipError_t launch_pass_c32_k0(const PassArgs &a, size_t lds, hipStream_t s)
+{
+    hipLaunchKernelGGL((pass_kernel<float, 16, 0>), dim3((unsigned)a.ntiles), dim3(a.bt * a.tpt),
+                       lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_c32_k0(const PassArgs *items, const int64_t *prefix, int nitems,
+                                unsigned long long *counter, int block, int grid, size_t lds,
+                                hipStream_t s)
+{
+    hipLaunchKernelGGL((batch_kernel<float, 16, 0>), dim3(grid), dim3(block), lds, s, items,
+                       prefix, nitems, counter);
+    return hipGetLastError();
+}
+
+}  // namespace mfft

@@ -1,0 +1,23 @@
+// Tile-kernel variant: double complex, kernel kind 1 (see tile.h), up to 16
+// elements per thread.
+#include "tile.h"
+
+namespace mfft {
+
+hipError_t launch_pass_c64_k1(const PassArgs &a, size_t lds, hipStream_t s)
+{
+    hipLaunchKernelGGL((pass_kernel<double, 16, 1>), dim3((unsigned)a.ntiles), dim3(a.bt * a.tpt),
+                       lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_c64_k1(const PassArgs *items, const int64_t *prefix, int nitems,
+                                unsigned long long *counter, int block, int grid, size_t lds,
+                                hipStream_t s)
+{
+    hipLaunchKernelGGL((batch_kernel<double, 16, 1>), dim3(grid), dim3(block), lds, s, items,
+                       prefix, nitems, counter);
+    return hipGetLastError();
+}
+
+}  // namespace mfft

@@ -1,0 +1,39 @@
+// Host-side launchers of the HIP kernels (definitions in kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "internal.h"
+
+namespace mfft {
+
+// Rank-0 plan (Section 4.2, "Rank-0 plans"): strided element copy over up to
+// 8 loops.  elem_bytes is 8 (FP32 complex) or 16 (FP64 complex).
+struct CopyArgs {
+    const void *in;
+    void *out;
+    int32_t rank;
+    int32_t elem_bytes;
+    int64_t total;
+    int64_t n[8], is[8], os[8];
+};
+
+hipError_t launch_pass(const PassArgs &a, int prec, int emax, size_t lds_bytes, hipStream_t s);
+hipError_t launch_batch(const PassArgs *items_dev, const int64_t *prefix_dev, int nitems,
+                        unsigned long long *counter, int prec, int kind, int block, int grid,
+                        size_t lds_bytes, hipStream_t s);
+int pass_kind(uint32_t flags);
+hipError_t launch_copy(const CopyArgs &a, hipStream_t s);
+hipError_t launch_gen_stage_twiddles(void *out, int prec, int Ns, int R, hipStream_t s);
+hipError_t launch_gen_tw4(void *hi, int64_t nhi, void *lo, int64_t nlo, int shift, int64_t N,
+                          hipStream_t s);
+hipError_t launch_gen_chirp(void *c, int64_t n, hipStream_t s);
+hipError_t launch_gen_bluestein_v(void *v, const void *c, int64_t n, int64_t M, hipStream_t s);
+hipError_t launch_gen_rader(int32_t *gather, int32_t *scatter, void *b, int64_t p, int64_t g,
+                            hipStream_t s);
+hipError_t launch_convert_scale(void *out, int prec, const void *in, int64_t count, double scale,
+                                hipStream_t s);
+hipError_t launch_zero_u64(unsigned long long *p, int count, hipStream_t s);
+
+}  // namespace mfft

@@ -1,0 +1,284 @@
+// HIP kernels for gfx950 besides the tile kernel: the rank-0 copy kernel, the
+// FP64 table generators (Section 6: twiddles computed accurately, here in FP64
+// on the GPU and rounded once), and the launch dispatch over the tile-kernel
+// variants.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "internal.h"
+#include "kernels.h"
+
+namespace mfft {
+
+template <typename T>
+struct alignas(2 * sizeof(T)) cpx {
+    T re, im;
+};
+
+// ------------------------------------------------------------ rank-0 copy
+
+__global__ void copy_kernel(CopyArgs a)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.total) return;
+    int64_t rem = i, oi = 0, oo = 0;
+    for (int d = a.rank - 1; d >= 0; --d) {
+        const int64_t q = rem / a.n[d];
+        const int64_t idx = rem - q * a.n[d];
+        rem = q;
+        oi += idx * a.is[d];
+        oo += idx * a.os[d];
+    }
+    if (a.elem_bytes == 8) {
+        ((uint2 *)a.out)[oo] = ((const uint2 *)a.in)[oi];
+    } else {
+        ((uint4 *)a.out)[oo] = ((const uint4 *)a.in)[oi];
+    }
+}
+
+// ------------------------------------------------------------ FP64 tables
+
+// exp(-2 pi i e / N) in FP64.  The angle is reduced with exact integer
+// arithmetic to at most an eighth of a turn before sincospi, so the
+// eighth roots of unity come out exact and the table is conjugate-symmetric.
+__device__ double2 root_fp64(int64_t e, int64_t N)
+{
+    e %= N;
+    if (e < 0) e += N;
+    // angle = num / den turns
+    int64_t num = e, den = N;
+    double ssign = 1.0, csign = 1.0;
+    bool swap = false;
+    if (2 * num > den) {          // a -> 1 - a : sin flips
+        num = den - num;
+        ssign = -1.0;
+    }
+    if (4 * num > den) {          // a -> 1/2 - a : cos flips
+        num = den - 2 * num;
+        den *= 2;
+        csign = -1.0;
+    }
+    if (8 * num > den) {          // a -> 1/4 - a : cos <-> sin
+        num = den - 4 * num;
+        den *= 4;
+        swap = true;
+    }
+    double s, c;
+    sincospi(2.0 * (double)num / (double)den, &s, &c);
+    if (swap) {
+        const double t = s;
+        s = c;
+        c = t;
+    }
+    return make_double2(csign * c, -(ssign * s));
+}
+
+template <typename T>
+__global__ void gen_stage_twiddles(cpx<T> *out, int32_t Ns, int32_t R)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)Ns * (R - 1)) return;
+    const int64_t j = e / (R - 1), k = e % (R - 1) + 1;
+    const double2 w = root_fp64(j * k, (int64_t)Ns * R);
+    out[e] = {T(w.x), T(w.y)};
+}
+
+__global__ void gen_tw4(double2 *hi, int64_t nhi, double2 *lo, int64_t nlo, int32_t shift, int64_t N)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < nhi) hi[e] = root_fp64(e << shift, N);
+    if (e < nlo) lo[e] = root_fp64(e, N);
+}
+
+// Bluestein chirp c_k = exp(-pi i (k^2 mod 2n) / n), k < n, FP64.
+__global__ void gen_chirp(double2 *c, int64_t n)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int64_t km = k % (2 * n);
+    const int64_t q = (int64_t)(((uint64_t)km * (uint64_t)km) % (uint64_t)(2 * n));   // n < 2^31
+    c[k] = root_fp64(q, 2 * n);
+}
+
+// Wrapped conj(chirp) sequence of length M for the convolution kernel.
+__global__ void gen_bluestein_v(double2 *v, const double2 *c, int64_t n, int64_t M)
+{
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= M) return;
+    double2 r = make_double2(0.0, 0.0);
+    if (m < n) r = make_double2(c[m].x, -c[m].y);
+    else if (M - m < n) r = make_double2(c[M - m].x, -c[M - m].y);
+    v[m] = r;
+}
+
+__device__ int64_t modpow(int64_t b, int64_t e, int64_t p)
+{
+    int64_t r = 1 % p;
+    b %= p;
+    while (e > 0) {
+        if (e & 1) r = (r * b) % p;
+        b = (b * b) % p;
+        e >>= 1;
+    }
+    return r;
+}
+
+// Rader tables for prime p with generator g: gather[j] = g^j, scatter[q] =
+// g^-q (mod p), and the sequence b_m = w_p^(g^-m) in FP64.
+__global__ void gen_rader(int32_t *gather, int32_t *scatter, double2 *b, int64_t p, int64_t g)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= p - 1) return;
+    gather[j] = (int32_t)modpow(g, j, p);
+    const int64_t inv = modpow(g, (p - 1 - j) % (p - 1), p);
+    scatter[j] = (int32_t)inv;
+    b[j] = root_fp64(inv, p);
+}
+
+// out[k] = T(in[k] * s) (FP64 product, one rounding)
+template <typename T>
+__global__ void convert_scale(cpx<T> *out, const double2 *in, int64_t count, double s)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= count) return;
+    out[k] = {T(in[k].x * s), T(in[k].y * s)};
+}
+
+// ------------------------------------------------------------ launchers
+
+static inline unsigned blocks_for(int64_t count, int threads)
+{
+    return (unsigned)((count + threads - 1) / threads);
+}
+
+// per-variant launchers (k_c32_k0.hip, ...)
+#define MFFT_VARIANT(P, K)                                                                   \
+    hipError_t launch_pass_##P##_k##K(const PassArgs &a, size_t lds, hipStream_t s);          \
+    hipError_t launch_batch_##P##_k##K(const PassArgs *items, const int64_t *prefix,         \
+                                       int nitems, unsigned long long *counter, int block,    \
+                                       int grid, size_t lds, hipStream_t s);
+MFFT_VARIANT(c32, 0)
+MFFT_VARIANT(c32, 1)
+MFFT_VARIANT(c32, 3)
+MFFT_VARIANT(c64, 0)
+MFFT_VARIANT(c64, 1)
+MFFT_VARIANT(c64, 3)
+#undef MFFT_VARIANT
+
+// Kernel kind needed by a pass: 0 plain, 1 Cooley-Tukey twiddles, 3 all features.
+int pass_kind(uint32_t flags)
+{
+    const uint32_t ext = PF_PRE_MUL | PF_GATHER | PF_CONV | PF_CONJ_A | PF_POST_MUL |
+                         PF_SCATTER | PF_RADER | PF_AUX_X0 | PF_AUX_A0 | PF_AUX_ADD;
+    if (flags & ext) return 3;
+    if (flags & PF_TW4) return 1;
+    return 0;
+}
+
+hipError_t launch_pass(const PassArgs &a, int prec, int emax, size_t lds_bytes, hipStream_t s)
+{
+    (void)emax;
+    if (a.ntiles <= 0) return hipSuccess;
+    if (a.ntiles > 0x7fffffffLL) return hipErrorInvalidValue;
+    const int k = pass_kind(a.flags);
+    if (prec == 0) {
+        if (k == 0) return launch_pass_c32_k0(a, lds_bytes, s);
+        if (k == 1) return launch_pass_c32_k1(a, lds_bytes, s);
+        return launch_pass_c32_k3(a, lds_bytes, s);
+    }
+    if (k == 0) return launch_pass_c64_k0(a, lds_bytes, s);
+    if (k == 1) return launch_pass_c64_k1(a, lds_bytes, s);
+    return launch_pass_c64_k3(a, lds_bytes, s);
+}
+
+hipError_t launch_batch(const PassArgs *items_dev, const int64_t *prefix_dev, int nitems,
+                        unsigned long long *counter, int prec, int kind, int block, int grid,
+                        size_t lds_bytes, hipStream_t s)
+{
+    if (prec == 0) {
+        if (kind == 0) return launch_batch_c32_k0(items_dev, prefix_dev, nitems, counter, block, grid, lds_bytes, s);
+        if (kind == 1) return launch_batch_c32_k1(items_dev, prefix_dev, nitems, counter, block, grid, lds_bytes, s);
+        return launch_batch_c32_k3(items_dev, prefix_dev, nitems, counter, block, grid, lds_bytes, s);
+    }
+    if (kind == 0) return launch_batch_c64_k0(items_dev, prefix_dev, nitems, counter, block, grid, lds_bytes, s);
+    if (kind == 1) return launch_batch_c64_k1(items_dev, prefix_dev, nitems, counter, block, grid, lds_bytes, s);
+    return launch_batch_c64_k3(items_dev, prefix_dev, nitems, counter, block, grid, lds_bytes, s);
+}
+
+hipError_t launch_copy(const CopyArgs &a, hipStream_t s)
+{
+    if (a.total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(copy_kernel, dim3(blocks_for(a.total, 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_gen_stage_twiddles(void *out, int prec, int Ns, int R, hipStream_t s)
+{
+    const int64_t cnt = (int64_t)Ns * (R - 1);
+    if (cnt <= 0) return hipSuccess;
+    if (prec == 0)
+        hipLaunchKernelGGL(gen_stage_twiddles<float>, dim3(blocks_for(cnt, 256)), dim3(256), 0, s,
+                           (cpx<float> *)out, Ns, R);
+    else
+        hipLaunchKernelGGL(gen_stage_twiddles<double>, dim3(blocks_for(cnt, 256)), dim3(256), 0,
+                           s, (cpx<double> *)out, Ns, R);
+    return hipGetLastError();
+}
+
+hipError_t launch_gen_tw4(void *hi, int64_t nhi, void *lo, int64_t nlo, int shift, int64_t N,
+                          hipStream_t s)
+{
+    const int64_t cnt = nhi > nlo ? nhi : nlo;
+    hipLaunchKernelGGL(gen_tw4, dim3(blocks_for(cnt, 256)), dim3(256), 0, s, (double2 *)hi, nhi,
+                       (double2 *)lo, nlo, shift, N);
+    return hipGetLastError();
+}
+
+hipError_t launch_gen_chirp(void *c, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(gen_chirp, dim3(blocks_for(n, 256)), dim3(256), 0, s, (double2 *)c, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_gen_bluestein_v(void *v, const void *c, int64_t n, int64_t M, hipStream_t s)
+{
+    hipLaunchKernelGGL(gen_bluestein_v, dim3(blocks_for(M, 256)), dim3(256), 0, s, (double2 *)v,
+                       (const double2 *)c, n, M);
+    return hipGetLastError();
+}
+
+hipError_t launch_gen_rader(int32_t *gather, int32_t *scatter, void *b, int64_t p, int64_t g,
+                            hipStream_t s)
+{
+    hipLaunchKernelGGL(gen_rader, dim3(blocks_for(p - 1, 256)), dim3(256), 0, s, gather, scatter,
+                       (double2 *)b, p, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_convert_scale(void *out, int prec, const void *in, int64_t count, double scale,
+                                hipStream_t s)
+{
+    if (prec == 0)
+        hipLaunchKernelGGL(convert_scale<float>, dim3(blocks_for(count, 256)), dim3(256), 0, s,
+                           (cpx<float> *)out, (const double2 *)in, count, scale);
+    else
+        hipLaunchKernelGGL(convert_scale<double>, dim3(blocks_for(count, 256)), dim3(256), 0, s,
+                           (cpx<double> *)out, (const double2 *)in, count, scale);
+    return hipGetLastError();
+}
+
+// Clears a counter array with a kernel (graph-capture friendly).
+__global__ void zero_u64(unsigned long long *p, int count)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = 0ull;
+}
+
+hipError_t launch_zero_u64(unsigned long long *p, int count, hipStream_t s)
+{
+    hipLaunchKernelGGL(zero_u64, dim3(blocks_for(count, 256)), dim3(256), 0, s, p, count);
+    return hipGetLastError();
+}
+
+}  // namespace mfft

@@ -1,0 +1,991 @@
+// The planner: turns a canonical dft(N, V, I, O) into a list of GPU passes.
+//
+// Plan steps (Section 4.2), each realized as passes of the tile kernel:
+//   - direct plan: a line of length n that fits one workgroup's LDS is one
+//     pass (the leaf, a Stockham FFT held in LDS);
+//   - Cooley-Tukey DIT step with radix r = n/m: pass A solves
+//     dft({(m, r*is, os)}, V u {(r, is, m*os)}, I, O) and multiplies by the
+//     twiddles w_n^(l2*k1) as it stores; pass B solves
+//     dft({(r, m*os, m*os)}, copy-o(V) u {(m, os, os)}, O, O)  (four-step,
+//     Section 3.1, used when n is larger than one leaf);
+//   - vector loops become the launch grid (Section 4.2, "Plans for higher
+//     vector ranks"); strided lines are loaded and stored through LDS tiles
+//     across a unit-stride vector loop (vector recursion, Section 4.2.5);
+//   - multi-dimensional transforms are one rank-1 step per dimension, the
+//     first out of place, the rest in place on the output with copy-o strides
+//     (Section 4.2 reduces rank > 1 to rank-1 problems);
+//   - prime sizes: Rader's algorithm when p-1 factors into the supported
+//     radices, Bluestein's chirp-z otherwise (Section 4.2, "Plans for prime
+//     sizes"), each one kernel when the convolution fits a leaf;
+//   - rank 0: a copy (Section 4.2, "Rank-0 plans").
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <sstream>
+
+#include "plan.h"
+
+namespace mfft {
+
+size_t g_lds_budget = 65536;   // bytes of LDS one workgroup may use
+
+static int elem_bytes(int prec) { return prec ? 16 : 8; }
+
+// ------------------------------------------------------------ memory
+
+void *dev_alloc(PlanImpl *p, size_t bytes)
+{
+    if (bytes == 0) return nullptr;
+    void *ptr = nullptr;
+    if (p->has_alloc && p->alloc.alloc) {
+        ptr = p->alloc.alloc(bytes, (void *)p->stream, p->alloc.ctx);
+    } else if (hipMalloc(&ptr, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        ptr = nullptr;
+    }
+    return ptr;
+}
+
+void dev_free(PlanImpl *p, void *ptr, size_t bytes)
+{
+    (void)bytes;
+    if (!ptr) return;
+    if (p->has_alloc && p->alloc.free) p->alloc.free(ptr, (void *)p->stream, p->alloc.ctx);
+    else (void)hipFree(ptr);
+}
+
+static void *table_alloc(PlanImpl *p, size_t bytes)
+{
+    void *ptr = dev_alloc(p, bytes);
+    if (ptr) {
+        p->tables.push_back({ptr, bytes});
+        p->table_bytes += bytes;
+    }
+    return ptr;
+}
+
+// ------------------------------------------------------------ leaf shapes
+
+struct Leaf {
+    int n = 0;
+    std::vector<int> rad;
+    int emax = 16;
+    int tpt = 0;
+    int lds_stride = 0;
+};
+
+static bool radices_for(int64_t n, std::vector<int> *r)
+{
+    if (n < 2 || !is_smooth7(n)) return false;
+    int64_t m = n;
+    int a = 0;
+    while (m % 2 == 0) {
+        m /= 2;
+        ++a;
+    }
+    std::vector<int> rad;
+    while (a >= 4) {
+        rad.push_back(16);
+        a -= 4;
+    }
+    if (a == 3) rad.push_back(8);
+    else if (a == 2) rad.push_back(4);
+    else if (a == 1) rad.push_back(2);
+    while (m % 7 == 0) {
+        rad.push_back(7);
+        m /= 7;
+    }
+    while (m % 5 == 0) {
+        rad.push_back(5);
+        m /= 5;
+    }
+    while (m % 3 == 0) {
+        rad.push_back(3);
+        m /= 3;
+    }
+    if ((int)rad.size() > kMaxStages) return false;
+    *r = rad;
+    return true;
+}
+
+static int line_lds_stride(int n)
+{
+    int s = lds_pad(n - 1) + 1;
+    return s | 1;
+}
+
+static size_t tile_lds_bytes(int n, int bt, int prec)
+{
+    return ((size_t)bt * line_lds_stride(n) + 2 * (size_t)bt) * elem_bytes(prec);
+}
+
+static bool make_leaf_shape(int64_t n, int emax, Leaf *L)
+{
+    if (n < 2 || n > (1 << 20)) return false;
+    std::vector<int> rad;
+    if (!radices_for(n, &rad)) return false;
+    int tpt = 1;
+    for (int R : rad) {
+        const int nbmax = emax / R;
+        if (nbmax < 1) return false;
+        const int nb = (int)(n / R);
+        tpt = std::max(tpt, (nb + nbmax - 1) / nbmax);
+    }
+    if (tpt > 1024) return false;
+    L->n = (int)n;
+    L->rad = rad;
+    L->emax = emax;
+    L->tpt = tpt;
+    L->lds_stride = line_lds_stride((int)n);
+    return true;
+}
+
+// A line of length n fits a leaf pass with at least `bt` lines per tile.
+static bool leaf_fits(int64_t n, int prec, int bt)
+{
+    Leaf L;
+    if (!make_leaf_shape(n, 16, &L)) return false;
+    return tile_lds_bytes((int)n, bt, prec) <= g_lds_budget && bt * L.tpt <= 1024;
+}
+
+// Stage twiddle table for a leaf: stage s holds w_(Ns*R)^(j*k) for j < Ns,
+// 1 <= k < R at [tw_off + j*(R-1) + k-1]; the stage sizes telescope to n-1.
+static int fill_leaf(PlanImpl *p, const Leaf &L, PassArgs *a,
+                     std::map<std::string, void *> *cache)
+{
+    std::ostringstream key;
+    key << p->prob.prec << ":" << L.n;
+    for (int R : L.rad) key << "," << R;
+    int64_t off = 0;
+    int Ns = 1;
+    a->n = L.n;
+    a->nst = (int)L.rad.size();
+    a->tpt = L.tpt;
+    a->lds_stride = L.lds_stride;
+    for (size_t s = 0; s < L.rad.size(); ++s) {
+        StageDesc &sd = a->st[s];
+        sd.R = L.rad[s];
+        sd.Ns = Ns;
+        div_magic((uint32_t)Ns, &sd.magic, &sd.shift);
+        sd.tw_off = (int32_t)off;
+        sd.nb = L.n / sd.R;
+        off += (int64_t)Ns * (sd.R - 1);
+        Ns *= sd.R;
+    }
+    auto it = cache->find(key.str());
+    if (it != cache->end()) {
+        a->tw = it->second;
+        return MFFT_OK;
+    }
+    const size_t eb = elem_bytes(p->prob.prec);
+    void *tw = table_alloc(p, (size_t)std::max<int64_t>(off, 1) * eb);
+    if (!tw) return fail(MFFT_ENOMEM, "twiddle table allocation failed");
+    for (size_t s = 0; s < L.rad.size(); ++s) {
+        const StageDesc &sd = a->st[s];
+        if (sd.Ns == 1) continue;
+        hipError_t e = launch_gen_stage_twiddles((char *)tw + (size_t)sd.tw_off * eb, p->prob.prec,
+                                                 sd.Ns, sd.R, p->stream);
+        if (e != hipSuccess) return fail(MFFT_EHIP, std::string("twiddle kernel: ") + hipGetErrorString(e));
+    }
+    (*cache)[key.str()] = tw;
+    a->tw = tw;
+    return MFFT_OK;
+}
+
+// ------------------------------------------------------------ pass building
+
+struct LineSpec {
+    Dim line;                  // (n, is, os) of the line
+    std::vector<Dim> V;        // vector loops
+    int inner = -1;            // forced index of the tiled loop in V (-1 = choose)
+    int src = BUF_IN, dst = BUF_OUT;
+    int64_t src_off = 0, dst_off = 0;
+    uint32_t flags = 0;
+    int64_t li_c = 0, li_l = 1, li_lim = -1;   // -1: n
+    int64_t lo_c = 0, lo_k = 1, lo_lim = -1;
+    int64_t tw4_N = 0;
+    const void *pre = nullptr, *post = nullptr, *conv = nullptr;
+    const int32_t *gather = nullptr, *scatter = nullptr;
+    int64_t aux_off = -1;
+    int64_t conv_n = 0;        // leaf length when it differs from line.n (Bluestein / Rader)
+    std::string what;
+};
+
+struct Builder {
+    PlanImpl *p;
+    std::map<std::string, void *> twcache;
+    std::map<int64_t, std::pair<void *, void *>> tw4cache;
+    int64_t scratch_top = 0;   // bytes
+    int64_t scratch_hi = 0;
+
+    int64_t scratch_take(int64_t bytes)
+    {
+        int64_t off = (scratch_top + 255) / 256 * 256;
+        scratch_top = off + bytes;
+        scratch_hi = std::max(scratch_hi, scratch_top);
+        return off;
+    }
+};
+
+static int ilog2(int x)
+{
+    int l = 0;
+    while ((1 << l) < x) ++l;
+    return l;
+}
+
+static int tw4_tables(Builder &b, int64_t N, PassArgs *a)
+{
+    int shift = 0;
+    while (((int64_t)1 << (2 * shift)) < N) ++shift;     // 2^shift ~ sqrt(N)
+    const int64_t nlo = (int64_t)1 << shift;
+    const int64_t nhi = (N + nlo - 1) / nlo;
+    auto it = b.tw4cache.find(N);
+    void *hi, *lo;
+    if (it != b.tw4cache.end()) {
+        hi = it->second.first;
+        lo = it->second.second;
+    } else {
+        hi = table_alloc(b.p, (size_t)nhi * 16);
+        lo = table_alloc(b.p, (size_t)nlo * 16);
+        if (!hi || !lo) return fail(MFFT_ENOMEM, "twiddle table allocation failed");
+        hipError_t e = launch_gen_tw4(hi, nhi, lo, nlo, shift, N, b.p->stream);
+        if (e != hipSuccess) return fail(MFFT_EHIP, std::string("tw4 kernel: ") + hipGetErrorString(e));
+        b.tw4cache[N] = {hi, lo};
+    }
+    a->tw4_hi = hi;
+    a->tw4_lo = lo;
+    a->tw4_N = N;
+    a->tw4_shift = shift;
+    a->tw4_mask = (int32_t)(nlo - 1);
+    return MFFT_OK;
+}
+
+static std::string dims_str(const Dim &d) {
+    std::ostringstream s;
+    s << "(" << d.n << "," << d.is << "," << d.os << ")";
+    return s.str();
+}
+
+static int add_line_pass(Builder &b, const LineSpec &ls)
+{
+    PlanImpl *p = b.p;
+    const int prec = p->prob.prec;
+    const int64_t n = ls.conv_n ? ls.conv_n : ls.line.n;
+    Pass ps;
+    PassArgs &a = ps.a;
+    Leaf L;
+    if (!make_leaf_shape(n, 16, &L)) return fail(MFFT_ENOTSUP, "no leaf shape for n");
+    ps.emax = L.emax;
+    int rc = fill_leaf(p, L, &a, &b.twcache);
+    if (rc) return rc;
+
+    // choose the tiled (inner) vector loop
+    std::vector<Dim> V = ls.V;
+    int inner = ls.inner;
+    const bool row_in = std::llabs(ls.line.is) == 1 || (ls.flags & PF_GATHER);
+    const bool row_out = std::llabs(ls.line.os) == 1 || (ls.flags & PF_SCATTER);
+    if (inner < 0 && !V.empty()) {
+        int best = -1;
+        int64_t best_score = INT64_MIN;
+        for (size_t i = 0; i < V.size(); ++i) {
+            int64_t sc = 0;
+            if (!row_in && std::llabs(V[i].is) == 1) sc += 4;
+            if (!row_out && std::llabs(V[i].os) == 1) sc += 4;
+            if (row_in && row_out) sc -= std::llabs(V[i].is);   // any loop; prefer small stride
+            sc = sc * 64 + std::min<int64_t>(V[i].n, 63);
+            if (sc > best_score) {
+                best_score = sc;
+                best = (int)i;
+            }
+        }
+        inner = best;
+    }
+    Dim in_dim{1, 0, 0};
+    if (inner >= 0) {
+        in_dim = V[inner];
+        V.erase(V.begin() + inner);
+    }
+    if ((int)V.size() > kMaxOuter) return fail(MFFT_ENOTSUP, "too many vector loops for one pass");
+    a.vn = in_dim.n;
+    a.vis = in_dim.is;
+    a.vos = in_dim.os;
+    a.nouter = (int)V.size();
+    int64_t nouter_total = 1;
+    for (size_t i = 0; i < V.size(); ++i) {
+        a.on[i] = V[i].n;
+        a.ois[i] = V[i].is;
+        a.oos[i] = V[i].os;
+        nouter_total *= V[i].n;
+    }
+    a.load_mode = (!row_in && std::llabs(in_dim.is) < std::llabs(ls.line.is) && in_dim.n > 1)
+                      ? kModeCol : kModeRow;
+    a.store_mode = (!row_out && std::llabs(in_dim.os) < std::llabs(ls.line.os) && in_dim.n > 1)
+                       ? kModeCol : kModeRow;
+    if ((ls.flags & PF_GATHER) && a.load_mode == kModeCol) a.load_mode = kModeRow;
+
+    // lines per tile: column phases want >= 128 B runs; row tiles aim at
+    // 256-thread workgroups.  Both bounded by the LDS budget.
+    const bool col = a.load_mode == kModeCol || a.store_mode == kModeCol;
+    int bt;
+    if (col) bt = prec ? 8 : 16;
+    else bt = std::max(1, 256 / L.tpt);
+    bt = 1 << ilog2(bt);
+    if (bt > 1 && (1 << ilog2(bt)) != bt) bt >>= 1;
+    while (bt > 1 && (tile_lds_bytes(L.n, bt, prec) > g_lds_budget || bt * L.tpt > 1024)) bt >>= 1;
+    while (bt > 1 && bt / 2 >= in_dim.n) bt >>= 1;   // no wider than the loop
+    if (tile_lds_bytes(L.n, bt, prec) > g_lds_budget || bt * L.tpt > 1024)
+        return fail(MFFT_ENOTSUP, "leaf does not fit the LDS budget");
+    a.bt = bt;
+    a.bt_log2 = ilog2(bt);
+    a.ntiles_inner = (a.vn + bt - 1) / bt;
+    a.ntiles = a.ntiles_inner * nouter_total;
+    ps.lds_bytes = tile_lds_bytes(L.n, bt, prec);
+
+    a.is = ls.line.is;
+    a.os = ls.line.os;
+    a.flags = ls.flags;
+    a.li_c = ls.li_c;
+    a.li_l = ls.li_l;
+    a.li_lim = ls.li_lim < 0 ? n : ls.li_lim;
+    a.lo_c = ls.lo_c;
+    a.lo_k = ls.lo_k;
+    a.lo_lim = ls.lo_lim < 0 ? n : ls.lo_lim;
+    a.pre = ls.pre;
+    a.post = ls.post;
+    a.conv = ls.conv;
+    a.gather = ls.gather;
+    a.scatter = ls.scatter;
+    if (ls.flags & PF_TW4) {
+        rc = tw4_tables(b, ls.tw4_N, &a);
+        if (rc) return rc;
+    }
+    ps.src = ls.src;
+    ps.dst = ls.dst;
+    ps.src_off = ls.src_off;
+    ps.dst_off = ls.dst_off;
+    ps.aux_off = ls.aux_off;
+    const int64_t lines = a.vn * nouter_total;
+    const int64_t nin = std::min<int64_t>(a.li_lim, n), nout = std::min<int64_t>(a.lo_lim, n);
+    ps.bytes = (double)lines * (double)(nin + nout) * elem_bytes(prec);
+    if (ls.flags & (PF_CONV)) ps.bytes = (double)lines * (double)(ls.line.n * 2) * elem_bytes(prec);
+    std::ostringstream d;
+    d << ls.what << " n=" << n << " rad=";
+    for (size_t i = 0; i < L.rad.size(); ++i) d << (i ? "x" : "") << L.rad[i];
+    d << " tpt=" << L.tpt << " bt=" << bt << " " << (a.load_mode ? "C" : "R")
+      << (a.store_mode ? "C" : "R") << " line=" << dims_str(ls.line) << " inner=" << dims_str(in_dim)
+      << " tiles=" << a.ntiles;
+    ps.desc = d.str();
+    p->passes.push_back(ps);
+    return MFFT_OK;
+}
+
+// ------------------------------------------------------------ rank-1 algorithms
+
+static std::vector<Dim> copy_o(const std::vector<Dim> &V)
+{
+    std::vector<Dim> r;
+    for (const Dim &d : V) r.push_back({d.n, d.os, d.os});
+    return r;
+}
+
+// Packed layout of the vector loops in a scratch buffer whose transforms are
+// `per` elements apart: returns V with input strides replaced (which=0) or
+// output strides replaced (which=1).
+static std::vector<Dim> packed(const std::vector<Dim> &V, int64_t per, int which)
+{
+    std::vector<Dim> r = V;
+    int64_t s = per;
+    for (int i = (int)r.size() - 1; i >= 0; --i) {
+        if (which == 0) r[i].is = s;
+        else r[i].os = s;
+        s *= r[i].n;
+    }
+    return r;
+}
+
+static int64_t vprod(const std::vector<Dim> &V)
+{
+    int64_t t = 1;
+    for (const Dim &d : V) t *= d.n;
+    return t;
+}
+
+struct Split {
+    int64_t m = 0, r = 0;
+};
+
+// Cooley-Tukey split n = m * r for a two-pass transform: both factors must be
+// leaves whose column tiles fit the LDS budget; the most balanced split wins
+// (the radix-sqrt(n) step of Section 3).
+static bool choose_split(int64_t n, int prec, Split *sp)
+{
+    const int btmin = prec ? 4 : 8;
+    int64_t best_m = 0;
+    double best = 1e300;
+    for (int64_t m = 2; m * m <= n * 64 && m < n; ++m) {
+        if (n % m) continue;
+        const int64_t r = n / m;
+        if (!leaf_fits(m, prec, btmin) || !leaf_fits(r, prec, btmin)) continue;
+        const double cost = std::fabs(std::log((double)m) - std::log((double)r));
+        if (cost < best) {
+            best = cost;
+            best_m = m;
+        }
+    }
+    if (!best_m) return false;
+    sp->m = best_m;
+    sp->r = n / best_m;
+    return true;
+}
+
+static int plan_line(Builder &b, Dim d, std::vector<Dim> V, int src, int dst, int64_t src_off,
+                     int64_t dst_off, bool conj_in, bool conj_out);
+
+// Leaf: one pass.
+static int plan_leaf(Builder &b, Dim d, const std::vector<Dim> &V, int src, int dst,
+                     int64_t src_off, int64_t dst_off, bool conj_in, bool conj_out)
+{
+    LineSpec ls;
+    ls.line = d;
+    ls.V = V;
+    ls.src = src;
+    ls.dst = dst;
+    ls.src_off = src_off;
+    ls.dst_off = dst_off;
+    ls.flags = (conj_in ? PF_CONJ_IN : 0) | (conj_out ? PF_CONJ_OUT : 0);
+    ls.what = "leaf";
+    return add_line_pass(b, ls);
+}
+
+// Cooley-Tukey DIT step, radix r = n/m (Section 4.2).
+static int plan_ct(Builder &b, Dim d, const std::vector<Dim> &V, int src, int dst,
+                   int64_t src_off, int64_t dst_off, bool conj_in, bool conj_out, Split sp)
+{
+    const int64_t n = d.n, m = sp.m, r = sp.r;
+    const int eb = elem_bytes(b.p->prob.prec);
+    const bool oop = !(src == dst && src_off == dst_off);
+    LineSpec A;
+    A.what = "ctA";
+    A.flags = PF_TW4 | (conj_in ? PF_CONJ_IN : 0);
+    A.tw4_N = n;
+    A.src = src;
+    A.src_off = src_off;
+    if (oop && dst != BUF_IN) {
+        // pass A straight into the output, pass B in place there
+        A.line = {m, r * d.is, d.os};
+        A.V = V;
+        A.V.push_back({r, d.is, m * d.os});
+        A.inner = (int)A.V.size() - 1;
+        A.dst = dst;
+        A.dst_off = dst_off;
+        int rc = add_line_pass(b, A);
+        if (rc) return rc;
+        Dim dB{r, m * d.os, m * d.os};
+        std::vector<Dim> VB = copy_o(V);
+        VB.push_back({m, d.os, d.os});
+        return plan_line(b, dB, VB, dst, dst, dst_off, dst_off, false, conj_out);
+    }
+    // in place: pass A into packed scratch (transform v at v*n, element l2*m + k1)
+    const int64_t H = vprod(V);
+    const int64_t off = b.scratch_take(H * n * eb) / eb;
+    A.line = {m, r * d.is, 1};
+    A.V = packed(V, n, 1);
+    A.V.push_back({r, d.is, m});
+    A.inner = (int)A.V.size() - 1;
+    A.dst = BUF_SCRATCH;
+    A.dst_off = off;
+    int rc = add_line_pass(b, A);
+    if (rc) return rc;
+    Dim dB{r, m, m * d.os};
+    std::vector<Dim> VB = packed(V, n, 0);
+    VB.push_back({m, 1, d.os});
+    return plan_line(b, dB, VB, BUF_SCRATCH, dst, off, dst_off, false, conj_out);
+}
+
+// Rader's algorithm for prime p (Section 4.2, "Plans for prime sizes"):
+// Y[0] = sum x; Y[g^-q] = x0 + sum_j x[g^j] w_p^(g^(j-q)), a cyclic
+// convolution of length p-1 evaluated by FFT, pointwise product with the
+// precomputed DFT of b_m = w_p^(g^-m), and inverse FFT.
+static int rader_tables(Builder &b, int64_t pr, int32_t **gather, int32_t **scatter,
+                        void **spec);
+static int bluestein_tables(Builder &b, int64_t n, int64_t M, void **chirp, void **spec);
+
+static int plan_rader(Builder &b, Dim d, const std::vector<Dim> &V, int src, int dst,
+                      int64_t src_off, int64_t dst_off, bool conj_in, bool conj_out)
+{
+    const int64_t pr = d.n, L = pr - 1;
+    const int eb = elem_bytes(b.p->prob.prec);
+    int32_t *gat, *sct;
+    void *spec;
+    int rc = rader_tables(b, pr, &gat, &sct, &spec);
+    if (rc) return rc;
+    const int btmin = b.p->prob.prec ? 4 : 8;
+    if (leaf_fits(L, b.p->prob.prec, 1)) {
+        LineSpec ls;
+        ls.what = "rader";
+        ls.line = d;
+        ls.conv_n = L;
+        ls.V = V;
+        ls.src = src;
+        ls.dst = dst;
+        ls.src_off = src_off;
+        ls.dst_off = dst_off;
+        ls.flags = PF_CONV | PF_RADER | PF_GATHER | PF_SCATTER | PF_CONJ_A |
+                   (conj_in ? PF_CONJ_IN : 0) | (conj_out ? PF_CONJ_OUT : 0);
+        ls.li_lim = L;
+        ls.lo_lim = L;
+        ls.gather = gat;
+        ls.scatter = sct;
+        ls.conv = spec;
+        if (src == dst && src_off == dst_off && d.is != d.os)
+            return fail(MFFT_ENOTSUP, "in-place Rader needs equal strides");
+        return add_line_pass(b, ls);
+    }
+    Split sp;
+    if (!choose_split(L, b.p->prob.prec, &sp)) return fail(MFFT_ENOTSUP, "Rader length too large");
+    (void)btmin;
+    const int64_t m1 = sp.m, r1 = sp.r;
+    const int64_t H = vprod(V);
+    const int64_t s0 = b.scratch_take(H * L * eb) / eb;
+    const int64_t s1 = b.scratch_take(H * L * eb) / eb;
+    const int64_t aux = b.scratch_take(H * 2 * eb);
+    std::vector<Dim> Vp = packed(V, L, 1);   // outputs packed in scratch
+    // P1: pass A over a[li] = x[g^li], li = c + l*r1, twiddled; saves x0
+    LineSpec A;
+    A.what = "raderA";
+    A.line = {m1, d.is, 1};
+    A.V = V;
+    for (size_t i = 0; i < A.V.size(); ++i) A.V[i].os = Vp[i].os;
+    A.V.push_back({r1, 0, m1});
+    A.inner = (int)A.V.size() - 1;
+    A.src = src;
+    A.src_off = src_off;
+    A.dst = BUF_SCRATCH;
+    A.dst_off = s0;
+    A.flags = PF_GATHER | PF_TW4 | PF_AUX_X0 | (conj_in ? PF_CONJ_IN : 0);
+    A.gather = gat;
+    A.li_c = 1;
+    A.li_l = r1;
+    A.li_lim = L;
+    A.tw4_N = L;
+    A.aux_off = aux;
+    rc = add_line_pass(b, A);
+    if (rc) return rc;
+    // P2: pass B in place on s0, spectrum multiply, save A0, conj for the inverse
+    LineSpec B;
+    B.what = "raderB";
+    B.line = {r1, m1, m1};
+    B.V = packed(packed(V, L, 0), L, 1);
+    B.V.push_back({m1, 1, 1});
+    B.inner = (int)B.V.size() - 1;
+    B.src = B.dst = BUF_SCRATCH;
+    B.src_off = B.dst_off = s0;
+    B.flags = PF_POST_MUL | PF_AUX_A0 | PF_CONJ_OUT;
+    B.post = spec;
+    B.lo_c = 1;
+    B.lo_k = m1;
+    B.lo_lim = L;
+    B.aux_off = aux;
+    rc = add_line_pass(b, B);
+    if (rc) return rc;
+    // P3: pass A of the inverse (forward FFT of the conjugate), s0 -> s1
+    LineSpec C;
+    C.what = "raderC";
+    C.line = {m1, r1, 1};
+    C.V = packed(packed(V, L, 0), L, 1);
+    C.V.push_back({r1, 1, m1});
+    C.inner = (int)C.V.size() - 1;
+    C.src = C.dst = BUF_SCRATCH;
+    C.src_off = s0;
+    C.dst_off = s1;
+    C.flags = PF_TW4;
+    C.tw4_N = L;
+    rc = add_line_pass(b, C);
+    if (rc) return rc;
+    // P4: pass B, conj back, add x0, scatter to Y[g^-q]; Y[0] = x0 + A0
+    LineSpec D;
+    D.what = "raderD";
+    D.line = {r1, m1, d.os};
+    D.V = packed(V, L, 0);
+    D.V.push_back({m1, 1, 0});
+    D.inner = (int)D.V.size() - 1;
+    D.src = BUF_SCRATCH;
+    D.src_off = s1;
+    D.dst = dst;
+    D.dst_off = dst_off;
+    D.flags = PF_CONJ_A | PF_AUX_ADD | PF_SCATTER | (conj_out ? PF_CONJ_OUT : 0);
+    D.scatter = sct;
+    D.lo_c = 1;
+    D.lo_k = m1;
+    D.lo_lim = L;
+    D.aux_off = aux;
+    return add_line_pass(b, D);
+}
+
+// Bluestein: Y_k = c_k sum_l (x_l c_l) conj(c_(k-l)), c_k = w_(2n)^(k^2 mod 2n),
+// a linear convolution done as a cyclic one of length M >= 2n-1.
+static int plan_bluestein(Builder &b, Dim d, const std::vector<Dim> &V, int src, int dst,
+                          int64_t src_off, int64_t dst_off, bool conj_in, bool conj_out)
+{
+    const int64_t n = d.n;
+    const int prec = b.p->prob.prec;
+    const int eb = elem_bytes(prec);
+    // smallest 7-smooth M >= 2n-1 that is a leaf, else one with a two-pass split
+    int64_t M = 0;
+    bool single = false;
+    for (int64_t c = 2 * n - 1; c <= 4 * n + 64; ++c) {
+        if (!is_smooth7(c)) continue;
+        if (leaf_fits(c, prec, 1)) {
+            M = c;
+            single = true;
+        }
+        break;
+    }
+    if (!M) {
+        for (int64_t c = 2 * n - 1; c <= 4 * n + 64; ++c) {
+            Split sp;
+            if (is_smooth7(c) && choose_split(c, prec, &sp)) {
+                M = c;
+                break;
+            }
+        }
+    }
+    if (!M) return fail(MFFT_ENOTSUP, "no Bluestein length");
+    void *chirp, *spec;
+    int rc = bluestein_tables(b, n, M, &chirp, &spec);
+    if (rc) return rc;
+    if (single) {
+        LineSpec ls;
+        ls.what = "bluestein";
+        ls.line = d;
+        ls.conv_n = M;
+        ls.V = V;
+        ls.src = src;
+        ls.dst = dst;
+        ls.src_off = src_off;
+        ls.dst_off = dst_off;
+        ls.flags = PF_CONV | PF_PRE_MUL | PF_POST_MUL | PF_CONJ_A | (conj_in ? PF_CONJ_IN : 0) |
+                   (conj_out ? PF_CONJ_OUT : 0);
+        ls.li_lim = n;
+        ls.lo_lim = n;
+        ls.pre = chirp;
+        ls.post = chirp;
+        ls.conv = spec;
+        if (src == dst && src_off == dst_off && d.is != d.os)
+            return fail(MFFT_ENOTSUP, "in-place Bluestein needs equal strides");
+        return add_line_pass(b, ls);
+    }
+    Split sp;
+    choose_split(M, prec, &sp);
+    const int64_t m1 = sp.m, r1 = sp.r;
+    const int64_t H = vprod(V);
+    const int64_t s0 = b.scratch_take(H * M * eb) / eb;
+    const int64_t s1 = b.scratch_take(H * M * eb) / eb;
+    std::vector<Dim> Vp = packed(V, M, 1);
+    LineSpec A;
+    A.what = "bluesteinA";
+    A.line = {m1, r1 * d.is, 1};
+    A.V = V;
+    for (size_t i = 0; i < A.V.size(); ++i) A.V[i].os = Vp[i].os;
+    A.V.push_back({r1, d.is, m1});
+    A.inner = (int)A.V.size() - 1;
+    A.src = src;
+    A.src_off = src_off;
+    A.dst = BUF_SCRATCH;
+    A.dst_off = s0;
+    A.flags = PF_PRE_MUL | PF_TW4 | (conj_in ? PF_CONJ_IN : 0);
+    A.pre = chirp;
+    A.li_c = 1;
+    A.li_l = r1;
+    A.li_lim = n;
+    A.tw4_N = M;
+    rc = add_line_pass(b, A);
+    if (rc) return rc;
+    LineSpec B;
+    B.what = "bluesteinB";
+    B.line = {r1, m1, m1};
+    B.V = packed(packed(V, M, 0), M, 1);
+    B.V.push_back({m1, 1, 1});
+    B.inner = (int)B.V.size() - 1;
+    B.src = B.dst = BUF_SCRATCH;
+    B.src_off = B.dst_off = s0;
+    B.flags = PF_POST_MUL | PF_CONJ_OUT;
+    B.post = spec;
+    B.lo_c = 1;
+    B.lo_k = m1;
+    B.lo_lim = M;
+    rc = add_line_pass(b, B);
+    if (rc) return rc;
+    LineSpec C;
+    C.what = "bluesteinC";
+    C.line = {m1, r1, 1};
+    C.V = packed(packed(V, M, 0), M, 1);
+    C.V.push_back({r1, 1, m1});
+    C.inner = (int)C.V.size() - 1;
+    C.src = C.dst = BUF_SCRATCH;
+    C.src_off = s0;
+    C.dst_off = s1;
+    C.flags = PF_TW4;
+    C.tw4_N = M;
+    rc = add_line_pass(b, C);
+    if (rc) return rc;
+    LineSpec D;
+    D.what = "bluesteinD";
+    D.line = {r1, m1, m1 * d.os};
+    D.V = packed(V, M, 0);
+    D.V.push_back({m1, 1, d.os});
+    D.inner = (int)D.V.size() - 1;
+    D.src = BUF_SCRATCH;
+    D.src_off = s1;
+    D.dst = dst;
+    D.dst_off = dst_off;
+    D.flags = PF_CONJ_A | PF_POST_MUL | (conj_out ? PF_CONJ_OUT : 0);
+    D.post = chirp;
+    D.lo_c = 1;
+    D.lo_k = m1;
+    D.lo_lim = n;
+    return add_line_pass(b, D);
+}
+
+static int plan_line(Builder &b, Dim d, std::vector<Dim> V, int src, int dst, int64_t src_off,
+                     int64_t dst_off, bool conj_in, bool conj_out)
+{
+    const int prec = b.p->prob.prec;
+    const int64_t n = d.n;
+    if (is_smooth7(n)) {
+        const bool strided = std::llabs(d.is) != 1 || std::llabs(d.os) != 1;
+        if (leaf_fits(n, prec, strided ? (prec ? 4 : 8) : 1) || leaf_fits(n, prec, 1)) {
+            const bool inplace = src == dst && src_off == dst_off;
+            if (!inplace || d.is == d.os)
+                return plan_leaf(b, d, V, src, dst, src_off, dst_off, conj_in, conj_out);
+        }
+        Split sp;
+        if (!choose_split(n, prec, &sp)) {
+            // three or more passes: peel the largest leaf factor and recurse
+            int64_t best = 0;
+            for (int64_t m = 2; m < n; ++m)
+                if (n % m == 0 && leaf_fits(m, prec, prec ? 4 : 8)) best = m;
+            if (!best) return fail(MFFT_ENOTSUP, "no Cooley-Tukey split");
+            sp.m = best;
+            sp.r = n / best;
+        }
+        return plan_ct(b, d, V, src, dst, src_off, dst_off, conj_in, conj_out, sp);
+    }
+    if (smallest_prime_factor(n) == n && is_smooth7(n - 1))
+        return plan_rader(b, d, V, src, dst, src_off, dst_off, conj_in, conj_out);
+    return plan_bluestein(b, d, V, src, dst, src_off, dst_off, conj_in, conj_out);
+}
+
+// ------------------------------------------------------------ tables for primes
+
+static int rader_tables(Builder &b, int64_t pr, int32_t **gather, int32_t **scatter, void **spec)
+{
+    PlanImpl *p = b.p;
+    const int64_t L = pr - 1;
+    const int64_t g = primitive_root(pr);
+    if (!g) return fail(MFFT_ENOTSUP, "no primitive root");
+    *gather = (int32_t *)table_alloc(p, (size_t)L * 4);
+    *scatter = (int32_t *)table_alloc(p, (size_t)L * 4);
+    *spec = table_alloc(p, (size_t)L * elem_bytes(p->prob.prec));
+    void *bseq = dev_alloc(p, (size_t)L * 16);
+    void *bhat = dev_alloc(p, (size_t)L * 16);
+    if (!*gather || !*scatter || !*spec || !bseq || !bhat)
+        return fail(MFFT_ENOMEM, "Rader table allocation failed");
+    hipError_t e = launch_gen_rader(*gather, *scatter, bseq, pr, g, p->stream);
+    if (e != hipSuccess) return fail(MFFT_EHIP, hipGetErrorString(e));
+    // DFT of b in FP64 with this library, then scale by 1/(p-1) and round
+    mfft_plan sub = nullptr;
+    mfft_iodim dim{L, 1, 1};
+    int rc = plan_internal(&sub, 1, &dim, 0, nullptr, 0, -1, MFFT_C64, p->stream);
+    if (rc) return rc;
+    rc = mfft_execute(sub, bseq, bhat, (void *)p->stream);
+    if (rc) {
+        mfft_plan_destroy(sub);
+        return rc;
+    }
+    e = launch_convert_scale(*spec, p->prob.prec, bhat, L, 1.0 / (double)L, p->stream);
+    (void)hipStreamSynchronize(p->stream);
+    mfft_plan_destroy(sub);
+    dev_free(p, bseq, (size_t)L * 16);
+    dev_free(p, bhat, (size_t)L * 16);
+    if (e != hipSuccess) return fail(MFFT_EHIP, hipGetErrorString(e));
+    return MFFT_OK;
+}
+
+static int bluestein_tables(Builder &b, int64_t n, int64_t M, void **chirp, void **spec)
+{
+    PlanImpl *p = b.p;
+    const int prec = p->prob.prec;
+    *chirp = table_alloc(p, (size_t)n * elem_bytes(prec));
+    *spec = table_alloc(p, (size_t)M * elem_bytes(prec));
+    void *c64 = dev_alloc(p, (size_t)n * 16);
+    void *v = dev_alloc(p, (size_t)M * 16);
+    void *vhat = dev_alloc(p, (size_t)M * 16);
+    if (!*chirp || !*spec || !c64 || !v || !vhat)
+        return fail(MFFT_ENOMEM, "Bluestein table allocation failed");
+    hipError_t e = launch_gen_chirp(c64, n, p->stream);
+    if (e == hipSuccess) e = launch_gen_bluestein_v(v, c64, n, M, p->stream);
+    if (e == hipSuccess) e = launch_convert_scale(*chirp, prec, c64, n, 1.0, p->stream);
+    if (e != hipSuccess) return fail(MFFT_EHIP, hipGetErrorString(e));
+    mfft_plan sub = nullptr;
+    mfft_iodim dim{M, 1, 1};
+    int rc = plan_internal(&sub, 1, &dim, 0, nullptr, 0, -1, MFFT_C64, p->stream);
+    if (rc) return rc;
+    rc = mfft_execute(sub, v, vhat, (void *)p->stream);
+    if (rc) {
+        mfft_plan_destroy(sub);
+        return rc;
+    }
+    e = launch_convert_scale(*spec, prec, vhat, M, 1.0 / (double)M, p->stream);
+    (void)hipStreamSynchronize(p->stream);
+    mfft_plan_destroy(sub);
+    dev_free(p, c64, (size_t)n * 16);
+    dev_free(p, v, (size_t)M * 16);
+    dev_free(p, vhat, (size_t)M * 16);
+    if (e != hipSuccess) return fail(MFFT_EHIP, hipGetErrorString(e));
+    return MFFT_OK;
+}
+
+// ------------------------------------------------------------ whole problems
+
+static int add_copy_pass(Builder &b, const std::vector<Dim> &dims, int src, int dst,
+                         int64_t src_off, int64_t dst_off, const char *what)
+{
+    Pass ps;
+    ps.kind = 1;
+    if (dims.size() > 8) return fail(MFFT_ENOTSUP, "copy of rank > 8");
+    ps.c.rank = (int)dims.size();
+    ps.c.elem_bytes = elem_bytes(b.p->prob.prec);
+    ps.c.total = 1;
+    for (size_t i = 0; i < dims.size(); ++i) {
+        ps.c.n[i] = dims[i].n;
+        ps.c.is[i] = dims[i].is;
+        ps.c.os[i] = dims[i].os;
+        ps.c.total *= dims[i].n;
+    }
+    ps.src = src;
+    ps.dst = dst;
+    ps.src_off = src_off;
+    ps.dst_off = dst_off;
+    ps.bytes = 2.0 * (double)ps.c.total * ps.c.elem_bytes;
+    std::ostringstream d;
+    d << what << " elements=" << ps.c.total;
+    ps.desc = d.str();
+    b.p->passes.push_back(ps);
+    return MFFT_OK;
+}
+
+int build_plan(PlanImpl *p)
+{
+    Builder b;
+    b.p = p;
+    const Problem &pr = p->prob;
+    p->passes.clear();
+    if (pr.empty) return MFFT_OK;
+    const bool conj = pr.sign > 0;
+    const int eb = elem_bytes(pr.prec);
+
+    std::vector<Dim> N = pr.N, V = pr.V;
+    int src = BUF_IN;
+    int64_t src_off = 0;
+    const int dst = pr.inplace ? BUF_IN : BUF_OUT;
+
+    bool same_layout = true;
+    for (const Dim &d : N) same_layout &= d.is == d.os;
+    for (const Dim &d : V) same_layout &= d.is == d.os;
+
+    if (N.empty()) {
+        if (pr.inplace && same_layout) return MFFT_OK;   // copy onto itself
+        std::vector<Dim> all = V;
+        if (pr.inplace) {
+            const int64_t off = b.scratch_take(pr.howmany * eb) / eb;
+            int rc = add_copy_pass(b, packed(all, 1, 1), BUF_IN, BUF_SCRATCH, 0, off, "snapshot");
+            if (rc) return rc;
+            rc = add_copy_pass(b, packed(all, 1, 0), BUF_SCRATCH, dst, off, 0, "copy");
+            if (rc) return rc;
+        } else {
+            int rc = add_copy_pass(b, all, BUF_IN, BUF_OUT, 0, 0, "copy");
+            if (rc) return rc;
+        }
+        p->scratch_bytes = (size_t)b.scratch_hi;
+        return MFFT_OK;
+    }
+
+    int64_t persistent = 0;
+    if (pr.inplace && !same_layout) {
+        // read the input before anything is written: copy it to packed scratch
+        std::vector<Dim> all = V;
+        all.insert(all.end(), N.begin(), N.end());
+        const int64_t total = pr.howmany * pr.n_total;
+        const int64_t off = b.scratch_take(total * eb) / eb;
+        int rc = add_copy_pass(b, packed(all, 1, 1), BUF_IN, BUF_SCRATCH, 0, off, "snapshot");
+        if (rc) return rc;
+        std::vector<Dim> pk = packed(all, 1, 1);
+        for (size_t i = 0; i < V.size(); ++i) V[i].is = pk[i].os;
+        for (size_t i = 0; i < N.size(); ++i) N[i].is = pk[V.size() + i].os;
+        src = BUF_SCRATCH;
+        src_off = off;
+        persistent = b.scratch_top;
+    }
+
+    // first dimension: smallest input stride (unit-stride rows load best)
+    std::vector<int> order(N.size());
+    for (size_t i = 0; i < N.size(); ++i) order[i] = (int)i;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        return std::llabs(N[x].is) < std::llabs(N[y].is);
+    });
+    for (size_t step = 0; step < order.size(); ++step) {
+        const int j = order[step];
+        b.scratch_top = persistent;
+        std::vector<Dim> Vs;
+        Dim d = N[j];
+        if (step == 0) {
+            Vs = V;
+            for (size_t i = 0; i < N.size(); ++i)
+                if ((int)i != j) Vs.push_back(N[i]);
+            int rc = plan_line(b, d, Vs, src, dst, src_off, 0, conj, conj);
+            if (rc) return rc;
+        } else {
+            Vs = copy_o(V);
+            for (size_t i = 0; i < N.size(); ++i)
+                if ((int)i != j) Vs.push_back({N[i].n, N[i].os, N[i].os});
+            d = {d.n, d.os, d.os};
+            int rc = plan_line(b, d, Vs, dst, dst, 0, 0, conj, conj);
+            if (rc) return rc;
+        }
+    }
+    p->scratch_bytes = (size_t)b.scratch_hi;
+    return MFFT_OK;
+}
+
+// ------------------------------------------------------------ execution
+
+int run_plan(const PlanImpl *p, const void *in, void *out, void *scratch, hipStream_t s)
+{
+    const int eb = elem_bytes(p->prob.prec);
+    for (const Pass &ps : p->passes) {
+        auto resolve = [&](int id, int64_t off) -> char * {
+            char *base = id == BUF_IN ? (char *)in : id == BUF_OUT ? (char *)out : (char *)scratch;
+            return base + off * eb;
+        };
+        hipError_t e;
+        if (ps.kind == 1) {
+            CopyArgs c = ps.c;
+            c.in = resolve(ps.src, ps.src_off);
+            c.out = resolve(ps.dst, ps.dst_off);
+            e = launch_copy(c, s);
+        } else {
+            PassArgs a = ps.a;
+            a.in = resolve(ps.src, ps.src_off);
+            a.out = resolve(ps.dst, ps.dst_off);
+            if (ps.aux_off >= 0) a.aux = (char *)scratch + ps.aux_off;
+            e = launch_pass(a, p->prob.prec, ps.emax, ps.lds_bytes, s);
+        }
+        if (e != hipSuccess) return fail(MFFT_EHIP, std::string("launch: ") + hipGetErrorString(e));
+    }
+    return MFFT_OK;
+}
+
+}  // namespace mfft

@@ -1,0 +1,106 @@
+// Host-side plan structures: canonical problems, passes, plans.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/mfft.h"
+#include "internal.h"
+#include "kernels.h"
+
+namespace mfft {
+
+struct Dim {
+    int64_t n, is, os;
+};
+
+// dft(N, V, I, O) after canonicalization (Section 4.1): no length-1
+// dimensions, mergeable vector loops merged.
+struct Problem {
+    std::vector<Dim> N, V;
+    int sign = -1;
+    int prec = 0;          // 0 = C32, 1 = C64
+    bool inplace = false;
+    bool empty = false;    // some length was 0: nothing to do
+    int64_t n_total = 1, howmany = 1;
+};
+
+// Status + message helpers (thread-local error text).
+void set_error(const std::string &msg);
+int fail(int code, const std::string &msg);
+
+// Validate and canonicalize; returns MFFT_OK or an error code (message set).
+int canonicalize(int rank, const mfft_iodim *dims, int howmany_rank, const mfft_iodim *hdims,
+                 int inplace, int sign, int prec, Problem *out);
+std::string problem_key(const Problem &p);
+
+// Buffer ids a pass reads and writes.
+enum : int { BUF_IN = 0, BUF_OUT = 1, BUF_SCRATCH = 2 };
+
+struct Pass {
+    int kind = 0;            // 0 = FFT tile pass, 1 = rank-0 copy
+    PassArgs a{};            // pointers filled at execute time (except tables)
+    CopyArgs c{};
+    int src = BUF_IN, dst = BUF_OUT;
+    int64_t src_off = 0, dst_off = 0;       // complex elements (scratch: region offset)
+    int64_t aux_off = -1;                    // bytes into scratch for Rader aux, or -1
+    int emax = 16;
+    size_t lds_bytes = 0;
+    double bytes = 0;        // HBM bytes the pass moves (algorithmic)
+    std::string desc;
+};
+
+// Tunable choices for one rank-1 leaf pass shape (what wisdom records).
+struct LeafChoice {
+    int emax = 16;
+    int bt = 0;        // 0 = heuristic
+};
+
+struct DeviceAlloc {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+
+struct PlanImpl {
+    Problem prob;
+    unsigned flags = 0;
+    std::vector<Pass> passes;
+    std::vector<DeviceAlloc> tables;
+    size_t table_bytes = 0;
+    size_t scratch_bytes = 0;
+    void *scratch = nullptr;             // plan-owned scratch (may be null)
+    mfft_allocator alloc{};
+    bool has_alloc = false;
+    hipStream_t stream = nullptr;
+    std::string desc;
+    double bytes_passes = 0;
+    int device = 0;
+};
+
+// Device memory through the plan's allocator.
+void *dev_alloc(PlanImpl *p, size_t bytes);
+void dev_free(PlanImpl *p, void *ptr, size_t bytes);
+
+// Build the pass list and tables of a plan (Section 4.2 plan steps).
+int build_plan(PlanImpl *p);
+
+// Enqueue the passes.
+int run_plan(const PlanImpl *p, const void *in, void *out, void *scratch, hipStream_t s);
+
+// Wisdom store (text): key -> choice string.
+bool wisdom_lookup(const std::string &key, std::string *val);
+void wisdom_record(const std::string &key, const std::string &val);
+
+// Plan without taking the global planner lock (FP64 sub-plans for tables).
+int plan_internal(mfft_plan *out, int rank, const mfft_iodim *dims, int howmany_rank,
+                  const mfft_iodim *hdims, int inplace, int sign, int prec, hipStream_t stream,
+                  unsigned flags = 0, const mfft_allocator *alloc = nullptr);
+
+int64_t smallest_prime_factor(int64_t n);
+bool is_smooth7(int64_t n);
+int64_t primitive_root(int64_t p);
+void div_magic(uint32_t d, uint32_t *magic, int *shift);
+
+}  // namespace mfft

@@ -1,0 +1,536 @@
+// Device code of the FFT tile kernel, included by one translation unit per
+// (precision, registers-per-thread) variant.
+//
+// Tile kernel (one workgroup = one tile of `bt` lines of length n):
+//   load   -> LDS (lanes along the lines' vector loop, for strided lines) or
+//             straight into registers for the first stage (unit-stride lines);
+//   stages -> Stockham autosort (Section 2: transforms back and forth between
+//             two arrays, one digit per stage, in-order output, no bit
+//             reversal).  Each stage loads R elements per butterfly into VGPRs,
+//             multiplies by the stage twiddles, runs a register-resident radix-R
+//             butterfly (R in 2,3,4,5,7,8,16) and writes back to LDS;
+//   store  -> from registers (unit-stride lines) or through LDS (strided).
+// The leaf is the "large base case" of Section 3.3: one workgroup completes a
+// whole sub-transform held in LDS, so every pass costs one HBM round trip.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "internal.h"
+
+namespace mfft {
+
+template <typename T>
+struct alignas(2 * sizeof(T)) cpx {
+    T re, im;
+};
+
+template <typename T>
+__device__ __forceinline__ cpx<T> cadd(cpx<T> a, cpx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T>
+__device__ __forceinline__ cpx<T> csub(cpx<T> a, cpx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T>
+__device__ __forceinline__ cpx<T> cmul(cpx<T> a, cpx<T> b)
+{
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+// multiply by -i
+template <typename T>
+__device__ __forceinline__ cpx<T> mul_mi(cpx<T> a) { return {a.im, -a.re}; }
+template <typename T>
+__device__ __forceinline__ cpx<T> conj(cpx<T> a) { return {a.re, -a.im}; }
+template <typename T>
+__device__ __forceinline__ cpx<T> scale(cpx<T> a, T s) { return {a.re * s, a.im * s}; }
+
+// ------------------------------------------------------------ butterflies
+// Forward (sign -1) DFTs of length R, natural order in and out, in place.
+
+template <typename T>
+__device__ __forceinline__ void dft2(cpx<T> *v)
+{
+    cpx<T> a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+}
+
+template <typename T>
+__device__ __forceinline__ void dft3(cpx<T> *v)
+{
+    const T s3 = T(0.86602540378443864676);  // sin(2 pi / 3)
+    cpx<T> t = cadd(v[1], v[2]);
+    cpx<T> u = scale(mul_mi(csub(v[1], v[2])), s3);
+    cpx<T> a = csub(v[0], scale(t, T(0.5)));
+    v[0] = cadd(v[0], t);
+    v[1] = cadd(a, u);
+    v[2] = csub(a, u);
+}
+
+template <typename T>
+__device__ __forceinline__ void dft4(cpx<T> *v)
+{
+    cpx<T> s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
+    cpx<T> s13 = cadd(v[1], v[3]), d13 = mul_mi(csub(v[1], v[3]));
+    v[0] = cadd(s02, s13);
+    v[2] = csub(s02, s13);
+    v[1] = cadd(d02, d13);
+    v[3] = csub(d02, d13);
+}
+
+template <typename T>
+__device__ __forceinline__ void dft5(cpx<T> *v)
+{
+    const T c1 = T(0.30901699437494742410), c2 = T(-0.80901699437494742410);
+    const T s1 = T(0.95105651629515357212), s2 = T(0.58778525229247312917);
+    cpx<T> t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
+    cpx<T> u1 = csub(v[1], v[4]), u2 = csub(v[2], v[3]);
+    cpx<T> x0 = v[0];
+    cpx<T> a1 = {x0.re + c1 * t1.re + c2 * t2.re, x0.im + c1 * t1.im + c2 * t2.im};
+    cpx<T> a2 = {x0.re + c2 * t1.re + c1 * t2.re, x0.im + c2 * t1.im + c1 * t2.im};
+    cpx<T> b1 = {s1 * u1.re + s2 * u2.re, s1 * u1.im + s2 * u2.im};
+    cpx<T> b2 = {s2 * u1.re - s1 * u2.re, s2 * u1.im - s1 * u2.im};
+    v[0] = cadd(x0, cadd(t1, t2));
+    v[1] = cadd(a1, mul_mi(b1));
+    v[4] = csub(a1, mul_mi(b1));
+    v[2] = cadd(a2, mul_mi(b2));
+    v[3] = csub(a2, mul_mi(b2));
+}
+
+template <typename T>
+__device__ __forceinline__ void dft7(cpx<T> *v)
+{
+    const T c1 = T(0.62348980185873353053), c2 = T(-0.22252093395631440429),
+            c3 = T(-0.90096886790241912624);
+    const T s1 = T(0.78183148246802980871), s2 = T(0.97492791218182360702),
+            s3 = T(0.43388373911755812048);
+    cpx<T> x0 = v[0];
+    cpx<T> t1 = cadd(v[1], v[6]), t2 = cadd(v[2], v[5]), t3 = cadd(v[3], v[4]);
+    cpx<T> u1 = csub(v[1], v[6]), u2 = csub(v[2], v[5]), u3 = csub(v[3], v[4]);
+    cpx<T> a1 = {x0.re + c1 * t1.re + c2 * t2.re + c3 * t3.re,
+                 x0.im + c1 * t1.im + c2 * t2.im + c3 * t3.im};
+    cpx<T> a2 = {x0.re + c2 * t1.re + c3 * t2.re + c1 * t3.re,
+                 x0.im + c2 * t1.im + c3 * t2.im + c1 * t3.im};
+    cpx<T> a3 = {x0.re + c3 * t1.re + c1 * t2.re + c2 * t3.re,
+                 x0.im + c3 * t1.im + c1 * t2.im + c2 * t3.im};
+    cpx<T> b1 = {s1 * u1.re + s2 * u2.re + s3 * u3.re, s1 * u1.im + s2 * u2.im + s3 * u3.im};
+    cpx<T> b2 = {s2 * u1.re - s3 * u2.re - s1 * u3.re, s2 * u1.im - s3 * u2.im - s1 * u3.im};
+    cpx<T> b3 = {s3 * u1.re - s1 * u2.re + s2 * u3.re, s3 * u1.im - s1 * u2.im + s2 * u3.im};
+    v[0] = cadd(x0, cadd(t1, cadd(t2, t3)));
+    v[1] = cadd(a1, mul_mi(b1));
+    v[6] = csub(a1, mul_mi(b1));
+    v[2] = cadd(a2, mul_mi(b2));
+    v[5] = csub(a2, mul_mi(b2));
+    v[3] = cadd(a3, mul_mi(b3));
+    v[4] = csub(a3, mul_mi(b3));
+}
+
+template <typename T>
+__device__ __forceinline__ void dft8(cpx<T> *v)
+{
+    const T h = T(0.70710678118654752440);
+    cpx<T> e[4] = {v[0], v[2], v[4], v[6]};
+    cpx<T> o[4] = {v[1], v[3], v[5], v[7]};
+    dft4(e);
+    dft4(o);
+    // o_k *= w_8^k
+    o[1] = {h * (o[1].re + o[1].im), h * (o[1].im - o[1].re)};
+    o[2] = mul_mi(o[2]);
+    o[3] = {h * (o[3].im - o[3].re), -h * (o[3].re + o[3].im)};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        v[k] = cadd(e[k], o[k]);
+        v[k + 4] = csub(e[k], o[k]);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void dft16(cpx<T> *v)
+{
+    // 16 = 4 x 4: inner DFT-4 over l1 of x[4 l1 + l2], twiddle w_16^(l2 k1),
+    // outer DFT-4 over l2, output y[k1 + 4 k2]  (eq. ct with n1 = n2 = 4).
+    const T h = T(0.70710678118654752440);
+    const T c = T(0.92387953251128675613), s = T(0.38268343236508977173);
+    cpx<T> z[4][4];
+#pragma unroll
+    for (int l2 = 0; l2 < 4; ++l2) {
+#pragma unroll
+        for (int l1 = 0; l1 < 4; ++l1) z[l2][l1] = v[4 * l1 + l2];
+        dft4(z[l2]);
+    }
+    // twiddles w_16^(l2 k1), l2, k1 in 1..3
+    z[1][1] = cmul(z[1][1], cpx<T>{c, -s});
+    z[1][2] = cmul(z[1][2], cpx<T>{h, -h});
+    z[1][3] = cmul(z[1][3], cpx<T>{s, -c});
+    z[2][1] = cmul(z[2][1], cpx<T>{h, -h});
+    z[2][2] = mul_mi(z[2][2]);
+    z[2][3] = cmul(z[2][3], cpx<T>{-h, -h});
+    z[3][1] = cmul(z[3][1], cpx<T>{s, -c});
+    z[3][2] = cmul(z[3][2], cpx<T>{-h, -h});
+    z[3][3] = cmul(z[3][3], cpx<T>{-c, s});
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+        cpx<T> w[4] = {z[0][k1], z[1][k1], z[2][k1], z[3][k1]};
+        dft4(w);
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = w[k2];
+    }
+}
+
+template <typename T, int R>
+__device__ __forceinline__ void dft(cpx<T> *v)
+{
+    if constexpr (R == 2) dft2(v);
+    else if constexpr (R == 3) dft3(v);
+    else if constexpr (R == 4) dft4(v);
+    else if constexpr (R == 5) dft5(v);
+    else if constexpr (R == 7) dft7(v);
+    else if constexpr (R == 8) dft8(v);
+    else if constexpr (R == 16) dft16(v);
+}
+
+// ------------------------------------------------------------ kernel kinds
+// Feature sets compiled into separate kernels so that plain leaf passes carry
+// no code (or registers) for the fused plan steps they do not use.
+enum : int {
+    K_TW4 = 1,   // Cooley-Tukey twiddles on store
+    K_EXT = 2,   // pre/post multiplies, gather/scatter, in-kernel convolution, Rader
+};
+
+// ------------------------------------------------------------ tile context
+
+template <typename T>
+struct Tile {
+    int tid, tr, t;
+    bool act;           // thread belongs to the tile's bt * tpt lanes
+    int64_t o;          // flattened outer index of the tile
+    int64_t c0;         // first line of the tile along the inner vector loop
+    int64_t ob_in, ob_out;
+    cpx<T> *lds;        // tile base
+    cpx<T> *my;         // this thread's line
+    cpx<T> x0, a0;      // Rader: x[0] and the zero-frequency sum of the permuted input
+};
+
+__device__ __forceinline__ double2 tw4_root(const PassArgs &a, int64_t e)
+{
+    // w_N^e = hi[e >> s] * lo[e & mask], both factors and the product in FP64
+    // (the two-table scheme of Section 6)
+    const double2 h = ((const double2 *)a.tw4_hi)[e >> a.tw4_shift];
+    const double2 l = ((const double2 *)a.tw4_lo)[e & a.tw4_mask];
+    return make_double2(h.x * l.x - h.y * l.y, h.x * l.y + h.y * l.x);
+}
+
+__device__ __forceinline__ double2 zmul(double2 a, double2 b)
+{
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+template <typename T>
+__device__ __forceinline__ cpx<T> mul_d(cpx<T> y, double2 w)
+{
+    // twiddle rounded once to T, product in T
+    const cpx<T> wt = {T(w.x), T(w.y)};
+    return cmul(y, wt);
+}
+
+// Load element idx of line c; zero outside the logical range.
+template <typename T, int KIND>
+__device__ __forceinline__ cpx<T> load_elem(const PassArgs &a, int64_t c, int64_t base, int idx,
+                                            bool ok)
+{
+    cpx<T> x = {T(0), T(0)};
+    if constexpr (KIND & K_EXT) {
+        const int64_t li = c * a.li_c + (int64_t)idx * a.li_l;
+        if (ok && li < a.li_lim) {
+            const int64_t e = (a.flags & PF_GATHER) ? (int64_t)a.gather[li] : (int64_t)idx;
+            x = ((const cpx<T> *)a.in)[base + e * a.is];
+            if (a.flags & PF_CONJ_IN) x = conj(x);
+            if (a.flags & PF_PRE_MUL) x = cmul(x, ((const cpx<T> *)a.pre)[li]);
+        }
+    } else {
+        if (ok) {
+            x = ((const cpx<T> *)a.in)[base + (int64_t)idx * a.is];
+            if (a.flags & PF_CONJ_IN) x = conj(x);
+        }
+    }
+    return x;
+}
+
+// Store element k of line c (after the optional twiddle already applied).
+template <typename T, int KIND>
+__device__ __forceinline__ void store_elem(const PassArgs &a, const Tile<T> &tl, int64_t c,
+                                           int64_t base, int k, cpx<T> y, bool ok)
+{
+    if constexpr (KIND & K_EXT) {
+        const int64_t lo = c * a.lo_c + (int64_t)k * a.lo_k;
+        if (!ok || lo >= a.lo_lim) return;
+        const uint32_t f = a.flags;
+        if (f & PF_CONJ_A) y = conj(y);
+        if ((f & PF_AUX_A0) && lo == 0) ((cpx<T> *)a.aux)[2 * tl.o + 1] = y;
+        if (f & PF_POST_MUL) y = cmul(y, ((const cpx<T> *)a.post)[lo]);
+        if (f & (PF_RADER | PF_AUX_ADD)) y = cadd(y, tl.x0);
+        if (f & PF_CONJ_OUT) y = conj(y);
+        const int64_t e = (f & PF_SCATTER) ? (int64_t)a.scatter[lo] : (int64_t)k;
+        cpx<T> *out = (cpx<T> *)a.out;
+        out[base + e * a.os] = y;
+        if ((f & (PF_RADER | PF_AUX_ADD)) && lo == 0) {
+            cpx<T> y0 = cadd(tl.x0, tl.a0);
+            if (f & PF_CONJ_OUT) y0 = conj(y0);
+            out[base] = y0;
+        }
+    } else {
+        if (!ok) return;
+        if (a.flags & PF_CONJ_OUT) y = conj(y);
+        ((cpx<T> *)a.out)[base + (int64_t)k * a.os] = y;
+    }
+}
+
+__device__ __forceinline__ int fast_div(int b, uint32_t magic, int shift)
+{
+    return (int)((__umulhi((uint32_t)b, magic) + (uint32_t)b) >> shift);
+}
+
+enum { F_LDS = 0, F_GLOBAL = 1, F_LDS_CONV = 2 };
+enum { E_LDS = 0, E_GLOBAL = 1 };
+
+template <typename T, int R, int EMAX, int KIND>
+__device__ __forceinline__ void stage(const PassArgs &a, const StageDesc &sd, Tile<T> &tl,
+                                      int fetch, int emit)
+{
+    constexpr int NB = EMAX / R;
+    // nb comes from the stage descriptor (not n / R) so that LDS addresses are
+    // computed inside the stage rather than hoisted for every radix up front
+    const int nb = sd.nb, tpt = a.tpt, Ns = sd.Ns;
+    const int64_t c = tl.c0 + tl.tr;
+    const bool ok = c < a.vn;
+    const int64_t in_base = tl.ob_in + c * a.vis;
+    const int64_t out_base = tl.ob_out + c * a.vos;
+    // lanes past the tile's bt*tpt threads (batched launches with a larger
+    // block) only take part in the barriers
+    const int nbl = tl.act ? nb : 0;
+    cpx<T> v[NB][R];
+
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        const int b = tl.t + i * tpt;
+        if (b < nbl) {
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                const int idx = b + k * nb;
+                if (fetch == F_GLOBAL) {
+                    v[i][k] = load_elem<T, KIND>(a, c, in_base, idx, ok);
+                } else {
+                    cpx<T> z = tl.my[lds_pad(idx)];
+                    if constexpr (KIND & K_EXT) {
+                        if (fetch == F_LDS_CONV) z = conj(cmul(z, ((const cpx<T> *)a.conv)[idx]));
+                    }
+                    v[i][k] = z;
+                }
+            }
+        }
+    }
+    if (fetch != F_GLOBAL) __syncthreads();
+
+    const cpx<T> *tw = (const cpx<T> *)a.tw + sd.tw_off;
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        const int b = tl.t + i * tpt;
+        if (b < nbl) {
+            const int q = fast_div(b, sd.magic, sd.shift);
+            const int j = b - q * Ns;
+            if (Ns > 1) {
+                const cpx<T> *w = tw + j * (R - 1);
+#pragma unroll
+                for (int k = 1; k < R; ++k) v[i][k] = cmul(v[i][k], w[k - 1]);
+            }
+            dft<T, R>(v[i]);
+            const int base = q * Ns * R + j;
+            if (emit == E_GLOBAL) {
+                if constexpr (KIND & K_TW4) {
+                    if (a.flags & PF_TW4) {
+                        // element base + k*Ns of line c takes w_N^(c*(j + k*Ns)):
+                        // start w_N^(c*j), step w_N^(c*Ns), products in FP64
+                        double2 w = tw4_root(a, c * j);
+                        const double2 ws = tw4_root(a, c * Ns);
+#pragma unroll
+                        for (int k = 0; k < R; ++k) {
+                            v[i][k] = mul_d(v[i][k], w);
+                            w = zmul(w, ws);
+                        }
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < R; ++k)
+                    store_elem<T, KIND>(a, tl, c, out_base, base + k * Ns, v[i][k], ok);
+            } else {
+#pragma unroll
+                for (int k = 0; k < R; ++k) tl.my[lds_pad(base + k * Ns)] = v[i][k];
+            }
+        }
+    }
+    if (emit != E_GLOBAL) __syncthreads();
+}
+
+template <typename T, int EMAX, int KIND>
+__device__ __forceinline__ void run_fft(const PassArgs &a, Tile<T> &tl, int first_fetch,
+                                        int last_emit)
+{
+    for (int s = 0; s < a.nst; ++s) {
+        const StageDesc &sd = a.st[s];
+        const int fetch = s == 0 ? first_fetch : F_LDS;
+        const int emit = s == a.nst - 1 ? last_emit : E_LDS;
+        switch (sd.R) {
+        case 2: stage<T, 2, EMAX, KIND>(a, sd, tl, fetch, emit); break;
+        case 3: stage<T, 3, EMAX, KIND>(a, sd, tl, fetch, emit); break;
+        case 4: stage<T, 4, EMAX, KIND>(a, sd, tl, fetch, emit); break;
+        case 5: stage<T, 5, EMAX, KIND>(a, sd, tl, fetch, emit); break;
+        case 7: stage<T, 7, EMAX, KIND>(a, sd, tl, fetch, emit); break;
+        case 8: stage<T, 8, EMAX, KIND>(a, sd, tl, fetch, emit); break;
+        default: stage<T, 16, EMAX, KIND>(a, sd, tl, fetch, emit); break;
+        }
+    }
+}
+
+template <typename T, int EMAX, int KIND>
+__device__ __forceinline__ void run_tile(const PassArgs &a, int64_t tile, cpx<T> *lds)
+{
+    Tile<T> tl;
+    tl.tid = threadIdx.x;
+    tl.tr = tl.tid / a.tpt;
+    tl.t = tl.tid - tl.tr * a.tpt;
+    tl.act = tl.tr < a.bt;
+    if (!tl.act) tl.tr = 0;
+    tl.o = tile / a.ntiles_inner;
+    tl.c0 = (tile - tl.o * a.ntiles_inner) * a.bt;
+    int64_t rem = tl.o, bi = 0, bo = 0;
+    for (int d = a.nouter - 1; d >= 0; --d) {
+        const int64_t q = rem / a.on[d];
+        const int64_t idx = rem - q * a.on[d];
+        rem = q;
+        bi += idx * a.ois[d];
+        bo += idx * a.oos[d];
+    }
+    tl.ob_in = bi;
+    tl.ob_out = bo;
+    tl.lds = lds;
+    tl.my = lds + tl.tr * a.lds_stride;
+    tl.x0 = {T(0), T(0)};
+    tl.a0 = {T(0), T(0)};
+
+    const int n = a.n, bt = a.bt, nthr = a.bt * a.tpt;
+    const uint32_t f = a.flags;
+    cpx<T> *slots = lds + a.bt * a.lds_stride;   // 2 per line: x0, a0
+
+    if constexpr (KIND & K_EXT) {
+        // per-transform scalars for Rader
+        if (f & (PF_RADER | PF_AUX_X0)) {
+            if (tl.act && tl.t == 0) {
+                const int64_t c = tl.c0 + tl.tr;
+                cpx<T> x0 = {T(0), T(0)};
+                if (c < a.vn) {
+                    x0 = ((const cpx<T> *)a.in)[tl.ob_in + c * a.vis];
+                    if (f & PF_CONJ_IN) x0 = conj(x0);
+                }
+                slots[2 * tl.tr] = x0;
+                if ((f & PF_AUX_X0) && c == 0) ((cpx<T> *)a.aux)[2 * tl.o] = x0;
+            }
+        }
+        if (f & PF_AUX_ADD) {
+            const cpx<T> *aux = (const cpx<T> *)a.aux;
+            tl.x0 = aux[2 * tl.o];
+            tl.a0 = aux[2 * tl.o + 1];
+        }
+    }
+
+    int first_fetch = F_GLOBAL;
+    if (a.load_mode == kModeCol) {
+        for (int q = tl.act ? tl.tid : bt * n; q < bt * n; q += nthr) {
+            const int trq = q & (bt - 1);
+            const int idx = q >> a.bt_log2;
+            const int64_t c = tl.c0 + trq;
+            lds[trq * a.lds_stride + lds_pad(idx)] =
+                load_elem<T, KIND>(a, c, tl.ob_in + c * a.vis, idx, c < a.vn);
+        }
+        __syncthreads();
+        first_fetch = F_LDS;
+    }
+    const int last_emit = a.store_mode == kModeCol ? E_LDS : E_GLOBAL;
+
+    bool conv = false;
+    if constexpr (KIND & K_EXT) conv = (f & PF_CONV) != 0;
+    if (conv) {
+        run_fft<T, EMAX, KIND>(a, tl, first_fetch, E_LDS);   // ends with a barrier
+        if (f & PF_RADER) {
+            // x0 and the zero-frequency term of the permuted sequence, read
+            // before the second transform overwrites the line
+            tl.x0 = slots[2 * tl.tr];
+            tl.a0 = tl.my[0];
+            if (tl.act && tl.t == 0) slots[2 * tl.tr + 1] = tl.a0;
+        }
+        run_fft<T, EMAX, KIND>(a, tl, F_LDS_CONV, last_emit);
+    } else {
+        run_fft<T, EMAX, KIND>(a, tl, first_fetch, last_emit);
+    }
+
+    if (a.store_mode == kModeCol) {
+        for (int q = tl.act ? tl.tid : bt * n; q < bt * n; q += nthr) {
+            const int trq = q & (bt - 1);
+            const int idx = q >> a.bt_log2;
+            const int64_t c = tl.c0 + trq;
+            cpx<T> y = lds[trq * a.lds_stride + lds_pad(idx)];
+            if constexpr (KIND & K_TW4) {
+                if (f & PF_TW4) y = mul_d(y, tw4_root(a, (int64_t)idx * c));
+            }
+            Tile<T> tq = tl;
+            if constexpr (KIND & K_EXT) {
+                if (f & PF_RADER) {
+                    tq.x0 = slots[2 * trq];
+                    tq.a0 = slots[2 * trq + 1];
+                }
+            }
+            store_elem<T, KIND>(a, tq, c, tl.ob_out + c * a.vos, idx, y, c < a.vn);
+        }
+    }
+    __syncthreads();  // the next tile of a persistent workgroup reuses LDS
+}
+
+template <typename T, int EMAX, int KIND>
+__global__ __launch_bounds__(1024) void pass_kernel(PassArgs a)
+{
+    extern __shared__ unsigned char smem[];
+    cpx<T> *lds = (cpx<T> *)smem;
+    // Read the argument block through the kernarg segment pointer so that the
+    // per-stage descriptors indexed at run time are scalar loads rather than a
+    // private copy of the whole block.
+    const PassArgs *ap = (const PassArgs *)__builtin_amdgcn_kernarg_segment_ptr();
+    run_tile<T, EMAX, KIND>(*ap, (int64_t)blockIdx.x, lds);
+}
+
+// Persistent batched kernel: workgroups pop tiles from a shared counter until
+// the list is exhausted.  items[i] covers tiles [prefix[i], prefix[i+1]).
+template <typename T, int EMAX, int KIND>
+__global__ __launch_bounds__(1024) void batch_kernel(const PassArgs *__restrict__ items,
+                                                     const int64_t *__restrict__ prefix, int nitems,
+                                                     unsigned long long *counter)
+{
+    extern __shared__ unsigned char smem[];
+    cpx<T> *lds = (cpx<T> *)smem;
+    __shared__ long long next;
+    const int64_t total = prefix[nitems];
+    for (;;) {
+        if (threadIdx.x == 0) next = (long long)atomicAdd(counter, 1ull);
+        __syncthreads();
+        const int64_t g = next;
+        __syncthreads();
+        if (g >= total) break;
+        // binary search for the item holding tile g
+        int lo = 0, hi = nitems - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (prefix[mid] <= g) lo = mid;
+            else hi = mid - 1;
+        }
+        run_tile<T, EMAX, KIND>(items[lo], g - prefix[lo], lds);
+    }
+}
+
+}  // namespace mfft

@@ -1,0 +1,84 @@
+"""CPU checks of the C-ABI library: it loads without a GPU, exports every
+function include/mfft.h declares, and its host-only problem validation follows
+the problem statement of Section 4.1 (non-negative lengths, integer strides)
+plus the library's conventions (sign +-1, no aliasing outputs)."""
+
+
+import pytest
+
+import paper_2602_23525_amd as mfft
+
+OK, EINVAL, ENOTSUP = 0, -1, -2
+
+
+def test_library_exports_every_header_function():
+    names = mfft.header_functions()
+    assert "mfft_plan_dft" in names and "mfft_execute" in names
+    L = mfft.lib()
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+    assert mfft.mfft_version().startswith("mfft")
+
+
+def test_header_declares_extern_c_block():
+    text = open(mfft.HEADER_PATH).read()
+    assert 'extern "C"' in text
+    assert "typedef struct" in text and "mfft_iodim" in text
+
+
+@pytest.mark.parametrize("dims,hdims,inplace,sign,prec,expect", [
+    ([(1024, 1, 1)], [], 0, -1, 0, OK),
+    ([(4096, 1, 1)], [(16384, 4096, 4096)], 0, -1, 0, OK),
+    ([(256, 65536, 65536), (256, 256, 256), (256, 1, 1)], [], 1, 1, 0, OK),
+    ([(2048, 2048, 1), (2048, 1, 2048)], [], 0, -1, 1, OK),
+    ([(0, 1, 1)], [(5, 1, 1)], 0, -1, 0, OK),              # n = 0: valid no-op
+    ([], [(10, 1, 1)], 0, -1, 0, OK),                      # rank 0: copy
+    ([], [(6, 10, 1), (10, 1, 6)], 1, -1, 0, OK),          # in-place transpose
+    ([(8, -1, 1)], [], 0, -1, 0, OK),                      # negative stride
+    ([(-1, 1, 1)], [], 0, -1, 0, EINVAL),                  # negative length
+    ([(8, 1, 1)], [], 0, 0, 0, EINVAL),                    # sign must be +-1
+    ([(8, 1, 1)], [], 0, 2, 0, EINVAL),
+    ([(8, 1, 1)], [], 0, -1, 7, EINVAL),                   # unknown precision
+    ([(8, 1, 1)], [], 2, -1, 0, EINVAL),                   # inplace flag
+    ([(8, 1, 0)], [], 0, -1, 0, EINVAL),                   # zero output stride aliases
+    ([(8, 1, 1)], [(4, 8, 4)], 0, -1, 0, EINVAL),          # overlapping outputs
+    ([(8, 0, 1)], [], 0, -1, 0, OK),                       # zero input stride: broadcast read
+    ([(1 << 41, 1, 1)], [], 0, -1, 0, EINVAL),             # too large
+    ([(1 << 30, 1 << 40, 1)], [], 0, -1, 0, EINVAL),       # stride * length overflows
+    ([(2, 1, 1)] * 9, [], 0, -1, 0, EINVAL),               # rank above 8
+])
+def test_problem_check(dims, hdims, inplace, sign, prec, expect):
+    assert mfft.mfft_problem_check(dims, hdims, inplace, sign, prec) == expect
+
+
+def test_problem_check_null_pointers():
+    L = mfft.lib()
+    assert L.mfft_problem_check(1, None, 0, None, 0, -1, 0) == EINVAL
+    assert L.mfft_problem_check(0, None, 0, None, 0, -1, 0) == OK
+    assert L.mfft_problem_check(0, None, 1, None, 0, -1, 0) == EINVAL
+
+
+def test_error_text_is_thread_local_string():
+    assert mfft.mfft_problem_check([(8, 1, 1)], [], 0, 3, 0) == EINVAL
+    assert "sign" in mfft.mfft_last_error()
+
+
+def test_plan_without_gpu_fails_cleanly():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("GPU present")
+    with pytest.raises(mfft.MfftError) as e:
+        mfft.mfft_plan_dft([(64, 1, 1)], stream=0)
+    assert e.value.code == -4      # MFFT_EHIP
+
+
+def test_wisdom_roundtrip_text():
+    mfft.mfft_wisdom_forget()
+    text = mfft.mfft_wisdom_export()
+    assert text.startswith("mfft-wisdom 1 ")
+    mfft.mfft_wisdom_import(text + "c32 s-1 op N:64,1,1 V => emax=16 bt=4\n")
+    assert "N:64,1,1" in mfft.mfft_wisdom_export()
+    with pytest.raises(mfft.MfftError):
+        mfft.mfft_wisdom_import("garbage")
+    mfft.mfft_wisdom_forget()
+    assert "N:64" not in mfft.mfft_wisdom_export()

@@ -1,0 +1,125 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded inputs.  Bounds: relative RMS <= 2e-6 (FP32), <= 1e-13 (FP64,
+n <= 2^20).  Output guard bands must stay untouched and out-of-place inputs
+unmodified."""
+import numpy as np
+import pytest
+
+from tests.gpu_util import run_case
+
+pytestmark = pytest.mark.gpu
+
+
+# ---------------------------------------------------------------- headline shapes
+
+def test_single_1024_fp64_forward_and_roundtrip():
+    run_case([(1024, 1, 1)], sign=-1, prec=1, seed=1, method="direct", name="n1024 c64")
+    run_case([(1024, 1, 1)], sign=+1, prec=1, seed=2, method="direct", name="n1024 c64 inv")
+
+
+@pytest.mark.parametrize("sign", [-1, 1])
+def test_batched_4096_fp32_small_batch(sign):
+    run_case([(4096, 1, 1)], [(64, 4096, 4096)], sign=sign, prec=0, seed=3, name="4096x64")
+
+
+@pytest.mark.parametrize("n", [2, 3, 4, 5, 7, 8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096,
+                               6, 9, 10, 12, 14, 15, 21, 25, 27, 30, 35, 49, 60, 100, 210, 243,
+                               343, 1000, 2187, 2401, 3125])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_leaf_sizes(n, prec):
+    b = max(1, min(37, 20000 // n))
+    run_case([(n, 1, 1)], [(b, n, n)], sign=-1, prec=prec, seed=n, name=f"leaf {n}")
+
+
+@pytest.mark.parametrize("n", [8192, 14175, 16384, 65536, 100000])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_cooley_tukey_two_pass(n, prec):
+    b = 3
+    run_case([(n, 1, 1)], [(b, n, n)], sign=-1, prec=prec, seed=n + 7, name=f"ct {n}")
+    run_case([(n, 1, 1)], [(b, n, n)], sign=1, prec=prec, seed=n + 8, name=f"ct {n} inv")
+
+
+@pytest.mark.parametrize("n", [11, 13, 17, 29, 97, 113, 127, 193, 257, 1009, 2017])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_rader_single_kernel(n, prec):
+    run_case([(n, 1, 1)], [(5, n, n)], sign=-1, prec=prec, seed=n, name=f"rader {n}")
+    run_case([(n, 1, 1)], [(5, n, n)], sign=1, prec=prec, seed=n + 1, name=f"rader {n} inv")
+
+
+@pytest.mark.parametrize("n", [23, 67, 89, 683, 1013, 2039])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_bluestein_single_kernel(n, prec):
+    run_case([(n, 1, 1)], [(5, n, n)], sign=-1, prec=prec, seed=n, name=f"bluestein {n}")
+    run_case([(n, 1, 1)], [(5, n, n)], sign=1, prec=prec, seed=n + 1, name=f"bluestein {n} inv")
+
+
+@pytest.mark.parametrize("n,prec", [(65537, 0), (65537, 1), (12289, 0), (65521, 0), (8191, 1)])
+def test_prime_multi_pass(n, prec):
+    run_case([(n, 1, 1)], [(2, n, n)], sign=-1, prec=prec, seed=n, name=f"prime {n}")
+    run_case([(n, 1, 1)], [(2, n, n)], sign=1, prec=prec, seed=n + 1, name=f"prime {n} inv")
+
+
+# ---------------------------------------------------------------- strides, ranks, in-place
+
+def test_columns_and_rows_examples():
+    n1, n2 = 48, 80
+    # rows in place: dft({(n2,1,1)}, {(n1,n2,n2)}, X, X)
+    run_case([(n2, 1, 1)], [(n1, n2, n2)], inplace=True, seed=11, name="rows ip")
+    # columns in place: dft({(n1,n2,n2)}, {(n2,1,1)}, X, X)
+    run_case([(n1, n2, n2)], [(n2, 1, 1)], inplace=True, seed=12, name="cols ip")
+    run_case([(n1, n2, n2)], [(n2, 1, 1)], inplace=True, prec=1, seed=13, name="cols ip c64")
+
+
+def test_3d_inplace_small():
+    n = 32
+    dims = [(n, n * n, n * n), (n, n, n), (n, 1, 1)]
+    run_case(dims, inplace=True, seed=14, name="3d ip")
+    run_case(dims, inplace=True, sign=1, seed=15, name="3d ip inv")
+
+
+def test_2d_transposed_output_fp64():
+    n = 128
+    run_case([(n, n, 1), (n, 1, n)], prec=1, seed=16, name="2d transposed")
+    run_case([(n, n, 1), (n, 1, n)], prec=0, seed=17, name="2d transposed c32")
+
+
+def test_2d_transposed_inplace_uses_snapshot():
+    n = 64
+    run_case([(n, n, 1), (n, 1, n)], prec=0, inplace=True, seed=18, name="2d transposed ip")
+
+
+def test_general_strides_and_negative():
+    run_case([(12, 3, -5)], [(4, 40, 1), (3, 7, 100)], seed=19, name="odd strides")
+    run_case([(64, -1, 1)], [(5, 64, 64)], seed=20, name="negative input stride")
+    run_case([(30, 2, 3)], [(7, 61, 97)], prec=1, seed=21, name="strided c64")
+
+
+def test_rank0_copy_and_transpose():
+    run_case([], [(1000, 1, 1)], seed=22, name="rank0 copy")
+    run_case([], [(24, 40, 1), (40, 1, 24)], inplace=True, seed=23, name="rank0 ip transpose")
+
+
+def test_degenerate_sizes():
+    run_case([(1, 1, 1)], [(50, 1, 1)], seed=24, name="n=1")
+    run_case([(0, 1, 1)], [(50, 1, 1)], seed=25, name="n=0", check_guard=True)
+    run_case([(256, 1, 1)], [(0, 256, 256)], seed=26, name="empty vector")
+
+
+def test_multidim_mixed_sizes():
+    run_case([(12, 35, 35), (35, 1, 1)], [(3, 420, 420)], seed=27, name="12x35 batched")
+    run_case([(7, 600, 600), (6, 100, 100), (100, 1, 1)], prec=1, seed=28, name="7x6x100")
+
+
+def test_bitwise_determinism():
+    import torch
+
+    import paper_2602_23525_amd as mfft
+    from synth import uniform_complex
+    x = torch.from_numpy(uniform_complex(4096 * 32, seed=29, dtype=np.complex64)).cuda()
+    y1 = torch.empty_like(x)
+    y2 = torch.empty_like(x)
+    p = mfft.Plan([(4096, 1, 1)], [(32, 4096, 4096)])
+    p.execute(x, y1)
+    p.execute(x, y2)
+    torch.cuda.synchronize()
+    assert torch.equal(y1, y2)
