@@ -1,0 +1,211 @@
+"""Benchmark: batched complex FFT throughput on one MI355X.
+
+Default workload: 16384 batched 1-D complex-to-complex forward transforms of
+n = 4096, FP32 interleaved, out of place, unit stride, distance n, inputs
+uniform on [-1, 1) (seeded, synthetic).  A step is one execution of the plan
+over the whole batch; the input is resident in HBM before timing starts.
+
+Prints one JSON line with the throughput (GFLOP/s, 5 n log2 n convention), the
+HBM roofline of the dominant kernel (HIP-event time per launch on the stream
+the kernel runs on) and the FP64 CPU oracle timed on the host's cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+METRIC = "batched C2C FFT GFLOP/s (5n log2 n) + % HBM peak; p50/p99 serve latency"
+
+WORKLOADS = {
+    # name: (dims, howmany_dims, prec, sign, inplace)
+    "c2c_1d_n4096_b16384_c32": ([(4096, 1, 1)], [(16384, 4096, 4096)], 0, -1, False),
+    "c2c_1d_n4096_b16384_c32_inv": ([(4096, 1, 1)], [(16384, 4096, 4096)], 0, 1, False),
+    "c2c_1d_n1024_b1_c64": ([(1024, 1, 1)], [], 1, -1, False),
+    "c2c_3d_256cubed_c32_inplace": ([(256, 65536, 65536), (256, 256, 256), (256, 1, 1)], [], 0,
+                                    -1, True),
+    "c2c_2d_2048sq_c64_transposed": ([(2048, 2048, 1), (2048, 1, 2048)], [], 1, -1, False),
+    "c2c_1d_n1000_b512_c32": ([(1000, 1, 1)], [(512, 1000, 1000)], 0, -1, False),
+    "c2c_1d_n2187_b512_c32": ([(2187, 1, 1)], [(512, 2187, 2187)], 0, -1, False),
+    "c2c_1d_n14175_b512_c32": ([(14175, 1, 1)], [(512, 14175, 14175)], 0, -1, False),
+    "c2c_1d_n1009_b512_c32": ([(1009, 1, 1)], [(512, 1009, 1009)], 0, -1, False),
+    "c2c_1d_n65537_b512_c32": ([(65537, 1, 1)], [(512, 65537, 65537)], 0, -1, False),
+    "copy_2p26_c32": ([], [(1 << 26, 1, 1)], 0, -1, False),
+}
+DEFAULT = "c2c_1d_n4096_b16384_c32"
+def counter_traffic(workload: str):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
+    --pmc summary (FETCH_SIZE / WRITE_SIZE, scaled by the copy-kernel factor),
+    or None when no summary matches the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"pmc_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    from paper_2602_23525_amd.rocprof_summary import kernel_source_hash
+    if d.get("source_hash") != kernel_source_hash():
+        return None
+    return d.get("traffic_bytes_per_launch")
+
+
+def cpu_baseline(x, dims, hdims, sign, n_total, howmany, budget_s=30.0):
+    """Time the FP64 oracle (as it stands) on a bounded sample of the workload."""
+    import numpy as np
+
+    import oracle
+    cores = oracle.default_threads()
+    n_items = howmany
+    # choose a sample of whole transforms that takes at most ~budget_s
+    sample = n_items
+    probe = min(n_items, max(1, cores * 4))
+    x64 = x[: probe * n_total].astype(np.complex128)
+    out = np.empty_like(x64)
+    vd = [(probe, n_total, n_total)] if probe > 1 else []
+    t0 = time.perf_counter()
+    oracle.dft(x64, out, dims, vd, sign=sign)
+    t_probe = time.perf_counter() - t0
+    per = t_probe / probe
+    sample = int(max(probe, min(n_items, budget_s / max(per, 1e-9) * 0.5)))
+    x64 = x[: sample * n_total].astype(np.complex128)
+    out = np.empty_like(x64)
+    vd = [(sample, n_total, n_total)] if sample > 1 else []
+    t0 = time.perf_counter()
+    oracle.dft(x64, out, dims, vd, sign=sign)
+    t = time.perf_counter() - t0
+    flops = 5.0 * n_total * math.log2(n_total) * sample
+    return {"value": round(flops / t / 1e9, 3), "unit": "GFLOP/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"{sample} of {n_items} transforms of n={n_total}, FP64 oracle "
+                      f"(mixed-radix recursion), {t:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default=DEFAULT)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--verify", action="store_true", help="check sampled outputs vs the oracle")
+    ap.add_argument("--n", type=int, default=0, help="custom 1-D workload: transform length")
+    ap.add_argument("--batch", type=int, default=1, help="custom 1-D workload: batch")
+    ap.add_argument("--prec", default="c32", choices=["c32", "c64"])
+    ap.add_argument("--sign", type=int, default=-1)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2602_23525_amd as mfft
+    from synth import uniform_complex
+
+    if args.n:
+        n, b = args.n, args.batch
+        args.workload = f"c2c_1d_n{n}_b{b}_{args.prec}"
+        WORKLOADS[args.workload] = ([(n, 1, 1)], [(b, n, n)] if b > 1 else [],
+                                    0 if args.prec == "c32" else 1, args.sign, False)
+    dims, hdims, prec, sign, inplace = WORKLOADS[args.workload]
+    n_total = int(np.prod([d[0] for d in dims])) if dims else 1
+    howmany = int(np.prod([d[0] for d in hdims])) if hdims else 1
+    span = 1
+    for d in dims + hdims:
+        span += (d[0] - 1) * abs(d[1])
+    cdt = np.complex64 if prec == 0 else np.complex128
+    eb = 8 if prec == 0 else 16
+    x = uniform_complex(span, seed=2, dtype=cdt)
+    dev = torch.device("cuda", 0)
+    xt = torch.from_numpy(x).to(dev)
+    yt = xt if inplace else torch.empty_like(xt)
+    stream = torch.cuda.current_stream()
+
+    t0 = time.perf_counter()
+    plan = mfft.Plan(dims, hdims, inplace=inplace, sign=sign, prec=prec)
+    plan_s = time.perf_counter() - t0
+    info = plan.info()
+
+    for _ in range(args.warmup):
+        plan.execute(xt, yt)
+    torch.cuda.synchronize()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    region0 = torch.cuda.Event(enable_timing=True)
+    region1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    # timed region 1: back-to-back steps bracketed by one event pair; with a
+    # one-pass plan this is the kernel's average duration per launch
+    w0 = time.perf_counter()
+    region0.record(stream)
+    for i in range(args.steps):
+        plan.execute(xt, yt)
+    region1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms_mean = region0.elapsed_time(region1) / args.steps
+    ms_step = wall * 1e3 / args.steps
+    # timed region 2: per-step event pairs for the spread
+    for i in range(args.steps):
+        starts[i].record(stream)
+        plan.execute(xt, yt)
+        ends[i].record(stream)
+    torch.cuda.synchronize()
+    times_ms = sorted(s.elapsed_time(e) for s, e in zip(starts, ends))
+
+    flops = info["flops"]
+    value = flops / (ms_step * 1e-3) / 1e9 if flops else 0.0
+    comp_bytes = info["bytes_compulsory"]
+    achieved = comp_bytes / (ms_mean * 1e-3) / 1e9
+    traffic = counter_traffic(args.workload)
+    out = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 5),
+        "kernel_ms_avg": round(ms_mean, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == 0 else "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "dims": dims, "howmany_dims": hdims,
+                   "sign": sign, "inplace": inplace, "passes": info["n_passes"],
+                   "plan_seconds": round(plan_s, 4),
+                   "kernel_ms_p10_p50_p90": [round(times_ms[len(times_ms) // 10], 5),
+                                             round(times_ms[len(times_ms) // 2], 5),
+                                             round(times_ms[(9 * len(times_ms)) // 10], 5)]},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                     "traffic": traffic},
+    }
+    if args.verify and howmany > 1 and dims:
+        import oracle
+        y = yt.cpu().numpy()
+        errs = []
+        for v in (0, howmany // 2, howmany - 1):
+            ref = np.zeros(n_total, np.complex128)
+            oracle.dft(x.astype(np.complex128), ref, [(n_total, 1, 1)], [], sign=sign,
+                       in_off=v * n_total)
+            errs.append(oracle.rel_rms(y[v * n_total:(v + 1) * n_total], ref))
+        out["config"]["sampled_relrms"] = max(errs)
+    if not args.no_cpu and dims:
+        out["cpu_baseline"] = cpu_baseline(x, [(n_total, 1, 1)] if len(dims) == 1 else dims,
+                                           hdims, sign, n_total, howmany)
+    plan.destroy()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

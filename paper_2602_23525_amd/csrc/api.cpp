@@ -19,6 +19,7 @@ namespace mfft {
 
 const char *last_error_text();
 extern size_t g_lds_budget;
+extern int g_num_cus;
 
 static std::mutex g_plan_mutex;
 static bool g_inited = false;
@@ -37,6 +38,7 @@ static int init_device()
     size_t lds = prop.sharedMemPerBlock;
     if (const char *env = getenv("MFFT_LDS_BUDGET")) lds = std::min(lds, (size_t)atol(env));
     g_lds_budget = std::min<size_t>(lds, 65536);
+    g_num_cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
     g_inited = true;
     return MFFT_OK;
 }
@@ -96,6 +98,20 @@ int plan_internal(mfft_plan *out, int rank, const mfft_iodim *dims, int howmany_
     }
     (void)hipGetDevice(&p->device);
     rc = build_plan(p);
+    if (rc == MFFT_OK && !p->prob.empty) {
+        // wisdom (stored choices) first, then measurement, else estimate defaults
+        const std::string key = problem_key(p->prob) + " " + g_arch;
+        std::string val;
+        const bool use_wisdom = !(flags & MFFT_NO_WISDOM);
+        if (use_wisdom && wisdom_lookup(key, &val) && apply_choices(p, val)) {
+            p->from_wisdom = true;
+        } else if (flags & MFFT_WISDOM_ONLY) {
+            rc = fail(MFFT_ENOWISDOM, "no stored plan for " + key);
+        } else if (flags & MFFT_MEASURE) {
+            rc = measure_plan(p);
+            if (rc == MFFT_OK && use_wisdom) wisdom_record(key, plan_choices(p));
+        }
+    }
     if (rc == MFFT_OK && p->scratch_bytes) {
         p->scratch = dev_alloc(p, p->scratch_bytes);
         if (!p->scratch) rc = fail(MFFT_ENOMEM, "scratch allocation failed");
@@ -113,9 +129,14 @@ int plan_internal(mfft_plan *out, int rank, const mfft_iodim *dims, int howmany_
     d << problem_key(p->prob) << "\n";
     p->bytes_passes = 0;
     for (const Pass &ps : p->passes) {
-        d << "  " << ps.desc << "\n";
+        d << "  " << ps.desc;
+        if (ps.kernel == 1)
+            d << " [leaf kernel v" << ps.variant << (ps.persistent ? " persistent" : "")
+              << " grid=" << ps.grid << "]";
+        d << "\n";
         p->bytes_passes += ps.bytes;
     }
+    if (p->from_wisdom) d << "  (choices from wisdom)\n";
     p->desc = d.str();
     *out = pl;
     return MFFT_OK;

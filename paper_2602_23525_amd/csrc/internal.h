@@ -96,6 +96,6 @@ struct PassArgs {
 
 // LDS index padding: one spare slot every 16 elements keeps radix-16 stride
 // writes free of bank conflicts.
-__host__ __device__ inline int lds_pad(int i) { return i + (i >> 4); }
+__host__ __device__ constexpr int lds_pad(int i) { return i + (i >> 4); }
 
 }  // namespace mfft

@@ -1,0 +1,115 @@
+// Instantiations of the specialized power-of-two leaf kernel (leaf.h) and
+// their launcher.  256 threads per workgroup for FP32, 128 for FP64, so that
+// one tile's LDS stays near 35 KB.
+#include "kernels.h"
+#include "leaf.h"
+
+namespace mfft {
+
+template <typename T, int N, int BT, bool PF, int WPE, int NT, int... Rs>
+static hipError_t go(const PassArgs &a, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL((leaf_kernel<T, N, BT, PF, WPE, NT, Rs...>), dim3(grid), dim3(BT * N / 16), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename T, int N, int BT, bool PF, int WPE, int NT, int... Rs>
+static int occ()
+{
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, leaf_kernel<T, N, BT, PF, WPE, NT, Rs...>,
+                                                     BT * N / 16, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        return 1;
+    }
+    return blocks > 0 ? blocks : 1;
+}
+
+// kind: 0 = launch, 1 = occupancy query
+template <typename T, int THREADS, bool PF, int WPE, int NT>
+static int dispatch(int kind, const PassArgs &a, int n, int grid, hipStream_t s, hipError_t *err)
+{
+#define LEAF_CASE(N, ...)                                                                  \
+    case N:                                                                                \
+        if (kind == 1) return occ<T, N, THREADS * 16 / N, PF, WPE, NT, __VA_ARGS__>();     \
+        *err = go<T, N, THREADS * 16 / N, PF, WPE, NT, __VA_ARGS__>(a, grid, s);           \
+        return 0;
+    switch (n) {
+        LEAF_CASE(64, 16, 4)
+        LEAF_CASE(128, 16, 8)
+        LEAF_CASE(256, 16, 16)
+        LEAF_CASE(512, 16, 16, 2)
+        LEAF_CASE(1024, 16, 16, 4)
+        LEAF_CASE(2048, 16, 16, 8)
+    default:
+        break;
+    }
+    if constexpr (THREADS == 256) {
+        if (n == 4096) {
+            if (kind == 1) return occ<T, 4096, 1, PF, WPE, NT, 16, 16, 16>();
+            *err = go<T, 4096, 1, PF, WPE, NT, 16, 16, 16>(a, grid, s);
+            return 0;
+        }
+    }
+#undef LEAF_CASE
+    *err = hipErrorInvalidValue;
+    return 0;
+}
+
+int leaf_max_n(int prec) { return prec == 0 ? 4096 : 2048; }
+
+int leaf_lines_per_tile(int prec, int n) { return (prec == 0 ? 256 : 128) * 16 / n; }
+
+bool leaf_supported(int prec, int64_t n)
+{
+    return n >= 64 && n <= leaf_max_n(prec) && (n & (n - 1)) == 0;
+}
+
+// variant bits: 0 prefetch; 1 occupancy floor of 3 waves per SIMD (else 2);
+// 3 non-temporal stores; 4 non-temporal loads (only together with stores).
+// Floors of 4 waves force spills at these sizes and are not built.
+template <typename T, int THREADS, bool PF, int WPE>
+static int run_nt(int kind, const PassArgs &a, int n, int nt, int grid, hipStream_t s,
+                  hipError_t *e)
+{
+    if (nt == 3) return dispatch<T, THREADS, PF, WPE, 3>(kind, a, n, grid, s, e);
+    if (nt == 1) return dispatch<T, THREADS, PF, WPE, 1>(kind, a, n, grid, s, e);
+    return dispatch<T, THREADS, PF, WPE, 0>(kind, a, n, grid, s, e);
+}
+
+template <typename T, int THREADS, bool PF>
+static int run_wpe(int kind, const PassArgs &a, int n, int w, int nt, int grid, hipStream_t s,
+                   hipError_t *e)
+{
+    if (w & 1) return run_nt<T, THREADS, PF, 3>(kind, a, n, nt, grid, s, e);
+    return run_nt<T, THREADS, PF, 2>(kind, a, n, nt, grid, s, e);
+}
+
+static int run(int kind, const PassArgs &a, int prec, int n, int variant, int grid,
+               hipStream_t s, hipError_t *e)
+{
+    const bool pf = variant & 1;
+    const int w = (variant >> 1) & 3, nt = (variant >> 3) & 3;
+    if (prec == 0) {
+        if (pf) return run_wpe<float, 256, true>(kind, a, n, w, nt, grid, s, e);
+        return run_wpe<float, 256, false>(kind, a, n, w, nt, grid, s, e);
+    }
+    if (pf) return run_wpe<double, 128, true>(kind, a, n, 0, nt, grid, s, e);
+    return run_wpe<double, 128, false>(kind, a, n, 0, nt, grid, s, e);
+}
+
+int leaf_blocks_per_cu(int prec, int n, int variant)
+{
+    hipError_t e = hipSuccess;
+    return run(1, PassArgs{}, prec, n, variant, 0, 0, &e);
+}
+
+hipError_t launch_leaf(const PassArgs &a, int prec, int n, int variant, int grid, hipStream_t s)
+{
+    hipError_t e = hipSuccess;
+    if (grid <= 0) return hipSuccess;
+    run(0, a, prec, n, variant, grid, s, &e);
+    return e;
+}
+
+}  // namespace mfft

@@ -78,8 +78,8 @@ template <typename T>
 __global__ void gen_stage_twiddles(cpx<T> *out, int32_t Ns, int32_t R)
 {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (int64_t)Ns * (R - 1)) return;
-    const int64_t j = e / (R - 1), k = e % (R - 1) + 1;
+    if (e >= (int64_t)Ns * R) return;
+    const int64_t j = e / R, k = e % R;
     const double2 w = root_fp64(j * k, (int64_t)Ns * R);
     out[e] = {T(w.x), T(w.y)};
 }
@@ -206,16 +206,39 @@ hipError_t launch_batch(const PassArgs *items_dev, const int64_t *prefix_dev, in
     return launch_batch_c64_k3(items_dev, prefix_dev, nitems, counter, block, grid, lds_bytes, s);
 }
 
+// Contiguous copy, 16-byte vectors, four per thread: the rank-0 plan of a
+// unit-stride loop (and the reference copy for bandwidth calibration).
+__global__ __launch_bounds__(256) void copy_contig_kernel(const uint4 *__restrict__ in,
+                                                          uint4 *__restrict__ out, int64_t n16)
+{
+    const int64_t base = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+    uint4 v[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        if (base + j * 256 < n16) v[j] = in[base + j * 256];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        if (base + j * 256 < n16) out[base + j * 256] = v[j];
+}
+
 hipError_t launch_copy(const CopyArgs &a, hipStream_t s)
 {
     if (a.total <= 0) return hipSuccess;
+    const int64_t bytes = a.total * a.elem_bytes;
+    if (a.rank == 1 && a.is[0] == 1 && a.os[0] == 1 && bytes % 16 == 0 &&
+        ((uintptr_t)a.in % 16) == 0 && ((uintptr_t)a.out % 16) == 0) {
+        const int64_t n16 = bytes / 16;
+        hipLaunchKernelGGL(copy_contig_kernel, dim3((unsigned)((n16 + 1023) / 1024)), dim3(256), 0,
+                           s, (const uint4 *)a.in, (uint4 *)a.out, n16);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(copy_kernel, dim3(blocks_for(a.total, 256)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_gen_stage_twiddles(void *out, int prec, int Ns, int R, hipStream_t s)
 {
-    const int64_t cnt = (int64_t)Ns * (R - 1);
+    const int64_t cnt = (int64_t)Ns * R;
     if (cnt <= 0) return hipSuccess;
     if (prec == 0)
         hipLaunchKernelGGL(gen_stage_twiddles<float>, dim3(blocks_for(cnt, 256)), dim3(256), 0, s,

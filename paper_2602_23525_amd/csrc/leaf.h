@@ -1,0 +1,249 @@
+// Specialized leaf kernel: unit-stride lines of a compile-time power-of-two
+// length N, 16 elements per thread, all index arithmetic folded at compile
+// time.  This is the direct plan of Section 4.2 ("Direct plans") for the sizes
+// that dominate batched workloads; the generic tile kernel covers the rest.
+//
+// Data flow per line (Stockham autosort, Section 2):
+//   thread t loads x[t + e*TPT], e < 16  (coalesced: consecutive lanes read
+//   consecutive elements), which are exactly the inputs of its stage-1
+//   butterflies; each stage twiddles, runs radix-R butterflies in VGPRs and
+//   exchanges through LDS; the last stage's outputs are y[t + e*TPT], stored
+//   coalesced.
+//
+// Workgroups are persistent over tiles (BT lines each).  With PF, the loads of
+// the next tile are issued before the current tile's butterflies so that each
+// workgroup keeps two tiles of HBM traffic in flight; the stage twiddles of a
+// thread do not depend on the tile and are loaded into registers once.
+#pragma once
+#include "tile.h"
+
+namespace mfft {
+
+template <int... Rs>
+struct Radices {};
+
+template <int R, int... Rest>
+constexpr int first_radix(Radices<R, Rest...>) { return R; }
+
+constexpr int ilog2c(int x) { return x <= 1 ? 0 : 1 + ilog2c(x / 2); }
+
+// Twiddles of one stage held in registers: for butterfly i the powers
+// w^(2^m), m < log2 R, of its base twiddle w = w_(NS*R)^j, read from the FP64-
+// generated table; the other powers are products of at most four of them
+// (Section 6: a small table plus a bounded number of complex multiplications).
+template <typename T, int R>
+struct StageTw {
+    cpx<T> w[16 / R][ilog2c(R)];
+};
+
+template <typename T, int N, int TPT, int NS, int R>
+__device__ __forceinline__ void load_stage_tw(StageTw<T, R> &tw, const cpx<T> *table, int t)
+{
+    constexpr int NB = 16 / R;
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        const int b = t + i * TPT;
+        const int j = b & (NS - 1);
+        const cpx<T> *row = table + j * R;
+#pragma unroll
+        for (int m = 0; m < ilog2c(R); ++m) tw.w[i][m] = row[1 << m];
+    }
+}
+
+// Opaque copy: keeps the compiler from hoisting the twiddle expansion out of
+// the tile loop (which would pin all R powers in registers for the kernel's
+// lifetime).
+template <typename T>
+__device__ __forceinline__ cpx<T> opaque(cpx<T> z)
+{
+    __asm__ volatile("" : "+v"(z.re), "+v"(z.im));
+    return z;
+}
+
+// All R twiddle powers of butterfly i from its power-of-two powers.
+template <typename T, int R>
+__device__ __forceinline__ void expand_tw(const cpx<T> *pin, cpx<T> (&w)[R])
+{
+    cpx<T> p[ilog2c(R)];
+#pragma unroll
+    for (int m = 0; m < ilog2c(R); ++m) p[m] = opaque(pin[m]);
+    w[0] = {T(1), T(0)};
+#pragma unroll
+    for (int k = 1; k < R; ++k) {
+        const int low = k & -k;                  // lowest set bit
+        if (k == low) w[k] = p[ilog2c(low)];
+        else w[k] = cmul(w[k - low], p[ilog2c(low)]);
+    }
+}
+
+// One stage on registers: x[i + k*NB] is element k of butterfly i.
+template <typename T, int N, int TPT, int NS, int R, bool LAST>
+__device__ __forceinline__ void fast_stage(cpx<T> (&x)[16], const StageTw<T, R> &tw, cpx<T> *line,
+                                           int t)
+{
+    constexpr int NB = 16 / R;
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        cpx<T> v[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) v[k] = x[i + k * NB];
+        if constexpr (NS > 1) {
+            cpx<T> w[R];
+            expand_tw<T, R>(tw.w[i], w);
+#pragma unroll
+            for (int k = 1; k < R; ++k) v[k] = cmul(v[k], w[k]);
+        }
+        dft<T, R>(v);
+        if constexpr (LAST) {
+#pragma unroll
+            for (int k = 0; k < R; ++k) x[i + k * NB] = v[k];
+        } else {
+            const int b = t + i * TPT;
+            const int j = b & (NS - 1);
+            const int q = b >> ilog2c(NS);
+            const int base = q * NS * R + j;
+#pragma unroll
+            for (int k = 0; k < R; ++k) line[lds_pad(base + k * NS)] = v[k];
+        }
+    }
+}
+
+template <typename T, int N, int TPT, int NS, int R, int... Rest>
+struct StageChain {
+    StageTw<T, R> tw;
+    StageChain<T, N, TPT, NS * R, Rest...> next;
+    __device__ __forceinline__ void load(const cpx<T> *table, int off, int t)
+    {
+        if constexpr (NS > 1) load_stage_tw<T, N, TPT, NS, R>(tw, table + off, t);
+        next.load(table, off + NS * R, t);
+    }
+    __device__ __forceinline__ void run(cpx<T> (&x)[16], cpx<T> *line, int t)
+    {
+        fast_stage<T, N, TPT, NS, R, false>(x, tw, line, t);
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < 16; ++e) x[e] = line[lds_pad(t + e * TPT)];
+        __syncthreads();
+        next.run(x, line, t);
+    }
+};
+
+template <typename T, int N, int TPT, int NS, int R>
+struct StageChain<T, N, TPT, NS, R> {
+    StageTw<T, R> tw;
+    __device__ __forceinline__ void load(const cpx<T> *table, int off, int t)
+    {
+        if constexpr (NS > 1) load_stage_tw<T, N, TPT, NS, R>(tw, table + off, t);
+    }
+    __device__ __forceinline__ void run(cpx<T> (&x)[16], cpx<T> *line, int t)
+    {
+        fast_stage<T, N, TPT, NS, R, true>(x, tw, line, t);
+    }
+};
+
+// WPE: occupancy floor in waves per SIMD (caps VGPRs at 512 / WPE).
+// NT: bit 0 streams the output with non-temporal stores, bit 1 the input with
+// non-temporal loads (neither is reused by this pass).
+template <typename T, int N, int BT, bool PF, int WPE, int NT, int... Rs>
+__global__ __launch_bounds__(BT *N / 16) __attribute__((amdgpu_waves_per_eu(WPE))) void leaf_kernel(PassArgs)
+{
+    constexpr int TPT = N / 16;
+    constexpr int STRIDE = (lds_pad(N - 1) + 1) | 1;
+    __shared__ cpx<T> lds[BT * STRIDE];
+    const PassArgs &a = *(const PassArgs *)__builtin_amdgcn_kernarg_segment_ptr();
+    const int tid = threadIdx.x;
+    const int tr = tid / TPT;
+    const int t = tid - tr * TPT;
+    cpx<T> *line = lds + tr * STRIDE;
+    const bool cin = (a.flags & PF_CONJ_IN) != 0, cout = (a.flags & PF_CONJ_OUT) != 0;
+
+    StageChain<T, N, TPT, 1, Rs...> chain;
+    chain.load((const cpx<T> *)a.tw, 0, t);
+
+    auto line_base = [&](int64_t tile, int64_t *ib, int64_t *obs, bool *ok) {
+        const int64_t o = tile / a.ntiles_inner;
+        const int64_t c = (tile - o * a.ntiles_inner) * BT + tr;
+        int64_t rem = o, bi = 0, bo = 0;
+        for (int d = a.nouter - 1; d >= 0; --d) {
+            const int64_t qd = rem / a.on[d];
+            const int64_t idx = rem - qd * a.on[d];
+            rem = qd;
+            bi += idx * a.ois[d];
+            bo += idx * a.oos[d];
+        }
+        *ok = c < a.vn;
+        *ib = bi + c * a.vis;
+        *obs = bo + c * a.vos;
+    };
+    auto load_line = [&](cpx<T>(&x)[16], int64_t ib, bool ok) {
+        const cpx<T> *src = (const cpx<T> *)a.in + ib;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            if constexpr (NT & 2) {
+                if (ok) {
+                    x[e].re = __builtin_nontemporal_load(&src[t + e * TPT].re);
+                    x[e].im = __builtin_nontemporal_load(&src[t + e * TPT].im);
+                } else {
+                    x[e] = cpx<T>{T(0), T(0)};
+                }
+            } else {
+                x[e] = ok ? src[t + e * TPT] : cpx<T>{T(0), T(0)};
+            }
+        }
+    };
+
+    const int64_t G = gridDim.x;
+    int64_t tile = blockIdx.x;
+    if (tile >= a.ntiles) return;
+    int64_t ib, ob;
+    bool ok;
+    line_base(tile, &ib, &ob, &ok);
+    cpx<T> x[16];
+    load_line(x, ib, ok);
+    for (;;) {
+        const int64_t next = tile + G;
+        int64_t ib2 = 0, ob2 = 0;
+        bool ok2 = false;
+        cpx<T> xn[16];
+        if constexpr (PF) {
+            if (next < a.ntiles) {
+                line_base(next, &ib2, &ob2, &ok2);
+                load_line(xn, ib2, ok2);
+            }
+        }
+        if (cin) {
+#pragma unroll
+            for (int e = 0; e < 16; ++e) x[e] = conj(x[e]);
+        }
+        chain.run(x, line, t);
+        if (ok) {
+            cpx<T> *dst = (cpx<T> *)a.out + ob;
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const cpx<T> y = cout ? conj(x[e]) : x[e];
+                if constexpr (NT & 1) {
+                    __builtin_nontemporal_store(y.re, &dst[t + e * TPT].re);
+                    __builtin_nontemporal_store(y.im, &dst[t + e * TPT].im);
+                } else {
+                    dst[t + e * TPT] = y;
+                }
+            }
+        }
+        if (next >= a.ntiles) break;
+        // no barrier needed here: every LDS read of this tile came before the
+        // barrier that ends the last exchange
+        tile = next;
+        if constexpr (PF) {
+            ib = ib2;
+            ob = ob2;
+            ok = ok2;
+#pragma unroll
+            for (int e = 0; e < 16; ++e) x[e] = xn[e];
+        } else {
+            line_base(tile, &ib, &ob, &ok);
+            load_line(x, ib, ok);
+        }
+    }
+}
+
+}  // namespace mfft

@@ -20,6 +20,7 @@
 //   - rank 0: a copy (Section 4.2, "Rank-0 plans").
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <sstream>
@@ -29,6 +30,8 @@
 namespace mfft {
 
 size_t g_lds_budget = 65536;   // bytes of LDS one workgroup may use
+int g_num_cus = 256;           // compute units of the device
+
 
 static int elem_bytes(int prec) { return prec ? 16 : 8; }
 
@@ -150,7 +153,8 @@ static bool leaf_fits(int64_t n, int prec, int bt)
 }
 
 // Stage twiddle table for a leaf: stage s holds w_(Ns*R)^(j*k) for j < Ns,
-// 1 <= k < R at [tw_off + j*(R-1) + k-1]; the stage sizes telescope to n-1.
+// 0 <= k < R at [tw_off + j*R + k] (rows of R so that a butterfly's twiddles
+// are one aligned run).
 static int fill_leaf(PlanImpl *p, const Leaf &L, PassArgs *a,
                      std::map<std::string, void *> *cache)
 {
@@ -170,7 +174,7 @@ static int fill_leaf(PlanImpl *p, const Leaf &L, PassArgs *a,
         div_magic((uint32_t)Ns, &sd.magic, &sd.shift);
         sd.tw_off = (int32_t)off;
         sd.nb = L.n / sd.R;
-        off += (int64_t)Ns * (sd.R - 1);
+        off += (int64_t)Ns * sd.R;
         Ns *= sd.R;
     }
     auto it = cache->find(key.str());
@@ -194,6 +198,31 @@ static int fill_leaf(PlanImpl *p, const Leaf &L, PassArgs *a,
 }
 
 // ------------------------------------------------------------ pass building
+
+// ------------------------------------------------------------ leaf variants
+
+// Estimate-mode choice of the leaf kernel variant (measured on MI355X over
+// batched unit-stride transforms): small lines gain from non-temporal stores,
+// lines of 2048 points and more (FP32) from a persistent grid that keeps the
+// next tile's loads in flight.
+LeafTune leaf_default(int prec, int n)
+{
+    if (n <= 256) return {8, 0};
+    if (prec == 0 && n >= 2048) return {25, 1};
+    return {0, 0};
+}
+
+void apply_leaf_tune(Pass *ps, const LeafTune &t)
+{
+    ps->variant = t.variant;
+    ps->persistent = t.persistent;
+    ps->grid = ps->a.ntiles;
+    if (t.persistent) {
+        const int64_t resident =
+            (int64_t)leaf_blocks_per_cu(ps->prec, ps->a.n, t.variant) * g_num_cus;
+        ps->grid = std::min<int64_t>(ps->a.ntiles, std::max<int64_t>(resident, 1));
+    }
+}
 
 struct LineSpec {
     Dim line;                  // (n, is, os) of the line
@@ -275,6 +304,7 @@ static int add_line_pass(Builder &b, const LineSpec &ls)
     const int64_t n = ls.conv_n ? ls.conv_n : ls.line.n;
     Pass ps;
     PassArgs &a = ps.a;
+    ps.prec = prec;
     Leaf L;
     if (!make_leaf_shape(n, 16, &L)) return fail(MFFT_ENOTSUP, "no leaf shape for n");
     ps.emax = L.emax;
@@ -361,6 +391,19 @@ static int add_line_pass(Builder &b, const LineSpec &ls)
         rc = tw4_tables(b, ls.tw4_N, &a);
         if (rc) return rc;
     }
+    // unit-stride plain lines of a power-of-two length: the specialized leaf kernel
+    const uint32_t plain = PF_CONJ_IN | PF_CONJ_OUT;
+    if (!(ls.flags & ~plain) && !ls.conv_n && ls.line.is == 1 && ls.line.os == 1 &&
+        a.load_mode == kModeRow && a.store_mode == kModeRow && leaf_supported(prec, n)) {
+        ps.kernel = 1;
+        a.bt = leaf_lines_per_tile(prec, (int)n);
+        a.bt_log2 = ilog2(a.bt);
+        a.ntiles_inner = (a.vn + a.bt - 1) / a.bt;
+        a.ntiles = a.ntiles_inner * nouter_total;
+        ps.lds_bytes = 0;
+        LeafTune t = leaf_default(prec, (int)n);
+        apply_leaf_tune(&ps, t);
+    }
     ps.src = ls.src;
     ps.dst = ls.dst;
     ps.src_off = ls.src_off;
@@ -373,7 +416,7 @@ static int add_line_pass(Builder &b, const LineSpec &ls)
     std::ostringstream d;
     d << ls.what << " n=" << n << " rad=";
     for (size_t i = 0; i < L.rad.size(); ++i) d << (i ? "x" : "") << L.rad[i];
-    d << " tpt=" << L.tpt << " bt=" << bt << " " << (a.load_mode ? "C" : "R")
+    d << " tpt=" << L.tpt << " bt=" << a.bt << " " << (a.load_mode ? "C" : "R")
       << (a.store_mode ? "C" : "R") << " line=" << dims_str(ls.line) << " inner=" << dims_str(in_dim)
       << " tiles=" << a.ntiles;
     ps.desc = d.str();
@@ -981,7 +1024,10 @@ int run_plan(const PlanImpl *p, const void *in, void *out, void *scratch, hipStr
             a.in = resolve(ps.src, ps.src_off);
             a.out = resolve(ps.dst, ps.dst_off);
             if (ps.aux_off >= 0) a.aux = (char *)scratch + ps.aux_off;
-            e = launch_pass(a, p->prob.prec, ps.emax, ps.lds_bytes, s);
+            if (ps.kernel == 1)
+                e = launch_leaf(a, p->prob.prec, a.n, ps.variant, (int)ps.grid, s);
+            else
+                e = launch_pass(a, p->prob.prec, ps.emax, ps.lds_bytes, s);
         }
         if (e != hipSuccess) return fail(MFFT_EHIP, std::string("launch: ") + hipGetErrorString(e));
     }

@@ -47,15 +47,21 @@ struct Pass {
     int64_t src_off = 0, dst_off = 0;       // complex elements (scratch: region offset)
     int64_t aux_off = -1;                    // bytes into scratch for Rader aux, or -1
     int emax = 16;
+    int kernel = 0;          // 0 = generic tile kernel, 1 = specialized leaf kernel
+    int variant = 0;         // leaf kernel variant bits
+    int persistent = 0;      // leaf kernel: grid of resident workgroups instead of one per tile
+    int64_t grid = 0;        // leaf kernel grid (workgroups)
+    int prec = 0;
     size_t lds_bytes = 0;
     double bytes = 0;        // HBM bytes the pass moves (algorithmic)
     std::string desc;
 };
 
-// Tunable choices for one rank-1 leaf pass shape (what wisdom records).
-struct LeafChoice {
-    int emax = 16;
-    int bt = 0;        // 0 = heuristic
+// Tunable choice of the specialized leaf kernel (what measure mode times and
+// wisdom records): variant bits (see k_leaf.hip) and grid kind.
+struct LeafTune {
+    int variant = 0;
+    int persistent = 0;
 };
 
 struct DeviceAlloc {
@@ -77,6 +83,7 @@ struct PlanImpl {
     std::string desc;
     double bytes_passes = 0;
     int device = 0;
+    bool from_wisdom = false;
 };
 
 // Device memory through the plan's allocator.
@@ -85,6 +92,14 @@ void dev_free(PlanImpl *p, void *ptr, size_t bytes);
 
 // Build the pass list and tables of a plan (Section 4.2 plan steps).
 int build_plan(PlanImpl *p);
+LeafTune leaf_default(int prec, int n);
+void apply_leaf_tune(Pass *ps, const LeafTune &t);
+
+// Planner rigor (Section 4.3): time the candidate kernel variants of every
+// tunable pass on the plan's stream and keep the fastest; apply / record wisdom.
+int measure_plan(PlanImpl *p);
+std::string plan_choices(const PlanImpl *p);
+bool apply_choices(PlanImpl *p, const std::string &text);
 
 // Enqueue the passes.
 int run_plan(const PlanImpl *p, const void *in, void *out, void *scratch, hipStream_t s);

@@ -338,9 +338,9 @@ __device__ __forceinline__ void stage(const PassArgs &a, const StageDesc &sd, Ti
             const int q = fast_div(b, sd.magic, sd.shift);
             const int j = b - q * Ns;
             if (Ns > 1) {
-                const cpx<T> *w = tw + j * (R - 1);
+                const cpx<T> *w = tw + j * R;
 #pragma unroll
-                for (int k = 1; k < R; ++k) v[i][k] = cmul(v[i][k], w[k - 1]);
+                for (int k = 1; k < R; ++k) v[i][k] = cmul(v[i][k], w[k]);
             }
             dft<T, R>(v[i]);
             const int base = q * Ns * R + j;

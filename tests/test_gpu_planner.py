@@ -1,0 +1,97 @@
+"""GPU tests of the planner modes (Section 4.3): estimate, measure, stored
+plans ("wisdom"), and the plan description."""
+import numpy as np
+import pytest
+
+import oracle
+from synth import uniform_complex
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(plan, x):
+    import torch
+    xt = torch.from_numpy(x).cuda()
+    yt = torch.empty_like(xt)
+    plan.execute(xt, yt)
+    torch.cuda.synchronize()
+    return yt.cpu().numpy()
+
+
+def test_measure_wisdom_roundtrip():
+    import paper_2602_23525_amd as mfft
+    n, b = 1024, 2048
+    x = uniform_complex(n * b, seed=41, dtype=np.complex64)
+    ref = oracle.fft(x.astype(np.complex128).reshape(b, n))
+    mfft.mfft_wisdom_forget()
+    with pytest.raises(mfft.MfftError) as e:
+        mfft.Plan([(n, 1, 1)], [(b, n, n)], flags=mfft.WISDOM_ONLY)
+    assert e.value.code == -10
+    pm = mfft.Plan([(n, 1, 1)], [(b, n, n)], flags=mfft.MEASURE)
+    ym = _run(pm, x)
+    assert oracle.rel_rms(ym.reshape(b, n), ref) <= 2e-6
+    text = mfft.mfft_wisdom_export()
+    assert "N:1024,1,1" in text
+    mfft.mfft_wisdom_forget()
+    mfft.mfft_wisdom_import(text)
+    pw = mfft.Plan([(n, 1, 1)], [(b, n, n)], flags=mfft.WISDOM_ONLY)
+    assert "choices from wisdom" in pw.info()["desc"]
+    yw = _run(pw, x)
+    assert np.array_equal(ym, yw), "same stored choices must give identical bits"
+    pe = mfft.Plan([(n, 1, 1)], [(b, n, n)], flags=mfft.ESTIMATE | mfft.NO_WISDOM)
+    ye = _run(pe, x)
+    assert oracle.rel_rms(ye.reshape(b, n), ref) <= 2e-6
+    for p in (pm, pw, pe):
+        p.destroy()
+    mfft.mfft_wisdom_forget()
+
+
+def test_plan_info_counts():
+    import paper_2602_23525_amd as mfft
+    p = mfft.Plan([(4096, 1, 1)], [(64, 4096, 4096)])
+    info = p.info()
+    assert info["n_passes"] == 1 and info["howmany"] == 64 and info["n_total"] == 4096
+    assert info["flops"] == pytest.approx(5 * 4096 * 12 * 64)
+    assert info["bytes_compulsory"] == pytest.approx(2 * 8 * 4096 * 64)
+    assert "leaf kernel" in info["desc"]
+    p.destroy()
+    p = mfft.Plan([(65536, 1, 1)], [(4, 65536, 65536)])
+    assert p.info()["n_passes"] == 2
+    p.destroy()
+
+
+def test_execute_argument_checks():
+    import torch
+
+    import paper_2602_23525_amd as mfft
+    p = mfft.Plan([(256, 1, 1)], [(4, 256, 256)])
+    x = torch.zeros(1024, dtype=torch.complex64, device="cuda")
+    with pytest.raises(mfft.MfftError) as e:
+        p.execute(x, x)                       # out-of-place plan, in == out
+    assert e.value.code == -5
+    with pytest.raises(mfft.MfftError) as e:
+        mfft.mfft_execute(p.handle, x.data_ptr() + 4, x.data_ptr() + 8192)   # misaligned
+    assert e.value.code == -5
+    p.destroy()
+    q = mfft.Plan([(256, 1, 1)], [(4, 256, 256)], inplace=True)
+    y = torch.zeros(1024, dtype=torch.complex64, device="cuda")
+    with pytest.raises(mfft.MfftError):
+        q.execute(x, y)                       # in-place plan, in != out
+    q.destroy()
+
+
+def test_torch_allocator_plan():
+    import torch
+
+    import paper_2602_23525_amd as mfft
+    alloc = mfft.torch_allocator()
+    n = 65536
+    x = uniform_complex(n * 2, seed=43, dtype=np.complex64)
+    p = mfft.Plan([(n, 1, 1)], [(2, n, n)], inplace=True, allocator=alloc)
+    xt = torch.from_numpy(x).cuda()
+    p.execute(xt, xt)
+    torch.cuda.synchronize()
+    ref = oracle.fft(x.astype(np.complex128).reshape(2, n))
+    assert oracle.rel_rms(xt.cpu().numpy().reshape(2, n), ref) <= 2e-6
+    assert p.info()["scratch_bytes"] > 0
+    p.destroy()
