@@ -145,6 +145,30 @@ int mfft_plan_info(mfft_plan plan, mfft_plan_info_t *info);
 /* Free the plan's device memory (stream-ordered on the plan's stream). */
 int mfft_plan_destroy(mfft_plan plan);
 
+/* ------------------------------------------------------------------ batch */
+/*
+ * Many planned transforms executed as one workload (the vector-loop rule of
+ * Section 4.2 extended across plans): pass k of every plan runs in one
+ * persistent launch per kernel family, whose workgroups pop tiles from a shared
+ * list ordered largest line first, so uneven sizes balance across the GPU.
+ *   count, plans, ins, outs: plan i runs on ins[i] -> outs[i] (device
+ *       pointers with the plan's in-place rule); plans must outlive the batch;
+ *       a plan that owns scratch may appear at most once.
+ *   flags: MFFT_BATCH_GRAPH captures the launches in a HIP graph at creation;
+ *       execute then launches the graph.
+ * Execution is asynchronous on hip_stream and allocates nothing.  Errors:
+ * EINVAL (bad arguments, shared scratch), ENOMEM, EHIP.
+ */
+typedef struct mfft_batch_s *mfft_batch;
+#define MFFT_BATCH_GRAPH 1u
+
+int mfft_batch_create(mfft_batch *out, int count, const mfft_plan *plans, const void *const *ins,
+                      void *const *outs, unsigned flags, void *hip_stream);
+int mfft_batch_execute(mfft_batch batch, void *hip_stream);
+/* Number of kernel launches per execute and total tiles. */
+int mfft_batch_info(mfft_batch batch, int *launches, int64_t *tiles);
+int mfft_batch_destroy(mfft_batch batch);
+
 /* ------------------------------------------------------------------ wisdom */
 /* Stored plans (Section 4.3: plans can be precomputed and loaded later).  The
  * text records, per canonical problem, precision, device architecture and

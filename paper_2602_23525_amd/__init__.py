@@ -18,7 +18,7 @@ __all__ = [
     "mfft_execute", "mfft_execute_scratch", "mfft_plan_info", "mfft_plan_destroy",
     "mfft_wisdom_export", "mfft_wisdom_import", "mfft_wisdom_forget", "mfft_last_error",
     "mfft_version", "C32", "C64", "ESTIMATE", "MEASURE", "WISDOM_ONLY", "NO_WISDOM",
-    "header_functions", "LIB_PATH", "HEADER_PATH",
+    "header_functions", "LIB_PATH", "HEADER_PATH", "Batch", "BATCH_GRAPH",
 ]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -92,6 +92,14 @@ def lib():
     L.mfft_wisdom_import.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
     L.mfft_wisdom_forget.argtypes = []
     L.mfft_free.argtypes = [p]
+    L.mfft_batch_create.argtypes = [ctypes.POINTER(p), ctypes.c_int, ctypes.POINTER(p),
+                                    ctypes.POINTER(p), ctypes.POINTER(p), ctypes.c_uint, p]
+    L.mfft_batch_execute.argtypes = [p, p]
+    L.mfft_batch_info.argtypes = [p, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int64)]
+    L.mfft_batch_destroy.argtypes = [p]
+    for name in ("mfft_batch_create", "mfft_batch_execute", "mfft_batch_info",
+                 "mfft_batch_destroy"):
+        getattr(L, name).restype = ctypes.c_int
     L.mfft_last_error.restype = ctypes.c_char_p
     L.mfft_version.restype = ctypes.c_char_p
     for name in ("mfft_problem_check", "mfft_plan_dft", "mfft_execute", "mfft_execute_scratch",
@@ -256,6 +264,47 @@ class Plan:
     def destroy(self):
         if self.handle:
             mfft_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+BATCH_GRAPH = 1
+
+
+class Batch:
+    """Many (plan, in, out) triples executed as one workload (mfft_batch_*)."""
+
+    def __init__(self, plans, ins, outs, graph=False, stream=None):
+        n = len(plans)
+        P = ctypes.c_void_p * max(1, n)
+        self._plans = list(plans)          # keep the plans alive
+        hp = P(*[pl.handle for pl in plans])
+        hi = P(*[_ptr(x) for x in ins])
+        ho = P(*[_ptr(y) for y in outs])
+        h = ctypes.c_void_p()
+        rc = lib().mfft_batch_create(ctypes.byref(h), n, hp, hi, ho,
+                                     BATCH_GRAPH if graph else 0, _stream(stream))
+        _check(rc, "mfft_batch_create")
+        self.handle = h.value
+
+    def execute(self, stream=None):
+        _check(lib().mfft_batch_execute(self.handle, _stream(stream)), "mfft_batch_execute")
+
+    def info(self):
+        la = ctypes.c_int()
+        ti = ctypes.c_int64()
+        _check(lib().mfft_batch_info(self.handle, ctypes.byref(la), ctypes.byref(ti)),
+               "mfft_batch_info")
+        return {"launches": la.value, "tiles": ti.value}
+
+    def destroy(self):
+        if self.handle:
+            lib().mfft_batch_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -11,10 +11,6 @@
 
 #include "plan.h"
 
-struct mfft_plan_s {
-    mfft::PlanImpl impl;
-};
-
 namespace mfft {
 
 const char *last_error_text();

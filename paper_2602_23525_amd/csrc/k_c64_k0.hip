@@ -20,4 +20,15 @@ hipError_t launch_batch_c64_k0(const PassArgs *items, const int64_t *prefix, int
     return hipGetLastError();
 }
 
+int batch_blocks_per_cu_c64_k0(int block, size_t lds)
+{
+    int b = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, batch_kernel<double, 16, 0>, block, lds) !=
+        hipSuccess) {
+        (void)hipGetLastError();
+        return 1;
+    }
+    return b > 0 ? b : 1;
+}
+
 }  // namespace mfft

@@ -157,7 +157,8 @@ static inline unsigned blocks_for(int64_t count, int threads)
     hipError_t launch_pass_##P##_k##K(const PassArgs &a, size_t lds, hipStream_t s);          \
     hipError_t launch_batch_##P##_k##K(const PassArgs *items, const int64_t *prefix,         \
                                        int nitems, unsigned long long *counter, int block,    \
-                                       int grid, size_t lds, hipStream_t s);
+                                       int grid, size_t lds, hipStream_t s);     \
+    int batch_blocks_per_cu_##P##_k##K(int block, size_t lds);
 MFFT_VARIANT(c32, 0)
 MFFT_VARIANT(c32, 1)
 MFFT_VARIANT(c32, 3)
@@ -190,6 +191,18 @@ hipError_t launch_pass(const PassArgs &a, int prec, int emax, size_t lds_bytes, 
     if (k == 0) return launch_pass_c64_k0(a, lds_bytes, s);
     if (k == 1) return launch_pass_c64_k1(a, lds_bytes, s);
     return launch_pass_c64_k3(a, lds_bytes, s);
+}
+
+int batch_blocks_per_cu(int prec, int kind, int block, size_t lds)
+{
+    if (prec == 0) {
+        if (kind == 0) return batch_blocks_per_cu_c32_k0(block, lds);
+        if (kind == 1) return batch_blocks_per_cu_c32_k1(block, lds);
+        return batch_blocks_per_cu_c32_k3(block, lds);
+    }
+    if (kind == 0) return batch_blocks_per_cu_c64_k0(block, lds);
+    if (kind == 1) return batch_blocks_per_cu_c64_k1(block, lds);
+    return batch_blocks_per_cu_c64_k3(block, lds);
 }
 
 hipError_t launch_batch(const PassArgs *items_dev, const int64_t *prefix_dev, int nitems,

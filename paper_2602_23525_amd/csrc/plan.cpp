@@ -1005,25 +1005,44 @@ int build_plan(PlanImpl *p)
 
 // ------------------------------------------------------------ execution
 
-int run_plan(const PlanImpl *p, const void *in, void *out, void *scratch, hipStream_t s)
+static char *resolve_buf(const PlanImpl *p, int id, int64_t off, const void *in, void *out,
+                         void *scratch)
 {
     const int eb = elem_bytes(p->prob.prec);
+    char *base = id == BUF_IN ? (char *)in : id == BUF_OUT ? (char *)out : (char *)scratch;
+    return base + off * eb;
+}
+
+PassArgs resolve_pass(const PlanImpl *p, const Pass &ps, const void *in, void *out, void *scratch)
+{
+    PassArgs a = ps.a;
+    a.in = resolve_buf(p, ps.src, ps.src_off, in, out, scratch);
+    a.out = resolve_buf(p, ps.dst, ps.dst_off, in, out, scratch);
+    if (ps.aux_off >= 0) a.aux = (char *)scratch + ps.aux_off;
+    return a;
+}
+
+CopyArgs resolve_copy(const PlanImpl *p, const Pass &ps, const void *in, void *out, void *scratch)
+{
+    CopyArgs c = ps.c;
+    c.in = resolve_buf(p, ps.src, ps.src_off, in, out, scratch);
+    c.out = resolve_buf(p, ps.dst, ps.dst_off, in, out, scratch);
+    return c;
+}
+
+size_t generic_lds_bytes(const Pass &ps)
+{
+    return tile_lds_bytes(ps.a.n, ps.a.bt, ps.prec);
+}
+
+int run_plan(const PlanImpl *p, const void *in, void *out, void *scratch, hipStream_t s)
+{
     for (const Pass &ps : p->passes) {
-        auto resolve = [&](int id, int64_t off) -> char * {
-            char *base = id == BUF_IN ? (char *)in : id == BUF_OUT ? (char *)out : (char *)scratch;
-            return base + off * eb;
-        };
         hipError_t e;
         if (ps.kind == 1) {
-            CopyArgs c = ps.c;
-            c.in = resolve(ps.src, ps.src_off);
-            c.out = resolve(ps.dst, ps.dst_off);
-            e = launch_copy(c, s);
+            e = launch_copy(resolve_copy(p, ps, in, out, scratch), s);
         } else {
-            PassArgs a = ps.a;
-            a.in = resolve(ps.src, ps.src_off);
-            a.out = resolve(ps.dst, ps.dst_off);
-            if (ps.aux_off >= 0) a.aux = (char *)scratch + ps.aux_off;
+            const PassArgs a = resolve_pass(p, ps, in, out, scratch);
             if (ps.kernel == 1)
                 e = launch_leaf(a, p->prob.prec, a.n, ps.variant, (int)ps.grid, s);
             else

@@ -86,6 +86,14 @@ struct PlanImpl {
     bool from_wisdom = false;
 };
 
+}  // namespace mfft
+
+struct mfft_plan_s {
+    mfft::PlanImpl impl;
+};
+
+namespace mfft {
+
 // Device memory through the plan's allocator.
 void *dev_alloc(PlanImpl *p, size_t bytes);
 void dev_free(PlanImpl *p, void *ptr, size_t bytes);
@@ -103,6 +111,12 @@ bool apply_choices(PlanImpl *p, const std::string &text);
 
 // Enqueue the passes.
 int run_plan(const PlanImpl *p, const void *in, void *out, void *scratch, hipStream_t s);
+
+// A pass with its buffer pointers resolved for given in/out/scratch pointers.
+PassArgs resolve_pass(const PlanImpl *p, const Pass &ps, const void *in, void *out, void *scratch);
+CopyArgs resolve_copy(const PlanImpl *p, const Pass &ps, const void *in, void *out, void *scratch);
+// LDS bytes the generic tile kernel needs for a pass.
+size_t generic_lds_bytes(const Pass &ps);
 
 // Wisdom store (text): key -> choice string.
 bool wisdom_lookup(const std::string &key, std::string *val);

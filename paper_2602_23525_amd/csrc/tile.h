@@ -519,7 +519,12 @@ __global__ __launch_bounds__(1024) void batch_kernel(const PassArgs *__restrict_
     for (;;) {
         if (threadIdx.x == 0) next = (long long)atomicAdd(counter, 1ull);
         __syncthreads();
-        const int64_t g = next;
+        // the popped index is the same for the whole workgroup: make it a
+        // scalar so the descriptor reads below are scalar loads
+        const uint64_t gv = (uint64_t)next;
+        const int64_t g = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane(
+                                         (int)(gv >> 32)) << 32) |
+                                    (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)gv));
         __syncthreads();
         if (g >= total) break;
         // binary search for the item holding tile g
