@@ -169,6 +169,74 @@ int mfft_batch_execute(mfft_batch batch, void *hip_stream);
 int mfft_batch_info(mfft_batch batch, int *launches, int64_t *tiles);
 int mfft_batch_destroy(mfft_batch batch);
 
+/* ------------------------------------------------------------------ server */
+/*
+ * Request server with continuous batching.  Requests (any problem the planner
+ * accepts) are queued; a scheduler thread admits them in arrival order while
+ * their memory fits the HBM budget and fewer than max_inflight are on the GPU,
+ * and launches everything admitted since the last launch as one batch (see
+ * mfft_batch_*) on the next of n_streams streams, so requests that arrive while
+ * others run are admitted as memory frees and overlap on the device.  Plans and
+ * their twiddle tables stay resident in a cache keyed by the problem.
+ *
+ *   hbm_budget_bytes: device memory the server may hold for request outputs,
+ *       scratch and launch descriptors (allocated once at creation).
+ *   max_inflight: admitted-but-unfinished request limit (>= 1); n_streams >= 1.
+ *   alloc: reserved, pass NULL.
+ * A request's input must stay valid until it completes.  If out is NULL the
+ * server allocates the output inside the budget; read it with
+ * mfft_server_output and give it back with mfft_server_release.
+ */
+typedef struct mfft_server_s *mfft_server;
+
+typedef struct {
+    int rank;
+    mfft_iodim dims[8];
+    int howmany_rank;
+    mfft_iodim howmany_dims[8];
+    int sign;            /* -1 or +1 */
+    mfft_prec prec;
+    const void *in;      /* device input tensor, element (0,...,0)              */
+    void *out;           /* device output, or NULL = allocate in the budget      */
+    double arrival;      /* steady-clock seconds of arrival (0 = at submission)  */
+} mfft_request;
+
+typedef struct {
+    uint64_t submitted, admitted, completed, rejected, failed, cancelled;
+    uint64_t launches;       /* batched launches (ticks)                           */
+    double p50_ms, p99_ms;   /* arrival -> completion observed, completed requests */
+    double mean_ms, max_ms;
+    double busy_s;           /* time with at least one launch on the GPU           */
+    double flops;            /* nominal 5 N log2 N flops of completed requests     */
+    double bytes;            /* compulsory bytes of completed requests             */
+    size_t bytes_in_use, peak_bytes;   /* within the budget                        */
+    size_t plan_bytes;       /* resident plan tables and scratch (outside budget)  */
+    int plans_cached;
+    int max_inflight_seen;
+} mfft_server_stats_t;
+
+/* Request status reported by mfft_server_wait. */
+#define MFFT_REQ_PENDING  1
+#define MFFT_REQ_RUNNING  2
+#define MFFT_REQ_DONE     0
+
+int mfft_server_create(mfft_server *out, size_t hbm_budget_bytes, int max_inflight, int n_streams,
+                       const mfft_allocator *alloc);
+/* EINVAL/ENOTSUP for a bad problem, EBUDGET if it can never fit the budget. */
+int mfft_server_submit(mfft_server server, const mfft_request *req, uint64_t *ticket);
+/* Wait up to timeout_ms (< 0: forever).  *status: MFFT_REQ_DONE, a negative
+ * error code of the request, or MFFT_REQ_PENDING / RUNNING on timeout
+ * (then the call returns MFFT_ETIMEOUT). */
+int mfft_server_wait(mfft_server server, uint64_t ticket, int timeout_ms, int *status);
+int mfft_server_output(mfft_server server, uint64_t ticket, void **out);
+/* Forget a finished request and free its server-allocated output. */
+int mfft_server_release(mfft_server server, uint64_t ticket);
+/* Cancel a request that has not been admitted (ESTATE if already running). */
+int mfft_server_cancel(mfft_server server, uint64_t ticket);
+int mfft_server_stats(mfft_server server, mfft_server_stats_t *stats);
+/* Stop accepting, finish in-flight work, free everything. */
+int mfft_server_destroy(mfft_server server);
+
 /* ------------------------------------------------------------------ wisdom */
 /* Stored plans (Section 4.3: plans can be precomputed and loaded later).  The
  * text records, per canonical problem, precision, device architecture and

@@ -18,7 +18,7 @@ __all__ = [
     "mfft_execute", "mfft_execute_scratch", "mfft_plan_info", "mfft_plan_destroy",
     "mfft_wisdom_export", "mfft_wisdom_import", "mfft_wisdom_forget", "mfft_last_error",
     "mfft_version", "C32", "C64", "ESTIMATE", "MEASURE", "WISDOM_ONLY", "NO_WISDOM",
-    "header_functions", "LIB_PATH", "HEADER_PATH", "Batch", "BATCH_GRAPH",
+    "header_functions", "LIB_PATH", "HEADER_PATH", "Batch", "BATCH_GRAPH", "Server", "Request",
 ]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -99,6 +99,19 @@ def lib():
     L.mfft_batch_destroy.argtypes = [p]
     for name in ("mfft_batch_create", "mfft_batch_execute", "mfft_batch_info",
                  "mfft_batch_destroy"):
+        getattr(L, name).restype = ctypes.c_int
+    u64 = ctypes.c_uint64
+    L.mfft_server_create.argtypes = [ctypes.POINTER(p), ctypes.c_size_t, ctypes.c_int, ctypes.c_int, p]
+    L.mfft_server_submit.argtypes = [p, p, ctypes.POINTER(u64)]
+    L.mfft_server_wait.argtypes = [p, u64, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+    L.mfft_server_output.argtypes = [p, u64, ctypes.POINTER(p)]
+    L.mfft_server_release.argtypes = [p, u64]
+    L.mfft_server_cancel.argtypes = [p, u64]
+    L.mfft_server_stats.argtypes = [p, p]
+    L.mfft_server_destroy.argtypes = [p]
+    for name in ("mfft_server_create", "mfft_server_submit", "mfft_server_wait",
+                 "mfft_server_output", "mfft_server_release", "mfft_server_cancel",
+                 "mfft_server_stats", "mfft_server_destroy"):
         getattr(L, name).restype = ctypes.c_int
     L.mfft_last_error.restype = ctypes.c_char_p
     L.mfft_version.restype = ctypes.c_char_p
@@ -305,6 +318,90 @@ class Batch:
     def destroy(self):
         if self.handle:
             lib().mfft_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("rank", ctypes.c_int), ("dims", IoDim * 8), ("howmany_rank", ctypes.c_int),
+                ("howmany_dims", IoDim * 8), ("sign", ctypes.c_int), ("prec", ctypes.c_int),
+                ("in_", ctypes.c_void_p), ("out", ctypes.c_void_p), ("arrival", ctypes.c_double)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_uint64) for k in ("submitted", "admitted", "completed", "rejected",
+                                               "failed", "cancelled", "launches")] + \
+               [(k, ctypes.c_double) for k in ("p50_ms", "p99_ms", "mean_ms", "max_ms", "busy_s",
+                                               "flops", "bytes")] + \
+               [("bytes_in_use", ctypes.c_size_t), ("peak_bytes", ctypes.c_size_t),
+                ("plan_bytes", ctypes.c_size_t), ("plans_cached", ctypes.c_int),
+                ("max_inflight_seen", ctypes.c_int)]
+
+
+REQ_DONE, REQ_PENDING, REQ_RUNNING = 0, 1, 2
+
+
+class Server:
+    """Request server with continuous batching (mfft_server_*)."""
+
+    def __init__(self, budget_bytes, max_inflight=64, n_streams=4):
+        L = lib()
+        h = ctypes.c_void_p()
+        _check(L.mfft_server_create(ctypes.byref(h), int(budget_bytes), int(max_inflight),
+                                    int(n_streams), None), "mfft_server_create")
+        self.handle = h.value
+
+    def submit(self, dims, howmany_dims=(), x=None, y=None, sign=-1, prec=C32, arrival=0.0):
+        r = Request()
+        r.rank = len(dims)
+        for i, d in enumerate(dims):
+            r.dims[i] = IoDim(*d)
+        r.howmany_rank = len(howmany_dims)
+        for i, d in enumerate(howmany_dims):
+            r.howmany_dims[i] = IoDim(*d)
+        r.sign, r.prec = int(sign), int(prec)
+        r.in_ = _ptr(x)
+        r.out = _ptr(y) if y is not None else None
+        r.arrival = float(arrival)
+        t = ctypes.c_uint64()
+        _check(lib().mfft_server_submit(self.handle, ctypes.byref(r), ctypes.byref(t)),
+               "mfft_server_submit")
+        return t.value
+
+    def wait(self, ticket, timeout_ms=-1):
+        st = ctypes.c_int()
+        rc = lib().mfft_server_wait(self.handle, ctypes.c_uint64(ticket), int(timeout_ms),
+                                    ctypes.byref(st))
+        if rc not in (0, -8):
+            _check(rc, "mfft_server_wait")
+        return st.value
+
+    def output(self, ticket) -> int:
+        p = ctypes.c_void_p()
+        _check(lib().mfft_server_output(self.handle, ctypes.c_uint64(ticket), ctypes.byref(p)),
+               "mfft_server_output")
+        return p.value or 0
+
+    def release(self, ticket):
+        _check(lib().mfft_server_release(self.handle, ctypes.c_uint64(ticket)),
+               "mfft_server_release")
+
+    def cancel(self, ticket):
+        _check(lib().mfft_server_cancel(self.handle, ctypes.c_uint64(ticket)), "mfft_server_cancel")
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        _check(lib().mfft_server_stats(self.handle, ctypes.byref(s)), "mfft_server_stats")
+        return {k: getattr(s, k) for k, _ in ServerStats._fields_}
+
+    def destroy(self):
+        if self.handle:
+            lib().mfft_server_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

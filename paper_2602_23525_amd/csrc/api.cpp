@@ -33,7 +33,8 @@ static int init_device()
     g_arch = prop.gcnArchName;
     size_t lds = prop.sharedMemPerBlock;
     if (const char *env = getenv("MFFT_LDS_BUDGET")) lds = std::min(lds, (size_t)atol(env));
-    g_lds_budget = std::min<size_t>(lds, 65536);
+    // keep a little LDS for the batched kernel's static variables
+    g_lds_budget = std::min<size_t>(lds, 163840) - 256;
     g_num_cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
     g_inited = true;
     return MFFT_OK;

@@ -3,13 +3,13 @@
 // problems instead of within one).
 //
 // Pass k of every plan forms phase k; within a phase, passes that share a
-// kernel family (precision, feature kind, workgroup size) become one launch of
-// the persistent tile kernel over a device descriptor list.  Tiles are numbered
-// item by item, items ordered by line length, largest first, and workgroups
-// pop tile indices from a counter, so long lines start early and short ones
-// fill the tail.  Phases run in order on the stream, so pass k+1 of a plan
-// always sees pass k complete.  Counters are cleared by a kernel (not a memset)
-// so that the whole sequence can be captured in a HIP graph.
+// kernel family (precision, feature kind, workgroup-size class) become one
+// launch of the persistent tile kernel over a device descriptor list.  Tiles
+// are numbered item by item, items ordered by line length, largest first, and
+// workgroups pop tile indices from a counter, so long lines start early and
+// short ones fill the tail.  Phases run in order on the stream, so pass k+1 of
+// a plan always sees pass k complete.  Counters are cleared by a kernel (not a
+// memset) so that the whole sequence can be captured in a HIP graph.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -18,60 +18,175 @@
 #include <tuple>
 #include <vector>
 
-#include "plan.h"
+#include "batch.h"
 
 namespace mfft {
 
 extern int g_num_cus;
+extern size_t g_lds_budget;
 
-struct BatchGroup {
-    int prec = 0, kind = 0, block = 0;
-    size_t lds = 0;
-    int grid = 0;
-    int nitems = 0;
-    int64_t tiles = 0;
-    PassArgs *d_items = nullptr;
-    int64_t *d_prefix = nullptr;
-    unsigned long long *d_counter = nullptr;
-};
-
-struct BatchStep {          // one launch: a group, or a copy pass
-    bool copy = false;
-    CopyArgs c{};
-    int group = -1;
-};
-
-}  // namespace mfft
-
-struct mfft_batch_s {
-    std::vector<mfft::BatchGroup> groups;
-    std::vector<mfft::BatchStep> steps;
-    void *dev_mem = nullptr;
-    hipStream_t cap_stream = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    int64_t tiles = 0;
-};
-
-namespace mfft {
-
-static int enqueue_steps(mfft_batch_s *b, hipStream_t s)
+// Retile a pass for a workgroup-size class: 256, 512 or 1024 threads, with
+// more lines per tile so few lanes idle in the class (tiles kept <= 64 KB).
+static int widen(const Pass &ps, PassArgs *a, size_t *lds)
 {
-    for (const BatchStep &st : b->steps) {
+    const int maxb = ps.prec ? 512 : 1024;
+    int block = std::min(256, maxb);
+    while (block < a->bt * a->tpt) block *= 2;
+    Pass wide = ps;
+    int bt = a->bt;
+    while (bt * 2 * a->tpt <= block && bt * 2 <= a->vn) {
+        wide.a.bt = bt * 2;
+        if (generic_lds_bytes(wide) > std::min<size_t>(g_lds_budget, 65536)) break;
+        bt *= 2;
+    }
+    wide.a.bt = bt;
+    if (bt != a->bt) {
+        const int64_t outer = a->ntiles / a->ntiles_inner;
+        a->bt = bt;
+        int l = 0;
+        while ((1 << l) < bt) ++l;
+        a->bt_log2 = l;
+        a->ntiles_inner = (a->vn + bt - 1) / bt;
+        a->ntiles = a->ntiles_inner * outer;
+    }
+    *lds = generic_lds_bytes(wide);
+    return block;
+}
+
+int build_batch_layout(const std::vector<BatchItem> &items, BatchLayout *L)
+{
+    struct Item {
+        PassArgs a;
+        int64_t n;
+    };
+    using Key = std::tuple<int, int, int, int>;   // phase, prec, kind, block
+    std::map<Key, std::vector<Item>> fam;
+    std::map<Key, size_t> fam_lds;
+    std::map<int, std::vector<CopyArgs>> copies;
+    int nphase = 0;
+    for (const BatchItem &it : items) {
+        const PlanImpl *p = it.plan;
+        for (size_t k = 0; k < p->passes.size(); ++k) {
+            const Pass &ps = p->passes[k];
+            nphase = std::max(nphase, (int)k + 1);
+            if (ps.kind == 1) {
+                copies[(int)k].push_back(resolve_copy(p, ps, it.in, it.out, it.scratch));
+                continue;
+            }
+            PassArgs a = resolve_pass(p, ps, it.in, it.out, it.scratch);
+            if (a.ntiles <= 0) continue;
+            size_t lds = 0;
+            const int block = widen(ps, &a, &lds);
+            const Key key{(int)k, p->prob.prec, pass_kind(a.flags), block};
+            fam[key].push_back({a, (int64_t)a.n});
+            fam_lds[key] = std::max(fam_lds[key], lds);
+        }
+    }
+    std::vector<std::pair<Key, std::vector<Item>>> order(fam.begin(), fam.end());
+    size_t bytes = 512 + sizeof(unsigned long long) * order.size();
+    for (auto &kv : order) {
+        std::stable_sort(kv.second.begin(), kv.second.end(),
+                         [](const Item &x, const Item &y) { return x.n > y.n; });
+        bytes += kv.second.size() * sizeof(PassArgs) + 256;
+        bytes += (kv.second.size() + 1) * sizeof(int64_t) + 256;
+    }
+    L->host.assign(bytes, 0);
+    size_t off = 0;
+    auto take = [&](size_t n) {
+        size_t o = (off + 255) / 256 * 256;
+        off = o + n;
+        return o;
+    };
+    L->counters_off = take(sizeof(unsigned long long) * std::max<size_t>(1, order.size()));
+    L->ncounters = (int)order.size();
+    L->groups.clear();
+    L->steps.clear();
+    L->tiles = 0;
+    for (size_t gi = 0; gi < order.size(); ++gi) {
+        auto &kv = order[gi];
+        BatchGroup g;
+        g.items_off = take(kv.second.size() * sizeof(PassArgs));
+        g.prefix_off = take((kv.second.size() + 1) * sizeof(int64_t));
+        g.counter_off = L->counters_off + gi * sizeof(unsigned long long);
+        PassArgs *dst = (PassArgs *)(L->host.data() + g.items_off);
+        int64_t *prefix = (int64_t *)(L->host.data() + g.prefix_off);
+        prefix[0] = 0;
+        for (size_t j = 0; j < kv.second.size(); ++j) {
+            dst[j] = kv.second[j].a;
+            prefix[j + 1] = prefix[j] + kv.second[j].a.ntiles;
+        }
+        g.prec = std::get<1>(kv.first);
+        g.kind = std::get<2>(kv.first);
+        g.block = std::get<3>(kv.first);
+        g.lds = fam_lds[kv.first];
+        g.nitems = (int)kv.second.size();
+        g.tiles = prefix[g.nitems];
+        L->tiles += g.tiles;
+        const int64_t resident =
+            (int64_t)batch_blocks_per_cu(g.prec, g.kind, g.block, g.lds) * g_num_cus;
+        g.grid = (int)std::max<int64_t>(1, std::min<int64_t>(g.tiles, resident));
+        L->groups.push_back(g);
+    }
+    L->bytes = off;
+    for (int k = 0; k < nphase; ++k) {
+        for (const CopyArgs &c : copies[k]) {
+            BatchStep st;
+            st.copy = true;
+            st.c = c;
+            L->steps.push_back(st);
+        }
+        for (size_t gi = 0; gi < order.size(); ++gi)
+            if (std::get<0>(order[gi].first) == k) {
+                BatchStep st;
+                st.group = (int)gi;
+                L->steps.push_back(st);
+            }
+    }
+    return MFFT_OK;
+}
+
+int enqueue_batch_layout(const BatchLayout &L, char *dev, hipStream_t s)
+{
+    if (L.ncounters > 0) {
+        hipError_t e = launch_zero_u64((unsigned long long *)(dev + L.counters_off), L.ncounters, s);
+        if (e != hipSuccess) return fail(MFFT_EHIP, std::string("batch launch: ") + hipGetErrorString(e));
+    }
+    for (const BatchStep &st : L.steps) {
         hipError_t e;
         if (st.copy) {
             e = launch_copy(st.c, s);
         } else {
-            const BatchGroup &g = b->groups[st.group];
-            e = launch_zero_u64(g.d_counter, 1, s);
-            if (e == hipSuccess)
-                e = launch_batch(g.d_items, g.d_prefix, g.nitems, g.d_counter, g.prec, g.kind,
-                                 g.block, g.grid, g.lds, s);
+            const BatchGroup &g = L.groups[st.group];
+            e = launch_batch((const PassArgs *)(dev + g.items_off),
+                             (const int64_t *)(dev + g.prefix_off), g.nitems,
+                             (unsigned long long *)(dev + g.counter_off), g.prec, g.kind, g.block,
+                             g.grid, g.lds, s);
+            if (e != hipSuccess)
+                return fail(MFFT_EHIP, std::string("batch launch (block ") + std::to_string(g.block) +
+                                           ", lds " + std::to_string(g.lds) + ", grid " +
+                                           std::to_string(g.grid) + "): " + hipGetErrorString(e));
         }
         if (e != hipSuccess) return fail(MFFT_EHIP, std::string("batch launch: ") + hipGetErrorString(e));
     }
     return MFFT_OK;
 }
+
+int batch_launch_count(const BatchLayout &L)
+{
+    return (int)L.steps.size() + (L.ncounters > 0 ? 1 : 0);
+}
+
+}  // namespace mfft
+
+struct mfft_batch_s {
+    mfft::BatchLayout layout;
+    void *dev_mem = nullptr;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace mfft {
 
 static void batch_free(mfft_batch_s *b)
 {
@@ -95,6 +210,7 @@ int mfft_batch_create(mfft_batch *out, int count, const mfft_plan *plans, const 
         return fail(MFFT_EINVAL, "bad batch arguments");
     *out = nullptr;
     std::set<const void *> scratch_seen;
+    std::vector<BatchItem> items;
     for (int i = 0; i < count; ++i) {
         if (!plans[i]) return fail(MFFT_EINVAL, "NULL plan in batch");
         const PlanImpl *p = &plans[i]->impl;
@@ -105,129 +221,43 @@ int mfft_batch_create(mfft_batch *out, int count, const mfft_plan *plans, const 
             if (!scratch_seen.insert(p->scratch).second)
                 return fail(MFFT_EINVAL, "a plan with scratch appears twice in one batch");
         }
+        items.push_back({p, ins[i], outs[i], p->scratch});
     }
     mfft_batch_s *b = new (std::nothrow) mfft_batch_s();
     if (!b) return fail(MFFT_ENOMEM, "host allocation failed");
-
-    // collect (phase, family) -> items
-    struct Item {
-        PassArgs a;
-        int64_t n;
-    };
-    using Key = std::tuple<int, int, int, int>;   // phase, prec, kind, block
-    std::map<Key, std::vector<Item>> fam;
-    std::map<Key, size_t> fam_lds;
-    std::map<int, std::vector<CopyArgs>> copies;
-    int nphase = 0;
-    for (int i = 0; i < count; ++i) {
-        const PlanImpl *p = &plans[i]->impl;
-        for (size_t k = 0; k < p->passes.size(); ++k) {
-            const Pass &ps = p->passes[k];
-            nphase = std::max(nphase, (int)k + 1);
-            if (ps.kind == 1) {
-                copies[(int)k].push_back(resolve_copy(p, ps, ins[i], outs[i], p->scratch));
-                continue;
-            }
-            PassArgs a = resolve_pass(p, ps, ins[i], outs[i], p->scratch);
-            if (a.ntiles <= 0) continue;
-            const int block = a.bt * a.tpt;
-            const Key key{(int)k, p->prob.prec, pass_kind(a.flags), block};
-            fam[key].push_back({a, (int64_t)a.n});
-            fam_lds[key] = std::max(fam_lds[key], generic_lds_bytes(ps));
-        }
+    int rc = build_batch_layout(items, &b->layout);
+    if (rc) {
+        batch_free(b);
+        return rc;
     }
-    // device layout: per group items[], prefix[], counter
-    size_t bytes = 0;
-    std::vector<std::pair<Key, std::vector<Item>>> order(fam.begin(), fam.end());
-    for (auto &kv : order) {
-        std::stable_sort(kv.second.begin(), kv.second.end(),
-                         [](const Item &x, const Item &y) { return x.n > y.n; });
-        bytes += kv.second.size() * sizeof(PassArgs) + 256;
-        bytes += (kv.second.size() + 1) * sizeof(int64_t) + 256;
-        bytes += 256;
-    }
-    std::vector<unsigned char> host(bytes ? bytes : 1);
-    size_t off = 0;
-    auto take = [&](size_t n) {
-        size_t o = (off + 255) / 256 * 256;
-        off = o + n;
-        return o;
-    };
-    struct Place {
-        size_t items, prefix, counter;
-    };
-    std::vector<Place> places;
-    for (auto &kv : order) {
-        Place pl;
-        pl.items = take(kv.second.size() * sizeof(PassArgs));
-        pl.prefix = take((kv.second.size() + 1) * sizeof(int64_t));
-        pl.counter = take(sizeof(unsigned long long));
-        places.push_back(pl);
-        PassArgs *items = (PassArgs *)(host.data() + pl.items);
-        int64_t *prefix = (int64_t *)(host.data() + pl.prefix);
-        prefix[0] = 0;
-        for (size_t j = 0; j < kv.second.size(); ++j) {
-            items[j] = kv.second[j].a;
-            prefix[j + 1] = prefix[j] + kv.second[j].a.ntiles;
-        }
-    }
-    if (off && hipMalloc(&b->dev_mem, off) != hipSuccess) {
+    if (b->layout.bytes && hipMalloc(&b->dev_mem, b->layout.bytes) != hipSuccess) {
         (void)hipGetLastError();
         batch_free(b);
         return fail(MFFT_ENOMEM, "batch descriptor allocation failed");
     }
-    hipStream_t s = (hipStream_t)hip_stream;
-    if (off && hipMemcpy(b->dev_mem, host.data(), off, hipMemcpyHostToDevice) != hipSuccess) {
+    if (b->layout.bytes &&
+        hipMemcpy(b->dev_mem, b->layout.host.data(), b->layout.bytes, hipMemcpyHostToDevice) !=
+            hipSuccess) {
         batch_free(b);
         return fail(MFFT_EHIP, "batch descriptor upload failed");
     }
-    for (size_t gi = 0; gi < order.size(); ++gi) {
-        const Key &key = order[gi].first;
-        BatchGroup g;
-        g.prec = std::get<1>(key);
-        g.kind = std::get<2>(key);
-        g.block = std::get<3>(key);
-        g.lds = fam_lds[key];
-        g.nitems = (int)order[gi].second.size();
-        const int64_t *prefix = (const int64_t *)(host.data() + places[gi].prefix);
-        g.tiles = prefix[g.nitems];
-        b->tiles += g.tiles;
-        const int64_t resident =
-            (int64_t)batch_blocks_per_cu(g.prec, g.kind, g.block, g.lds) * g_num_cus;
-        g.grid = (int)std::max<int64_t>(1, std::min<int64_t>(g.tiles, resident));
-        char *base = (char *)b->dev_mem;
-        g.d_items = (PassArgs *)(base + places[gi].items);
-        g.d_prefix = (int64_t *)(base + places[gi].prefix);
-        g.d_counter = (unsigned long long *)(base + places[gi].counter);
-        b->groups.push_back(g);
-    }
-    for (int k = 0; k < nphase; ++k) {
-        for (const CopyArgs &c : copies[k]) {
-            BatchStep st;
-            st.copy = true;
-            st.c = c;
-            b->steps.push_back(st);
-        }
-        for (size_t gi = 0; gi < order.size(); ++gi)
-            if (std::get<0>(order[gi].first) == k) {
-                BatchStep st;
-                st.group = (int)gi;
-                b->steps.push_back(st);
-            }
-    }
+    (void)hip_stream;
     if (flags & MFFT_BATCH_GRAPH) {
         hipError_t e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeRelaxed);
-        int rc = e == hipSuccess ? enqueue_steps(b, b->cap_stream) : MFFT_EHIP;
-        hipError_t e2 = hipStreamEndCapture(b->cap_stream, &b->graph);
-        if (e == hipSuccess) e = e2;
-        if (e == hipSuccess && rc == MFFT_OK) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+        rc = e == hipSuccess ? enqueue_batch_layout(b->layout, (char *)b->dev_mem, b->cap_stream)
+                             : MFFT_EHIP;
+        if (e == hipSuccess) {
+            hipError_t e2 = hipStreamEndCapture(b->cap_stream, &b->graph);
+            if (e2 != hipSuccess) e = e2;
+        }
+        if (e == hipSuccess && rc == MFFT_OK)
+            e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
         if (e != hipSuccess || rc != MFFT_OK) {
             batch_free(b);
             return fail(MFFT_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
         }
     }
-    (void)s;
     *out = b;
     return MFFT_OK;
 }
@@ -241,18 +271,14 @@ int mfft_batch_execute(mfft_batch batch, void *hip_stream)
         if (e != hipSuccess) return fail(MFFT_EHIP, std::string("graph launch: ") + hipGetErrorString(e));
         return MFFT_OK;
     }
-    return enqueue_steps(batch, s);
+    return enqueue_batch_layout(batch->layout, (char *)batch->dev_mem, s);
 }
 
 int mfft_batch_info(mfft_batch batch, int *launches, int64_t *tiles)
 {
     if (!batch) return fail(MFFT_EINVAL, "batch is NULL");
-    if (launches) {
-        int n = 0;
-        for (const BatchStep &st : batch->steps) n += st.copy ? 1 : 2;   // counter clear + kernel
-        *launches = n;
-    }
-    if (tiles) *tiles = batch->tiles;
+    if (launches) *launches = batch_launch_count(batch->layout);
+    if (tiles) *tiles = batch->layout.tiles;
     return MFFT_OK;
 }
 

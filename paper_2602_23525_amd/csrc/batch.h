@@ -1,0 +1,47 @@
+// Batch layout shared by mfft_batch_* and the request server: the host image
+// of the descriptor lists, prefix sums and counters, and the launch sequence.
+#pragma once
+#include <vector>
+
+#include "plan.h"
+
+namespace mfft {
+
+struct BatchItem {
+    const PlanImpl *plan;
+    const void *in;
+    void *out;
+    void *scratch;   // the plan's scratch or a caller-provided region of the same size
+};
+
+struct BatchGroup {
+    int prec = 0, kind = 0, block = 0;
+    size_t lds = 0;
+    int grid = 0;
+    int nitems = 0;
+    int64_t tiles = 0;
+    size_t items_off = 0, prefix_off = 0, counter_off = 0;   // offsets in the image
+};
+
+struct BatchStep {   // one launch: a group, or a copy pass
+    bool copy = false;
+    CopyArgs c{};
+    int group = -1;
+};
+
+struct BatchLayout {
+    std::vector<unsigned char> host;   // device image (upload `bytes` of it)
+    size_t bytes = 0;
+    size_t counters_off = 0;
+    int ncounters = 0;
+    std::vector<BatchGroup> groups;
+    std::vector<BatchStep> steps;
+    int64_t tiles = 0;
+};
+
+int build_batch_layout(const std::vector<BatchItem> &items, BatchLayout *L);
+// Launch the sequence with the image resident at `dev`.
+int enqueue_batch_layout(const BatchLayout &L, char *dev, hipStream_t s);
+int batch_launch_count(const BatchLayout &L);
+
+}  // namespace mfft

@@ -6,6 +6,12 @@ namespace mfft {
 
 hipError_t launch_pass_c32_k3(const PassArgs &a, size_t lds, hipStream_t s)
 {
+    static size_t big = 65536;   // dynamic LDS allowed so far (gfx950: up to 160 KB)
+    if (lds > big) {
+        (void)hipFuncSetAttribute((const void *)pass_kernel<float, 16, 3>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        big = lds;
+    }
     hipLaunchKernelGGL((pass_kernel<float, 16, 3>), dim3((unsigned)a.ntiles), dim3(a.bt * a.tpt),
                        lds, s, a);
     return hipGetLastError();
@@ -15,6 +21,12 @@ hipError_t launch_batch_c32_k3(const PassArgs *items, const int64_t *prefix, int
                                 unsigned long long *counter, int block, int grid, size_t lds,
                                 hipStream_t s)
 {
+    static size_t big = 65536;
+    if (lds > big) {
+        (void)hipFuncSetAttribute((const void *)batch_kernel<float, 16, 3>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        big = lds;
+    }
     hipLaunchKernelGGL((batch_kernel<float, 16, 3>), dim3(grid), dim3(block), lds, s, items,
                        prefix, nitems, counter);
     return hipGetLastError();

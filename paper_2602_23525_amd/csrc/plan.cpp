@@ -34,6 +34,8 @@ int g_num_cus = 256;           // compute units of the device
 
 
 static int elem_bytes(int prec) { return prec ? 16 : 8; }
+// workgroup size limit of the generic kernels (launch bounds in tile.h)
+static int max_threads(int prec) { return prec ? 512 : 1024; }
 
 // ------------------------------------------------------------ memory
 
@@ -149,7 +151,7 @@ static bool leaf_fits(int64_t n, int prec, int bt)
 {
     Leaf L;
     if (!make_leaf_shape(n, 16, &L)) return false;
-    return tile_lds_bytes((int)n, bt, prec) <= g_lds_budget && bt * L.tpt <= 1024;
+    return tile_lds_bytes((int)n, bt, prec) <= g_lds_budget && bt * L.tpt <= max_threads(prec);
 }
 
 // Stage twiddle table for a leaf: stage s holds w_(Ns*R)^(j*k) for j < Ns,
@@ -358,14 +360,19 @@ static int add_line_pass(Builder &b, const LineSpec &ls)
     // lines per tile: column phases want >= 128 B runs; row tiles aim at
     // 256-thread workgroups.  Both bounded by the LDS budget.
     const bool col = a.load_mode == kModeCol || a.store_mode == kModeCol;
+    // Prefer tiles of at most 64 KB (several workgroups per CU); column tiles
+    // may grow to the full LDS rather than drop below 64-byte runs.
     int bt;
     if (col) bt = prec ? 8 : 16;
     else bt = std::max(1, 256 / L.tpt);
     bt = 1 << ilog2(bt);
     if (bt > 1 && (1 << ilog2(bt)) != bt) bt >>= 1;
-    while (bt > 1 && (tile_lds_bytes(L.n, bt, prec) > g_lds_budget || bt * L.tpt > 1024)) bt >>= 1;
+    const int bt_floor = col ? (prec ? 4 : 8) : 1;
+    const int mt = max_threads(prec);
+    while (bt > bt_floor && (tile_lds_bytes(L.n, bt, prec) > 65536 || bt * L.tpt > mt)) bt >>= 1;
+    while (bt > 1 && (tile_lds_bytes(L.n, bt, prec) > g_lds_budget || bt * L.tpt > mt)) bt >>= 1;
     while (bt > 1 && bt / 2 >= in_dim.n) bt >>= 1;   // no wider than the loop
-    if (tile_lds_bytes(L.n, bt, prec) > g_lds_budget || bt * L.tpt > 1024)
+    if (tile_lds_bytes(L.n, bt, prec) > g_lds_budget || bt * L.tpt > mt)
         return fail(MFFT_ENOTSUP, "leaf does not fit the LDS budget");
     a.bt = bt;
     a.bt_log2 = ilog2(bt);

@@ -443,12 +443,30 @@ __device__ __forceinline__ void run_tile(const PassArgs &a, int64_t tile, cpx<T>
 
     int first_fetch = F_GLOBAL;
     if (a.load_mode == kModeCol) {
-        for (int q = tl.act ? tl.tid : bt * n; q < bt * n; q += nthr) {
-            const int trq = q & (bt - 1);
-            const int idx = q >> a.bt_log2;
+        // nthr is a multiple of bt, so each lane keeps one line of the tile
+        // (consecutive lanes on consecutive lines: unit vector stride) and walks
+        // that line's elements in steps of tpt
+        if (tl.act) {
+            const int trq = tl.tid & (bt - 1);
             const int64_t c = tl.c0 + trq;
-            lds[trq * a.lds_stride + lds_pad(idx)] =
-                load_elem<T, KIND>(a, c, tl.ob_in + c * a.vis, idx, c < a.vn);
+            const bool okc = c < a.vn;
+            const int64_t base = tl.ob_in + c * a.vis;
+            cpx<T> *dst = lds + trq * a.lds_stride;
+            const int step = a.tpt;
+            int idx = tl.tid >> a.bt_log2;
+            if constexpr (KIND & K_EXT) {
+                for (; idx < n; idx += step) dst[lds_pad(idx)] = load_elem<T, KIND>(a, c, base, idx, okc);
+            } else {
+                const bool cj = (f & PF_CONJ_IN) != 0;
+                const int64_t inc = (int64_t)step * a.is;
+                const cpx<T> *p = (const cpx<T> *)a.in + base + (int64_t)idx * a.is;
+#pragma unroll 4
+                for (; idx < n; idx += step, p += inc) {
+                    cpx<T> x = {T(0), T(0)};
+                    if (okc) x = *p;
+                    dst[lds_pad(idx)] = cj ? conj(x) : x;
+                }
+            }
         }
         __syncthreads();
         first_fetch = F_LDS;
@@ -472,29 +490,51 @@ __device__ __forceinline__ void run_tile(const PassArgs &a, int64_t tile, cpx<T>
     }
 
     if (a.store_mode == kModeCol) {
-        for (int q = tl.act ? tl.tid : bt * n; q < bt * n; q += nthr) {
-            const int trq = q & (bt - 1);
-            const int idx = q >> a.bt_log2;
+        if (tl.act) {
+            const int trq = tl.tid & (bt - 1);
             const int64_t c = tl.c0 + trq;
-            cpx<T> y = lds[trq * a.lds_stride + lds_pad(idx)];
-            if constexpr (KIND & K_TW4) {
-                if (f & PF_TW4) y = mul_d(y, tw4_root(a, (int64_t)idx * c));
-            }
-            Tile<T> tq = tl;
-            if constexpr (KIND & K_EXT) {
-                if (f & PF_RADER) {
-                    tq.x0 = slots[2 * trq];
-                    tq.a0 = slots[2 * trq + 1];
+            const bool okc = c < a.vn;
+            const int64_t base = tl.ob_out + c * a.vos;
+            const cpx<T> *src = lds + trq * a.lds_stride;
+            const int step = a.tpt;
+            int idx = tl.tid >> a.bt_log2;
+            if constexpr (KIND & (K_EXT | K_TW4)) {
+                Tile<T> tq = tl;
+                if constexpr (KIND & K_EXT) {
+                    if (f & PF_RADER) {
+                        tq.x0 = slots[2 * trq];
+                        tq.a0 = slots[2 * trq + 1];
+                    }
+                }
+                for (; idx < n; idx += step) {
+                    cpx<T> y = src[lds_pad(idx)];
+                    if constexpr (KIND & K_TW4) {
+                        if (f & PF_TW4) y = mul_d(y, tw4_root(a, (int64_t)idx * c));
+                    }
+                    store_elem<T, KIND>(a, tq, c, base, idx, y, okc);
+                }
+            } else if (okc) {
+                const bool cj = (f & PF_CONJ_OUT) != 0;
+                const int64_t inc = (int64_t)step * a.os;
+                cpx<T> *p = (cpx<T> *)a.out + base + (int64_t)idx * a.os;
+#pragma unroll 4
+                for (; idx < n; idx += step, p += inc) {
+                    const cpx<T> y = src[lds_pad(idx)];
+                    *p = cj ? conj(y) : y;
                 }
             }
-            store_elem<T, KIND>(a, tq, c, tl.ob_out + c * a.vos, idx, y, c < a.vn);
         }
     }
     __syncthreads();  // the next tile of a persistent workgroup reuses LDS
 }
 
+// Largest workgroup of the generic kernels: FP64 lines keep 512 threads so the
+// compiler may use up to 256 VGPRs without spilling.
+template <typename T>
+constexpr int max_block() { return sizeof(T) == 8 ? 512 : 1024; }
+
 template <typename T, int EMAX, int KIND>
-__global__ __launch_bounds__(1024) void pass_kernel(PassArgs a)
+__global__ __launch_bounds__(max_block<T>()) void pass_kernel(PassArgs a)
 {
     extern __shared__ unsigned char smem[];
     cpx<T> *lds = (cpx<T> *)smem;
@@ -508,7 +548,7 @@ __global__ __launch_bounds__(1024) void pass_kernel(PassArgs a)
 // Persistent batched kernel: workgroups pop tiles from a shared counter until
 // the list is exhausted.  items[i] covers tiles [prefix[i], prefix[i+1]).
 template <typename T, int EMAX, int KIND>
-__global__ __launch_bounds__(1024) void batch_kernel(const PassArgs *__restrict__ items,
+__global__ __launch_bounds__(max_block<T>()) void batch_kernel(const PassArgs *__restrict__ items,
                                                      const int64_t *__restrict__ prefix, int nitems,
                                                      unsigned long long *counter)
 {

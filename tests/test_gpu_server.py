@@ -1,0 +1,164 @@
+"""GPU tests of the request server (continuous batching under an HBM budget):
+every response matches the oracle, a request's result is identical alone and
+in a mix, oversized requests are rejected, pending requests can be cancelled,
+and the statistics are consistent."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import serve_trace, uniform_complex
+
+pytestmark = pytest.mark.gpu
+
+
+def _contig(dims):
+    out, s = [], 1
+    for n in reversed(dims):
+        out.append((n, s, s))
+        s *= n
+    return list(reversed(out))
+
+
+def _mk(req_dims, batch, prec, seed):
+    import torch
+    tot = int(np.prod(req_dims)) * batch
+    cdt = np.complex64 if prec == 0 else np.complex128
+    x = uniform_complex(tot, seed=seed, dtype=cdt)
+    return x, torch.from_numpy(x).cuda()
+
+
+def _problem(req_dims, batch):
+    dims = _contig(req_dims)
+    ntot = int(np.prod(req_dims))
+    hd = [(batch, ntot, ntot)] if batch > 1 else []
+    return dims, hd
+
+
+def _read(ptr, count, prec):
+    import torch
+    dt = torch.complex64 if prec == 0 else torch.complex128
+    t = torch.empty(count, dtype=dt, device="cuda")
+    nbytes = count * (8 if prec == 0 else 16)
+    # copy from the server-owned output through torch's stream
+    import ctypes
+    hip = ctypes.CDLL("libamdhip64.so.7")
+    hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    assert hip.hipMemcpy(t.data_ptr(), ptr, nbytes, 3) == 0
+    return t.cpu().numpy()
+
+
+def test_server_mixed_requests_match_oracle():
+    import paper_2602_23525_amd as mfft
+    srv = mfft.Server(budget_bytes=2 << 30, max_inflight=32, n_streams=3)
+    reqs = []
+    specs = [((4096,), 8, 0, -1), ((1000,), 4, 0, 1), ((64, 64), 3, 1, -1), ((16, 12, 10), 2, 0, 1),
+             ((65536,), 2, 0, -1), ((1009,), 5, 1, -1), ((256, 256), 1, 0, -1), ((97,), 30, 0, 1),
+             ((2048,), 16, 1, 1), ((30, 42), 6, 0, -1)]
+    for i, (shape, b, prec, sign) in enumerate(specs):
+        x, xt = _mk(shape, b, prec, 900 + i)
+        dims, hd = _problem(shape, b)
+        t = srv.submit(dims, hd, xt, None, sign=sign, prec=prec)
+        reqs.append((t, x, xt, dims, hd, prec, sign))
+    for t, x, xt, dims, hd, prec, sign in reqs:
+        assert srv.wait(t, 60000) == 0
+        y = _read(srv.output(t), x.size, prec)
+        ref = np.zeros(x.size, np.complex128)
+        oracle.dft(x.astype(np.complex128), ref, dims, hd, sign=sign)
+        assert oracle.rel_rms(y, ref) <= (2e-6 if prec == 0 else 1e-13)
+        srv.release(t)
+    st = srv.stats()
+    assert st["completed"] == len(specs) and st["failed"] == 0
+    assert st["launches"] >= 1 and st["p99_ms"] >= st["p50_ms"] > 0
+    assert st["bytes_in_use"] == 0 and st["peak_bytes"] > 0
+    srv.destroy()
+
+
+def test_result_same_alone_and_in_mix():
+    import paper_2602_23525_amd as mfft
+    shape, b, prec = (4096,), 4, 0
+    x, xt = _mk(shape, b, prec, 77)
+    dims, hd = _problem(shape, b)
+    srv = mfft.Server(budget_bytes=1 << 30, max_inflight=64, n_streams=4)
+    t = srv.submit(dims, hd, xt, None)
+    assert srv.wait(t, 60000) == 0
+    alone = _read(srv.output(t), x.size, prec)
+    srv.release(t)
+    # the same request among many others arriving together
+    others = []
+    for i in range(24):
+        n = [128, 1000, 2187, 8192, 97][i % 5]
+        xo, xot = _mk((n,), 3, 0, 1000 + i)
+        d2, h2 = _problem((n,), 3)
+        others.append((srv.submit(d2, h2, xot, None), xot))
+        if i == 11:
+            t = srv.submit(dims, hd, xt, None)
+    assert srv.wait(t, 60000) == 0
+    mixed = _read(srv.output(t), x.size, prec)
+    srv.release(t)
+    for to, _ in others:
+        assert srv.wait(to, 60000) == 0
+        srv.release(to)
+    assert np.array_equal(alone, mixed)
+    ref = oracle.fft(x.astype(np.complex128).reshape(b, 4096))
+    assert oracle.rel_rms(mixed.reshape(b, 4096), ref) <= 2e-6
+    srv.destroy()
+
+
+def test_budget_rejection_and_cancel():
+    import torch
+
+    import paper_2602_23525_amd as mfft
+    srv = mfft.Server(budget_bytes=10 << 20, max_inflight=1, n_streams=1)
+    big = torch.zeros(1 << 21, dtype=torch.complex64, device="cuda")        # 16 MiB output
+    with pytest.raises(mfft.MfftError) as e:
+        srv.submit([(1 << 21, 1, 1)], [], big, None)
+    assert e.value.code == -6
+    # a queue of requests that each take most of the budget: later ones wait
+    x = torch.zeros(1 << 19, dtype=torch.complex64, device="cuda")          # 4 MiB
+    tickets = [srv.submit([(1 << 19, 1, 1)], [], x, None) for _ in range(6)]
+    srv.cancel(tickets[-1])
+    assert srv.wait(tickets[-1], 1000) == -9
+    for t in tickets[:-1]:
+        assert srv.wait(t, 60000) == 0
+        srv.release(t)
+    st = srv.stats()
+    assert st["rejected"] == 1 and st["cancelled"] == 1 and st["completed"] == 5
+    assert st["peak_bytes"] <= 10 << 20
+    srv.destroy()
+
+
+def test_poisson_trace_small():
+    """A short seeded Poisson trace through the server, responses sampled
+    against the oracle."""
+    import torch
+
+    import paper_2602_23525_amd as mfft
+    trace = serve_trace(40, rate_hz=2000.0, seed=6, hi_exp=16, max_batch=4)
+    srv = mfft.Server(budget_bytes=1 << 30, max_inflight=16, n_streams=4)
+    pools = {0: torch.from_numpy(uniform_complex(1 << 19, seed=3, dtype=np.complex64)).cuda(),
+             1: torch.from_numpy(uniform_complex(1 << 19, seed=4, dtype=np.complex128)).cuda()}
+    t0 = time.monotonic()
+    sub = []
+    for r in trace:
+        while time.monotonic() - t0 < r.arrival:
+            pass
+        prec = 0 if r.prec == "c32" else 1
+        view = pools[prec]
+        dims, hd = _problem(r.dims, r.batch)
+        t = srv.submit(dims, hd, view, None, sign=r.sign, prec=prec, arrival=t0 + r.arrival)
+        sub.append((t, r, prec, view, dims, hd))
+    for k, (t, r, prec, view, dims, hd) in enumerate(sub):
+        assert srv.wait(t, 60000) == 0
+        if k % 5 == 0:
+            cnt = int(np.prod(r.dims)) * r.batch
+            y = _read(srv.output(t), cnt, prec)
+            x = view[:cnt].cpu().numpy().astype(np.complex128)
+            ref = np.zeros(cnt, np.complex128)
+            oracle.dft(x, ref, dims, hd, sign=r.sign)
+            assert oracle.rel_rms(y, ref) <= (2e-6 if prec == 0 else 1e-13)
+        srv.release(t)
+    st = srv.stats()
+    assert st["completed"] == len(trace)
+    srv.destroy()
