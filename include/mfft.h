@@ -234,6 +234,8 @@ int mfft_server_release(mfft_server server, uint64_t ticket);
 /* Cancel a request that has not been admitted (ESTATE if already running). */
 int mfft_server_cancel(mfft_server server, uint64_t ticket);
 int mfft_server_stats(mfft_server server, mfft_server_stats_t *stats);
+/* Clear the counters and latency samples (e.g. after a warm-up phase). */
+int mfft_server_reset_stats(mfft_server server);
 /* Stop accepting, finish in-flight work, free everything. */
 int mfft_server_destroy(mfft_server server);
 

@@ -109,9 +109,10 @@ def lib():
     L.mfft_server_cancel.argtypes = [p, u64]
     L.mfft_server_stats.argtypes = [p, p]
     L.mfft_server_destroy.argtypes = [p]
+    L.mfft_server_reset_stats.argtypes = [p]
     for name in ("mfft_server_create", "mfft_server_submit", "mfft_server_wait",
                  "mfft_server_output", "mfft_server_release", "mfft_server_cancel",
-                 "mfft_server_stats", "mfft_server_destroy"):
+                 "mfft_server_stats", "mfft_server_destroy", "mfft_server_reset_stats"):
         getattr(L, name).restype = ctypes.c_int
     L.mfft_last_error.restype = ctypes.c_char_p
     L.mfft_version.restype = ctypes.c_char_p
@@ -393,6 +394,9 @@ class Server:
 
     def cancel(self, ticket):
         _check(lib().mfft_server_cancel(self.handle, ctypes.c_uint64(ticket)), "mfft_server_cancel")
+
+    def reset_stats(self):
+        _check(lib().mfft_server_reset_stats(self.handle), "mfft_server_reset_stats")
 
     def stats(self) -> dict:
         s = ServerStats()

@@ -41,7 +41,14 @@ enum : uint32_t {
     PF_AUX_X0 = 1u << 10,    // save x0 of each transform to aux (multi-pass Rader)
     PF_AUX_A0 = 1u << 11,    // save the k=0 output (before post multiply) to aux
     PF_AUX_ADD = 1u << 12,   // add aux x0 on store, write Y[0] = x0 + A0 (multi-pass Rader)
+    PF_XCD = 1u << 13,       // map consecutive tiles to one XCD (L2 locality of gathers)
 };
+
+// Workgroups are dispatched round-robin over the chip's 8 XCDs, each with its
+// own L2.  With PF_XCD the launch has a multiple of 8 workgroups and workgroup
+// b runs tile (b % 8) * (grid / 8) + b / 8, so each XCD walks a contiguous
+// range of tiles (all tiles of one transform share an L2).
+constexpr int kXcds = 8;
 
 // One Stockham stage of radix R after sub-transforms of size Ns are complete.
 struct StageDesc {

@@ -12,8 +12,9 @@ hipError_t launch_pass_c32_k1(const PassArgs &a, size_t lds, hipStream_t s)
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         big = lds;
     }
-    hipLaunchKernelGGL((pass_kernel<float, 16, 1>), dim3((unsigned)a.ntiles), dim3(a.bt * a.tpt),
-                       lds, s, a);
+    const int64_t grid = (a.flags & PF_XCD) ? (a.ntiles + kXcds - 1) / kXcds * kXcds : a.ntiles;
+    hipLaunchKernelGGL((pass_kernel<float, 16, 1>), dim3((unsigned)grid),
+                       dim3(a.bt * a.tpt), lds, s, a);
     return hipGetLastError();
 }
 

@@ -172,6 +172,7 @@ int pass_kind(uint32_t flags)
 {
     const uint32_t ext = PF_PRE_MUL | PF_GATHER | PF_CONV | PF_CONJ_A | PF_POST_MUL |
                          PF_SCATTER | PF_RADER | PF_AUX_X0 | PF_AUX_A0 | PF_AUX_ADD;
+    // PF_XCD only changes the tile order and is handled by every kind
     if (flags & ext) return 3;
     if (flags & PF_TW4) return 1;
     return 0;
@@ -181,7 +182,7 @@ hipError_t launch_pass(const PassArgs &a, int prec, int emax, size_t lds_bytes, 
 {
     (void)emax;
     if (a.ntiles <= 0) return hipSuccess;
-    if (a.ntiles > 0x7fffffffLL) return hipErrorInvalidValue;
+    if (a.ntiles > 0x7fffffffLL - kXcds) return hipErrorInvalidValue;
     const int k = pass_kind(a.flags);
     if (prec == 0) {
         if (k == 0) return launch_pass_c32_k0(a, lds_bytes, s);

@@ -137,6 +137,8 @@ static bool make_leaf_shape(int64_t n, int emax, Leaf *L)
         const int nb = (int)(n / R);
         tpt = std::max(tpt, (nb + nbmax - 1) / nbmax);
     }
+    // the column loops unroll EMAX + 2 elements per thread
+    tpt = std::max(tpt, (int)((n + emax + 1) / (emax + 2)));
     if (tpt > 1024) return false;
     L->n = (int)n;
     L->rad = rad;
@@ -614,7 +616,7 @@ static int plan_rader(Builder &b, Dim d, const std::vector<Dim> &V, int src, int
     A.src_off = src_off;
     A.dst = BUF_SCRATCH;
     A.dst_off = s0;
-    A.flags = PF_GATHER | PF_TW4 | PF_AUX_X0 | (conj_in ? PF_CONJ_IN : 0);
+    A.flags = PF_GATHER | PF_TW4 | PF_AUX_X0 | PF_XCD | (conj_in ? PF_CONJ_IN : 0);
     A.gather = gat;
     A.li_c = 1;
     A.li_l = r1;
@@ -665,7 +667,7 @@ static int plan_rader(Builder &b, Dim d, const std::vector<Dim> &V, int src, int
     D.src_off = s1;
     D.dst = dst;
     D.dst_off = dst_off;
-    D.flags = PF_CONJ_A | PF_AUX_ADD | PF_SCATTER | (conj_out ? PF_CONJ_OUT : 0);
+    D.flags = PF_CONJ_A | PF_AUX_ADD | PF_SCATTER | PF_XCD | (conj_out ? PF_CONJ_OUT : 0);
     D.scatter = sct;
     D.lo_c = 1;
     D.lo_k = m1;

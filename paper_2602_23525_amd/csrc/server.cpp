@@ -564,6 +564,20 @@ int mfft_server_stats(mfft_server S, mfft_server_stats_t *st)
     return MFFT_OK;
 }
 
+int mfft_server_reset_stats(mfft_server S)
+{
+    if (!S) return fail(MFFT_EINVAL, "NULL server");
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->submitted = S->admitted = S->completed = S->rejected = S->failed = S->cancelled = 0;
+    S->launches = 0;
+    S->lat_ms.clear();
+    S->busy_s = 0;
+    if (S->busy_since >= 0) S->busy_since = now_s();
+    S->flops = S->bytes = 0;
+    S->max_inflight_seen = S->admitted_open;
+    return MFFT_OK;
+}
+
 int mfft_server_destroy(mfft_server S)
 {
     if (!S) return MFFT_OK;

@@ -457,15 +457,21 @@ __device__ __forceinline__ void run_tile(const PassArgs &a, int64_t tile, cpx<T>
             if constexpr (KIND & K_EXT) {
                 for (; idx < n; idx += step) dst[lds_pad(idx)] = load_elem<T, KIND>(a, c, base, idx, okc);
             } else {
+                // all of a lane's loads are issued before the first LDS write,
+                // so a tile costs one memory round trip (n / tpt <= EMAX + 2)
                 const bool cj = (f & PF_CONJ_IN) != 0;
                 const int64_t inc = (int64_t)step * a.is;
                 const cpx<T> *p = (const cpx<T> *)a.in + base + (int64_t)idx * a.is;
-#pragma unroll 4
-                for (; idx < n; idx += step, p += inc) {
-                    cpx<T> x = {T(0), T(0)};
-                    if (okc) x = *p;
-                    dst[lds_pad(idx)] = cj ? conj(x) : x;
+                constexpr int KMAX = EMAX + 2;
+                cpx<T> r[KMAX];
+#pragma unroll
+                for (int k = 0; k < KMAX; ++k) {
+                    r[k] = {T(0), T(0)};
+                    if (okc && idx + k * step < n) r[k] = p[k * inc];
                 }
+#pragma unroll
+                for (int k = 0; k < KMAX; ++k)
+                    if (idx + k * step < n) dst[lds_pad(idx + k * step)] = cj ? conj(r[k]) : r[k];
             }
         }
         __syncthreads();
@@ -517,10 +523,13 @@ __device__ __forceinline__ void run_tile(const PassArgs &a, int64_t tile, cpx<T>
                 const bool cj = (f & PF_CONJ_OUT) != 0;
                 const int64_t inc = (int64_t)step * a.os;
                 cpx<T> *p = (cpx<T> *)a.out + base + (int64_t)idx * a.os;
-#pragma unroll 4
-                for (; idx < n; idx += step, p += inc) {
-                    const cpx<T> y = src[lds_pad(idx)];
-                    *p = cj ? conj(y) : y;
+                constexpr int KMAX = EMAX + 2;
+#pragma unroll
+                for (int k = 0; k < KMAX; ++k) {
+                    if (idx + k * step < n) {
+                        const cpx<T> y = src[lds_pad(idx + k * step)];
+                        p[k * inc] = cj ? conj(y) : y;
+                    }
                 }
             }
         }
@@ -542,7 +551,13 @@ __global__ __launch_bounds__(max_block<T>()) void pass_kernel(PassArgs a)
     // per-stage descriptors indexed at run time are scalar loads rather than a
     // private copy of the whole block.
     const PassArgs *ap = (const PassArgs *)__builtin_amdgcn_kernarg_segment_ptr();
-    run_tile<T, EMAX, KIND>(*ap, (int64_t)blockIdx.x, lds);
+    int64_t tile = blockIdx.x;
+    if (ap->flags & PF_XCD) {
+        const int64_t per = gridDim.x / kXcds;
+        tile = (int64_t)(blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
+        if (tile >= ap->ntiles) return;   // whole workgroup leaves together
+    }
+    run_tile<T, EMAX, KIND>(*ap, tile, lds);
 }
 
 // Persistent batched kernel: workgroups pop tiles from a shared counter until
