@@ -99,6 +99,10 @@ struct PassArgs {
     int64_t tw4_N;
     int32_t tw4_shift;
     int32_t tw4_mask;
+
+    // in-kernel convolution: element idx of line c is multiplied by
+    // conv[c * conv_c + idx * conv_k]
+    int64_t conv_c, conv_k;
 };
 
 // LDS index padding: one spare slot every 16 elements keeps radix-16 stride

@@ -242,6 +242,7 @@ struct LineSpec {
     const int32_t *gather = nullptr, *scatter = nullptr;
     int64_t aux_off = -1;
     int64_t conv_n = 0;        // leaf length when it differs from line.n (Bluestein / Rader)
+    int64_t conv_c = 0, conv_k = 1;   // convolution table index c*conv_c + k*conv_k
     std::string what;
 };
 
@@ -394,6 +395,8 @@ static int add_line_pass(Builder &b, const LineSpec &ls)
     a.pre = ls.pre;
     a.post = ls.post;
     a.conv = ls.conv;
+    a.conv_c = ls.conv_c;
+    a.conv_k = ls.conv_k;
     a.gather = ls.gather;
     a.scatter = ls.scatter;
     if (ls.flags & PF_TW4) {
@@ -604,7 +607,7 @@ static int plan_rader(Builder &b, Dim d, const std::vector<Dim> &V, int src, int
     const int64_t s1 = b.scratch_take(H * L * eb) / eb;
     const int64_t aux = b.scratch_take(H * 2 * eb);
     std::vector<Dim> Vp = packed(V, L, 1);   // outputs packed in scratch
-    // P1: pass A over a[li] = x[g^li], li = c + l*r1, twiddled; saves x0
+    // P1: DIT pass A over a[li] = x[g^li], li = c + l*r1 (c < r1), twiddled; saves x0
     LineSpec A;
     A.what = "raderA";
     A.line = {m1, d.is, 1};
@@ -625,43 +628,36 @@ static int plan_rader(Builder &b, Dim d, const std::vector<Dim> &V, int src, int
     A.aux_off = aux;
     rc = add_line_pass(b, A);
     if (rc) return rc;
-    // P2: pass B in place on s0, spectrum multiply, save A0, conj for the inverse
+    // P2: on the same lines k1 (stride m1): the forward r1-point DFTs (DIT pass B),
+    // the pointwise product with the spectrum (index k1 + k2*m1), and the first
+    // step of the inverse transform in decimation-in-frequency order (r1-point
+    // DFTs of the conjugate, then the twiddle w_L^(k1*j1)); saves the zero
+    // frequency of line 0.  Stored at j1*m1 + k1.
     LineSpec B;
     B.what = "raderB";
     B.line = {r1, m1, m1};
     B.V = packed(packed(V, L, 0), L, 1);
     B.V.push_back({m1, 1, 1});
     B.inner = (int)B.V.size() - 1;
-    B.src = B.dst = BUF_SCRATCH;
-    B.src_off = B.dst_off = s0;
-    B.flags = PF_POST_MUL | PF_AUX_A0 | PF_CONJ_OUT;
-    B.post = spec;
-    B.lo_c = 1;
-    B.lo_k = m1;
-    B.lo_lim = L;
+    B.src = BUF_SCRATCH;
+    B.src_off = s0;
+    B.dst = BUF_SCRATCH;
+    B.dst_off = s1;
+    B.flags = PF_CONV | PF_TW4 | PF_AUX_A0;
+    B.conv = spec;
+    B.conv_c = 1;
+    B.conv_k = m1;
+    B.tw4_N = L;
     B.aux_off = aux;
     rc = add_line_pass(b, B);
     if (rc) return rc;
-    // P3: pass A of the inverse (forward FFT of the conjugate), s0 -> s1
-    LineSpec C;
-    C.what = "raderC";
-    C.line = {m1, r1, 1};
-    C.V = packed(packed(V, L, 0), L, 1);
-    C.V.push_back({r1, 1, m1});
-    C.inner = (int)C.V.size() - 1;
-    C.src = C.dst = BUF_SCRATCH;
-    C.src_off = s0;
-    C.dst_off = s1;
-    C.flags = PF_TW4;
-    C.tw4_N = L;
-    rc = add_line_pass(b, C);
-    if (rc) return rc;
-    // P4: pass B, conj back, add x0, scatter to Y[g^-q]; Y[0] = x0 + A0
+    // P3: inverse, second step: m1-point DFTs over k1 (contiguous rows j1), back
+    // from the conjugate, add x0, scatter Y[g^-q] for q = j1 + j2*r1; Y[0] = x0 + A0
     LineSpec D;
-    D.what = "raderD";
-    D.line = {r1, m1, d.os};
+    D.what = "raderC";
+    D.line = {m1, 1, d.os};
     D.V = packed(V, L, 0);
-    D.V.push_back({m1, 1, 0});
+    D.V.push_back({r1, m1, 0});
     D.inner = (int)D.V.size() - 1;
     D.src = BUF_SCRATCH;
     D.src_off = s1;
@@ -670,7 +666,7 @@ static int plan_rader(Builder &b, Dim d, const std::vector<Dim> &V, int src, int
     D.flags = PF_CONJ_A | PF_AUX_ADD | PF_SCATTER | PF_XCD | (conj_out ? PF_CONJ_OUT : 0);
     D.scatter = sct;
     D.lo_c = 1;
-    D.lo_k = m1;
+    D.lo_k = r1;
     D.lo_lim = L;
     D.aux_off = aux;
     return add_line_pass(b, D);
@@ -736,6 +732,7 @@ static int plan_bluestein(Builder &b, Dim d, const std::vector<Dim> &V, int src,
     const int64_t s0 = b.scratch_take(H * M * eb) / eb;
     const int64_t s1 = b.scratch_take(H * M * eb) / eb;
     std::vector<Dim> Vp = packed(V, M, 1);
+    // P1: chirp multiply, zero padding, DIT pass A of the length-M transform
     LineSpec A;
     A.what = "bluesteinA";
     A.line = {m1, r1 * d.is, 1};
@@ -755,39 +752,32 @@ static int plan_bluestein(Builder &b, Dim d, const std::vector<Dim> &V, int src,
     A.tw4_N = M;
     rc = add_line_pass(b, A);
     if (rc) return rc;
+    // P2: DIT pass B, spectrum product (index k1 + k2*m1), first
+    // decimation-in-frequency step of the inverse, twiddle; stored at j1*m1 + k1
     LineSpec B;
     B.what = "bluesteinB";
     B.line = {r1, m1, m1};
     B.V = packed(packed(V, M, 0), M, 1);
     B.V.push_back({m1, 1, 1});
     B.inner = (int)B.V.size() - 1;
-    B.src = B.dst = BUF_SCRATCH;
-    B.src_off = B.dst_off = s0;
-    B.flags = PF_POST_MUL | PF_CONJ_OUT;
-    B.post = spec;
-    B.lo_c = 1;
-    B.lo_k = m1;
-    B.lo_lim = M;
+    B.src = BUF_SCRATCH;
+    B.src_off = s0;
+    B.dst = BUF_SCRATCH;
+    B.dst_off = s1;
+    B.flags = PF_CONV | PF_TW4;
+    B.conv = spec;
+    B.conv_c = 1;
+    B.conv_k = m1;
+    B.tw4_N = M;
     rc = add_line_pass(b, B);
     if (rc) return rc;
-    LineSpec C;
-    C.what = "bluesteinC";
-    C.line = {m1, r1, 1};
-    C.V = packed(packed(V, M, 0), M, 1);
-    C.V.push_back({r1, 1, m1});
-    C.inner = (int)C.V.size() - 1;
-    C.src = C.dst = BUF_SCRATCH;
-    C.src_off = s0;
-    C.dst_off = s1;
-    C.flags = PF_TW4;
-    C.tw4_N = M;
-    rc = add_line_pass(b, C);
-    if (rc) return rc;
+    // P3: second inverse step over contiguous rows, back from the conjugate,
+    // chirp multiply, keep outputs j = j1 + j2*r1 < n
     LineSpec D;
-    D.what = "bluesteinD";
-    D.line = {r1, m1, m1 * d.os};
+    D.what = "bluesteinC";
+    D.line = {m1, 1, r1 * d.os};
     D.V = packed(V, M, 0);
-    D.V.push_back({m1, 1, d.os});
+    D.V.push_back({r1, m1, d.os});
     D.inner = (int)D.V.size() - 1;
     D.src = BUF_SCRATCH;
     D.src_off = s1;
@@ -796,7 +786,7 @@ static int plan_bluestein(Builder &b, Dim d, const std::vector<Dim> &V, int src,
     D.flags = PF_CONJ_A | PF_POST_MUL | (conj_out ? PF_CONJ_OUT : 0);
     D.post = chirp;
     D.lo_c = 1;
-    D.lo_k = m1;
+    D.lo_k = r1;
     D.lo_lim = n;
     return add_line_pass(b, D);
 }

@@ -265,7 +265,7 @@ __device__ __forceinline__ void store_elem(const PassArgs &a, const Tile<T> &tl,
         if (!ok || lo >= a.lo_lim) return;
         const uint32_t f = a.flags;
         if (f & PF_CONJ_A) y = conj(y);
-        if ((f & PF_AUX_A0) && lo == 0) ((cpx<T> *)a.aux)[2 * tl.o + 1] = y;
+        if ((f & PF_AUX_A0) && !(f & PF_CONV) && lo == 0) ((cpx<T> *)a.aux)[2 * tl.o + 1] = y;
         if (f & PF_POST_MUL) y = cmul(y, ((const cpx<T> *)a.post)[lo]);
         if (f & (PF_RADER | PF_AUX_ADD)) y = cadd(y, tl.x0);
         if (f & PF_CONJ_OUT) y = conj(y);
@@ -321,7 +321,8 @@ __device__ __forceinline__ void stage(const PassArgs &a, const StageDesc &sd, Ti
                 } else {
                     cpx<T> z = tl.my[lds_pad(idx)];
                     if constexpr (KIND & K_EXT) {
-                        if (fetch == F_LDS_CONV) z = conj(cmul(z, ((const cpx<T> *)a.conv)[idx]));
+                        if (fetch == F_LDS_CONV)
+                            z = conj(cmul(z, ((const cpx<T> *)a.conv)[c * a.conv_c + (int64_t)idx * a.conv_k]));
                     }
                     v[i][k] = z;
                 }
@@ -455,7 +456,15 @@ __device__ __forceinline__ void run_tile(const PassArgs &a, int64_t tile, cpx<T>
             const int step = a.tpt;
             int idx = tl.tid >> a.bt_log2;
             if constexpr (KIND & K_EXT) {
-                for (; idx < n; idx += step) dst[lds_pad(idx)] = load_elem<T, KIND>(a, c, base, idx, okc);
+                // same single round trip as below, through the general element load
+                constexpr int KMAX = EMAX + 2;
+                cpx<T> r[KMAX];
+#pragma unroll
+                for (int k = 0; k < KMAX; ++k)
+                    r[k] = load_elem<T, KIND>(a, c, base, idx + k * step, okc && idx + k * step < n);
+#pragma unroll
+                for (int k = 0; k < KMAX; ++k)
+                    if (idx + k * step < n) dst[lds_pad(idx + k * step)] = r[k];
             } else {
                 // all of a lane's loads are issued before the first LDS write,
                 // so a tile costs one memory round trip (n / tpt <= EMAX + 2)
@@ -490,6 +499,8 @@ __device__ __forceinline__ void run_tile(const PassArgs &a, int64_t tile, cpx<T>
             tl.a0 = tl.my[0];
             if (tl.act && tl.t == 0) slots[2 * tl.tr + 1] = tl.a0;
         }
+        if ((f & PF_AUX_A0) && tl.act && tl.t == 0 && tl.c0 + tl.tr == 0)
+            ((cpx<T> *)a.aux)[2 * tl.o + 1] = tl.my[0];   // zero frequency of line 0
         run_fft<T, EMAX, KIND>(a, tl, F_LDS_CONV, last_emit);
     } else {
         run_fft<T, EMAX, KIND>(a, tl, first_fetch, last_emit);
@@ -512,12 +523,28 @@ __device__ __forceinline__ void run_tile(const PassArgs &a, int64_t tile, cpx<T>
                         tq.a0 = slots[2 * trq + 1];
                     }
                 }
-                for (; idx < n; idx += step) {
-                    cpx<T> y = src[lds_pad(idx)];
-                    if constexpr (KIND & K_TW4) {
-                        if (f & PF_TW4) y = mul_d(y, tw4_root(a, (int64_t)idx * c));
+                // this lane's elements idx + k*step of line c take w_N^(c*idx) times
+                // powers of w_N^(c*step): two table lookups per lane, FP64 products
+                double2 w = make_double2(1.0, 0.0), ws = make_double2(1.0, 0.0);
+                bool tw = false;
+                if constexpr (KIND & K_TW4) {
+                    tw = (f & PF_TW4) != 0;
+                    if (tw) {
+                        w = tw4_root(a, (int64_t)idx * c);
+                        ws = tw4_root(a, (int64_t)step * c);
                     }
-                    store_elem<T, KIND>(a, tq, c, base, idx, y, okc);
+                }
+                constexpr int KMAX = EMAX + 2;
+#pragma unroll
+                for (int k = 0; k < KMAX; ++k) {
+                    if (idx + k * step < n) {
+                        cpx<T> y = src[lds_pad(idx + k * step)];
+                        if (tw) {
+                            y = mul_d(y, w);
+                            w = zmul(w, ws);
+                        }
+                        store_elem<T, KIND>(a, tq, c, base, idx + k * step, y, okc);
+                    }
                 }
             } else if (okc) {
                 const bool cj = (f & PF_CONJ_OUT) != 0;
