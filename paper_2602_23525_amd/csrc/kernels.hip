@@ -79,7 +79,7 @@ __global__ void gen_stage_twiddles(cpx<T> *out, int32_t Ns, int32_t R)
 {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= (int64_t)Ns * R) return;
-    const int64_t j = e / R, k = e % R;
+    const int64_t k = e / Ns, j = e % Ns;
     const double2 w = root_fp64(j * k, (int64_t)Ns * R);
     out[e] = {T(w.x), T(w.y)};
 }

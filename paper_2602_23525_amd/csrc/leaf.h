@@ -44,9 +44,8 @@ __device__ __forceinline__ void load_stage_tw(StageTw<T, R> &tw, const cpx<T> *t
     for (int i = 0; i < NB; ++i) {
         const int b = t + i * TPT;
         const int j = b & (NS - 1);
-        const cpx<T> *row = table + j * R;
 #pragma unroll
-        for (int m = 0; m < ilog2c(R); ++m) tw.w[i][m] = row[1 << m];
+        for (int m = 0; m < ilog2c(R); ++m) tw.w[i][m] = table[(1 << m) * NS + j];
     }
 }
 

@@ -157,8 +157,8 @@ static bool leaf_fits(int64_t n, int prec, int bt)
 }
 
 // Stage twiddle table for a leaf: stage s holds w_(Ns*R)^(j*k) for j < Ns,
-// 0 <= k < R at [tw_off + j*R + k] (rows of R so that a butterfly's twiddles
-// are one aligned run).
+// 0 <= k < R at [tw_off + k*Ns + j] (k-major, so that the lanes of a wave,
+// which work on consecutive j, read consecutive entries).
 static int fill_leaf(PlanImpl *p, const Leaf &L, PassArgs *a,
                      std::map<std::string, void *> *cache)
 {

@@ -232,55 +232,137 @@ __device__ __forceinline__ cpx<T> mul_d(cpx<T> y, double2 w)
     return cmul(y, wt);
 }
 
-// Load element idx of line c; zero outside the logical range.
-template <typename T, int KIND>
-__device__ __forceinline__ cpx<T> load_elem(const PassArgs &a, int64_t c, int64_t base, int idx,
-                                            bool ok)
+// Elements per chunk of the table-driven (K_EXT) loads and stores.
+template <typename T>
+constexpr int ext_chunk() { return 4; }
+
+// Tile load of one lane: elements idx0 + k*tpt (k < EMAX + 2, below n) of
+// tile line `line` go to LDS.  Every global load of the lane is issued before
+// the first LDS write, so a tile costs one memory round trip (two with a
+// gather table).  Lanes past the vector loop or past the logical range read an
+// in-range address and drop the value (zero padding beyond li_lim).
+template <typename T, int EMAX, int KIND>
+__device__ __forceinline__ void load_line(const PassArgs &a, const Tile<T> &tl, cpx<T> *lds,
+                                          int line, int idx0)
 {
-    cpx<T> x = {T(0), T(0)};
+    constexpr int KMAX = EMAX + 2;
+    const int n = a.n, step = a.tpt;
+    const int64_t c = tl.c0 + line;
+    const bool okc = c < a.vn;
+    const cpx<T> *in = (const cpx<T> *)a.in + tl.ob_in + (okc ? c : tl.c0) * a.vis;
+    cpx<T> *dst = lds + line * a.lds_stride;
+    const bool cj = (a.flags & PF_CONJ_IN) != 0;
+    cpx<T> r[KMAX];
     if constexpr (KIND & K_EXT) {
-        const int64_t li = c * a.li_c + (int64_t)idx * a.li_l;
-        if (ok && li < a.li_lim) {
-            const int64_t e = (a.flags & PF_GATHER) ? (int64_t)a.gather[li] : (int64_t)idx;
-            x = ((const cpx<T> *)a.in)[base + e * a.is];
-            if (a.flags & PF_CONJ_IN) x = conj(x);
-            if (a.flags & PF_PRE_MUL) x = cmul(x, ((const cpx<T> *)a.pre)[li]);
+        // in chunks of CH elements to bound the registers held by the tables
+        constexpr int CH = ext_chunk<T>();
+        const uint32_t f = a.flags;
+        const int64_t cl = c * a.li_c;
+#pragma unroll
+        for (int k0 = 0; k0 < KMAX; k0 += CH) {
+            int li[CH], e[CH];
+            bool val[CH];
+            cpx<T> pm[CH];
+#pragma unroll
+            for (int q = 0; q < CH; ++q) {
+                const int idx = idx0 + (k0 + q) * step;
+                const int64_t l = cl + (int64_t)idx * a.li_l;
+                val[q] = k0 + q < KMAX && okc && idx < n && l < a.li_lim;
+                li[q] = val[q] ? (int)l : 0;
+                e[q] = val[q] ? idx : 0;
+            }
+            if (f & PF_GATHER) {
+#pragma unroll
+                for (int q = 0; q < CH; ++q) e[q] = a.gather[li[q]];
+            }
+#pragma unroll
+            for (int q = 0; q < CH; ++q) r[q] = in[(int64_t)e[q] * a.is];
+            if (f & PF_PRE_MUL) {
+#pragma unroll
+                for (int q = 0; q < CH; ++q) pm[q] = ((const cpx<T> *)a.pre)[li[q]];
+            }
+#pragma unroll
+            for (int q = 0; q < CH; ++q) {
+                const int idx = idx0 + (k0 + q) * step;
+                if (k0 + q < KMAX && idx < n) {
+                    cpx<T> x = val[q] ? r[q] : cpx<T>{T(0), T(0)};
+                    if (cj) x = conj(x);
+                    if (f & PF_PRE_MUL) x = cmul(x, pm[q]);
+                    dst[lds_pad(idx)] = x;
+                }
+            }
         }
     } else {
-        if (ok) {
-            x = ((const cpx<T> *)a.in)[base + (int64_t)idx * a.is];
-            if (a.flags & PF_CONJ_IN) x = conj(x);
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) {
+            const int idx = idx0 + k * step;
+            r[k] = in[(int64_t)(idx < n ? idx : 0) * a.is];
+        }
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) {
+            const int idx = idx0 + k * step;
+            if (idx < n) dst[lds_pad(idx)] = cj ? conj(r[k]) : r[k];
         }
     }
-    return x;
 }
 
-// Store element k of line c (after the optional twiddle already applied).
-template <typename T, int KIND>
-__device__ __forceinline__ void store_elem(const PassArgs &a, const Tile<T> &tl, int64_t c,
-                                           int64_t base, int k, cpx<T> y, bool ok)
+// Store M elements kk[m] of line c (values y[m]; kk[m] in range where in[m]).
+// With K_EXT, the table reads of all M elements (post multiply, scatter
+// index) are issued before the first store.
+template <typename T, int M, int KIND>
+__device__ __forceinline__ void store_run(const PassArgs &a, const Tile<T> &tl, int64_t c, bool okc,
+                                          int64_t base, const int (&kk)[M], const bool (&in)[M],
+                                          const cpx<T> (&y)[M])
 {
+    cpx<T> *out = (cpx<T> *)a.out + base;
+    const uint32_t f = a.flags;
     if constexpr (KIND & K_EXT) {
-        const int64_t lo = c * a.lo_c + (int64_t)k * a.lo_k;
-        if (!ok || lo >= a.lo_lim) return;
-        const uint32_t f = a.flags;
-        if (f & PF_CONJ_A) y = conj(y);
-        if ((f & PF_AUX_A0) && !(f & PF_CONV) && lo == 0) ((cpx<T> *)a.aux)[2 * tl.o + 1] = y;
-        if (f & PF_POST_MUL) y = cmul(y, ((const cpx<T> *)a.post)[lo]);
-        if (f & (PF_RADER | PF_AUX_ADD)) y = cadd(y, tl.x0);
-        if (f & PF_CONJ_OUT) y = conj(y);
-        const int64_t e = (f & PF_SCATTER) ? (int64_t)a.scatter[lo] : (int64_t)k;
-        cpx<T> *out = (cpx<T> *)a.out;
-        out[base + e * a.os] = y;
-        if ((f & (PF_RADER | PF_AUX_ADD)) && lo == 0) {
-            cpx<T> y0 = cadd(tl.x0, tl.a0);
-            if (f & PF_CONJ_OUT) y0 = conj(y0);
-            out[base] = y0;
+        constexpr int CH = ext_chunk<T>();
+        const int64_t cl = c * a.lo_c;
+#pragma unroll
+        for (int m0 = 0; m0 < M; m0 += CH) {
+            int lo[CH], e[CH];
+            bool val[CH];
+            cpx<T> pm[CH];
+#pragma unroll
+            for (int q = 0; q < CH; ++q) {
+                const int m = m0 + q < M ? m0 + q : M - 1;
+                const int64_t l = cl + (int64_t)kk[m] * a.lo_k;
+                val[q] = m0 + q < M && okc && in[m] && l < a.lo_lim;
+                lo[q] = val[q] ? (int)l : 0;
+                e[q] = kk[m];
+            }
+            if (f & PF_SCATTER) {
+#pragma unroll
+                for (int q = 0; q < CH; ++q) e[q] = a.scatter[lo[q]];
+            }
+            if (f & PF_POST_MUL) {
+#pragma unroll
+                for (int q = 0; q < CH; ++q) pm[q] = ((const cpx<T> *)a.post)[lo[q]];
+            }
+#pragma unroll
+            for (int q = 0; q < CH; ++q) {
+                if (!val[q]) continue;
+                cpx<T> v = y[m0 + q < M ? m0 + q : M - 1];
+                if (f & PF_CONJ_A) v = conj(v);
+                if ((f & PF_AUX_A0) && !(f & PF_CONV) && lo[q] == 0)
+                    ((cpx<T> *)a.aux)[2 * tl.o + 1] = v;
+                if (f & PF_POST_MUL) v = cmul(v, pm[q]);
+                if (f & (PF_RADER | PF_AUX_ADD)) v = cadd(v, tl.x0);
+                if (f & PF_CONJ_OUT) v = conj(v);
+                out[(int64_t)e[q] * a.os] = v;
+                if ((f & (PF_RADER | PF_AUX_ADD)) && lo[q] == 0) {
+                    cpx<T> y0 = cadd(tl.x0, tl.a0);
+                    if (f & PF_CONJ_OUT) y0 = conj(y0);
+                    out[0] = y0;
+                }
+            }
         }
     } else {
-        if (!ok) return;
-        if (a.flags & PF_CONJ_OUT) y = conj(y);
-        ((cpx<T> *)a.out)[base + (int64_t)k * a.os] = y;
+        const bool cj = (f & PF_CONJ_OUT) != 0;
+#pragma unroll
+        for (int m = 0; m < M; ++m)
+            if (okc && in[m]) out[(int64_t)kk[m] * a.os] = cj ? conj(y[m]) : y[m];
     }
 }
 
@@ -289,7 +371,7 @@ __device__ __forceinline__ int fast_div(int b, uint32_t magic, int shift)
     return (int)((__umulhi((uint32_t)b, magic) + (uint32_t)b) >> shift);
 }
 
-enum { F_LDS = 0, F_GLOBAL = 1, F_LDS_CONV = 2 };
+enum { F_LDS = 0, F_LDS_CONV = 2 };
 enum { E_LDS = 0, E_GLOBAL = 1 };
 
 template <typename T, int R, int EMAX, int KIND>
@@ -302,7 +384,6 @@ __device__ __forceinline__ void stage(const PassArgs &a, const StageDesc &sd, Ti
     const int nb = sd.nb, tpt = a.tpt, Ns = sd.Ns;
     const int64_t c = tl.c0 + tl.tr;
     const bool ok = c < a.vn;
-    const int64_t in_base = tl.ob_in + c * a.vis;
     const int64_t out_base = tl.ob_out + c * a.vos;
     // lanes past the tile's bt*tpt threads (batched launches with a larger
     // block) only take part in the barriers
@@ -316,20 +397,16 @@ __device__ __forceinline__ void stage(const PassArgs &a, const StageDesc &sd, Ti
 #pragma unroll
             for (int k = 0; k < R; ++k) {
                 const int idx = b + k * nb;
-                if (fetch == F_GLOBAL) {
-                    v[i][k] = load_elem<T, KIND>(a, c, in_base, idx, ok);
-                } else {
-                    cpx<T> z = tl.my[lds_pad(idx)];
-                    if constexpr (KIND & K_EXT) {
-                        if (fetch == F_LDS_CONV)
-                            z = conj(cmul(z, ((const cpx<T> *)a.conv)[c * a.conv_c + (int64_t)idx * a.conv_k]));
-                    }
-                    v[i][k] = z;
+                cpx<T> z = tl.my[lds_pad(idx)];
+                if constexpr (KIND & K_EXT) {
+                    if (fetch == F_LDS_CONV)
+                        z = conj(cmul(z, ((const cpx<T> *)a.conv)[c * a.conv_c + (int64_t)idx * a.conv_k]));
                 }
+                v[i][k] = z;
             }
         }
     }
-    if (fetch != F_GLOBAL) __syncthreads();
+    __syncthreads();
 
     const cpx<T> *tw = (const cpx<T> *)a.tw + sd.tw_off;
 #pragma unroll
@@ -339,9 +416,10 @@ __device__ __forceinline__ void stage(const PassArgs &a, const StageDesc &sd, Ti
             const int q = fast_div(b, sd.magic, sd.shift);
             const int j = b - q * Ns;
             if (Ns > 1) {
-                const cpx<T> *w = tw + j * R;
+                // k-major table: lanes with consecutive j read consecutive entries
+                const cpx<T> *w = tw + j;
 #pragma unroll
-                for (int k = 1; k < R; ++k) v[i][k] = cmul(v[i][k], w[k]);
+                for (int k = 1; k < R; ++k) v[i][k] = cmul(v[i][k], w[k * Ns]);
             }
             dft<T, R>(v[i]);
             const int base = q * Ns * R + j;
@@ -359,9 +437,14 @@ __device__ __forceinline__ void stage(const PassArgs &a, const StageDesc &sd, Ti
                         }
                     }
                 }
+                int kk[R];
+                bool inr[R];
 #pragma unroll
-                for (int k = 0; k < R; ++k)
-                    store_elem<T, KIND>(a, tl, c, out_base, base + k * Ns, v[i][k], ok);
+                for (int k = 0; k < R; ++k) {
+                    kk[k] = base + k * Ns;
+                    inr[k] = true;
+                }
+                store_run<T, R, KIND>(a, tl, c, ok, out_base, kk, inr, v[i]);
             } else {
 #pragma unroll
                 for (int k = 0; k < R; ++k) tl.my[lds_pad(base + k * Ns)] = v[i][k];
@@ -442,50 +525,18 @@ __device__ __forceinline__ void run_tile(const PassArgs &a, int64_t tile, cpx<T>
         }
     }
 
-    int first_fetch = F_GLOBAL;
-    if (a.load_mode == kModeCol) {
-        // nthr is a multiple of bt, so each lane keeps one line of the tile
-        // (consecutive lanes on consecutive lines: unit vector stride) and walks
-        // that line's elements in steps of tpt
-        if (tl.act) {
-            const int trq = tl.tid & (bt - 1);
-            const int64_t c = tl.c0 + trq;
-            const bool okc = c < a.vn;
-            const int64_t base = tl.ob_in + c * a.vis;
-            cpx<T> *dst = lds + trq * a.lds_stride;
-            const int step = a.tpt;
-            int idx = tl.tid >> a.bt_log2;
-            if constexpr (KIND & K_EXT) {
-                // same single round trip as below, through the general element load
-                constexpr int KMAX = EMAX + 2;
-                cpx<T> r[KMAX];
-#pragma unroll
-                for (int k = 0; k < KMAX; ++k)
-                    r[k] = load_elem<T, KIND>(a, c, base, idx + k * step, okc && idx + k * step < n);
-#pragma unroll
-                for (int k = 0; k < KMAX; ++k)
-                    if (idx + k * step < n) dst[lds_pad(idx + k * step)] = r[k];
-            } else {
-                // all of a lane's loads are issued before the first LDS write,
-                // so a tile costs one memory round trip (n / tpt <= EMAX + 2)
-                const bool cj = (f & PF_CONJ_IN) != 0;
-                const int64_t inc = (int64_t)step * a.is;
-                const cpx<T> *p = (const cpx<T> *)a.in + base + (int64_t)idx * a.is;
-                constexpr int KMAX = EMAX + 2;
-                cpx<T> r[KMAX];
-#pragma unroll
-                for (int k = 0; k < KMAX; ++k) {
-                    r[k] = {T(0), T(0)};
-                    if (okc && idx + k * step < n) r[k] = p[k * inc];
-                }
-#pragma unroll
-                for (int k = 0; k < KMAX; ++k)
-                    if (idx + k * step < n) dst[lds_pad(idx + k * step)] = cj ? conj(r[k]) : r[k];
-            }
-        }
-        __syncthreads();
-        first_fetch = F_LDS;
+    // Load the tile into LDS.  Row mode: consecutive lanes walk one line's
+    // elements (unit line stride).  Column mode: nthr is a multiple of bt and
+    // consecutive lanes take consecutive lines (unit vector stride), each lane
+    // walking its line in steps of tpt.
+    if (tl.act) {
+        if (a.load_mode == kModeCol)
+            load_line<T, EMAX, KIND>(a, tl, lds, tl.tid & (bt - 1), tl.tid >> a.bt_log2);
+        else
+            load_line<T, EMAX, KIND>(a, tl, lds, tl.tr, tl.t);
     }
+    __syncthreads();
+    const int first_fetch = F_LDS;
     const int last_emit = a.store_mode == kModeCol ? E_LDS : E_GLOBAL;
 
     bool conv = false;
@@ -508,56 +559,50 @@ __device__ __forceinline__ void run_tile(const PassArgs &a, int64_t tile, cpx<T>
 
     if (a.store_mode == kModeCol) {
         if (tl.act) {
+            constexpr int KMAX = EMAX + 2;
             const int trq = tl.tid & (bt - 1);
             const int64_t c = tl.c0 + trq;
             const bool okc = c < a.vn;
             const int64_t base = tl.ob_out + c * a.vos;
             const cpx<T> *src = lds + trq * a.lds_stride;
             const int step = a.tpt;
-            int idx = tl.tid >> a.bt_log2;
-            if constexpr (KIND & (K_EXT | K_TW4)) {
-                Tile<T> tq = tl;
-                if constexpr (KIND & K_EXT) {
-                    if (f & PF_RADER) {
-                        tq.x0 = slots[2 * trq];
-                        tq.a0 = slots[2 * trq + 1];
-                    }
+            const int idx = tl.tid >> a.bt_log2;
+            Tile<T> tq = tl;
+            if constexpr (KIND & K_EXT) {
+                if (f & PF_RADER) {
+                    tq.x0 = slots[2 * trq];
+                    tq.a0 = slots[2 * trq + 1];
                 }
-                // this lane's elements idx + k*step of line c take w_N^(c*idx) times
-                // powers of w_N^(c*step): two table lookups per lane, FP64 products
-                double2 w = make_double2(1.0, 0.0), ws = make_double2(1.0, 0.0);
-                bool tw = false;
-                if constexpr (KIND & K_TW4) {
-                    tw = (f & PF_TW4) != 0;
+            }
+            // this lane's elements idx + k*step of line c take the Cooley-Tukey
+            // twiddle w_N^(c*idx) times powers of w_N^(c*step): two table
+            // lookups per lane, FP64 products
+            double2 w = make_double2(1.0, 0.0), ws = w;
+            bool tw = false;
+            if constexpr (KIND & K_TW4) {
+                tw = (f & PF_TW4) != 0;
+                if (tw) {
+                    w = tw4_root(a, (int64_t)idx * c);
+                    ws = tw4_root(a, (int64_t)step * c);
+                }
+            }
+            constexpr int CH = (KIND & K_EXT) ? ext_chunk<T>() : KMAX;
+#pragma unroll
+            for (int k0 = 0; k0 < KMAX; k0 += CH) {
+                int kk[CH];
+                bool inr[CH];
+                cpx<T> y[CH];
+#pragma unroll
+                for (int q = 0; q < CH; ++q) {
+                    kk[q] = idx + (k0 + q) * step;
+                    inr[q] = k0 + q < KMAX && kk[q] < n;
+                    y[q] = inr[q] ? src[lds_pad(kk[q])] : cpx<T>{T(0), T(0)};
                     if (tw) {
-                        w = tw4_root(a, (int64_t)idx * c);
-                        ws = tw4_root(a, (int64_t)step * c);
+                        y[q] = mul_d(y[q], w);
+                        w = zmul(w, ws);
                     }
                 }
-                constexpr int KMAX = EMAX + 2;
-#pragma unroll
-                for (int k = 0; k < KMAX; ++k) {
-                    if (idx + k * step < n) {
-                        cpx<T> y = src[lds_pad(idx + k * step)];
-                        if (tw) {
-                            y = mul_d(y, w);
-                            w = zmul(w, ws);
-                        }
-                        store_elem<T, KIND>(a, tq, c, base, idx + k * step, y, okc);
-                    }
-                }
-            } else if (okc) {
-                const bool cj = (f & PF_CONJ_OUT) != 0;
-                const int64_t inc = (int64_t)step * a.os;
-                cpx<T> *p = (cpx<T> *)a.out + base + (int64_t)idx * a.os;
-                constexpr int KMAX = EMAX + 2;
-#pragma unroll
-                for (int k = 0; k < KMAX; ++k) {
-                    if (idx + k * step < n) {
-                        const cpx<T> y = src[lds_pad(idx + k * step)];
-                        p[k * inc] = cj ? conj(y) : y;
-                    }
-                }
+                store_run<T, CH, KIND>(a, tq, c, okc, base, kk, inr, y);
             }
         }
     }
