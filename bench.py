@@ -4,6 +4,9 @@ Default workload: 16384 batched 1-D complex-to-complex forward transforms of
 n = 4096, FP32 interleaved, out of place, unit stride, distance n, inputs
 uniform on [-1, 1) (seeded, synthetic).  A step is one execution of the plan
 over the whole batch; the input is resident in HBM before timing starts.
+Workloads whose buffers total less than 512 MB are timed on enough rotating
+buffer sets (over 2 GB in all) that no step finds its data in L2 or the
+Infinity Cache; the single-set (warm) time is reported beside it.
 
 Prints one JSON line with the throughput (GFLOP/s, 5 n log2 n convention), the
 HBM roofline of the dominant kernel (HIP-event time per launch on the stream
@@ -28,6 +31,7 @@ WORKLOADS = {
     # name: (dims, howmany_dims, prec, sign, inplace)
     "c2c_1d_n4096_b16384_c32": ([(4096, 1, 1)], [(16384, 4096, 4096)], 0, -1, False),
     "c2c_1d_n4096_b16384_c32_inv": ([(4096, 1, 1)], [(16384, 4096, 4096)], 0, 1, False),
+    "c2c_1d_n4096_b16384_c64": ([(4096, 1, 1)], [(16384, 4096, 4096)], 1, -1, False),
     "c2c_1d_n1024_b1_c64": ([(1024, 1, 1)], [], 1, -1, False),
     "c2c_3d_256cubed_c32_inplace": ([(256, 65536, 65536), (256, 256, 256), (256, 1, 1)], [], 0,
                                     -1, True),
@@ -218,10 +222,14 @@ def run_serve(args):
     flops_total = sum(q[5] for q in reqs)
     budget = 64 << 30
 
-    def replay(max_inflight, n_streams, scale):
-        """scale: seconds per unit of the unit-rate trace (None = all at once)."""
+    def log(msg):
+        print(f"serve: {msg}", file=sys.stderr, flush=True)
+
+    def make_server(max_inflight, n_streams):
+        """A server with its plan cache warmed by every distinct problem of the
+        trace (plan time excluded from the replays)."""
+        t0 = time.perf_counter()
         srv = mfft.Server(budget, max_inflight=max_inflight, n_streams=n_streams)
-        # warm the plan cache with every distinct problem (plan time excluded)
         seen = set()
         warm = []
         for dims, hd, prec, sign, _, _ in reqs:
@@ -230,9 +238,22 @@ def run_serve(args):
                 continue
             seen.add(key)
             warm.append(srv.submit(dims, hd, pool32 if prec == 0 else pool64, None, sign, prec))
-        for t in warm:
-            srv.wait(t)
-            srv.release(t)
+            if len(seen) % 500 == 0:
+                log(f"planned {len(seen)} problems")
+            if len(warm) >= 64:
+                for tk in warm:
+                    srv.wait(tk)
+                    srv.release(tk)
+                warm = []
+        for tk in warm:
+            srv.wait(tk)
+            srv.release(tk)
+        log(f"server (inflight {max_inflight}, streams {n_streams}) warmed with {len(seen)} "
+            f"distinct problems in {time.perf_counter() - t0:.1f} s")
+        return srv
+
+    def replay(srv, scale, name):
+        """scale: seconds per unit of the unit-rate trace (None = all at once)."""
         srv.reset_stats()
         tickets = [None] * len(reqs)
         done = threading.Event()
@@ -250,6 +271,11 @@ def run_serve(args):
         t0 = time.monotonic() + 0.01
         for i, (dims, hd, prec, sign, arr, _) in enumerate(reqs):
             ta = t0 + (arr * scale if scale else 0.0)
+            # sleep (releasing the interpreter lock for the draining thread)
+            # until just before the arrival time, then spin
+            dt = ta - time.monotonic()
+            if dt > 3e-4:
+                time.sleep(dt - 2e-4)
             while time.monotonic() < ta:
                 pass
             tickets[i] = srv.submit(dims, hd, pool32 if prec == 0 else pool64, None, sign, prec,
@@ -258,23 +284,28 @@ def run_serve(args):
         th.join()
         wall = time.monotonic() - t0
         st = srv.stats()
-        srv.destroy()
-        return {"p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
-                "mean_ms": round(st["mean_ms"], 3), "wall_s": round(wall, 4),
-                "req_per_s": round(len(reqs) / wall, 1),
-                "gflops": round(flops_total / wall / 1e9, 1),
-                "launches": st["launches"], "busy_s": round(st["busy_s"], 4),
-                "peak_bytes": st["peak_bytes"], "max_inflight_seen": st["max_inflight_seen"]}
+        r = {"p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
+             "mean_ms": round(st["mean_ms"], 3), "wall_s": round(wall, 4),
+             "req_per_s": round(len(reqs) / wall, 1),
+             "gflops": round(flops_total / wall / 1e9, 1),
+             "launches": st["launches"], "busy_s": round(st["busy_s"], 4),
+             "peak_bytes": st["peak_bytes"], "max_inflight_seen": st["max_inflight_seen"]}
+        log(f"{name}: {r['req_per_s']} req/s, p50 {r['p50_ms']} ms, p99 {r['p99_ms']} ms")
+        return r
 
-    seq_cap = replay(1, 1, None)
+    seq = make_server(1, 1)
+    bat = make_server(64, 4)
+    seq_cap = replay(seq, None, "closed-loop sequential")
     mu = len(reqs) / seq_cap["wall_s"]
     res = {"sequential_capacity_req_per_s": round(mu, 1), "closed_loop_sequential": seq_cap}
-    res["closed_loop_batched"] = replay(64, 4, None)
+    res["closed_loop_batched"] = replay(bat, None, "closed-loop batched")
     for rho in (0.5, 0.8, 1.2):
         # the trace has unit mean rate: stretch it to a mean rate of rho * mu
         sc = 1.0 / (rho * mu)
-        res[f"rho{rho}_batched"] = replay(64, 4, sc)
-        res[f"rho{rho}_sequential"] = replay(1, 1, sc)
+        res[f"rho{rho}_batched"] = replay(bat, sc, f"rho {rho} batched")
+        res[f"rho{rho}_sequential"] = replay(seq, sc, f"rho {rho} sequential")
+    seq.destroy()
+    bat.destroy()
     b8 = res["rho0.8_batched"]
     out = {"metric": METRIC, "value": b8["gflops"], "unit": "GFLOP/s", "n_gpus": 1,
            "steps": len(reqs), "warmup": 0, "ms_per_step": round(1e3 / b8["req_per_s"], 4),
@@ -292,19 +323,24 @@ def main():
     ap.add_argument("--workload", default=DEFAULT)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--verify", action="store_true", help="check sampled outputs vs the oracle")
+    ap.add_argument("--warm", action="store_true",
+                    help="time small workloads on one resident buffer set only")
     ap.add_argument("--n", type=int, default=0, help="custom 1-D workload: transform length")
     ap.add_argument("--batch", type=int, default=1, help="custom 1-D workload: batch")
     ap.add_argument("--prec", default="c32", choices=["c32", "c64"])
     ap.add_argument("--sign", type=int, default=-1)
-    ap.add_argument("--items", type=int, default=10000, help="uneven_batch: number of items")
+    ap.add_argument("--items", type=int, default=None,
+                    help="uneven_batch: items (default 10000); serve: requests (default 2000)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     if args.workload == "uneven_batch":
+        args.items = args.items or 10000
         return run_uneven(args)
     if args.workload == "serve":
+        args.items = args.items or 2000
         return run_serve(args)
 
     import numpy as np
@@ -337,38 +373,76 @@ def main():
     plan_s = time.perf_counter() - t0
     info = plan.info()
 
-    for _ in range(args.warmup):
-        plan.execute(xt, yt)
+    # Buffer sets: one, or (cold-buffer rotation) enough distinct sets that
+    # their total exceeds 2 GB, so no launch finds its data in the caches
+    # (L2, 256 MB Infinity Cache) left behind by the previous one.
+    set_bytes = (1 if inplace else 2) * span * eb
+    nsets = 1
+    if set_bytes < (512 << 20) and not args.warm:
+        nsets = min(4096, -(-(2 << 30) // set_bytes))
+    sets = [(xt, yt)]
+    for _ in range(nsets - 1):
+        xi = xt.clone()
+        sets.append((xi, xi if inplace else torch.empty_like(xt)))
+
+    def run(i):
+        xi, yi = sets[i % nsets]
+        plan.execute(xi, yi)
+
+    for i in range(max(args.warmup, nsets)):
+        run(i)
     torch.cuda.synchronize()
+
+    def region(steps, first):
+        """Back-to-back steps bracketed by one event pair on the stream the
+        kernels run on; with a one-pass plan this is the kernel's average
+        duration per launch.  Returns (event ms per step, wall ms per step)."""
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        e0.record(stream)
+        for i in range(steps):
+            run(first + i)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps, (time.perf_counter() - w0) * 1e3 / steps
+
+    # timed region: exactly `steps` steps
+    ms_mean, ms_step = region(args.steps, 0)
+    # per-step event pairs for the spread
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    region0 = torch.cuda.Event(enable_timing=True)
-    region1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    # timed region 1: back-to-back steps bracketed by one event pair; with a
-    # one-pass plan this is the kernel's average duration per launch
-    w0 = time.perf_counter()
-    region0.record(stream)
-    for i in range(args.steps):
-        plan.execute(xt, yt)
-    region1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
-    ms_mean = region0.elapsed_time(region1) / args.steps
-    ms_step = wall * 1e3 / args.steps
-    # timed region 2: per-step event pairs for the spread
     for i in range(args.steps):
         starts[i].record(stream)
-        plan.execute(xt, yt)
+        run(args.steps + i)
         ends[i].record(stream)
     torch.cuda.synchronize()
     times_ms = sorted(s.elapsed_time(e) for s, e in zip(starts, ends))
+    warm = None
+    if nsets > 1:
+        # the same plan on one resident buffer set, for comparison
+        nsets_saved, nsets = nsets, 1
+        for i in range(args.warmup):
+            run(i)
+        warm = region(args.steps, 0)[0]
+        nsets = nsets_saved
 
     flops = info["flops"]
     value = flops / (ms_step * 1e-3) / 1e9 if flops else 0.0
     comp_bytes = info["bytes_compulsory"]
     achieved = comp_bytes / (ms_mean * 1e-3) / 1e9
     traffic = counter_traffic(args.workload)
+    cfg = {"workload": args.workload, "dims": dims, "howmany_dims": hdims,
+           "sign": sign, "inplace": inplace, "passes": info["n_passes"],
+           "plan_seconds": round(plan_s, 4),
+           "kernel_ms_p10_p50_p90": [round(times_ms[len(times_ms) // 10], 5),
+                                     round(times_ms[len(times_ms) // 2], 5),
+                                     round(times_ms[(9 * len(times_ms)) // 10], 5)],
+           "buffer_sets": nsets}
+    if warm is not None:
+        cfg["warm_kernel_ms_avg"] = round(warm, 5)
+        cfg["warm_hbm_frac"] = round(comp_bytes / (warm * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)
     out = {
         "metric": METRIC,
         "value": round(value, 2),
@@ -383,26 +457,60 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if prec == 0 else "f64",
         "data": "synthetic",
-        "config": {"workload": args.workload, "dims": dims, "howmany_dims": hdims,
-                   "sign": sign, "inplace": inplace, "passes": info["n_passes"],
-                   "plan_seconds": round(plan_s, 4),
-                   "kernel_ms_p10_p50_p90": [round(times_ms[len(times_ms) // 10], 5),
-                                             round(times_ms[len(times_ms) // 2], 5),
-                                             round(times_ms[(9 * len(times_ms)) // 10], 5)]},
+        "config": cfg,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": traffic},
     }
-    if args.verify and howmany > 1 and dims:
+    one_d = len(dims) == 1 and dims[0][1] == 1 and dims[0][2] == 1 and not inplace
+    if one_d and howmany > 1 and (args.verify or args.workload == DEFAULT):
+        # sampled accuracy against the FP64 oracle (three whole transforms)
         import oracle
-        y = yt.cpu().numpy()
-        errs = []
-        for v in (0, howmany // 2, howmany - 1):
-            ref = np.zeros(n_total, np.complex128)
-            oracle.dft(x.astype(np.complex128), ref, [(n_total, 1, 1)], [], sign=sign,
-                       in_off=v * n_total)
-            errs.append(oracle.rel_rms(y[v * n_total:(v + 1) * n_total], ref))
-        out["config"]["sampled_relrms"] = max(errs)
+
+        def sampled_relrms(y):
+            worst = 0.0
+            for v in (0, howmany // 2, howmany - 1):
+                ref = np.zeros(n_total, np.complex128)
+                oracle.dft(x.astype(np.complex128), ref, [(n_total, 1, 1)], [], sign=sign,
+                           in_off=v * n_total)
+                worst = max(worst, oracle.rel_rms(y[v * n_total:(v + 1) * n_total], ref))
+            return worst
+
+        plan.execute(xt, yt)
+        torch.cuda.synchronize()
+        cfg["sampled_relrms"] = sampled_relrms(yt.cpu().numpy())
+        if prec == 0:
+            # accuracy ablation: stage twiddles evaluated in FP32 arithmetic
+            abl = mfft.Plan(dims, hdims, sign=sign, prec=prec,
+                            flags=mfft.FP32_TWIDDLES | mfft.NO_WISDOM)
+            abl.execute(xt, yt)
+            torch.cuda.synchronize()
+            cfg["sampled_relrms_fp32_twiddles"] = sampled_relrms(yt.cpu().numpy())
+            abl.destroy()
+    if one_d and howmany > 1 and args.workload == DEFAULT:
+        # the plain form: one plan of a single transform, one launch per
+        # transform, all on one stream (no batching across the vector loop)
+        single = mfft.Plan(dims, [], sign=sign, prec=prec)
+        xp, yp, sp = xt.data_ptr(), yt.data_ptr(), int(stream.cuda_stream)
+
+        def plain_step():
+            for v in range(howmany):
+                single.execute(xp + v * n_total * eb, yp + v * n_total * eb, sp)
+
+        plain_step()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        w0 = time.perf_counter()
+        e0.record(stream)
+        plain_step()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        wall_plain = (time.perf_counter() - w0) * 1e3
+        single.destroy()
+        cfg["plain_ms_per_step"] = round(wall_plain, 3)
+        cfg["plain_gpu_ms_per_step"] = round(e0.elapsed_time(e1), 3)
+        cfg["batched_over_plain"] = round(wall_plain / ms_step, 2)
     if not args.no_cpu and dims:
         out["cpu_baseline"] = cpu_baseline(x, [(n_total, 1, 1)] if len(dims) == 1 else dims,
                                            hdims, sign, n_total, howmany)

@@ -65,6 +65,11 @@ typedef enum { MFFT_C32 = 0, MFFT_C64 = 1 } mfft_prec;
 #define MFFT_MEASURE     1u  /* time candidate plans on the stream, keep fastest */
 #define MFFT_WISDOM_ONLY 2u  /* only a stored plan; else MFFT_ENOWISDOM          */
 #define MFFT_NO_WISDOM   4u  /* neither consult nor record stored plans          */
+/* Accuracy ablation of Section 6 (FP32 plans only, not for production use):
+ * the stage twiddle tables are evaluated in FP32 arithmetic (angle, sine and
+ * cosine) instead of FP64 rounded once to FP32.  The index product is still
+ * reduced exactly in integer arithmetic. */
+#define MFFT_FP32_TWIDDLES 8u
 
 /* Optional device allocator (e.g. a framework's caching allocator).  alloc
  * returns NULL on failure.  NULL allocator = hipMalloc / hipFree. */
@@ -110,7 +115,10 @@ int mfft_problem_check(int rank, const mfft_iodim *dims, int howmany_rank,
  * Plan dft(N, V, I, O) (Section 4: a plan is a composition of algorithmic
  * steps chosen by the planner; here each step is one GPU pass).
  * Arguments as for mfft_problem_check, plus
- *   flags:      MFFT_ESTIMATE / MFFT_MEASURE / MFFT_WISDOM_ONLY | MFFT_NO_WISDOM;
+ *   flags:      MFFT_ESTIMATE / MFFT_MEASURE / MFFT_WISDOM_ONLY | MFFT_NO_WISDOM
+ *               (| MFFT_FP32_TWIDDLES for the accuracy ablation); other bits,
+ *               or MFFT_FP32_TWIDDLES with MFFT_C64, give EINVAL before any
+ *               device work;
  *   alloc:      allocator for the plan's tables and scratch (NULL = hipMalloc);
  *   hip_stream: stream for table generation and measurement.
  * On success *out receives a plan that owns its device tables and scratch.
@@ -236,7 +244,8 @@ int mfft_server_cancel(mfft_server server, uint64_t ticket);
 int mfft_server_stats(mfft_server server, mfft_server_stats_t *stats);
 /* Clear the counters and latency samples (e.g. after a warm-up phase). */
 int mfft_server_reset_stats(mfft_server server);
-/* Stop accepting, finish in-flight work, free everything. */
+/* Stop accepting, cancel requests not yet admitted (their wait returns
+ * MFFT_ECANCELED), finish in-flight work, free everything. */
 int mfft_server_destroy(mfft_server server);
 
 /* ------------------------------------------------------------------ wisdom */

@@ -155,6 +155,10 @@ int mfft_plan_dft(mfft_plan *out, int rank, const mfft_iodim *dims, int howmany_
 {
     if (!out) return fail(MFFT_EINVAL, "out is NULL");
     *out = nullptr;
+    const unsigned known = MFFT_MEASURE | MFFT_WISDOM_ONLY | MFFT_NO_WISDOM | MFFT_FP32_TWIDDLES;
+    if (flags & ~known) return fail(MFFT_EINVAL, "unknown planner flag bits");
+    if ((flags & MFFT_FP32_TWIDDLES) && prec != MFFT_C32)
+        return fail(MFFT_EINVAL, "MFFT_FP32_TWIDDLES applies to MFFT_C32 plans only");
     std::lock_guard<std::mutex> lk(g_plan_mutex);
     return plan_internal(out, rank, dims, howmany_rank, howmany_dims, inplace, sign, (int)prec,
                          (hipStream_t)hip_stream, flags, alloc);

@@ -26,7 +26,8 @@ hipError_t launch_batch(const PassArgs *items_dev, const int64_t *prefix_dev, in
 int pass_kind(uint32_t flags);
 int batch_blocks_per_cu(int prec, int kind, int block, size_t lds);
 hipError_t launch_copy(const CopyArgs &a, hipStream_t s);
-hipError_t launch_gen_stage_twiddles(void *out, int prec, int Ns, int R, hipStream_t s);
+hipError_t launch_gen_stage_twiddles(void *out, int prec, int Ns, int R, hipStream_t s,
+                                     bool fp32_math = false);
 hipError_t launch_gen_tw4(void *hi, int64_t nhi, void *lo, int64_t nlo, int shift, int64_t N,
                           hipStream_t s);
 hipError_t launch_gen_chirp(void *c, int64_t n, hipStream_t s);

@@ -84,6 +84,21 @@ __global__ void gen_stage_twiddles(cpx<T> *out, int32_t Ns, int32_t R)
     out[e] = {T(w.x), T(w.y)};
 }
 
+// Accuracy ablation: the same FP32 table with the angle 2 pi m / N and its
+// sine and cosine evaluated in FP32 (m = j*k reduced exactly in integer).
+__global__ void gen_stage_twiddles_f32(cpx<float> *out, int32_t Ns, int32_t R)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t N = (int64_t)Ns * R;
+    if (e >= N) return;
+    const int64_t k = e / Ns, j = e % Ns;
+    const int64_t m = (j * k) % N;
+    const float ang = -2.0f * 3.14159265358979f * (float)m / (float)N;
+    float s, c;
+    sincosf(ang, &s, &c);
+    out[e] = {c, s};
+}
+
 __global__ void gen_tw4(double2 *hi, int64_t nhi, double2 *lo, int64_t nlo, int32_t shift, int64_t N)
 {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -250,11 +265,15 @@ hipError_t launch_copy(const CopyArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_gen_stage_twiddles(void *out, int prec, int Ns, int R, hipStream_t s)
+hipError_t launch_gen_stage_twiddles(void *out, int prec, int Ns, int R, hipStream_t s,
+                                     bool fp32_math)
 {
     const int64_t cnt = (int64_t)Ns * R;
     if (cnt <= 0) return hipSuccess;
-    if (prec == 0)
+    if (prec == 0 && fp32_math)
+        hipLaunchKernelGGL(gen_stage_twiddles_f32, dim3(blocks_for(cnt, 256)), dim3(256), 0, s,
+                           (cpx<float> *)out, Ns, R);
+    else if (prec == 0)
         hipLaunchKernelGGL(gen_stage_twiddles<float>, dim3(blocks_for(cnt, 256)), dim3(256), 0, s,
                            (cpx<float> *)out, Ns, R);
     else

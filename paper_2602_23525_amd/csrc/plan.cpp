@@ -193,7 +193,8 @@ static int fill_leaf(PlanImpl *p, const Leaf &L, PassArgs *a,
         const StageDesc &sd = a->st[s];
         if (sd.Ns == 1) continue;
         hipError_t e = launch_gen_stage_twiddles((char *)tw + (size_t)sd.tw_off * eb, p->prob.prec,
-                                                 sd.Ns, sd.R, p->stream);
+                                                 sd.Ns, sd.R, p->stream,
+                                                 (p->flags & MFFT_FP32_TWIDDLES) != 0);
         if (e != hipSuccess) return fail(MFFT_EHIP, std::string("twiddle kernel: ") + hipGetErrorString(e));
     }
     (*cache)[key.str()] = tw;

@@ -157,6 +157,7 @@ struct mfft_server_s {
     std::vector<hipStream_t> streams;
     size_t next_stream = 0;
     uint64_t next_id = 1;
+    uint64_t wake_gen = 0;   // bumped when memory is released or a request is cancelled
     std::deque<std::shared_ptr<mfft::Req>> pending;
     std::unordered_map<uint64_t, std::shared_ptr<mfft::Req>> reqs;
     std::deque<mfft::Launch> inflight;
@@ -241,9 +242,22 @@ static void server_loop(mfft_server_s *S)
         }
         if (progressed) S->cv_done.notify_all();
 
+        // ---- on shutdown, requests not yet admitted are cancelled
+        if (S->stop && !S->pending.empty()) {
+            for (auto &q : S->pending) {
+                if (q->state == MFFT_REQ_PENDING) {
+                    q->state = MFFT_ECANCELED;
+                    S->cancelled++;
+                }
+            }
+            S->pending.clear();
+            S->cv_done.notify_all();
+        }
+
         // ---- admit
         std::vector<std::shared_ptr<Req>> tick;
         size_t desc_need = 512;   // upper bound of the tick's descriptor image
+        bool mem_blocked = false;   // the queue head waits for arena memory
         while (!S->pending.empty() && S->admitted_open < S->max_inflight) {
             std::shared_ptr<Req> q = S->pending.front();
             if (q->cancelled) {
@@ -304,12 +318,16 @@ static void server_loop(mfft_server_s *S)
             void *scratch = nullptr;
             if (!out && q->out_bytes) {
                 out = S->arena.alloc(q->out_bytes);
-                if (!out) break;   // wait for memory
+                if (!out) {   // wait for memory (FIFO: the head blocks the queue)
+                    mem_blocked = true;
+                    break;
+                }
             }
             if (p->scratch_bytes) {
                 scratch = S->arena.alloc(p->scratch_bytes);
                 if (!scratch) {
                     if (!q->r.out) S->arena.release(out);
+                    mem_blocked = true;
                     break;
                 }
             }
@@ -379,7 +397,12 @@ static void server_loop(mfft_server_s *S)
             std::this_thread::sleep_for(std::chrono::microseconds(20));
             lk.lock();
         } else {
-            S->cv_work.wait(lk, [&] { return S->stop || !S->pending.empty(); });
+            // idle, or the queue head waits for memory that only a client's
+            // release (or a cancel) can free: sleep until one of them happens
+            const uint64_t gen = S->wake_gen;
+            S->cv_work.wait(lk, [&] {
+                return S->stop || (!S->pending.empty() && (!mem_blocked || S->wake_gen != gen));
+            });
         }
     }
 }
@@ -506,6 +529,7 @@ int mfft_server_release(mfft_server S, uint64_t ticket)
     if (q->own_out) S->arena.release(q->out);
     q->out = nullptr;
     S->reqs.erase(it);
+    S->wake_gen++;
     S->cv_work.notify_one();   // memory may admit the next request
     return MFFT_OK;
 }
@@ -521,6 +545,8 @@ int mfft_server_cancel(mfft_server S, uint64_t ticket)
     q->cancelled = true;
     q->state = MFFT_ECANCELED;
     S->cancelled++;
+    S->wake_gen++;
+    S->cv_work.notify_one();
     S->cv_done.notify_all();
     return MFFT_OK;
 }

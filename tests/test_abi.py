@@ -72,6 +72,15 @@ def test_plan_without_gpu_fails_cleanly():
     assert e.value.code == -4      # MFFT_EHIP
 
 
+@pytest.mark.parametrize("flags,prec", [(16, 0), (1 << 31, 0), (8, 1)])
+def test_plan_rejects_bad_flags_before_device_work(flags, prec):
+    # unknown flag bits, and the FP32-twiddle ablation on an FP64 plan
+    with pytest.raises(mfft.MfftError) as e:
+        mfft.mfft_plan_dft([(64, 1, 1)], prec=prec, flags=flags, stream=0)
+    assert e.value.code == EINVAL
+    assert "flag" in mfft.mfft_last_error() or "FP32" in mfft.mfft_last_error()
+
+
 def test_wisdom_roundtrip_text():
     mfft.mfft_wisdom_forget()
     text = mfft.mfft_wisdom_export()

@@ -95,3 +95,28 @@ def test_torch_allocator_plan():
     assert oracle.rel_rms(xt.cpu().numpy().reshape(2, n), ref) <= 2e-6
     assert p.info()["scratch_bytes"] > 0
     p.destroy()
+
+
+def test_fp32_twiddle_ablation_is_less_accurate():
+    """Section 6: twiddles must be accurate.  Stage tables evaluated in FP32
+    arithmetic (the ablation flag) are no more accurate than FP64 tables
+    rounded once, and both stay near FP32 precision."""
+    import torch
+
+    import paper_2602_23525_amd as mfft
+    n, b = 4096, 64
+    x = uniform_complex(n * b, seed=31, dtype=np.complex64)
+    xt = torch.from_numpy(x).cuda()
+    ref = oracle.fft(x.astype(np.complex128).reshape(b, n))
+    errs = {}
+    for flags in (mfft.NO_WISDOM, mfft.NO_WISDOM | mfft.FP32_TWIDDLES):
+        yt = torch.empty_like(xt)
+        p = mfft.Plan([(n, 1, 1)], [(b, n, n)], flags=flags)
+        p.execute(xt, yt)
+        torch.cuda.synchronize()
+        p.destroy()
+        errs[flags] = oracle.rel_rms(yt.cpu().numpy().reshape(b, n), ref)
+    e64, e32 = errs[mfft.NO_WISDOM], errs[mfft.NO_WISDOM | mfft.FP32_TWIDDLES]
+    print(f"relRMS FP64-generated twiddles {e64:.3e}, FP32-evaluated twiddles {e32:.3e}")
+    assert e64 <= 2e-6 and e32 <= 1e-5
+    assert e64 <= 1.05 * e32

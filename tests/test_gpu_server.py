@@ -162,3 +162,27 @@ def test_poisson_trace_small():
     st = srv.stats()
     assert st["completed"] == len(trace)
     srv.destroy()
+
+
+def test_memory_blocked_head_waits_for_release():
+    """The queue head waits for arena memory held by finished, unreleased
+    outputs; a client's release admits it, and shutdown cancels a request
+    still blocked (neither may stall the scheduler)."""
+    import torch
+
+    import paper_2602_23525_amd as mfft
+    srv = mfft.Server(budget_bytes=10 << 20, max_inflight=8, n_streams=2)
+    x = torch.zeros(1 << 19, dtype=torch.complex64, device="cuda")          # 4 MiB
+    dims = [(1 << 19, 1, 1)]
+    t = [srv.submit(dims, [], x, None) for _ in range(3)]
+    assert srv.wait(t[0], 60000) == 0 and srv.wait(t[1], 60000) == 0
+    assert srv.wait(t[2], 200) == mfft.REQ_PENDING        # two 4 MiB outputs held
+    srv.release(t[0])
+    assert srv.wait(t[2], 60000) == 0
+    srv.release(t[1])
+    srv.release(t[2])
+    t2 = [srv.submit(dims, [], x, None) for _ in range(3)]
+    assert srv.wait(t2[0], 60000) == 0 and srv.wait(t2[1], 60000) == 0
+    st = srv.stats()
+    assert st["completed"] == 5
+    srv.destroy()                                           # t2[2] is cancelled
