@@ -44,17 +44,17 @@ WORKLOADS = {
     "copy_2p26_c32": ([], [(1 << 26, 1, 1)], 0, -1, False),
 }
 DEFAULT = "c2c_1d_n4096_b16384_c32"
-def counter_traffic(workload: str):
+def counter_traffic(workload: str, plan_desc: str):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3
     --pmc summary (FETCH_SIZE / WRITE_SIZE, scaled by the copy-kernel factor),
-    or None when no summary matches the current kernel sources."""
+    or None when no summary matches the current kernel sources and plan."""
     path = os.path.join(ROOT, "profiles", f"pmc_{workload}.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         d = json.load(fh)
     from paper_2602_23525_amd.rocprof_summary import kernel_source_hash
-    if d.get("source_hash") != kernel_source_hash():
+    if d.get("source_hash") != kernel_source_hash() or d.get("plan") != plan_desc:
         return None
     return d.get("traffic_bytes_per_launch")
 
@@ -323,6 +323,9 @@ def main():
     ap.add_argument("--workload", default=DEFAULT)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--verify", action="store_true", help="check sampled outputs vs the oracle")
+    ap.add_argument("--timing-only", action="store_true",
+                    help="skip the accuracy samples, the FP32-twiddle ablation and the plain "
+                         "one-launch-per-transform form (for profiler runs)")
     ap.add_argument("--warm", action="store_true",
                     help="time small workloads on one resident buffer set only")
     ap.add_argument("--n", type=int, default=0, help="custom 1-D workload: transform length")
@@ -432,9 +435,9 @@ def main():
     value = flops / (ms_step * 1e-3) / 1e9 if flops else 0.0
     comp_bytes = info["bytes_compulsory"]
     achieved = comp_bytes / (ms_mean * 1e-3) / 1e9
-    traffic = counter_traffic(args.workload)
+    traffic = counter_traffic(args.workload, info["desc"])
     cfg = {"workload": args.workload, "dims": dims, "howmany_dims": hdims,
-           "sign": sign, "inplace": inplace, "passes": info["n_passes"],
+           "sign": sign, "inplace": inplace, "passes": info["n_passes"], "plan": info["desc"],
            "plan_seconds": round(plan_s, 4),
            "kernel_ms_p10_p50_p90": [round(times_ms[len(times_ms) // 10], 5),
                                      round(times_ms[len(times_ms) // 2], 5),
@@ -463,7 +466,8 @@ def main():
                      "traffic": traffic},
     }
     one_d = len(dims) == 1 and dims[0][1] == 1 and dims[0][2] == 1 and not inplace
-    if one_d and howmany > 1 and (args.verify or args.workload == DEFAULT):
+    extras = args.workload == DEFAULT and not args.timing_only
+    if one_d and howmany > 1 and (args.verify or extras):
         # sampled accuracy against the FP64 oracle (three whole transforms)
         import oracle
 
@@ -487,7 +491,7 @@ def main():
             torch.cuda.synchronize()
             cfg["sampled_relrms_fp32_twiddles"] = sampled_relrms(yt.cpu().numpy())
             abl.destroy()
-    if one_d and howmany > 1 and args.workload == DEFAULT:
+    if one_d and howmany > 1 and extras:
         # the plain form: one plan of a single transform, one launch per
         # transform, all on one stream (no batching across the vector loop)
         single = mfft.Plan(dims, [], sign=sign, prec=prec)

@@ -15,7 +15,8 @@
 // workgroup keeps two tiles of HBM traffic in flight; the stage twiddles of a
 // thread do not depend on the tile and are loaded into registers once.
 #pragma once
-#include "tile.h"
+#include "butterfly.h"
+#include "internal.h"
 
 namespace mfft {
 
