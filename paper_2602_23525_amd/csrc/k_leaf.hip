@@ -1,6 +1,7 @@
 // Instantiations of the specialized power-of-two leaf kernel (leaf.h) and
 // their launcher.  256 threads per workgroup for FP32, 128 for FP64, so that
-// one tile's LDS stays near 35 KB.
+// one tile's LDS stays near 35 KB (n = 4096: one line of 256 threads in both
+// precisions, 35 KB FP32, 70 KB FP64).
 #include "kernels.h"
 #include "leaf.h"
 
@@ -44,21 +45,24 @@ static int dispatch(int kind, const PassArgs &a, int n, int grid, hipStream_t s,
     default:
         break;
     }
-    if constexpr (THREADS == 256) {
-        if (n == 4096) {
-            if (kind == 1) return occ<T, 4096, 1, PF, WPE, NT, 16, 16, 16>();
-            *err = go<T, 4096, 1, PF, WPE, NT, 16, 16, 16>(a, grid, s);
-            return 0;
-        }
+    if (n == 4096) {
+        // one line of 256 threads per workgroup in both precisions
+        if (kind == 1) return occ<T, 4096, 1, PF, WPE, NT, 16, 16, 16>();
+        *err = go<T, 4096, 1, PF, WPE, NT, 16, 16, 16>(a, grid, s);
+        return 0;
     }
 #undef LEAF_CASE
     *err = hipErrorInvalidValue;
     return 0;
 }
 
-int leaf_max_n(int prec) { return prec == 0 ? 4096 : 2048; }
+int leaf_max_n(int) { return 4096; }
 
-int leaf_lines_per_tile(int prec, int n) { return (prec == 0 ? 256 : 128) * 16 / n; }
+int leaf_lines_per_tile(int prec, int n)
+{
+    const int lines = (prec == 0 ? 256 : 128) * 16 / n;
+    return lines > 0 ? lines : 1;
+}
 
 bool leaf_supported(int prec, int64_t n)
 {

@@ -22,6 +22,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <sstream>
 
@@ -80,36 +81,79 @@ struct Leaf {
     int lds_stride = 0;
 };
 
-static bool radices_for(int64_t n, std::vector<int> *r)
+// Threads per line that a stage of radix R needs when a thread holds at most
+// emax elements per stage.
+static int stage_threads(int64_t n, int R, int emax)
+{
+    const int nbmax = emax / R;
+    if (nbmax < 1) return INT32_MAX;
+    return (int)((n / R + nbmax - 1) / nbmax);
+}
+
+// Radix sequence of a leaf of length n (7-smooth): the fewest stages over the
+// radices the tile kernel compiles whose thread need fits max_tpt (each stage
+// is one LDS exchange); among those, the smallest thread count, then larger
+// radices first.  A dynamic program over the exponents of 2, 3, 5 and 7.
+static bool radices_for(int64_t n, int emax, int max_tpt, std::vector<int> *r)
 {
     if (n < 2 || !is_smooth7(n)) return false;
-    int64_t m = n;
-    int a = 0;
-    while (m % 2 == 0) {
-        m /= 2;
-        ++a;
-    }
+    static const int kRad[] = {16, 15, 14, 12, 10, 9, 8, 7, 6, 5, 4, 3, 2};
+    static const int kPrime[4] = {2, 3, 5, 7};
+    auto expo = [](int64_t v, int (&e)[4]) {
+        for (int i = 0; i < 4; ++i) {
+            e[i] = 0;
+            while (v % kPrime[i] == 0) {
+                v /= kPrime[i];
+                ++e[i];
+            }
+        }
+    };
+    int en[4];
+    expo(n, en);
+    const int d1 = en[0] + 1, d2 = en[1] + 1, d3 = en[2] + 1, d4 = en[3] + 1;
+    struct Best {
+        int stages = -1, need = 0, rad = 0;   // stages < 0: not computed; INT32_MAX: none
+    };
+    std::vector<Best> memo((size_t)d1 * d2 * d3 * d4);
+    std::vector<int> allowed;
+    for (int R : kRad)
+        if (stage_threads(n, R, emax) <= max_tpt) allowed.push_back(R);
+    std::function<Best(int, int, int, int)> solve = [&](int a2, int a3, int a5, int a7) -> Best {
+        Best &m = memo[(((size_t)a2 * d2 + a3) * d3 + a5) * d4 + a7];
+        if (m.stages >= 0) return m;
+        Best best;
+        best.stages = (a2 | a3 | a5 | a7) ? INT32_MAX : 0;
+        if (best.stages) {
+            for (int R : allowed) {
+                int e[4];
+                expo(R, e);
+                if (e[0] > a2 || e[1] > a3 || e[2] > a5 || e[3] > a7) continue;
+                const Best sub = solve(a2 - e[0], a3 - e[1], a5 - e[2], a7 - e[3]);
+                if (sub.stages == INT32_MAX) continue;
+                const int st = sub.stages + 1;
+                const int need = std::max(sub.need, stage_threads(n, R, emax));
+                if (st < best.stages || (st == best.stages && need < best.need)) {
+                    best.stages = st;
+                    best.need = need;
+                    best.rad = R;
+                }
+            }
+        }
+        m = best;
+        return best;
+    };
+    const Best top = solve(en[0], en[1], en[2], en[3]);
+    if (top.stages == INT32_MAX || top.stages > kMaxStages) return false;
     std::vector<int> rad;
-    while (a >= 4) {
-        rad.push_back(16);
-        a -= 4;
+    int a[4] = {en[0], en[1], en[2], en[3]};
+    while (a[0] | a[1] | a[2] | a[3]) {
+        const Best b = solve(a[0], a[1], a[2], a[3]);
+        rad.push_back(b.rad);
+        int e[4];
+        expo(b.rad, e);
+        for (int i = 0; i < 4; ++i) a[i] -= e[i];
     }
-    if (a == 3) rad.push_back(8);
-    else if (a == 2) rad.push_back(4);
-    else if (a == 1) rad.push_back(2);
-    while (m % 7 == 0) {
-        rad.push_back(7);
-        m /= 7;
-    }
-    while (m % 5 == 0) {
-        rad.push_back(5);
-        m /= 5;
-    }
-    while (m % 3 == 0) {
-        rad.push_back(3);
-        m /= 3;
-    }
-    if ((int)rad.size() > kMaxStages) return false;
+    std::sort(rad.begin(), rad.end(), std::greater<int>());
     *r = rad;
     return true;
 }
@@ -125,18 +169,13 @@ static size_t tile_lds_bytes(int n, int bt, int prec)
     return ((size_t)bt * line_lds_stride(n) + 2 * (size_t)bt) * elem_bytes(prec);
 }
 
-static bool make_leaf_shape(int64_t n, int emax, Leaf *L)
+static bool make_leaf_shape(int64_t n, int emax, int max_tpt, Leaf *L)
 {
     if (n < 2 || n > (1 << 20)) return false;
     std::vector<int> rad;
-    if (!radices_for(n, &rad)) return false;
+    if (!radices_for(n, emax, max_tpt, &rad)) return false;
     int tpt = 1;
-    for (int R : rad) {
-        const int nbmax = emax / R;
-        if (nbmax < 1) return false;
-        const int nb = (int)(n / R);
-        tpt = std::max(tpt, (nb + nbmax - 1) / nbmax);
-    }
+    for (int R : rad) tpt = std::max(tpt, stage_threads(n, R, emax));
     // the column loops unroll EMAX + 2 elements per thread
     tpt = std::max(tpt, (int)((n + emax + 1) / (emax + 2)));
     if (tpt > 1024) return false;
@@ -152,7 +191,7 @@ static bool make_leaf_shape(int64_t n, int emax, Leaf *L)
 static bool leaf_fits(int64_t n, int prec, int bt)
 {
     Leaf L;
-    if (!make_leaf_shape(n, 16, &L)) return false;
+    if (!make_leaf_shape(n, 16, max_threads(prec) / bt, &L)) return false;
     return tile_lds_bytes((int)n, bt, prec) <= g_lds_budget && bt * L.tpt <= max_threads(prec);
 }
 
@@ -311,12 +350,6 @@ static int add_line_pass(Builder &b, const LineSpec &ls)
     Pass ps;
     PassArgs &a = ps.a;
     ps.prec = prec;
-    Leaf L;
-    if (!make_leaf_shape(n, 16, &L)) return fail(MFFT_ENOTSUP, "no leaf shape for n");
-    ps.emax = L.emax;
-    int rc = fill_leaf(p, L, &a, &b.twcache);
-    if (rc) return rc;
-
     // choose the tiled (inner) vector loop
     std::vector<Dim> V = ls.V;
     int inner = ls.inner;
@@ -364,6 +397,14 @@ static int add_line_pass(Builder &b, const LineSpec &ls)
     // lines per tile: column phases want >= 128 B runs; row tiles aim at
     // 256-thread workgroups.  Both bounded by the LDS budget.
     const bool col = a.load_mode == kModeCol || a.store_mode == kModeCol;
+    const int bt_floor = col ? (prec ? 4 : 8) : 1;
+    const int mt = max_threads(prec);
+    Leaf L;
+    if (!make_leaf_shape(n, 16, mt / bt_floor, &L) && !make_leaf_shape(n, 16, mt, &L))
+        return fail(MFFT_ENOTSUP, "no leaf shape for n");
+    ps.emax = L.emax;
+    int rc = fill_leaf(p, L, &a, &b.twcache);
+    if (rc) return rc;
     // Prefer tiles of at most 64 KB (several workgroups per CU); column tiles
     // may grow to the full LDS rather than drop below 64-byte runs.
     int bt;
@@ -371,8 +412,6 @@ static int add_line_pass(Builder &b, const LineSpec &ls)
     else bt = std::max(1, 256 / L.tpt);
     bt = 1 << ilog2(bt);
     if (bt > 1 && (1 << ilog2(bt)) != bt) bt >>= 1;
-    const int bt_floor = col ? (prec ? 4 : 8) : 1;
-    const int mt = max_threads(prec);
     while (bt > bt_floor && (tile_lds_bytes(L.n, bt, prec) > 65536 || bt * L.tpt > mt)) bt >>= 1;
     while (bt > 1 && (tile_lds_bytes(L.n, bt, prec) > g_lds_budget || bt * L.tpt > mt)) bt >>= 1;
     while (bt > 1 && bt / 2 >= in_dim.n) bt >>= 1;   // no wider than the loop

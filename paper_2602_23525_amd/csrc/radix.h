@@ -1,0 +1,118 @@
+// Butterflies of the generic tile kernel: the radices of butterfly.h plus the
+// composites 6, 9, 10, 12, 14 and 15, each one step of eq. ct with constant
+// twiddles (fewer LDS exchanges for sizes with factors 3, 5 and 7).
+#pragma once
+#include <utility>
+
+#include "butterfly.h"
+
+namespace mfft {
+
+// ------------------------------------------------------------ composite radices
+// cos and sin of 2 pi m / R at compile time: the angle is split as
+// q pi/2 + pi j/(2R) with q = round(4m/R) (exact integers, |j| <= R/2), the
+// remainder evaluated by its Taylor series (|x| <= pi/4, 12 terms: below one
+// FP64 ulp) and rotated back by the quadrant exactly.
+struct CPair {
+    double c, s;
+};
+
+constexpr CPair cx_cis_small(int j, int R)
+{
+    const double x = 3.14159265358979323846 * j / (2.0 * R);
+    double s = 0, c = 0, ts = x, tc = 1;
+    for (int k = 0; k < 12; ++k) {
+        s += ts;
+        c += tc;
+        ts *= -x * x / ((2.0 * k + 2) * (2.0 * k + 3));
+        tc *= -x * x / ((2.0 * k + 1) * (2.0 * k + 2));
+    }
+    return {c, s};
+}
+
+constexpr CPair cx_root(int m, int R)
+{
+    m %= R;
+    const int q = (8 * m + R) / (2 * R);   // round(4m / R)
+    const CPair r = cx_cis_small(4 * m - q * R, R);
+    switch (q & 3) {
+    case 0: return {r.c, r.s};
+    case 1: return {-r.s, r.c};
+    case 2: return {-r.c, -r.s};
+    default: return {r.s, -r.c};
+    }
+}
+
+// z * w_R^M (forward sign), quarter turns exact
+template <typename T, int R, int M>
+__device__ __forceinline__ cpx<T> twiddle_const(cpx<T> z)
+{
+    constexpr int m = M % R;
+    if constexpr (m == 0) return z;
+    else if constexpr (4 * m == R) return mul_mi(z);
+    else if constexpr (2 * m == R) return cpx<T>{-z.re, -z.im};
+    else if constexpr (4 * m == 3 * R) return cpx<T>{-z.im, z.re};
+    else {
+        constexpr CPair p = cx_root(m, R);
+        return cmul(z, cpx<T>{T(p.c), T(-p.s)});
+    }
+}
+
+template <typename F, int... I>
+__device__ __forceinline__ void static_for_impl(F &f, std::integer_sequence<int, I...>)
+{
+    (f(std::integral_constant<int, I>{}), ...);
+}
+
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+template <typename T, int R>
+__device__ __forceinline__ void dftx(cpx<T> *v);
+
+// R = A * B by eq. ct with constant twiddles: DFT-A over l1 of x[B l1 + l2]
+// for each l2, twiddle w_R^(l2 k1), DFT-B over l2, output y[k1 + A k2].
+template <typename T, int A, int B>
+__device__ __forceinline__ void dft_ab(cpx<T> *v)
+{
+    cpx<T> z[B][A];
+#pragma unroll
+    for (int l2 = 0; l2 < B; ++l2) {
+#pragma unroll
+        for (int l1 = 0; l1 < A; ++l1) z[l2][l1] = v[B * l1 + l2];
+        dftx<T, A>(z[l2]);
+    }
+    static_for<B>([&](auto l2c) {
+        constexpr int l2 = decltype(l2c)::value;
+        static_for<A>([&](auto k1c) {
+            constexpr int k1 = decltype(k1c)::value;
+            z[l2][k1] = twiddle_const<T, A * B, l2 * k1>(z[l2][k1]);
+        });
+    });
+#pragma unroll
+    for (int k1 = 0; k1 < A; ++k1) {
+        cpx<T> w[B];
+#pragma unroll
+        for (int l2 = 0; l2 < B; ++l2) w[l2] = z[l2][k1];
+        dftx<T, B>(w);
+#pragma unroll
+        for (int k2 = 0; k2 < B; ++k2) v[k1 + A * k2] = w[k2];
+    }
+}
+
+template <typename T, int R>
+__device__ __forceinline__ void dftx(cpx<T> *v)
+{
+    if constexpr (R == 6) dft_ab<T, 3, 2>(v);
+    else if constexpr (R == 9) dft_ab<T, 3, 3>(v);
+    else if constexpr (R == 10) dft_ab<T, 5, 2>(v);
+    else if constexpr (R == 12) dft_ab<T, 4, 3>(v);
+    else if constexpr (R == 14) dft_ab<T, 7, 2>(v);
+    else if constexpr (R == 15) dft_ab<T, 5, 3>(v);
+    else dft<T, R>(v);
+}
+
+}  // namespace mfft

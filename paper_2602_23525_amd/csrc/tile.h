@@ -17,7 +17,7 @@
 
 #include <cstdint>
 
-#include "butterfly.h"
+#include "radix.h"
 #include "internal.h"
 
 namespace mfft {
@@ -255,7 +255,7 @@ __device__ __forceinline__ void stage(const PassArgs &a, const StageDesc &sd, Ti
 #pragma unroll
                 for (int k = 1; k < R; ++k) v[i][k] = cmul(v[i][k], w[k * Ns]);
             }
-            dft<T, R>(v[i]);
+            dftx<T, R>(v[i]);
             const int base = q * Ns * R + j;
             if (emit == E_GLOBAL) {
                 if constexpr (KIND & K_TW4) {
@@ -303,6 +303,12 @@ __device__ __forceinline__ void run_fft(const PassArgs &a, Tile<T> &tl, int firs
         case 5: stage<T, 5, EMAX, KIND>(a, sd, tl, fetch, emit); break;
         case 7: stage<T, 7, EMAX, KIND>(a, sd, tl, fetch, emit); break;
         case 8: stage<T, 8, EMAX, KIND>(a, sd, tl, fetch, emit); break;
+        case 6: stage<T, 6, EMAX, KIND>(a, sd, tl, fetch, emit); break;
+        case 9: stage<T, 9, EMAX, KIND>(a, sd, tl, fetch, emit); break;
+        case 10: stage<T, 10, EMAX, KIND>(a, sd, tl, fetch, emit); break;
+        case 12: stage<T, 12, EMAX, KIND>(a, sd, tl, fetch, emit); break;
+        case 14: stage<T, 14, EMAX, KIND>(a, sd, tl, fetch, emit); break;
+        case 15: stage<T, 15, EMAX, KIND>(a, sd, tl, fetch, emit); break;
         default: stage<T, 16, EMAX, KIND>(a, sd, tl, fetch, emit); break;
         }
     }

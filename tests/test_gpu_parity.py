@@ -22,9 +22,15 @@ def test_batched_4096_fp32_small_batch(sign):
     run_case([(4096, 1, 1)], [(64, 4096, 4096)], sign=sign, prec=0, seed=3, name="4096x64")
 
 
+@pytest.mark.parametrize("sign", [-1, 1])
+def test_batched_4096_fp64_small_batch(sign):
+    run_case([(4096, 1, 1)], [(8, 4096, 4096)], sign=sign, prec=1, seed=4, name="4096x8 fp64")
+
+
 @pytest.mark.parametrize("n", [2, 3, 4, 5, 7, 8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096,
                                6, 9, 10, 12, 14, 15, 21, 25, 27, 30, 35, 49, 60, 100, 210, 243,
-                               343, 1000, 2187, 2401, 3125])
+                               343, 1000, 2187, 2401, 3125, 18, 36, 45, 63, 90, 126, 150, 225,
+                               270, 441, 1008, 1050, 2025, 6144, 14175])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_leaf_sizes(n, prec):
     b = max(1, min(37, 20000 // n))
