@@ -68,7 +68,53 @@ __device__ __forceinline__ cpx<T> mul_d(cpx<T> y, double2 w)
 
 // Elements per chunk of the table-driven (K_EXT) loads and stores.
 template <typename T>
-constexpr int ext_chunk() { return 4; }
+constexpr int ext_chunk() { return sizeof(T) == 4 ? 3 : 4; }
+
+// Plain tile load: all loads of the lane issued, then the LDS writes.  Element
+// idx0 + k*step of the lane's line sits at p0 + k*pst; past the line's end (or
+// past the vector loop, where the lane reads line c0) the lane re-reads an
+// in-range element.
+template <typename T, int EMAX>
+__device__ __forceinline__ void issue_plain(const PassArgs &a, const Tile<T> &tl, int line,
+                                            int idx0, cpx<T> (&r)[EMAX + 2])
+{
+    constexpr int KMAX = EMAX + 2;
+    const int n = a.n, step = a.tpt;
+    const int64_t c = tl.c0 + line;
+    const cpx<T> *p0 = (const cpx<T> *)a.in + tl.ob_in + (c < a.vn ? c : tl.c0) * a.vis +
+                       (int64_t)idx0 * a.is;
+    const int64_t pst = (int64_t)step * a.is;
+    const cpx<T> *p = p0;
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+        r[k] = *(idx0 + k * step < n ? p : p0);
+        p += pst;
+    }
+}
+
+template <typename T, int EMAX>
+__device__ __forceinline__ void commit_plain(const PassArgs &a, cpx<T> *lds, int line, int idx0,
+                                             const cpx<T> (&r)[EMAX + 2])
+{
+    constexpr int KMAX = EMAX + 2;
+    const int n = a.n, step = a.tpt;
+    cpx<T> *dst = lds + line * a.lds_stride;
+    const bool cj = (a.flags & PF_CONJ_IN) != 0;
+    if ((step & 15) == 0) {
+        // padded LDS index of idx0 + k*step is linear in k
+        cpx<T> *d0 = dst + lds_pad(idx0);
+        const int ps = step + (step >> 4);
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k)
+            if (idx0 + k * step < n) d0[k * ps] = cj ? conj(r[k]) : r[k];
+    } else {
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) {
+            const int idx = idx0 + k * step;
+            if (idx < n) dst[lds_pad(idx)] = cj ? conj(r[k]) : r[k];
+        }
+    }
+}
 
 // Tile load of one lane: elements idx0 + k*tpt (k < EMAX + 2, below n) of
 // tile line `line` go to LDS.  Every global load of the lane is issued before
@@ -127,32 +173,24 @@ __device__ __forceinline__ void load_line(const PassArgs &a, const Tile<T> &tl, 
             }
         }
     } else {
-#pragma unroll
-        for (int k = 0; k < KMAX; ++k) {
-            const int idx = idx0 + k * step;
-            r[k] = in[(int64_t)(idx < n ? idx : 0) * a.is];
-        }
-#pragma unroll
-        for (int k = 0; k < KMAX; ++k) {
-            const int idx = idx0 + k * step;
-            if (idx < n) dst[lds_pad(idx)] = cj ? conj(r[k]) : r[k];
-        }
+        issue_plain<T, EMAX>(a, tl, line, idx0, r);
+        commit_plain<T, EMAX>(a, lds, line, idx0, r);
     }
 }
 
-// Store M elements kk[m] of line c (values y[m]; kk[m] in range where in[m]).
-// With K_EXT, the table reads of all M elements (post multiply, scatter
-// index) are issued before the first store.
-template <typename T, int M, int KIND>
+// Store M elements k0 + m*ks (m < M) of line c, values y[m]; with CHECK,
+// only those below n.  With K_EXT, the table reads of a chunk (post multiply,
+// scatter index) are issued before its first store.
+template <typename T, int M, int KIND, bool CHECK>
 __device__ __forceinline__ void store_run(const PassArgs &a, const Tile<T> &tl, int64_t c, bool okc,
-                                          int64_t base, const int (&kk)[M], const bool (&in)[M],
-                                          const cpx<T> (&y)[M])
+                                          int64_t base, int k0, int ks, const cpx<T> (&y)[M])
 {
     cpx<T> *out = (cpx<T> *)a.out + base;
     const uint32_t f = a.flags;
+    const int n = a.n;
     if constexpr (KIND & K_EXT) {
         constexpr int CH = ext_chunk<T>();
-        const int64_t cl = c * a.lo_c;
+        const int64_t l0 = c * a.lo_c + (int64_t)k0 * a.lo_k, lst = (int64_t)ks * a.lo_k;
 #pragma unroll
         for (int m0 = 0; m0 < M; m0 += CH) {
             int lo[CH], e[CH];
@@ -160,11 +198,11 @@ __device__ __forceinline__ void store_run(const PassArgs &a, const Tile<T> &tl, 
             cpx<T> pm[CH];
 #pragma unroll
             for (int q = 0; q < CH; ++q) {
-                const int m = m0 + q < M ? m0 + q : M - 1;
-                const int64_t l = cl + (int64_t)kk[m] * a.lo_k;
-                val[q] = m0 + q < M && okc && in[m] && l < a.lo_lim;
+                const int m = m0 + q;
+                const int64_t l = l0 + m * lst;
+                val[q] = m < M && okc && (!CHECK || k0 + m * ks < n) && l < a.lo_lim;
                 lo[q] = val[q] ? (int)l : 0;
-                e[q] = kk[m];
+                e[q] = k0 + m * ks;
             }
             if (f & PF_SCATTER) {
 #pragma unroll
@@ -193,10 +231,16 @@ __device__ __forceinline__ void store_run(const PassArgs &a, const Tile<T> &tl, 
             }
         }
     } else {
-        const bool cj = (f & PF_CONJ_OUT) != 0;
+        if (okc) {
+            const bool cj = (f & PF_CONJ_OUT) != 0;
+            const int64_t pst = (int64_t)ks * a.os;
+            cpx<T> *p = out + (int64_t)k0 * a.os;
 #pragma unroll
-        for (int m = 0; m < M; ++m)
-            if (okc && in[m]) out[(int64_t)kk[m] * a.os] = cj ? conj(y[m]) : y[m];
+            for (int m = 0; m < M; ++m) {
+                if (!CHECK || k0 + m * ks < n) *p = cj ? conj(y[m]) : y[m];
+                p += pst;
+            }
+        }
     }
 }
 
@@ -224,19 +268,41 @@ __device__ __forceinline__ void stage(const PassArgs &a, const StageDesc &sd, Ti
     const int nbl = tl.act ? nb : 0;
     cpx<T> v[NB][R];
 
+    // padded LDS index of x + k*d is linear in k when d is a multiple of 16
+    if ((nb & 15) == 0) {
+        const int pnb = nb + (nb >> 4);
 #pragma unroll
-    for (int i = 0; i < NB; ++i) {
-        const int b = tl.t + i * tpt;
-        if (b < nbl) {
+        for (int i = 0; i < NB; ++i) {
+            const int b = tl.t + i * tpt;
+            if (b < nbl) {
+                const cpx<T> *src = tl.my + lds_pad(b);
 #pragma unroll
-            for (int k = 0; k < R; ++k) {
-                const int idx = b + k * nb;
-                cpx<T> z = tl.my[lds_pad(idx)];
-                if constexpr (KIND & K_EXT) {
-                    if (fetch == F_LDS_CONV)
-                        z = conj(cmul(z, ((const cpx<T> *)a.conv)[c * a.conv_c + (int64_t)idx * a.conv_k]));
+                for (int k = 0; k < R; ++k) v[i][k] = src[k * pnb];
+            }
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            const int b = tl.t + i * tpt;
+            if (b < nbl) {
+#pragma unroll
+                for (int k = 0; k < R; ++k) v[i][k] = tl.my[lds_pad(b + k * nb)];
+            }
+        }
+    }
+    if constexpr (KIND & K_EXT) {
+        if (fetch == F_LDS_CONV) {
+            // in-kernel convolution: element idx of line c times the spectrum
+            // entry conv[c*conv_c + idx*conv_k], conjugated (inverse by conjugation)
+#pragma unroll
+            for (int i = 0; i < NB; ++i) {
+                const int b = tl.t + i * tpt;
+                if (b < nbl) {
+                    const cpx<T> *cv = (const cpx<T> *)a.conv + c * a.conv_c + (int64_t)b * a.conv_k;
+                    const int64_t cst = (int64_t)nb * a.conv_k;
+#pragma unroll
+                    for (int k = 0; k < R; ++k) v[i][k] = conj(cmul(v[i][k], cv[k * cst]));
                 }
-                v[i][k] = z;
             }
         }
     }
@@ -271,14 +337,12 @@ __device__ __forceinline__ void stage(const PassArgs &a, const StageDesc &sd, Ti
                         }
                     }
                 }
-                int kk[R];
-                bool inr[R];
+                store_run<T, R, KIND, false>(a, tl, c, ok, out_base, base, Ns, v[i]);
+            } else if ((Ns & 15) == 0) {
+                cpx<T> *dst = tl.my + lds_pad(base);
+                const int pns = Ns + (Ns >> 4);
 #pragma unroll
-                for (int k = 0; k < R; ++k) {
-                    kk[k] = base + k * Ns;
-                    inr[k] = true;
-                }
-                store_run<T, R, KIND>(a, tl, c, ok, out_base, kk, inr, v[i]);
+                for (int k = 0; k < R; ++k) dst[k * pns] = v[i][k];
             } else {
 #pragma unroll
                 for (int k = 0; k < R; ++k) tl.my[lds_pad(base + k * Ns)] = v[i][k];
@@ -314,8 +378,9 @@ __device__ __forceinline__ void run_fft(const PassArgs &a, Tile<T> &tl, int firs
     }
 }
 
-template <typename T, int EMAX, int KIND>
-__device__ __forceinline__ void run_tile(const PassArgs &a, int64_t tile, cpx<T> *lds)
+// Tile context: lines c0 .. c0+bt-1 of the inner vector loop at outer index o.
+template <typename T>
+__device__ __forceinline__ Tile<T> tile_setup(const PassArgs &a, int64_t tile, cpx<T> *lds)
 {
     Tile<T> tl;
     tl.tid = threadIdx.x;
@@ -340,42 +405,34 @@ __device__ __forceinline__ void run_tile(const PassArgs &a, int64_t tile, cpx<T>
     tl.x0 = {T(0), T(0)};
     tl.a0 = {T(0), T(0)};
 
-    const int n = a.n, bt = a.bt, nthr = a.bt * a.tpt;
+    return tl;
+}
+
+// Lane's line and first element in the tile load.  Row mode: consecutive
+// lanes walk one line's elements (unit line stride).  Column mode: nthr is a
+// multiple of bt and consecutive lanes take consecutive lines (unit vector
+// stride), each lane walking its line in steps of tpt.
+template <typename T>
+__device__ __forceinline__ void load_lane(const PassArgs &a, const Tile<T> &tl, int *line, int *idx0)
+{
+    if (a.load_mode == kModeCol) {
+        *line = tl.tid & (a.bt - 1);
+        *idx0 = tl.tid >> a.bt_log2;
+    } else {
+        *line = tl.tr;
+        *idx0 = tl.t;
+    }
+}
+
+// Everything after the tile load: the stages (two transforms around the
+// spectrum product for an in-kernel convolution) and the store.  Ends with a
+// barrier, so the workgroup may load its next tile into LDS.
+template <typename T, int EMAX, int KIND>
+__device__ __forceinline__ void tile_body(const PassArgs &a, Tile<T> &tl, cpx<T> *lds)
+{
+    const int n = a.n, bt = a.bt;
     const uint32_t f = a.flags;
     cpx<T> *slots = lds + a.bt * a.lds_stride;   // 2 per line: x0, a0
-
-    if constexpr (KIND & K_EXT) {
-        // per-transform scalars for Rader
-        if (f & (PF_RADER | PF_AUX_X0)) {
-            if (tl.act && tl.t == 0) {
-                const int64_t c = tl.c0 + tl.tr;
-                cpx<T> x0 = {T(0), T(0)};
-                if (c < a.vn) {
-                    x0 = ((const cpx<T> *)a.in)[tl.ob_in + c * a.vis];
-                    if (f & PF_CONJ_IN) x0 = conj(x0);
-                }
-                slots[2 * tl.tr] = x0;
-                if ((f & PF_AUX_X0) && c == 0) ((cpx<T> *)a.aux)[2 * tl.o] = x0;
-            }
-        }
-        if (f & PF_AUX_ADD) {
-            const cpx<T> *aux = (const cpx<T> *)a.aux;
-            tl.x0 = aux[2 * tl.o];
-            tl.a0 = aux[2 * tl.o + 1];
-        }
-    }
-
-    // Load the tile into LDS.  Row mode: consecutive lanes walk one line's
-    // elements (unit line stride).  Column mode: nthr is a multiple of bt and
-    // consecutive lanes take consecutive lines (unit vector stride), each lane
-    // walking its line in steps of tpt.
-    if (tl.act) {
-        if (a.load_mode == kModeCol)
-            load_line<T, EMAX, KIND>(a, tl, lds, tl.tid & (bt - 1), tl.tid >> a.bt_log2);
-        else
-            load_line<T, EMAX, KIND>(a, tl, lds, tl.tr, tl.t);
-    }
-    __syncthreads();
     const int first_fetch = F_LDS;
     const int last_emit = a.store_mode == kModeCol ? E_LDS : E_GLOBAL;
 
@@ -427,26 +484,66 @@ __device__ __forceinline__ void run_tile(const PassArgs &a, int64_t tile, cpx<T>
                 }
             }
             constexpr int CH = (KIND & K_EXT) ? ext_chunk<T>() : KMAX;
+            // padded LDS index of idx + k*step is linear in k when step % 16 == 0
+            const bool lin = (step & 15) == 0;
+            const int pidx = lds_pad(idx), pstep = step + (step >> 4);
 #pragma unroll
             for (int k0 = 0; k0 < KMAX; k0 += CH) {
-                int kk[CH];
-                bool inr[CH];
+                // the last chunk may run past KMAX: those elements lie past
+                // the line's end (n <= KMAX * step) and are not stored
                 cpx<T> y[CH];
 #pragma unroll
                 for (int q = 0; q < CH; ++q) {
-                    kk[q] = idx + (k0 + q) * step;
-                    inr[q] = k0 + q < KMAX && kk[q] < n;
-                    y[q] = inr[q] ? src[lds_pad(kk[q])] : cpx<T>{T(0), T(0)};
+                    const int kk = idx + (k0 + q) * step;
+                    const int pk = lin ? pidx + (k0 + q) * pstep : lds_pad(kk);
+                    y[q] = kk < n ? src[pk] : cpx<T>{T(0), T(0)};
                     if (tw) {
                         y[q] = mul_d(y[q], w);
                         w = zmul(w, ws);
                     }
                 }
-                store_run<T, CH, KIND>(a, tq, c, okc, base, kk, inr, y);
+                store_run<T, CH, KIND, true>(a, tq, c, okc, base, idx + k0 * step, step, y);
             }
         }
     }
     __syncthreads();  // the next tile of a persistent workgroup reuses LDS
+}
+
+
+template <typename T, int EMAX, int KIND>
+__device__ __forceinline__ void run_tile(const PassArgs &a, int64_t tile, cpx<T> *lds)
+{
+    Tile<T> tl = tile_setup<T>(a, tile, lds);
+    const uint32_t f = a.flags;
+    cpx<T> *slots = lds + a.bt * a.lds_stride;   // 2 per line: x0, a0
+    if constexpr (KIND & K_EXT) {
+        // per-transform scalars for Rader
+        if (f & (PF_RADER | PF_AUX_X0)) {
+            if (tl.act && tl.t == 0) {
+                const int64_t c = tl.c0 + tl.tr;
+                cpx<T> x0 = {T(0), T(0)};
+                if (c < a.vn) {
+                    x0 = ((const cpx<T> *)a.in)[tl.ob_in + c * a.vis];
+                    if (f & PF_CONJ_IN) x0 = conj(x0);
+                }
+                slots[2 * tl.tr] = x0;
+                if ((f & PF_AUX_X0) && c == 0) ((cpx<T> *)a.aux)[2 * tl.o] = x0;
+            }
+        }
+        if (f & PF_AUX_ADD) {
+            const cpx<T> *aux = (const cpx<T> *)a.aux;
+            tl.x0 = aux[2 * tl.o];
+            tl.a0 = aux[2 * tl.o + 1];
+        }
+    }
+
+    if (tl.act) {
+        int line, idx0;
+        load_lane(a, tl, &line, &idx0);
+        load_line<T, EMAX, KIND>(a, tl, lds, line, idx0);
+    }
+    __syncthreads();
+    tile_body<T, EMAX, KIND>(a, tl, lds);
 }
 
 // Largest workgroup of the generic kernels: FP64 lines keep 512 threads so the
@@ -463,6 +560,7 @@ __global__ __launch_bounds__(max_block<T>()) void pass_kernel(PassArgs a)
     // per-stage descriptors indexed at run time are scalar loads rather than a
     // private copy of the whole block.
     const PassArgs *ap = (const PassArgs *)__builtin_amdgcn_kernarg_segment_ptr();
+    // one tile per workgroup; with PF_XCD consecutive tiles go to one XCD
     int64_t tile = blockIdx.x;
     if (ap->flags & PF_XCD) {
         const int64_t per = gridDim.x / kXcds;
