@@ -13,7 +13,10 @@ Functions follow Johnson & Frigo, "Implementing FFTs in Practice":
     algorithms O1 (eq. dft, Section 2), O2 (eq. ct, Section 2, decimation in time
     by the smallest prime factor; Algorithm 1 is its radix-2 case) and O3
     (Bluestein's chirp-z, Section 4.2 "Plans for prime sizes");
-  * ``root`` -- exp(sign 2 pi i m / n) from the oracle's own octant-reduced table.
+  * ``root`` -- exp(sign 2 pi i m / n) from the oracle's own octant-reduced table;
+  * ``rfft`` / ``irfft`` -- real-input DFTs (the conjugate-symmetric case of
+    eq. dft that Sections 5 and 7 single out): the forward DFT of real data keeping
+    outputs 0 .. n//2, and its unnormalized inverse from such a half spectrum.
 """
 from __future__ import annotations
 
@@ -192,3 +195,31 @@ def max_err(y, yref) -> float:
     rms = np.sqrt(np.mean(np.abs(yref) ** 2)) if yref.size else 0.0
     d = np.max(np.abs(y - yref)) if y.size else 0.0
     return float(d / rms) if rms > 0 else float(d)
+
+
+def rfft(x, nthreads: int | None = None) -> np.ndarray:
+    """Forward DFT (eq. dft, sign -1) of real data along the last axis, outputs
+    k = 0 .. n//2.  The others follow from conjugate symmetry, Y[n-k] = conj(Y[k]),
+    which holds for every real input (Section 5 notes the factor of two this
+    redundancy saves)."""
+    x = np.asarray(x, np.float64)
+    n = x.shape[-1]
+    y = fft(x.astype(np.complex128), sign=-1, nthreads=nthreads)
+    return y[..., : n // 2 + 1]
+
+
+def irfft(y, n: int, nthreads: int | None = None) -> np.ndarray:
+    """Inverse of ``rfft`` without normalization (irfft(rfft(x), n) = n x): the half
+    spectrum k = 0 .. n//2 is extended by Y[n-k] = conj(Y[k]), the imaginary parts of
+    Y[0] and (n even) Y[n/2] are dropped -- a conjugate-symmetric spectrum has them
+    zero -- and the sign +1 DFT of the extension is real; its real part is returned."""
+    y = np.asarray(y, np.complex128)
+    h = n // 2 + 1
+    full = np.zeros(y.shape[:-1] + (n,), np.complex128)
+    full[..., :h] = y[..., :h]
+    full[..., 0] = full[..., 0].real
+    if n % 2 == 0:
+        full[..., n // 2] = full[..., n // 2].real
+    k = np.arange(h, n)
+    full[..., h:] = np.conj(y[..., n - k])
+    return fft(full, sign=+1, nthreads=nthreads).real
