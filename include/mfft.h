@@ -88,9 +88,10 @@ typedef struct {
     int rank, howmany_rank;   /* after canonicalization                        */
     int inplace;              /* plan expects in == out                        */
     int n_passes;             /* kernel launches per execute                   */
-    int64_t n_total;          /* product of transform lengths                  */
+    int64_t n_total;          /* product of transform lengths (real plans: n)  */
     int64_t howmany;          /* product of vector lengths                     */
-    double flops;             /* nominal 5 N log2 N per transform, x howmany   */
+    double flops;             /* nominal 5 N log2 N per transform (real plans:
+                               * 2.5 N log2 N), x howmany                     */
     double bytes_compulsory;  /* read input once + write output once           */
     double bytes_passes;      /* bytes the passes move to and from HBM         */
     size_t scratch_bytes;     /* device scratch owned by the plan              */
@@ -129,6 +130,39 @@ int mfft_problem_check(int rank, const mfft_iodim *dims, int howmany_rank,
 int mfft_plan_dft(mfft_plan *out, int rank, const mfft_iodim *dims, int howmany_rank,
                   const mfft_iodim *howmany_dims, int inplace, int sign, mfft_prec prec,
                   unsigned flags, const mfft_allocator *alloc, void *hip_stream);
+
+/*
+ * Real-data transforms.  A DFT of real input is conjugate symmetric,
+ * Y[n-k] = conj(Y[k]), so outputs 0 .. n/2 determine it (the real-data case
+ * Sections 5 and 7 single out: about half the work).  rank must be 1
+ * (MFFT_ENOTSUP otherwise); dims[0].n = n is the real length.
+ *   mfft_plan_dft_r2c: forward (sign -1) DFT of n real inputs (stride
+ *     dims[0].is in real elements of the precision) to n/2+1 complex outputs
+ *     (stride dims[0].os in complex elements).  howmany dims: is in real, os in
+ *     complex elements.
+ *   mfft_plan_dft_c2r: the unnormalized inverse (sign +1): n/2+1 complex inputs
+ *     (dims[0].is, complex elements; the imaginary parts of bins 0 and n/2,
+ *     zero for a conjugate-symmetric spectrum, are ignored) to n real outputs
+ *     (dims[0].os, real elements).  howmany dims: is complex, os real.
+ * c2r(r2c(x)) = n x.  inplace = 1: input and output share one buffer (the plan
+ * reads the input completely before writing).  Real buffers must be aligned
+ * to the complex element size like complex ones.  Even n with unit real
+ * stride and even real vector strides runs a complex DFT of length n/2 plus
+ * one elementwise pass; other shapes run a length-n complex DFT.  Executed
+ * with mfft_execute / mfft_execute_scratch; other arguments and errors as for
+ * mfft_plan_dft (MFFT_FP32_TWIDDLES included).
+ */
+/* Host-only validation of a real-data problem (inverse 0: r2c, 1: c2r);
+ * returns what planning would for the problem itself (MFFT_OK, MFFT_EINVAL,
+ * MFFT_ENOTSUP), without touching the GPU. */
+int mfft_problem_check_real(int inverse, int rank, const mfft_iodim *dims, int howmany_rank,
+                            const mfft_iodim *howmany_dims, int inplace, mfft_prec prec);
+int mfft_plan_dft_r2c(mfft_plan *out, int rank, const mfft_iodim *dims, int howmany_rank,
+                      const mfft_iodim *howmany_dims, int inplace, mfft_prec prec, unsigned flags,
+                      const mfft_allocator *alloc, void *hip_stream);
+int mfft_plan_dft_c2r(mfft_plan *out, int rank, const mfft_iodim *dims, int howmany_rank,
+                      const mfft_iodim *howmany_dims, int inplace, mfft_prec prec, unsigned flags,
+                      const mfft_allocator *alloc, void *hip_stream);
 
 /*
  * Enqueue the transform on hip_stream (asynchronous; no allocation, no

@@ -15,7 +15,7 @@ import re
 
 __all__ = [
     "lib", "IoDim", "PlanInfo", "MfftError", "Plan", "mfft_problem_check", "mfft_plan_dft",
-    "mfft_execute", "mfft_execute_scratch", "mfft_plan_info", "mfft_plan_destroy",
+    "mfft_execute", "mfft_execute_scratch", "mfft_plan_dft_real", "mfft_problem_check_real", "mfft_plan_info", "mfft_plan_destroy",
     "mfft_wisdom_export", "mfft_wisdom_import", "mfft_wisdom_forget", "mfft_last_error",
     "mfft_version", "C32", "C64", "ESTIMATE", "MEASURE", "WISDOM_ONLY", "NO_WISDOM",
     "FP32_TWIDDLES",
@@ -85,6 +85,14 @@ def lib():
     L.mfft_plan_dft.argtypes = [ctypes.POINTER(p), ctypes.c_int, dims_p, ctypes.c_int, dims_p,
                                 ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint,
                                 ctypes.POINTER(Allocator), p]
+    L.mfft_problem_check_real.argtypes = [ctypes.c_int, ctypes.c_int, dims_p, ctypes.c_int,
+                                          dims_p, ctypes.c_int, ctypes.c_int]
+    L.mfft_problem_check_real.restype = ctypes.c_int
+    for name in ("mfft_plan_dft_r2c", "mfft_plan_dft_c2r"):
+        f = getattr(L, name)
+        f.argtypes = [ctypes.POINTER(p), ctypes.c_int, dims_p, ctypes.c_int, dims_p, ctypes.c_int,
+                      ctypes.c_int, ctypes.c_uint, ctypes.POINTER(Allocator), p]
+        f.restype = ctypes.c_int
     L.mfft_execute.argtypes = [p, p, p, p]
     L.mfft_execute_scratch.argtypes = [p, p, p, p, p]
     L.mfft_plan_info.argtypes = [p, ctypes.POINTER(PlanInfo)]
@@ -188,6 +196,28 @@ def mfft_plan_dft(dims, howmany_dims=(), inplace=0, sign=-1, prec=C32, flags=EST
     return h.value
 
 
+def mfft_problem_check_real(kind: str, dims, howmany_dims=(), inplace=0, prec=C32) -> int:
+    """Host-only validation of an r2c / c2r problem; returns the status code."""
+    nr, nd = _dims(dims)
+    vr, vd = _dims(howmany_dims)
+    return lib().mfft_problem_check_real(1 if kind == "c2r" else 0, nr, nd, vr, vd, int(inplace),
+                                         int(prec))
+
+
+def mfft_plan_dft_real(kind: str, dims, howmany_dims=(), inplace=0, prec=C32, flags=ESTIMATE,
+                       allocator=None, stream=None) -> int:
+    """kind "r2c" (real input, n/2+1 complex outputs) or "c2r" (the inverse);
+    strides in elements of each side's type.  Returns a plan handle."""
+    nr, nd = _dims(dims)
+    vr, vd = _dims(howmany_dims)
+    h = ctypes.c_void_p()
+    fn = {"r2c": lib().mfft_plan_dft_r2c, "c2r": lib().mfft_plan_dft_c2r}[kind]
+    rc = fn(ctypes.byref(h), nr, nd, vr, vd, int(inplace), int(prec), int(flags), allocator,
+            _stream(stream))
+    _check(rc, f"mfft_plan_dft_{kind}")
+    return h.value
+
+
 def mfft_execute(plan: int, x, y, stream=None):
     _check(lib().mfft_execute(plan, _ptr(x), _ptr(y), _stream(stream)), "mfft_execute")
 
@@ -250,19 +280,26 @@ def torch_allocator(device=None):
 
 
 class Plan:
-    """A planned dft(N, V, I, O); strides in complex elements."""
+    """A planned dft(N, V, I, O); strides in complex elements.  kind "r2c" /
+    "c2r" plans the real-data transforms (strides in elements of each side's
+    type, sign implied)."""
 
     def __init__(self, dims, howmany_dims=(), inplace=False, sign=-1, prec=C32,
-                 flags=ESTIMATE, stream=None, allocator=None):
+                 flags=ESTIMATE, stream=None, allocator=None, kind="c2c"):
         self.dims = [tuple(d) for d in dims]
         self.howmany_dims = [tuple(d) for d in howmany_dims]
         self.inplace = bool(inplace)
-        self.sign = sign
+        self.kind = kind
+        self.sign = sign if kind == "c2c" else (-1 if kind == "r2c" else 1)
         self.prec = prec
         self._alloc = allocator
-        self.handle = mfft_plan_dft(dims, howmany_dims, int(inplace), sign, prec, flags,
-                                    ctypes.byref(allocator) if allocator is not None else None,
-                                    stream)
+        al = ctypes.byref(allocator) if allocator is not None else None
+        if kind == "c2c":
+            self.handle = mfft_plan_dft(dims, howmany_dims, int(inplace), sign, prec, flags, al,
+                                        stream)
+        else:
+            self.handle = mfft_plan_dft_real(kind, dims, howmany_dims, int(inplace), prec, flags,
+                                             al, stream)
 
     def execute(self, x, y=None, stream=None):
         y = x if y is None else y

@@ -74,7 +74,7 @@ static void destroy_impl(PlanImpl *p)
 // Rader and Bluestein spectra while another plan is being made).
 int plan_internal(mfft_plan *out, int rank, const mfft_iodim *dims, int howmany_rank,
                   const mfft_iodim *hdims, int inplace, int sign, int prec, hipStream_t stream,
-                  unsigned flags, const mfft_allocator *alloc)
+                  unsigned flags, const mfft_allocator *alloc, int kind)
 {
     *out = nullptr;
     int rc = init_device();
@@ -82,7 +82,8 @@ int plan_internal(mfft_plan *out, int rank, const mfft_iodim *dims, int howmany_
     mfft_plan pl = new (std::nothrow) mfft_plan_s();
     if (!pl) return fail(MFFT_ENOMEM, "host allocation failed");
     PlanImpl *p = &pl->impl;
-    rc = canonicalize(rank, dims, howmany_rank, hdims, inplace, sign, prec, &p->prob);
+    rc = kind ? canonicalize_real(kind, rank, dims, howmany_rank, hdims, inplace, prec, &p->prob)
+              : canonicalize(rank, dims, howmany_rank, hdims, inplace, sign, prec, &p->prob);
     if (rc) {
         delete pl;
         return rc;
@@ -149,19 +150,52 @@ const char *mfft_last_error(void) { return last_error_text(); }
 
 const char *mfft_version(void) { return "mfft 0.1.0 (gfx950)"; }
 
+static int check_flags(unsigned flags, mfft_prec prec)
+{
+    const unsigned known = MFFT_MEASURE | MFFT_WISDOM_ONLY | MFFT_NO_WISDOM | MFFT_FP32_TWIDDLES;
+    if (flags & ~known) return fail(MFFT_EINVAL, "unknown planner flag bits");
+    if ((flags & MFFT_FP32_TWIDDLES) && prec != MFFT_C32)
+        return fail(MFFT_EINVAL, "MFFT_FP32_TWIDDLES applies to MFFT_C32 plans only");
+    return MFFT_OK;
+}
+
 int mfft_plan_dft(mfft_plan *out, int rank, const mfft_iodim *dims, int howmany_rank,
                   const mfft_iodim *howmany_dims, int inplace, int sign, mfft_prec prec,
                   unsigned flags, const mfft_allocator *alloc, void *hip_stream)
 {
     if (!out) return fail(MFFT_EINVAL, "out is NULL");
     *out = nullptr;
-    const unsigned known = MFFT_MEASURE | MFFT_WISDOM_ONLY | MFFT_NO_WISDOM | MFFT_FP32_TWIDDLES;
-    if (flags & ~known) return fail(MFFT_EINVAL, "unknown planner flag bits");
-    if ((flags & MFFT_FP32_TWIDDLES) && prec != MFFT_C32)
-        return fail(MFFT_EINVAL, "MFFT_FP32_TWIDDLES applies to MFFT_C32 plans only");
+    int rc = check_flags(flags, prec);
+    if (rc) return rc;
     std::lock_guard<std::mutex> lk(g_plan_mutex);
     return plan_internal(out, rank, dims, howmany_rank, howmany_dims, inplace, sign, (int)prec,
                          (hipStream_t)hip_stream, flags, alloc);
+}
+
+int mfft_plan_dft_r2c(mfft_plan *out, int rank, const mfft_iodim *dims, int howmany_rank,
+                      const mfft_iodim *howmany_dims, int inplace, mfft_prec prec, unsigned flags,
+                      const mfft_allocator *alloc, void *hip_stream)
+{
+    if (!out) return fail(MFFT_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = check_flags(flags, prec);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(g_plan_mutex);
+    return plan_internal(out, rank, dims, howmany_rank, howmany_dims, inplace, -1, (int)prec,
+                         (hipStream_t)hip_stream, flags, alloc, 1);
+}
+
+int mfft_plan_dft_c2r(mfft_plan *out, int rank, const mfft_iodim *dims, int howmany_rank,
+                      const mfft_iodim *howmany_dims, int inplace, mfft_prec prec, unsigned flags,
+                      const mfft_allocator *alloc, void *hip_stream)
+{
+    if (!out) return fail(MFFT_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = check_flags(flags, prec);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(g_plan_mutex);
+    return plan_internal(out, rank, dims, howmany_rank, howmany_dims, inplace, 1, (int)prec,
+                         (hipStream_t)hip_stream, flags, alloc, 2);
 }
 
 int mfft_execute_scratch(mfft_plan plan, const void *in, void *out, void *scratch,
@@ -202,8 +236,15 @@ int mfft_plan_info(mfft_plan plan, mfft_plan_info_t *info)
     info->n_total = p->prob.empty ? 0 : p->prob.n_total;
     info->howmany = p->prob.empty ? 0 : p->prob.howmany;
     const double N = (double)info->n_total;
+    const double eb = p->prob.prec ? 16.0 : 8.0;
     info->flops = N > 1 ? 5.0 * N * std::log2(N) * (double)info->howmany : 0.0;
-    info->bytes_compulsory = 2.0 * (p->prob.prec ? 16.0 : 8.0) * N * (double)info->howmany;
+    info->bytes_compulsory = 2.0 * eb * N * (double)info->howmany;
+    if (p->prob.kind != 0) {
+        // real data: half the nominal flops; n reals one way, n/2+1 complex the other
+        info->flops *= 0.5;
+        info->bytes_compulsory =
+            (eb / 2 * N + eb * (double)(p->prob.N[0].n / 2 + 1)) * (double)info->howmany;
+    }
     info->bytes_passes = p->bytes_passes;
     info->scratch_bytes = p->scratch_bytes;
     info->table_bytes = p->table_bytes;

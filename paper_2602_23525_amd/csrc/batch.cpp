@@ -63,6 +63,7 @@ int build_batch_layout(const std::vector<BatchItem> &items, BatchLayout *L)
     std::map<Key, std::vector<Item>> fam;
     std::map<Key, size_t> fam_lds;
     std::map<int, std::vector<CopyArgs>> copies;
+    std::map<int, std::vector<std::pair<RealArgs, int>>> reals;
     int nphase = 0;
     for (const BatchItem &it : items) {
         const PlanImpl *p = it.plan;
@@ -71,6 +72,10 @@ int build_batch_layout(const std::vector<BatchItem> &items, BatchLayout *L)
             nphase = std::max(nphase, (int)k + 1);
             if (ps.kind == 1) {
                 copies[(int)k].push_back(resolve_copy(p, ps, it.in, it.out, it.scratch));
+                continue;
+            }
+            if (ps.kind == 2) {
+                reals[(int)k].push_back({resolve_real(p, ps, it.in, it.out, it.scratch), ps.prec});
                 continue;
             }
             PassArgs a = resolve_pass(p, ps, it.in, it.out, it.scratch);
@@ -135,6 +140,13 @@ int build_batch_layout(const std::vector<BatchItem> &items, BatchLayout *L)
             st.c = c;
             L->steps.push_back(st);
         }
+        for (const auto &rp : reals[k]) {
+            BatchStep st;
+            st.real = true;
+            st.r = rp.first;
+            st.prec = rp.second;
+            L->steps.push_back(st);
+        }
         for (size_t gi = 0; gi < order.size(); ++gi)
             if (std::get<0>(order[gi].first) == k) {
                 BatchStep st;
@@ -155,6 +167,8 @@ int enqueue_batch_layout(const BatchLayout &L, char *dev, hipStream_t s)
         hipError_t e;
         if (st.copy) {
             e = launch_copy(st.c, s);
+        } else if (st.real) {
+            e = launch_real(st.r, st.prec, s);
         } else {
             const BatchGroup &g = L.groups[st.group];
             e = launch_batch((const PassArgs *)(dev + g.items_off),

@@ -23,9 +23,12 @@ struct BatchGroup {
     size_t items_off = 0, prefix_off = 0, counter_off = 0;   // offsets in the image
 };
 
-struct BatchStep {   // one launch: a group, or a copy pass
+struct BatchStep {   // one launch: a group, a copy pass or a real-data step
     bool copy = false;
     CopyArgs c{};
+    bool real = false;
+    RealArgs r{};
+    int prec = 0;
     int group = -1;
 };
 

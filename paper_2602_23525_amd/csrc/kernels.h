@@ -19,6 +19,34 @@ struct CopyArgs {
     int64_t n[8], is[8], os[8];
 };
 
+// Elementwise steps of the real-data plans (one line = one transform, the
+// vector loops as for copies).  n is the real length, h = n/2.
+enum : int {
+    RK_UNTANGLE = 0,  // Z (h complex) -> X (h+1 complex): split the transform of the
+                      // packed sequence x[2j] + i x[2j+1] into the real transform
+    RK_TANGLE = 1,    // X (h+1 complex) -> Z' (h complex): the reverse, for the inverse
+    RK_WIDEN = 2,     // real -> complex with zero imaginary part (n elements)
+    RK_HERM = 3,      // X (n/2+1 complex) -> conjugate-symmetric extension (n complex)
+    RK_REAL = 4,      // complex -> its real part (n elements)
+};
+
+struct RealArgs {
+    const void *in;
+    void *out;
+    const void *tw;      // RK_UNTANGLE / RK_TANGLE: w_n^k, k <= h/2 (element type)
+    int32_t mode;
+    int32_t vrank;
+    int64_t n;           // real length of the transform
+    int64_t cnt;         // work items per line
+    int64_t total;       // lines * cnt
+    int64_t is, os;      // line strides, in elements of the input / output type
+    int64_t vn[8], vis[8], vos[8];
+};
+
+hipError_t launch_real(const RealArgs &a, int prec, hipStream_t s);
+// w_N^k (sign -1), k < count, FP64-evaluated and rounded to the precision
+hipError_t launch_gen_roots(void *out, int prec, int64_t count, int64_t N, hipStream_t s);
+
 hipError_t launch_pass(const PassArgs &a, int prec, int emax, size_t lds_bytes, hipStream_t s);
 hipError_t launch_batch(const PassArgs *items_dev, const int64_t *prefix_dev, int nitems,
                         unsigned long long *counter, int prec, int kind, int block, int grid,

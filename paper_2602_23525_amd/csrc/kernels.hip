@@ -6,15 +6,11 @@
 
 #include <cstdint>
 
+#include "butterfly.h"
 #include "internal.h"
 #include "kernels.h"
 
 namespace mfft {
-
-template <typename T>
-struct alignas(2 * sizeof(T)) cpx {
-    T re, im;
-};
 
 // ------------------------------------------------------------ rank-0 copy
 
@@ -114,6 +110,88 @@ __global__ void gen_chirp(double2 *c, int64_t n)
     const int64_t km = k % (2 * n);
     const int64_t q = (int64_t)(((uint64_t)km * (uint64_t)km) % (uint64_t)(2 * n));   // n < 2^31
     c[k] = root_fp64(q, 2 * n);
+}
+
+template <typename T>
+__global__ void gen_roots(cpx<T> *out, int64_t count, int64_t N)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= count) return;
+    const double2 w = root_fp64(k, N);
+    out[k] = {T(w.x), T(w.y)};
+}
+
+// ------------------------------------------------------------ real-data steps
+// A real sequence of even length n = 2h packed as z[j] = x[2j] + i x[2j+1]
+// has Z = DFT_h(z) = E + iO with E, O the transforms of the even and odd
+// samples, both conjugate-symmetric; X[k] = E[k] + w_n^k O[k] (the DIT step of
+// eq. ct with radix 2).  With A = Z[k], B = Z[h-k]:
+//   E = (A + conj B)/2,  O = -i (A - conj B)/2,
+//   X[k] = E + w O,  X[h-k] = conj(E - w O),  w = w_n^k.
+// The inverse builds Z'[k] = E'[k] + i O'[k] with E' = X[k] + conj X[h-k] and
+// O' = w_n^-k (X[k] - conj X[h-k]); an unnormalized inverse DFT of length h
+// then yields x[2j] + i x[2j+1].
+template <typename T>
+__global__ void real_kernel(RealArgs a)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.total) return;
+    int64_t line = i / a.cnt;
+    const int64_t k = i - line * a.cnt;
+    int64_t bi = 0, bo = 0;
+    for (int d = a.vrank - 1; d >= 0; --d) {
+        const int64_t q = line / a.vn[d];
+        const int64_t idx = line - q * a.vn[d];
+        line = q;
+        bi += idx * a.vis[d];
+        bo += idx * a.vos[d];
+    }
+    const T half = T(0.5);
+    if (a.mode == RK_UNTANGLE) {
+        const cpx<T> *Z = (const cpx<T> *)a.in + bi;
+        cpx<T> *X = (cpx<T> *)a.out + bo;
+        const int64_t h = a.n / 2;
+        const cpx<T> A = Z[(k % h) * a.is];
+        if (k == 0) {
+            X[0] = {A.re + A.im, T(0)};
+            X[h * a.os] = {A.re - A.im, T(0)};
+            return;
+        }
+        const cpx<T> B = Z[(h - k) * a.is];
+        const cpx<T> E = {half * (A.re + B.re), half * (A.im - B.im)};
+        const cpx<T> O = {half * (A.im + B.im), half * (B.re - A.re)};   // -i (A - conj B) / 2
+        const cpx<T> w = ((const cpx<T> *)a.tw)[k];
+        const cpx<T> wO = cmul(w, O);
+        X[k * a.os] = cadd(E, wO);
+        if (2 * k != h) X[(h - k) * a.os] = conj(csub(E, wO));
+    } else if (a.mode == RK_TANGLE) {
+        const cpx<T> *X = (const cpx<T> *)a.in + bi;
+        cpx<T> *Z = (cpx<T> *)a.out + bo;
+        const int64_t h = a.n / 2;
+        cpx<T> A = X[k * a.is], B = X[(h - k) * a.is];
+        if (k == 0) {
+            // bins 0 and n/2 of a conjugate-symmetric spectrum are real
+            Z[0] = {A.re + B.re, A.re - B.re};
+            return;
+        }
+        const cpx<T> P = {A.re + B.re, A.im - B.im};    // A + conj B
+        const cpx<T> M = {A.re - B.re, A.im + B.im};    // A - conj B
+        const cpx<T> w = ((const cpx<T> *)a.tw)[k];
+        const cpx<T> wM = cmul(conj(w), M);
+        const cpx<T> iwM = {-wM.im, wM.re};
+        Z[k * a.os] = cadd(P, iwM);
+        if (2 * k != h) Z[(h - k) * a.os] = conj(csub(P, iwM));
+    } else if (a.mode == RK_WIDEN) {
+        const T x = ((const T *)a.in)[bi + k * a.is];
+        ((cpx<T> *)a.out)[bo + k * a.os] = {x, T(0)};
+    } else if (a.mode == RK_HERM) {
+        const cpx<T> *X = (const cpx<T> *)a.in + bi;
+        cpx<T> y = k <= a.n / 2 ? X[k * a.is] : conj(X[(a.n - k) * a.is]);
+        if (k == 0 || 2 * k == a.n) y.im = T(0);
+        ((cpx<T> *)a.out)[bo + k * a.os] = y;
+    } else {
+        ((T *)a.out)[bo + k * a.os] = ((const cpx<T> *)a.in)[bi + k * a.is].re;
+    }
 }
 
 // Wrapped conj(chirp) sequence of length M for the convolution kernel.
@@ -288,6 +366,28 @@ hipError_t launch_gen_tw4(void *hi, int64_t nhi, void *lo, int64_t nlo, int shif
     const int64_t cnt = nhi > nlo ? nhi : nlo;
     hipLaunchKernelGGL(gen_tw4, dim3(blocks_for(cnt, 256)), dim3(256), 0, s, (double2 *)hi, nhi,
                        (double2 *)lo, nlo, shift, N);
+    return hipGetLastError();
+}
+
+hipError_t launch_real(const RealArgs &a, int prec, hipStream_t s)
+{
+    if (a.total <= 0) return hipSuccess;
+    if (prec == 0)
+        hipLaunchKernelGGL(real_kernel<float>, dim3(blocks_for(a.total, 256)), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(real_kernel<double>, dim3(blocks_for(a.total, 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_gen_roots(void *out, int prec, int64_t count, int64_t N, hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    if (prec == 0)
+        hipLaunchKernelGGL(gen_roots<float>, dim3(blocks_for(count, 256)), dim3(256), 0, s,
+                           (cpx<float> *)out, count, N);
+    else
+        hipLaunchKernelGGL(gen_roots<double>, dim3(blocks_for(count, 256)), dim3(256), 0, s,
+                           (cpx<double> *)out, count, N);
     return hipGetLastError();
 }
 

@@ -959,8 +959,149 @@ static int add_copy_pass(Builder &b, const std::vector<Dim> &dims, int src, int 
     return MFFT_OK;
 }
 
+// ------------------------------------------------------------ real data
+
+static int add_real_pass(Builder &b, int mode, int64_t n, int64_t cnt, int64_t is, int64_t os,
+                         const std::vector<Dim> &V, int src, int64_t src_off, int dst,
+                         int64_t dst_off, const void *tw, const char *what)
+{
+    Pass ps;
+    ps.kind = 2;
+    ps.prec = b.p->prob.prec;
+    if (V.size() > 8) return fail(MFFT_ENOTSUP, "more than 8 vector loops");
+    RealArgs &r = ps.r;
+    r.mode = mode;
+    r.n = n;
+    r.cnt = cnt;
+    r.is = is;
+    r.os = os;
+    r.tw = tw;
+    r.vrank = (int)V.size();
+    int64_t lines = 1;
+    for (size_t i = 0; i < V.size(); ++i) {
+        r.vn[i] = V[i].n;
+        r.vis[i] = V[i].is;
+        r.vos[i] = V[i].os;
+        lines *= V[i].n;
+    }
+    r.total = lines * cnt;
+    ps.src = src;
+    ps.dst = dst;
+    ps.src_off = src_off;
+    ps.dst_off = dst_off;
+    const double eb = elem_bytes(ps.prec);
+    const double per_line = mode == RK_UNTANGLE ? (n / 2) * eb + (n / 2 + 1) * eb
+                            : mode == RK_TANGLE ? (n / 2 + 1) * eb + (n / 2) * eb
+                            : mode == RK_WIDEN  ? n * eb / 2 + n * eb
+                            : mode == RK_HERM   ? (n / 2 + 1) * eb + n * eb
+                                                : n * eb + n * eb / 2;
+    ps.bytes = per_line * (double)lines;
+    std::ostringstream d;
+    d << what << " n=" << n << " lines=" << lines;
+    ps.desc = d.str();
+    b.p->passes.push_back(ps);
+    return MFFT_OK;
+}
+
+// Real-data plans.  Even n with unit stride on the real side: the real
+// sequence is read as n/2 complex values x[2j] + i x[2j+1] (no copy), so the
+// transform costs a complex DFT of half the length plus one elementwise pass
+// that separates (or, inverse, combines) the even and odd halves (a radix-2
+// DIT step of eq. ct).  Otherwise the real data is widened to complex, a
+// length-n complex DFT runs, and the half spectrum (or real part) is kept.
+// The inverse is the sign +1 transform, by conjugation like complex plans.
+static int build_real_plan(PlanImpl *p)
+{
+    Builder b;
+    b.p = p;
+    const Problem &pr = p->prob;
+    p->passes.clear();
+    if (pr.empty) return MFFT_OK;
+    const int prec = pr.prec;
+    const int eb = elem_bytes(prec);
+    const Dim d = pr.N[0];
+    const int64_t n = d.n, H = pr.howmany;
+    const int dst = pr.inplace ? BUF_IN : BUF_OUT;
+    const bool fwd = pr.kind == 1;
+    bool pack = n % 2 == 0 && (fwd ? d.is == 1 : d.os == 1);
+    for (const Dim &v : pr.V) pack &= (fwd ? v.is : v.os) % 2 == 0;
+    if (pack) {
+        const int64_t h = n / 2;
+        void *tw = table_alloc(p, (size_t)(h / 2 + 1) * eb);
+        if (!tw) return fail(MFFT_ENOMEM, "twiddle table allocation failed");
+        hipError_t e = launch_gen_roots(tw, prec, h / 2 + 1, n, p->stream);
+        if (e != hipSuccess) return fail(MFFT_EHIP, std::string("twiddle kernel: ") + hipGetErrorString(e));
+        const int64_t off = b.scratch_take(H * h * eb) / eb;
+        // the real side viewed as complex: vector strides halve
+        std::vector<Dim> Vc = pr.V;
+        for (Dim &v : Vc) (fwd ? v.is : v.os) /= 2;
+        if (fwd) {
+            int src = BUF_IN;
+            int64_t src_off = 0;
+            std::vector<Dim> Vu = packed(pr.V, h, 0);   // untangle reads packed Z
+            int64_t zis = 1;
+            if (h > 1) {
+                int rc = plan_line(b, Dim{h, 1, 1}, packed(Vc, h, 1), BUF_IN, BUF_SCRATCH, 0, off,
+                                   false, false);
+                if (rc) return rc;
+                src = BUF_SCRATCH;
+                src_off = off;
+            } else {
+                for (size_t i = 0; i < Vu.size(); ++i) Vu[i].is = Vc[i].is;
+            }
+            int rc = add_real_pass(b, RK_UNTANGLE, n, h / 2 + 1, zis, d.os, Vu, src, src_off, dst, 0,
+                                   tw, "untangle");
+            if (rc) return rc;
+        } else {
+            int rc = add_real_pass(b, RK_TANGLE, n, h / 2 + 1, d.is, 1, packed(pr.V, h, 1), BUF_IN, 0,
+                                   BUF_SCRATCH, off, tw, "tangle");
+            if (rc) return rc;
+            std::vector<Dim> Vi = packed(Vc, h, 0);
+            if (h > 1) {
+                rc = plan_line(b, Dim{h, 1, 1}, Vi, BUF_SCRATCH, dst, off, 0, true, true);
+            } else {
+                std::vector<Dim> all = Vi;
+                all.push_back({1, 1, 1});
+                rc = add_copy_pass(b, all, BUF_SCRATCH, dst, off, 0, "copy");
+            }
+            if (rc) return rc;
+        }
+    } else {
+        const int64_t o0 = b.scratch_take(H * n * eb) / eb;
+        const int64_t o1 = n > 1 ? b.scratch_take(H * n * eb) / eb : o0;
+        std::vector<Dim> Vp = packed(packed(pr.V, n, 0), n, 1);
+        if (fwd) {
+            int rc = add_real_pass(b, RK_WIDEN, n, n, d.is, 1, packed(pr.V, n, 1), BUF_IN, 0,
+                                   BUF_SCRATCH, o0, nullptr, "widen");
+            if (rc) return rc;
+            if (n > 1) {
+                rc = plan_line(b, Dim{n, 1, 1}, Vp, BUF_SCRATCH, BUF_SCRATCH, o0, o1, false, false);
+                if (rc) return rc;
+            }
+            std::vector<Dim> all = packed(pr.V, n, 0);
+            all.push_back({n / 2 + 1, 1, d.os});
+            rc = add_copy_pass(b, all, BUF_SCRATCH, dst, o1, 0, "half spectrum");
+            if (rc) return rc;
+        } else {
+            int rc = add_real_pass(b, RK_HERM, n, n, d.is, 1, packed(pr.V, n, 1), BUF_IN, 0,
+                                   BUF_SCRATCH, o0, nullptr, "symmetric extension");
+            if (rc) return rc;
+            if (n > 1) {
+                rc = plan_line(b, Dim{n, 1, 1}, Vp, BUF_SCRATCH, BUF_SCRATCH, o0, o1, true, true);
+                if (rc) return rc;
+            }
+            rc = add_real_pass(b, RK_REAL, n, n, 1, d.os, packed(pr.V, n, 0), BUF_SCRATCH, o1, dst, 0,
+                               nullptr, "real part");
+            if (rc) return rc;
+        }
+    }
+    p->scratch_bytes = (size_t)b.scratch_hi;
+    return MFFT_OK;
+}
+
 int build_plan(PlanImpl *p)
 {
+    if (p->prob.kind != 0) return build_real_plan(p);
     Builder b;
     b.p = p;
     const Problem &pr = p->prob;
@@ -1069,6 +1210,14 @@ CopyArgs resolve_copy(const PlanImpl *p, const Pass &ps, const void *in, void *o
     return c;
 }
 
+RealArgs resolve_real(const PlanImpl *p, const Pass &ps, const void *in, void *out, void *scratch)
+{
+    RealArgs r = ps.r;
+    r.in = resolve_buf(p, ps.src, ps.src_off, in, out, scratch);
+    r.out = resolve_buf(p, ps.dst, ps.dst_off, in, out, scratch);
+    return r;
+}
+
 size_t generic_lds_bytes(const Pass &ps)
 {
     return tile_lds_bytes(ps.a.n, ps.a.bt, ps.prec);
@@ -1080,6 +1229,8 @@ int run_plan(const PlanImpl *p, const void *in, void *out, void *scratch, hipStr
         hipError_t e;
         if (ps.kind == 1) {
             e = launch_copy(resolve_copy(p, ps, in, out, scratch), s);
+        } else if (ps.kind == 2) {
+            e = launch_real(resolve_real(p, ps, in, out, scratch), p->prob.prec, s);
         } else {
             const PassArgs a = resolve_pass(p, ps, in, out, scratch);
             if (ps.kernel == 1)

@@ -20,6 +20,10 @@ struct Dim {
 // dimensions, mergeable vector loops merged.
 struct Problem {
     std::vector<Dim> N, V;
+    // 0: complex dft(N, V, I, O); 1: real input, half spectrum out (N has one
+    // dim: n real points, is in real / os in complex elements); 2: the inverse
+    // (is in complex / os in real elements).  V strides use the same units.
+    int kind = 0;
     int sign = -1;
     int prec = 0;          // 0 = C32, 1 = C64
     bool inplace = false;
@@ -34,15 +38,19 @@ int fail(int code, const std::string &msg);
 // Validate and canonicalize; returns MFFT_OK or an error code (message set).
 int canonicalize(int rank, const mfft_iodim *dims, int howmany_rank, const mfft_iodim *hdims,
                  int inplace, int sign, int prec, Problem *out);
+// The same for real-data problems (kind 1 or 2).
+int canonicalize_real(int kind, int rank, const mfft_iodim *dims, int howmany_rank,
+                      const mfft_iodim *hdims, int inplace, int prec, Problem *out);
 std::string problem_key(const Problem &p);
 
 // Buffer ids a pass reads and writes.
 enum : int { BUF_IN = 0, BUF_OUT = 1, BUF_SCRATCH = 2 };
 
 struct Pass {
-    int kind = 0;            // 0 = FFT tile pass, 1 = rank-0 copy
+    int kind = 0;            // 0 = FFT tile pass, 1 = rank-0 copy, 2 = real-data step
     PassArgs a{};            // pointers filled at execute time (except tables)
     CopyArgs c{};
+    RealArgs r{};
     int src = BUF_IN, dst = BUF_OUT;
     int64_t src_off = 0, dst_off = 0;       // complex elements (scratch: region offset)
     int64_t aux_off = -1;                    // bytes into scratch for Rader aux, or -1
@@ -115,6 +123,7 @@ int run_plan(const PlanImpl *p, const void *in, void *out, void *scratch, hipStr
 // A pass with its buffer pointers resolved for given in/out/scratch pointers.
 PassArgs resolve_pass(const PlanImpl *p, const Pass &ps, const void *in, void *out, void *scratch);
 CopyArgs resolve_copy(const PlanImpl *p, const Pass &ps, const void *in, void *out, void *scratch);
+RealArgs resolve_real(const PlanImpl *p, const Pass &ps, const void *in, void *out, void *scratch);
 // LDS bytes the generic tile kernel needs for a pass.
 size_t generic_lds_bytes(const Pass &ps);
 
@@ -125,7 +134,7 @@ void wisdom_record(const std::string &key, const std::string &val);
 // Plan without taking the global planner lock (FP64 sub-plans for tables).
 int plan_internal(mfft_plan *out, int rank, const mfft_iodim *dims, int howmany_rank,
                   const mfft_iodim *hdims, int inplace, int sign, int prec, hipStream_t stream,
-                  unsigned flags = 0, const mfft_allocator *alloc = nullptr);
+                  unsigned flags = 0, const mfft_allocator *alloc = nullptr, int kind = 0);
 
 int64_t smallest_prime_factor(int64_t n);
 bool is_smooth7(int64_t n);

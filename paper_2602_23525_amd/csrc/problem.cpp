@@ -163,9 +163,48 @@ int canonicalize(int rank, const mfft_iodim *dims, int howmany_rank, const mfft_
     return MFFT_OK;
 }
 
+int canonicalize_real(int kind, int rank, const mfft_iodim *dims, int howmany_rank,
+                      const mfft_iodim *hdims, int inplace, int prec, Problem *out)
+{
+    if (kind != 1 && kind != 2) return fail(MFFT_EINVAL, "unknown real transform kind");
+    if (rank < 0 || rank > 8) return fail(MFFT_EINVAL, "rank must be in [0, 8]");
+    if (rank != 1) return fail(MFFT_ENOTSUP, "real-data transforms are planned for rank 1");
+    if (!dims) return fail(MFFT_EINVAL, "dims is NULL");
+    // the vector loops alone: validated, merged and ordered as for complex data
+    Problem p;
+    int rc = canonicalize(0, nullptr, howmany_rank, hdims, inplace, kind == 1 ? -1 : 1, prec, &p);
+    if (rc) return rc;
+    const mfft_iodim d = dims[0];
+    if (d.n < 0) return fail(MFFT_EINVAL, "negative length");
+    if (d.n > ((int64_t)1 << 40)) return fail(MFFT_EINVAL, "length too large");
+    p.kind = kind;
+    if (d.n == 0) p.empty = true;
+    if (p.empty) {
+        *out = p;
+        return MFFT_OK;
+    }
+    if (mul_overflows(d.n, d.is) || mul_overflows(d.n, d.os))
+        return fail(MFFT_EINVAL, "stride * length overflows");
+    // outputs: n/2+1 complex values (forward) or n real values (inverse) per line
+    const int64_t nout = kind == 1 ? d.n / 2 + 1 : d.n;
+    std::vector<Dim> all = p.V;
+    all.push_back({nout, d.is, d.os});
+    __int128 tot = nout;
+    for (const Dim &v : p.V) tot *= v.n;
+    if (tot > ((__int128)1 << 40)) return fail(MFFT_EINVAL, "problem has more than 2^40 elements");
+    if (!outputs_injective(all))
+        return fail(MFFT_EINVAL, "two output elements share one address (aliasing output strides)");
+    p.N = {{d.n, d.is, d.os}};
+    p.n_total = d.n;
+    *out = p;
+    return MFFT_OK;
+}
+
 std::string problem_key(const Problem &p)
 {
     std::ostringstream s;
+    if (p.kind == 1) s << "r2c ";
+    else if (p.kind == 2) s << "c2r ";
     s << (p.prec ? "c64" : "c32") << " s" << p.sign << (p.inplace ? " ip" : " op") << " N";
     for (const Dim &d : p.N) s << ":" << d.n << "," << d.is << "," << d.os;
     s << " V";
@@ -246,4 +285,14 @@ extern "C" int mfft_problem_check(int rank, const mfft_iodim *dims, int howmany_
 {
     mfft::Problem p;
     return mfft::canonicalize(rank, dims, howmany_rank, howmany_dims, inplace, sign, (int)prec, &p);
+}
+
+extern "C" int mfft_problem_check_real(int inverse, int rank, const mfft_iodim *dims,
+                                       int howmany_rank, const mfft_iodim *howmany_dims,
+                                       int inplace, mfft_prec prec)
+{
+    if (inverse != 0 && inverse != 1) return mfft::fail(MFFT_EINVAL, "inverse must be 0 or 1");
+    mfft::Problem p;
+    return mfft::canonicalize_real(inverse ? 2 : 1, rank, dims, howmany_rank, howmany_dims, inplace,
+                                   (int)prec, &p);
 }

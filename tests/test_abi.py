@@ -91,3 +91,17 @@ def test_wisdom_roundtrip_text():
         mfft.mfft_wisdom_import("garbage")
     mfft.mfft_wisdom_forget()
     assert "N:64" not in mfft.mfft_wisdom_export()
+
+
+@pytest.mark.parametrize("kind,dims,hdims,inplace,prec,expect", [
+    ("r2c", [(16, 1, 1)], [(4, 16, 9)], 0, 0, 0),
+    ("c2r", [(16, 1, 1)], [(4, 9, 16)], 0, 1, 0),
+    ("r2c", [(17, 1, 1)], [], 0, 0, 0),
+    ("r2c", [(8, 1, 1), (8, 8, 5)], [], 0, 0, -2),        # rank 2: not planned
+    ("r2c", [(16, 1, 1)], [(4, 16, 4)], 0, 0, -1),        # 9 outputs per row at distance 4 alias
+    ("c2r", [(16, 1, 1)], [(4, 9, 8)], 0, 0, -1),         # 16 real outputs at distance 8 alias
+    ("r2c", [(-1, 1, 1)], [], 0, 0, -1),
+    ("r2c", [(0, 1, 1)], [(3, 1, 1)], 0, 0, 0),           # empty
+])
+def test_problem_check_real(kind, dims, hdims, inplace, prec, expect):
+    assert mfft.mfft_problem_check_real(kind, dims, hdims, inplace, prec) == expect
