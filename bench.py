@@ -42,6 +42,9 @@ WORKLOADS = {
     "c2c_1d_n1009_b512_c32": ([(1009, 1, 1)], [(512, 1009, 1009)], 0, -1, False),
     "c2c_1d_n65537_b512_c32": ([(65537, 1, 1)], [(512, 65537, 65537)], 0, -1, False),
     "copy_2p26_c32": ([], [(1 << 26, 1, 1)], 0, -1, False),
+    # real input, n/2+1 complex outputs per transform (same bytes as the
+    # complex n = 4096 x 16384 workload)
+    "r2c_1d_n8192_b16384_c32": ([(8192, 1, 1)], [(16384, 8192, 4097)], 0, -1, False, "r2c"),
 }
 DEFAULT = "c2c_1d_n4096_b16384_c32"
 def counter_traffic(workload: str, plan_desc: str):
@@ -357,7 +360,9 @@ def main():
         args.workload = f"c2c_1d_n{n}_b{b}_{args.prec}"
         WORKLOADS[args.workload] = ([(n, 1, 1)], [(b, n, n)] if b > 1 else [],
                                     0 if args.prec == "c32" else 1, args.sign, False)
-    dims, hdims, prec, sign, inplace = WORKLOADS[args.workload]
+    w = WORKLOADS[args.workload]
+    dims, hdims, prec, sign, inplace = w[:5]
+    kind = w[5] if len(w) > 5 else "c2c"
     n_total = int(np.prod([d[0] for d in dims])) if dims else 1
     howmany = int(np.prod([d[0] for d in hdims])) if hdims else 1
     span = 1
@@ -365,28 +370,39 @@ def main():
         span += (d[0] - 1) * abs(d[1])
     cdt = np.complex64 if prec == 0 else np.complex128
     eb = 8 if prec == 0 else 16
-    x = uniform_complex(span, seed=2, dtype=cdt)
     dev = torch.device("cuda", 0)
-    xt = torch.from_numpy(x).to(dev)
-    yt = xt if inplace else torch.empty_like(xt)
+    if kind == "c2c":
+        x = uniform_complex(span, seed=2, dtype=cdt)
+        xt = torch.from_numpy(x).to(dev)
+        yt = xt if inplace else torch.empty_like(xt)
+    else:
+        # r2c: span real inputs, half spectra out (contiguous workloads only)
+        nh = n_total // 2 + 1
+        z = uniform_complex((span + 1) // 2, seed=2, dtype=np.complex128)
+        x = np.stack([z.real, z.imag], axis=-1).reshape(-1)[:span]
+        x = x.astype(np.float32 if prec == 0 else np.float64)
+        xt = torch.from_numpy(x).to(dev)
+        yt = torch.empty(howmany * nh, dtype=torch.complex64 if prec == 0 else torch.complex128,
+                         device=dev)
     stream = torch.cuda.current_stream()
 
     t0 = time.perf_counter()
-    plan = mfft.Plan(dims, hdims, inplace=inplace, sign=sign, prec=prec)
+    plan = mfft.Plan(dims, hdims, inplace=inplace, sign=sign, prec=prec, kind=kind)
     plan_s = time.perf_counter() - t0
     info = plan.info()
 
     # Buffer sets: one, or (cold-buffer rotation) enough distinct sets that
     # their total exceeds 2 GB, so no launch finds its data in the caches
     # (L2, 256 MB Infinity Cache) left behind by the previous one.
-    set_bytes = (1 if inplace else 2) * span * eb
+    set_bytes = (1 if inplace else 2) * span * eb if kind == "c2c" else \
+        xt.numel() * xt.element_size() + yt.numel() * yt.element_size()
     nsets = 1
     if set_bytes < (512 << 20) and not args.warm:
         nsets = min(4096, -(-(2 << 30) // set_bytes))
     sets = [(xt, yt)]
     for _ in range(nsets - 1):
         xi = xt.clone()
-        sets.append((xi, xi if inplace else torch.empty_like(xt)))
+        sets.append((xi, xi if inplace else torch.empty_like(yt)))
 
     def run(i):
         xi, yi = sets[i % nsets]
@@ -465,7 +481,8 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": traffic},
     }
-    one_d = len(dims) == 1 and dims[0][1] == 1 and dims[0][2] == 1 and not inplace
+    one_d = (len(dims) == 1 and dims[0][1] == 1 and dims[0][2] == 1 and not inplace
+             and kind == "c2c")
     extras = args.workload == DEFAULT and not args.timing_only
     if one_d and howmany > 1 and (args.verify or extras):
         # sampled accuracy against the FP64 oracle (three whole transforms)
@@ -515,7 +532,7 @@ def main():
         cfg["plain_ms_per_step"] = round(wall_plain, 3)
         cfg["plain_gpu_ms_per_step"] = round(e0.elapsed_time(e1), 3)
         cfg["batched_over_plain"] = round(wall_plain / ms_step, 2)
-    if not args.no_cpu and dims:
+    if not args.no_cpu and dims and kind == "c2c":
         out["cpu_baseline"] = cpu_baseline(x, [(n_total, 1, 1)] if len(dims) == 1 else dims,
                                            hdims, sign, n_total, howmany)
     plan.destroy()

@@ -64,6 +64,7 @@ int build_batch_layout(const std::vector<BatchItem> &items, BatchLayout *L)
     std::map<Key, size_t> fam_lds;
     std::map<int, std::vector<CopyArgs>> copies;
     std::map<int, std::vector<std::pair<RealArgs, int>>> reals;
+    std::map<int, std::vector<BatchStep>> leaves;
     int nphase = 0;
     for (const BatchItem &it : items) {
         const PlanImpl *p = it.plan;
@@ -80,6 +81,17 @@ int build_batch_layout(const std::vector<BatchItem> &items, BatchLayout *L)
             }
             PassArgs a = resolve_pass(p, ps, it.in, it.out, it.scratch);
             if (a.ntiles <= 0) continue;
+            if (a.flags & (PF_R2C | PF_C2R)) {
+                // the fused split/combine exists only in the specialized leaf kernel
+                BatchStep st;
+                st.leaf = true;
+                st.a = a;
+                st.leaf_variant = ps.variant;
+                st.leaf_grid = (int)ps.grid;
+                st.prec = ps.prec;
+                leaves[(int)k].push_back(st);
+                continue;
+            }
             size_t lds = 0;
             const int block = widen(ps, &a, &lds);
             const Key key{(int)k, p->prob.prec, pass_kind(a.flags), block};
@@ -140,6 +152,7 @@ int build_batch_layout(const std::vector<BatchItem> &items, BatchLayout *L)
             st.c = c;
             L->steps.push_back(st);
         }
+        for (const BatchStep &st : leaves[k]) L->steps.push_back(st);
         for (const auto &rp : reals[k]) {
             BatchStep st;
             st.real = true;
@@ -169,6 +182,8 @@ int enqueue_batch_layout(const BatchLayout &L, char *dev, hipStream_t s)
             e = launch_copy(st.c, s);
         } else if (st.real) {
             e = launch_real(st.r, st.prec, s);
+        } else if (st.leaf) {
+            e = launch_leaf(st.a, st.prec, st.a.n, st.leaf_variant, st.leaf_grid, s);
         } else {
             const BatchGroup &g = L.groups[st.group];
             e = launch_batch((const PassArgs *)(dev + g.items_off),

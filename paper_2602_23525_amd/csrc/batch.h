@@ -28,6 +28,9 @@ struct BatchStep {   // one launch: a group, a copy pass or a real-data step
     CopyArgs c{};
     bool real = false;
     RealArgs r{};
+    bool leaf = false;   // a specialized leaf pass with a real-data fusion
+    PassArgs a{};
+    int leaf_variant = 0, leaf_grid = 0;
     int prec = 0;
     int group = -1;
 };

@@ -42,6 +42,8 @@ enum : uint32_t {
     PF_AUX_A0 = 1u << 11,    // save the k=0 output (before post multiply) to aux
     PF_AUX_ADD = 1u << 12,   // add aux x0 on store, write Y[0] = x0 + A0 (multi-pass Rader)
     PF_XCD = 1u << 13,       // map consecutive tiles to one XCD (L2 locality of gathers)
+    PF_R2C = 1u << 14,       // leaf kernel: split the packed real transform on store (n+1 out)
+    PF_C2R = 1u << 15,       // leaf kernel: combine a half spectrum on load (n+1 in)
 };
 
 // Workgroups are dispatched round-robin over the chip's 8 XCDs, each with its

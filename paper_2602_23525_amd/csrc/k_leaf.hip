@@ -7,18 +7,18 @@
 
 namespace mfft {
 
-template <typename T, int N, int BT, bool PF, int WPE, int NT, int... Rs>
+template <typename T, int N, int BT, bool PF, int WPE, int NT, int RD, int... Rs>
 static hipError_t go(const PassArgs &a, int grid, hipStream_t s)
 {
-    hipLaunchKernelGGL((leaf_kernel<T, N, BT, PF, WPE, NT, Rs...>), dim3(grid), dim3(BT * N / 16), 0, s, a);
+    hipLaunchKernelGGL((leaf_kernel<T, N, BT, PF, WPE, NT, RD, Rs...>), dim3(grid), dim3(BT * N / 16), 0, s, a);
     return hipGetLastError();
 }
 
-template <typename T, int N, int BT, bool PF, int WPE, int NT, int... Rs>
+template <typename T, int N, int BT, bool PF, int WPE, int NT, int RD, int... Rs>
 static int occ()
 {
     int blocks = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, leaf_kernel<T, N, BT, PF, WPE, NT, Rs...>,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, leaf_kernel<T, N, BT, PF, WPE, NT, RD, Rs...>,
                                                      BT * N / 16, 0) != hipSuccess) {
         (void)hipGetLastError();
         return 1;
@@ -27,13 +27,13 @@ static int occ()
 }
 
 // kind: 0 = launch, 1 = occupancy query
-template <typename T, int THREADS, bool PF, int WPE, int NT>
+template <typename T, int THREADS, bool PF, int WPE, int NT, int RD = 0>
 static int dispatch(int kind, const PassArgs &a, int n, int grid, hipStream_t s, hipError_t *err)
 {
 #define LEAF_CASE(N, ...)                                                                  \
     case N:                                                                                \
-        if (kind == 1) return occ<T, N, THREADS * 16 / N, PF, WPE, NT, __VA_ARGS__>();     \
-        *err = go<T, N, THREADS * 16 / N, PF, WPE, NT, __VA_ARGS__>(a, grid, s);           \
+        if (kind == 1) return occ<T, N, THREADS * 16 / N, PF, WPE, NT, RD, __VA_ARGS__>(); \
+        *err = go<T, N, THREADS * 16 / N, PF, WPE, NT, RD, __VA_ARGS__>(a, grid, s);       \
         return 0;
     switch (n) {
         LEAF_CASE(64, 16, 4)
@@ -47,8 +47,8 @@ static int dispatch(int kind, const PassArgs &a, int n, int grid, hipStream_t s,
     }
     if (n == 4096) {
         // one line of 256 threads per workgroup in both precisions
-        if (kind == 1) return occ<T, 4096, 1, PF, WPE, NT, 16, 16, 16>();
-        *err = go<T, 4096, 1, PF, WPE, NT, 16, 16, 16>(a, grid, s);
+        if (kind == 1) return occ<T, 4096, 1, PF, WPE, NT, RD, 16, 16, 16>();
+        *err = go<T, 4096, 1, PF, WPE, NT, RD, 16, 16, 16>(a, grid, s);
         return 0;
     }
 #undef LEAF_CASE
@@ -92,6 +92,19 @@ static int run_wpe(int kind, const PassArgs &a, int n, int w, int nt, int grid, 
 static int run(int kind, const PassArgs &a, int prec, int n, int variant, int grid,
                hipStream_t s, hipError_t *e)
 {
+    // real-data fusions: one configuration each (prefetch with a persistent
+    // grid for the long FP32 lines, as the plain default)
+    if (a.flags & (PF_R2C | PF_C2R)) {
+        const bool pf = variant & 1;
+        if (a.flags & PF_R2C) {
+            if (prec == 0)
+                return pf ? dispatch<float, 256, true, 2, 0, 1>(kind, a, n, grid, s, e)
+                          : dispatch<float, 256, false, 2, 0, 1>(kind, a, n, grid, s, e);
+            return dispatch<double, 128, false, 2, 0, 1>(kind, a, n, grid, s, e);
+        }
+        if (prec == 0) return dispatch<float, 256, false, 2, 0, 2>(kind, a, n, grid, s, e);
+        return dispatch<double, 128, false, 2, 0, 2>(kind, a, n, grid, s, e);
+    }
     const bool pf = variant & 1;
     const int w = (variant >> 1) & 3, nt = (variant >> 3) & 3;
     if (prec == 0) {

@@ -141,10 +141,13 @@ struct StageChain<T, N, TPT, NS, R> {
     }
 };
 
+// RD: 0 plain; 1 the line is the transform of a packed real sequence, split
+// into the n+1 outputs of the real transform on store (PF_R2C); 2 the line is
+// combined from n+1 values of a half spectrum on load (PF_C2R).
 // WPE: occupancy floor in waves per SIMD (caps VGPRs at 512 / WPE).
 // NT: bit 0 streams the output with non-temporal stores, bit 1 the input with
 // non-temporal loads (neither is reused by this pass).
-template <typename T, int N, int BT, bool PF, int WPE, int NT, int... Rs>
+template <typename T, int N, int BT, bool PF, int WPE, int NT, int RD, int... Rs>
 __global__ __launch_bounds__(BT *N / 16) __attribute__((amdgpu_waves_per_eu(WPE))) void leaf_kernel(PassArgs)
 {
     constexpr int TPT = N / 16;
@@ -192,6 +195,62 @@ __global__ __launch_bounds__(BT *N / 16) __attribute__((amdgpu_waves_per_eu(WPE)
         }
     };
 
+    // Real-data fusions (one line = the n-point complex transform of a packed
+    // real sequence of length 2n): PF_C2R combines the n+1 values of a half
+    // spectrum into the packed input on load, PF_R2C splits the result into the
+    // n+1 outputs on store (both as the elementwise real-data steps, through
+    // LDS since the partners k and n-k sit in different lanes).
+    constexpr bool r2c = RD == 1, c2r = RD == 2;
+    const cpx<T> *rtw = (const cpx<T> *)a.post;   // w_2n^k, k <= n/2
+    // half spectrum X (n+1 values from ib) -> packed Z' in LDS, lane t taking
+    // the pairs (k, n-k); ends with a barrier
+    auto combine_half_spectrum = [&](int64_t ib, bool ok) {
+        const cpx<T> *X = (const cpx<T> *)a.in + ib;
+        for (int k = t; k <= N / 2; k += TPT) {
+            cpx<T> A = {T(0), T(0)}, B = A;
+            if (ok) {
+                A = X[k];
+                B = X[N - k];
+            }
+            if (k == 0) {   // bins 0 and n of the real transform are real
+                line[0] = {A.re + B.re, A.re - B.re};
+                continue;
+            }
+            const cpx<T> P = {A.re + B.re, A.im - B.im}, M = {A.re - B.re, A.im + B.im};
+            const cpx<T> wM = cmul(conj(rtw[k]), M);
+            const cpx<T> iwM = {-wM.im, wM.re};
+            line[lds_pad(k)] = {P.re + iwM.re, P.im + iwM.im};
+            if (2 * k != N) line[lds_pad(N - k)] = {P.re - iwM.re, iwM.im - P.im};
+        }
+        __syncthreads();
+    };
+    // packed transform Z (in x, element t + e*TPT) -> the n+1 outputs of the
+    // real transform at ob; ends with a barrier so the next tile may reuse LDS
+    auto split_to_half_spectrum = [&](const cpx<T>(&z)[16], int64_t ob, bool ok) {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) line[lds_pad(t + e * TPT)] = z[e];
+        __syncthreads();
+        if (ok) {
+            cpx<T> *X = (cpx<T> *)a.out + ob;
+            const T half = T(0.5);
+            for (int k = t; k <= N / 2; k += TPT) {
+                const cpx<T> A = line[lds_pad(k)];
+                if (k == 0) {
+                    X[0] = {A.re + A.im, T(0)};
+                    X[N] = {A.re - A.im, T(0)};
+                    continue;
+                }
+                const cpx<T> B = line[lds_pad(N - k)];
+                const cpx<T> E = {half * (A.re + B.re), half * (A.im - B.im)};
+                const cpx<T> O = {half * (A.im + B.im), half * (B.re - A.re)};
+                const cpx<T> wO = cmul(rtw[k], O);
+                X[k] = {E.re + wO.re, E.im + wO.im};
+                if (2 * k != N) X[N - k] = {E.re - wO.re, wO.im - E.im};
+            }
+        }
+        __syncthreads();
+    };
+
     const int64_t G = gridDim.x;
     int64_t tile = blockIdx.x;
     if (tile >= a.ntiles) return;
@@ -199,24 +258,32 @@ __global__ __launch_bounds__(BT *N / 16) __attribute__((amdgpu_waves_per_eu(WPE)
     bool ok;
     line_base(tile, &ib, &ob, &ok);
     cpx<T> x[16];
-    load_line(x, ib, ok);
+    if constexpr (!c2r) load_line(x, ib, ok);
     for (;;) {
         const int64_t next = tile + G;
         int64_t ib2 = 0, ob2 = 0;
         bool ok2 = false;
         cpx<T> xn[16];
         if constexpr (PF) {
-            if (next < a.ntiles) {
+            if (next < a.ntiles && !c2r) {
                 line_base(next, &ib2, &ob2, &ok2);
                 load_line(xn, ib2, ok2);
             }
+        }
+        if constexpr (c2r) {
+            combine_half_spectrum(ib, ok);
+#pragma unroll
+            for (int e = 0; e < 16; ++e) x[e] = line[lds_pad(t + e * TPT)];
+            __syncthreads();   // the first stage overwrites the line
         }
         if (cin) {
 #pragma unroll
             for (int e = 0; e < 16; ++e) x[e] = conj(x[e]);
         }
         chain.run(x, line, t);
-        if (ok) {
+        if constexpr (r2c) {
+            split_to_half_spectrum(x, ob, ok);
+        } else if (ok) {
             cpx<T> *dst = (cpx<T> *)a.out + ob;
 #pragma unroll
             for (int e = 0; e < 16; ++e) {
@@ -233,15 +300,20 @@ __global__ __launch_bounds__(BT *N / 16) __attribute__((amdgpu_waves_per_eu(WPE)
         // no barrier needed here: every LDS read of this tile came before the
         // barrier that ends the last exchange
         tile = next;
+        bool prefetched = false;
         if constexpr (PF) {
-            ib = ib2;
-            ob = ob2;
-            ok = ok2;
+            if (!c2r) {
+                ib = ib2;
+                ob = ob2;
+                ok = ok2;
 #pragma unroll
-            for (int e = 0; e < 16; ++e) x[e] = xn[e];
-        } else {
+                for (int e = 0; e < 16; ++e) x[e] = xn[e];
+                prefetched = true;
+            }
+        }
+        if (!prefetched) {
             line_base(tile, &ib, &ob, &ok);
-            load_line(x, ib, ok);
+            if constexpr (!c2r) load_line(x, ib, ok);
         }
     }
 }

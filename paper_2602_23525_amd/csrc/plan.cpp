@@ -1031,10 +1031,34 @@ static int build_real_plan(PlanImpl *p)
         if (!tw) return fail(MFFT_ENOMEM, "twiddle table allocation failed");
         hipError_t e = launch_gen_roots(tw, prec, h / 2 + 1, n, p->stream);
         if (e != hipSuccess) return fail(MFFT_EHIP, std::string("twiddle kernel: ") + hipGetErrorString(e));
-        const int64_t off = b.scratch_take(H * h * eb) / eb;
         // the real side viewed as complex: vector strides halve
         std::vector<Dim> Vc = pr.V;
         for (Dim &v : Vc) (fwd ? v.is : v.os) /= 2;
+        // one pass when the half-length transform is a specialized leaf: the
+        // split (or combine) runs in its store (load) through LDS.  In place
+        // only when each real row starts where its complex row does.
+        bool same_rows = true;
+        for (const Dim &v : pr.V) same_rows &= fwd ? v.is == 2 * v.os : v.os == 2 * v.is;
+        if (leaf_supported(prec, h) && (fwd ? d.os == 1 : d.is == 1) &&
+            (!pr.inplace || same_rows)) {
+            const size_t before = p->passes.size();
+            const int64_t top = b.scratch_top, hi = b.scratch_hi;
+            int rc = plan_line(b, Dim{h, 1, 1}, Vc, BUF_IN, dst, 0, 0, !fwd, !fwd);
+            if (rc) return rc;
+            if (p->passes.size() == before + 1 && p->passes.back().kernel == 1) {
+                Pass &ps = p->passes.back();
+                ps.a.flags |= fwd ? PF_R2C : PF_C2R;
+                ps.a.post = tw;
+                if (!fwd) ps.variant &= ~1;   // the combine replaces the prefetch
+                ps.desc += fwd ? " +split" : " +combine";
+                p->scratch_bytes = (size_t)b.scratch_hi;
+                return MFFT_OK;
+            }
+            p->passes.resize(before);
+            b.scratch_top = top;
+            b.scratch_hi = hi;
+        }
+        const int64_t off = b.scratch_take(H * h * eb) / eb;
         if (fwd) {
             int src = BUF_IN;
             int64_t src_off = 0;

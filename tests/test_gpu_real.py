@@ -104,8 +104,9 @@ def c2r_case(n, b, prec, is_=1, dist_in=None, os_=1, dist_out=None, inplace=Fals
     return err
 
 
-SIZES = [1, 2, 3, 4, 5, 6, 8, 15, 16, 17, 30, 64, 100, 243, 1000, 1009, 1024, 2187, 4096, 8192,
-         14175, 65536, 65537]
+# 128 .. 8192 take the one-pass path (a specialized leaf of half the length)
+SIZES = [1, 2, 3, 4, 5, 6, 8, 15, 16, 17, 30, 64, 100, 128, 243, 256, 512, 1000, 1009, 1024,
+         2048, 2187, 4096, 8192, 14175, 65536, 65537]
 
 
 @pytest.mark.parametrize("n", SIZES)
@@ -132,7 +133,7 @@ def test_strided_and_odd_distances(n):
     c2r_case(n, 4, 1, dist_in=n // 2 + 3, dist_out=n + 2, seed=6)
 
 
-@pytest.mark.parametrize("n", [16, 1000, 4096, 65536, 17])
+@pytest.mark.parametrize("n", [16, 1000, 4096, 8192, 65536, 17])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_in_place(n, prec):
     h = n // 2 + 1
@@ -171,7 +172,7 @@ def test_real_plans_in_a_batch():
     import torch
 
     import paper_2602_23525_amd as mfft
-    shapes = [(4096, 8), (1000, 5), (17, 3), (65536, 2)]
+    shapes = [(4096, 8), (1000, 5), (17, 3), (65536, 2), (8192, 3)]
     plans, ins, outs, alone = [], [], [], []
     refs = []
     for i, (n, b) in enumerate(shapes):
