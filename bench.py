@@ -45,6 +45,7 @@ WORKLOADS = {
     # real input, n/2+1 complex outputs per transform (same bytes as the
     # complex n = 4096 x 16384 workload)
     "r2c_1d_n8192_b16384_c32": ([(8192, 1, 1)], [(16384, 8192, 4097)], 0, -1, False, "r2c"),
+    "c2r_1d_n8192_b16384_c32": ([(8192, 1, 1)], [(16384, 4097, 8192)], 0, 1, False, "c2r"),
 }
 DEFAULT = "c2c_1d_n4096_b16384_c32"
 def counter_traffic(workload: str, plan_desc: str):
@@ -375,14 +376,21 @@ def main():
         x = uniform_complex(span, seed=2, dtype=cdt)
         xt = torch.from_numpy(x).to(dev)
         yt = xt if inplace else torch.empty_like(xt)
-    else:
-        # r2c: span real inputs, half spectra out (contiguous workloads only)
+    elif kind == "r2c":
+        # span real inputs, half spectra out (contiguous workloads only)
         nh = n_total // 2 + 1
         z = uniform_complex((span + 1) // 2, seed=2, dtype=np.complex128)
         x = np.stack([z.real, z.imag], axis=-1).reshape(-1)[:span]
         x = x.astype(np.float32 if prec == 0 else np.float64)
         xt = torch.from_numpy(x).to(dev)
         yt = torch.empty(howmany * nh, dtype=torch.complex64 if prec == 0 else torch.complex128,
+                         device=dev)
+    else:
+        # c2r: half spectra in (n/2+1 per transform), n real outputs each
+        nh = n_total // 2 + 1
+        x = uniform_complex(howmany * nh, seed=2, dtype=cdt)
+        xt = torch.from_numpy(x).to(dev)
+        yt = torch.empty(howmany * n_total, dtype=torch.float32 if prec == 0 else torch.float64,
                          device=dev)
     stream = torch.cuda.current_stream()
 
