@@ -19,6 +19,7 @@
 //     sizes"), each one kernel when the convolution fits a leaf;
 //   - rank 0: a copy (Section 4.2, "Rank-0 plans").
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -90,68 +91,83 @@ static int stage_threads(int64_t n, int R, int emax)
     return (int)((n / R + nbmax - 1) / nbmax);
 }
 
-// Radix sequence of a leaf of length n (7-smooth): the fewest stages over the
+// Radix sequence of a leaf of length n (smooth): the fewest stages over the
 // radices the tile kernel compiles whose thread need fits max_tpt (each stage
 // is one LDS exchange); among those, the smallest thread count, then larger
-// radices first.  A dynamic program over the exponents of 2, 3, 5 and 7.
+// radices first.  A dynamic program over the exponents of 2, 3, 5, 7, 11, 13.
 static bool radices_for(int64_t n, int emax, int max_tpt, std::vector<int> *r)
 {
-    if (n < 2 || !is_smooth7(n)) return false;
-    static const int kRad[] = {16, 15, 14, 12, 10, 9, 8, 7, 6, 5, 4, 3, 2};
-    static const int kPrime[4] = {2, 3, 5, 7};
-    auto expo = [](int64_t v, int (&e)[4]) {
-        for (int i = 0; i < 4; ++i) {
-            e[i] = 0;
+    if (n < 2 || !is_smooth(n)) return false;
+    constexpr int NP = 6;
+    static const int kRad[] = {16, 15, 14, 13, 12, 11, 10, 9, 8, 7, 6, 5, 4, 3, 2};
+    static const int kPrime[NP] = {2, 3, 5, 7, 11, 13};
+    using Ex = std::array<int, NP>;
+    auto expo = [](int64_t v) {
+        Ex e{};
+        for (int i = 0; i < NP; ++i)
             while (v % kPrime[i] == 0) {
                 v /= kPrime[i];
                 ++e[i];
             }
-        }
+        return e;
     };
-    int en[4];
-    expo(n, en);
-    const int d1 = en[0] + 1, d2 = en[1] + 1, d3 = en[2] + 1, d4 = en[3] + 1;
+    const Ex en = expo(n);
+    size_t states = 1;
+    for (int i = 0; i < NP; ++i) states *= (size_t)(en[i] + 1);
+    auto index = [&](const Ex &e) {
+        size_t x = 0;
+        for (int i = 0; i < NP; ++i) x = x * (size_t)(en[i] + 1) + (size_t)e[i];
+        return x;
+    };
     struct Best {
         int stages = -1, need = 0, rad = 0;   // stages < 0: not computed; INT32_MAX: none
     };
-    std::vector<Best> memo((size_t)d1 * d2 * d3 * d4);
-    std::vector<int> allowed;
+    std::vector<Best> memo(states);
+    std::vector<std::pair<int, Ex>> allowed;
     for (int R : kRad)
-        if (stage_threads(n, R, emax) <= max_tpt) allowed.push_back(R);
-    std::function<Best(int, int, int, int)> solve = [&](int a2, int a3, int a5, int a7) -> Best {
-        Best &m = memo[(((size_t)a2 * d2 + a3) * d3 + a5) * d4 + a7];
+        if (stage_threads(n, R, emax) <= max_tpt) allowed.push_back({R, expo(R)});
+    std::function<Best(const Ex &)> solve = [&](const Ex &a) -> Best {
+        Best &m = memo[index(a)];
         if (m.stages >= 0) return m;
         Best best;
-        best.stages = (a2 | a3 | a5 | a7) ? INT32_MAX : 0;
-        if (best.stages) {
-            for (int R : allowed) {
-                int e[4];
-                expo(R, e);
-                if (e[0] > a2 || e[1] > a3 || e[2] > a5 || e[3] > a7) continue;
-                const Best sub = solve(a2 - e[0], a3 - e[1], a5 - e[2], a7 - e[3]);
+        bool done = true;
+        for (int i = 0; i < NP; ++i) done &= a[i] == 0;
+        best.stages = done ? 0 : INT32_MAX;
+        if (!done) {
+            for (const auto &re : allowed) {
+                Ex rest = a;
+                bool fits = true;
+                for (int i = 0; i < NP; ++i) {
+                    rest[i] -= re.second[i];
+                    fits &= rest[i] >= 0;
+                }
+                if (!fits) continue;
+                const Best sub = solve(rest);
                 if (sub.stages == INT32_MAX) continue;
                 const int st = sub.stages + 1;
-                const int need = std::max(sub.need, stage_threads(n, R, emax));
+                const int need = std::max(sub.need, stage_threads(n, re.first, emax));
                 if (st < best.stages || (st == best.stages && need < best.need)) {
                     best.stages = st;
                     best.need = need;
-                    best.rad = R;
+                    best.rad = re.first;
                 }
             }
         }
-        m = best;
+        memo[index(a)] = best;
         return best;
     };
-    const Best top = solve(en[0], en[1], en[2], en[3]);
+    const Best top = solve(en);
     if (top.stages == INT32_MAX || top.stages > kMaxStages) return false;
     std::vector<int> rad;
-    int a[4] = {en[0], en[1], en[2], en[3]};
-    while (a[0] | a[1] | a[2] | a[3]) {
-        const Best b = solve(a[0], a[1], a[2], a[3]);
+    Ex a = en;
+    for (;;) {
+        bool done = true;
+        for (int i = 0; i < NP; ++i) done &= a[i] == 0;
+        if (done) break;
+        const Best b = solve(a);
         rad.push_back(b.rad);
-        int e[4];
-        expo(b.rad, e);
-        for (int i = 0; i < 4; ++i) a[i] -= e[i];
+        const Ex e = expo(b.rad);
+        for (int i = 0; i < NP; ++i) a[i] -= e[i];
     }
     std::sort(rad.begin(), rad.end(), std::greater<int>());
     *r = rad;
@@ -720,11 +736,11 @@ static int plan_bluestein(Builder &b, Dim d, const std::vector<Dim> &V, int src,
     const int64_t n = d.n;
     const int prec = b.p->prob.prec;
     const int eb = elem_bytes(prec);
-    // smallest 7-smooth M >= 2n-1 that is a leaf, else one with a two-pass split
+    // smallest smooth M >= 2n-1 that is a leaf, else one with a two-pass split
     int64_t M = 0;
     bool single = false;
     for (int64_t c = 2 * n - 1; c <= 4 * n + 64; ++c) {
-        if (!is_smooth7(c)) continue;
+        if (!is_smooth(c)) continue;
         if (leaf_fits(c, prec, 1)) {
             M = c;
             single = true;
@@ -734,7 +750,7 @@ static int plan_bluestein(Builder &b, Dim d, const std::vector<Dim> &V, int src,
     if (!M) {
         for (int64_t c = 2 * n - 1; c <= 4 * n + 64; ++c) {
             Split sp;
-            if (is_smooth7(c) && choose_split(c, prec, &sp)) {
+            if (is_smooth(c) && choose_split(c, prec, &sp)) {
                 M = c;
                 break;
             }
@@ -836,7 +852,7 @@ static int plan_line(Builder &b, Dim d, std::vector<Dim> V, int src, int dst, in
 {
     const int prec = b.p->prob.prec;
     const int64_t n = d.n;
-    if (is_smooth7(n)) {
+    if (is_smooth(n)) {
         const bool strided = std::llabs(d.is) != 1 || std::llabs(d.os) != 1;
         if (leaf_fits(n, prec, strided ? (prec ? 4 : 8) : 1) || leaf_fits(n, prec, 1)) {
             const bool inplace = src == dst && src_off == dst_off;
@@ -855,7 +871,7 @@ static int plan_line(Builder &b, Dim d, std::vector<Dim> V, int src, int dst, in
         }
         return plan_ct(b, d, V, src, dst, src_off, dst_off, conj_in, conj_out, sp);
     }
-    if (smallest_prime_factor(n) == n && is_smooth7(n - 1))
+    if (smallest_prime_factor(n) == n && is_smooth(n - 1))
         return plan_rader(b, d, V, src, dst, src_off, dst_off, conj_in, conj_out);
     return plan_bluestein(b, d, V, src, dst, src_off, dst_off, conj_in, conj_out);
 }

@@ -222,10 +222,11 @@ int64_t smallest_prime_factor(int64_t n)
     return n;
 }
 
-bool is_smooth7(int64_t n)
+// Lengths the leaf butterflies factor completely: prime factors 2 .. 13.
+bool is_smooth(int64_t n)
 {
     if (n < 1) return false;
-    for (int64_t f : {2, 3, 5, 7})
+    for (int64_t f : {2, 3, 5, 7, 11, 13})
         while (n % f == 0) n /= f;
     return n == 1;
 }

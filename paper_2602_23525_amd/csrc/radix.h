@@ -1,6 +1,7 @@
-// Butterflies of the generic tile kernel: the radices of butterfly.h plus the
+// Butterflies of the generic tile kernel: the radices of butterfly.h, the
 // composites 6, 9, 10, 12, 14 and 15, each one step of eq. ct with constant
-// twiddles (fewer LDS exchanges for sizes with factors 3, 5 and 7).
+// twiddles (fewer LDS exchanges for sizes with factors 3, 5 and 7), and the
+// primes 11 and 13 by the definition with paired terms.
 #pragma once
 #include <utility>
 
@@ -103,6 +104,40 @@ __device__ __forceinline__ void dft_ab(cpx<T> *v)
     }
 }
 
+// Odd prime R by the definition with paired terms: for k = 1 .. (R-1)/2,
+//   a_k = v0 + sum_j cos(2 pi jk/R) (v_j + v_(R-j)),
+//   b_k = sum_j sin(2 pi jk/R) (v_j - v_(R-j)),
+//   y_k = a_k - i b_k,  y_(R-k) = a_k + i b_k  (forward sign), y_0 = sum v.
+template <typename T, int R>
+__device__ __forceinline__ void dft_odd_prime(cpx<T> *v)
+{
+    constexpr int H = (R - 1) / 2;
+    cpx<T> s[H], d[H];
+    cpx<T> y0 = v[0];
+#pragma unroll
+    for (int j = 1; j <= H; ++j) {
+        s[j - 1] = cadd(v[j], v[R - j]);
+        d[j - 1] = csub(v[j], v[R - j]);
+        y0 = cadd(y0, s[j - 1]);
+    }
+    cpx<T> out[R];
+    out[0] = y0;
+    static_for<H>([&](auto kc) {
+        constexpr int k = decltype(kc)::value + 1;
+        cpx<T> a = v[0], b = {T(0), T(0)};
+        static_for<H>([&](auto jc) {
+            constexpr int j = decltype(jc)::value + 1;
+            constexpr CPair w = cx_root((j * k) % R, R);
+            a = {a.re + T(w.c) * s[j - 1].re, a.im + T(w.c) * s[j - 1].im};
+            b = {b.re + T(w.s) * d[j - 1].re, b.im + T(w.s) * d[j - 1].im};
+        });
+        out[k] = {a.re + b.im, a.im - b.re};       // a - i b
+        out[R - k] = {a.re - b.im, a.im + b.re};   // a + i b
+    });
+#pragma unroll
+    for (int k = 0; k < R; ++k) v[k] = out[k];
+}
+
 template <typename T, int R>
 __device__ __forceinline__ void dftx(cpx<T> *v)
 {
@@ -112,6 +147,7 @@ __device__ __forceinline__ void dftx(cpx<T> *v)
     else if constexpr (R == 12) dft_ab<T, 4, 3>(v);
     else if constexpr (R == 14) dft_ab<T, 7, 2>(v);
     else if constexpr (R == 15) dft_ab<T, 5, 3>(v);
+    else if constexpr (R == 11 || R == 13) dft_odd_prime<T, R>(v);
     else dft<T, R>(v);
 }
 

@@ -262,6 +262,9 @@ __device__ __forceinline__ void stage(const PassArgs &a, const StageDesc &sd, Ti
     const int nb = sd.nb, tpt = a.tpt, Ns = sd.Ns;
     const int64_t c = tl.c0 + tl.tr;
     const bool ok = c < a.vn;
+    // lines past the vector loop (the last tile's padding) compute on an
+    // in-range line's tables and store nothing: table reads stay in bounds
+    const int64_t cs = ok ? c : tl.c0;
     const int64_t out_base = tl.ob_out + c * a.vos;
     // lanes past the tile's bt*tpt threads (batched launches with a larger
     // block) only take part in the barriers
@@ -298,7 +301,7 @@ __device__ __forceinline__ void stage(const PassArgs &a, const StageDesc &sd, Ti
             for (int i = 0; i < NB; ++i) {
                 const int b = tl.t + i * tpt;
                 if (b < nbl) {
-                    const cpx<T> *cv = (const cpx<T> *)a.conv + c * a.conv_c + (int64_t)b * a.conv_k;
+                    const cpx<T> *cv = (const cpx<T> *)a.conv + cs * a.conv_c + (int64_t)b * a.conv_k;
                     const int64_t cst = (int64_t)nb * a.conv_k;
 #pragma unroll
                     for (int k = 0; k < R; ++k) v[i][k] = conj(cmul(v[i][k], cv[k * cst]));
@@ -328,8 +331,8 @@ __device__ __forceinline__ void stage(const PassArgs &a, const StageDesc &sd, Ti
                     if (a.flags & PF_TW4) {
                         // element base + k*Ns of line c takes w_N^(c*(j + k*Ns)):
                         // start w_N^(c*j), step w_N^(c*Ns), products in FP64
-                        double2 w = tw4_root(a, c * j);
-                        const double2 ws = tw4_root(a, c * Ns);
+                        double2 w = tw4_root(a, cs * j);
+                        const double2 ws = tw4_root(a, cs * Ns);
 #pragma unroll
                         for (int k = 0; k < R; ++k) {
                             v[i][k] = mul_d(v[i][k], w);
@@ -373,6 +376,8 @@ __device__ __forceinline__ void run_fft(const PassArgs &a, Tile<T> &tl, int firs
         case 12: stage<T, 12, EMAX, KIND>(a, sd, tl, fetch, emit); break;
         case 14: stage<T, 14, EMAX, KIND>(a, sd, tl, fetch, emit); break;
         case 15: stage<T, 15, EMAX, KIND>(a, sd, tl, fetch, emit); break;
+        case 11: stage<T, 11, EMAX, KIND>(a, sd, tl, fetch, emit); break;
+        case 13: stage<T, 13, EMAX, KIND>(a, sd, tl, fetch, emit); break;
         default: stage<T, 16, EMAX, KIND>(a, sd, tl, fetch, emit); break;
         }
     }
@@ -479,8 +484,9 @@ __device__ __forceinline__ void tile_body(const PassArgs &a, Tile<T> &tl, cpx<T>
             if constexpr (KIND & K_TW4) {
                 tw = (f & PF_TW4) != 0;
                 if (tw) {
-                    w = tw4_root(a, (int64_t)idx * c);
-                    ws = tw4_root(a, (int64_t)step * c);
+                    const int64_t cs = okc ? c : tl.c0;   // padding lines: in-range tables
+                    w = tw4_root(a, (int64_t)idx * cs);
+                    ws = tw4_root(a, (int64_t)step * cs);
                 }
             }
             constexpr int CH = (KIND & K_EXT) ? ext_chunk<T>() : KMAX;

@@ -30,7 +30,8 @@ def test_batched_4096_fp64_small_batch(sign):
 @pytest.mark.parametrize("n", [2, 3, 4, 5, 7, 8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096,
                                6, 9, 10, 12, 14, 15, 21, 25, 27, 30, 35, 49, 60, 100, 210, 243,
                                343, 1000, 2187, 2401, 3125, 18, 36, 45, 63, 90, 126, 150, 225,
-                               270, 441, 1008, 1050, 2025, 6144, 14175])
+                               270, 441, 1008, 1050, 2025, 6144, 14175,
+                               11, 13, 22, 26, 121, 143, 169, 1001, 2197, 2288, 3328])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_leaf_sizes(n, prec):
     b = max(1, min(37, 20000 // n))
@@ -45,21 +46,23 @@ def test_cooley_tukey_two_pass(n, prec):
     run_case([(n, 1, 1)], [(b, n, n)], sign=1, prec=prec, seed=n + 8, name=f"ct {n} inv")
 
 
-@pytest.mark.parametrize("n", [11, 13, 17, 29, 97, 113, 127, 193, 257, 1009, 2017])
+@pytest.mark.parametrize("n", [11, 13, 17, 29, 97, 113, 127, 193, 257, 1009, 2017,
+                               23, 53, 79, 157, 859])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_rader_single_kernel(n, prec):
     run_case([(n, 1, 1)], [(5, n, n)], sign=-1, prec=prec, seed=n, name=f"rader {n}")
     run_case([(n, 1, 1)], [(5, n, n)], sign=1, prec=prec, seed=n + 1, name=f"rader {n} inv")
 
 
-@pytest.mark.parametrize("n", [23, 67, 89, 683, 1013, 2039])
+@pytest.mark.parametrize("n", [47, 59, 83, 683, 1013, 2039])   # p - 1 not 13-smooth
 @pytest.mark.parametrize("prec", [0, 1])
 def test_bluestein_single_kernel(n, prec):
     run_case([(n, 1, 1)], [(5, n, n)], sign=-1, prec=prec, seed=n, name=f"bluestein {n}")
     run_case([(n, 1, 1)], [(5, n, n)], sign=1, prec=prec, seed=n + 1, name=f"bluestein {n} inv")
 
 
-@pytest.mark.parametrize("n,prec", [(65537, 0), (65537, 1), (12289, 0), (65521, 0), (8191, 1)])
+@pytest.mark.parametrize("n,prec", [(65537, 0), (65537, 1), (12289, 0), (65521, 0), (8191, 1),
+                                    (8009, 1), (5281, 0), (65519, 0)])
 def test_prime_multi_pass(n, prec):
     run_case([(n, 1, 1)], [(2, n, n)], sign=-1, prec=prec, seed=n, name=f"prime {n}")
     run_case([(n, 1, 1)], [(2, n, n)], sign=1, prec=prec, seed=n + 1, name=f"prime {n} inv")
