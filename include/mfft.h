@@ -134,17 +134,21 @@ int mfft_plan_dft(mfft_plan *out, int rank, const mfft_iodim *dims, int howmany_
 /*
  * Real-data transforms.  A DFT of real input is conjugate symmetric,
  * Y[n-k] = conj(Y[k]), so outputs 0 .. n/2 determine it (the real-data case
- * Sections 5 and 7 single out: about half the work).  rank must be 1
- * (MFFT_ENOTSUP otherwise); dims[0].n = n is the real length.
- *   mfft_plan_dft_r2c: forward (sign -1) DFT of n real inputs (stride
- *     dims[0].is in real elements of the precision) to n/2+1 complex outputs
- *     (stride dims[0].os in complex elements).  howmany dims: is in real, os in
- *     complex elements.
- *   mfft_plan_dft_c2r: the unnormalized inverse (sign +1): n/2+1 complex inputs
- *     (dims[0].is, complex elements; the imaginary parts of bins 0 and n/2,
- *     zero for a conjugate-symmetric spectrum, are ignored) to n real outputs
- *     (dims[0].os, real elements).  howmany dims: is complex, os real.
- * c2r(r2c(x)) = n x.  inplace = 1: input and output share one buffer (the plan
+ * Sections 5 and 7 single out: about half the work).  rank 1 .. 8; the LAST
+ * dimension, dims[rank-1] with n real points, is the one halved (n/2+1
+ * complex values); the other dimensions keep their length.  Below, "the
+ * dimension" is dims[rank-1]; the other dims and the howmany dims take strides
+ * in the same units as it on each side.
+ *   mfft_plan_dft_r2c: forward (sign -1) DFT of real inputs (input strides
+ *     in real elements of the precision) to complex outputs (output strides in
+ *     complex elements).
+ *   mfft_plan_dft_c2r: the unnormalized inverse (sign +1) from the half
+ *     spectrum (input strides in complex elements; along the halved dimension
+ *     the imaginary parts of bins 0 and n/2, zero for a conjugate-symmetric
+ *     spectrum, are ignored; for rank > 1 the input must be such a spectrum)
+ *     to real outputs (output strides in real elements).
+ * c2r(r2c(x)) = N x (N = product of the lengths).  inplace = 1: input and
+ * output share one buffer (the plan
  * reads the input completely before writing).  Real buffers must be aligned
  * to the complex element size like complex ones.  Even n with unit real
  * stride and even real vector strides runs a complex DFT of length n/2 plus

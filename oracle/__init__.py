@@ -16,7 +16,8 @@ Functions follow Johnson & Frigo, "Implementing FFTs in Practice":
   * ``root`` -- exp(sign 2 pi i m / n) from the oracle's own octant-reduced table;
   * ``rfft`` / ``irfft`` -- real-input DFTs (the conjugate-symmetric case of
     eq. dft that Sections 5 and 7 single out): the forward DFT of real data keeping
-    outputs 0 .. n//2, and its unnormalized inverse from such a half spectrum.
+    outputs 0 .. n//2, and its unnormalized inverse from such a half spectrum;
+    ``rfftn`` / ``irfftn`` the same over the trailing axes, the last one halved.
 """
 from __future__ import annotations
 
@@ -223,3 +224,26 @@ def irfft(y, n: int, nthreads: int | None = None) -> np.ndarray:
     k = np.arange(h, n)
     full[..., h:] = np.conj(y[..., n - k])
     return fft(full, sign=+1, nthreads=nthreads).real
+
+
+def rfftn(x, ndim: int, nthreads: int | None = None) -> np.ndarray:
+    """Multi-dimensional forward DFT of real data over the trailing ``ndim`` axes
+    (the separable product of eq. dft), keeping indices 0 .. n//2 of the last axis."""
+    x = np.asarray(x, np.float64)
+    n = x.shape[-1]
+    y = fftn(x.astype(np.complex128), ndim, sign=-1, nthreads=nthreads)
+    return y[..., : n // 2 + 1]
+
+
+def irfftn(y, shape, nthreads: int | None = None) -> np.ndarray:
+    """Inverse of ``rfftn`` without normalization over the trailing axes of real
+    lengths ``shape``: sign +1 DFTs along all but the last axis, then ``irfft``
+    along the last (whose bins 0 and n/2 keep only their real parts)."""
+    y = np.asarray(y, np.complex128)
+    z = y
+    if len(shape) > 1:
+        # move the halved axis out of the way, transform the others, move it back
+        z = np.moveaxis(z, -1, 0)
+        z = fftn(z, len(shape) - 1, sign=+1, nthreads=nthreads)
+        z = np.moveaxis(z, 0, -1)
+    return irfft(z, shape[-1], nthreads=nthreads)

@@ -242,8 +242,9 @@ int mfft_plan_info(mfft_plan plan, mfft_plan_info_t *info)
     if (p->prob.kind != 0) {
         // real data: half the nominal flops; n reals one way, n/2+1 complex the other
         info->flops *= 0.5;
+        const int64_t nl = p->prob.N.back().n;
         info->bytes_compulsory =
-            (eb / 2 * N + eb * (double)(p->prob.N[0].n / 2 + 1)) * (double)info->howmany;
+            (eb / 2 * N + eb * N / (double)nl * (double)(nl / 2 + 1)) * (double)info->howmany;
     }
     info->bytes_passes = p->bytes_passes;
     info->scratch_bytes = p->scratch_bytes;

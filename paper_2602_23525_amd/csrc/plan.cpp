@@ -1026,21 +1026,21 @@ static int add_real_pass(Builder &b, int mode, int64_t n, int64_t cnt, int64_t i
 // DIT step of eq. ct).  Otherwise the real data is widened to complex, a
 // length-n complex DFT runs, and the half spectrum (or real part) is kept.
 // The inverse is the sign +1 transform, by conjugation like complex plans.
-static int build_real_plan(PlanImpl *p)
+//
+// One real dimension d (is, os in the units of each side) over vector loops V,
+// from buffer src (offset in complex elements) to dst; `same_buf` when src and
+// dst are one buffer (in place).
+static int plan_real_line(Builder &b, bool fwd, Dim d, const std::vector<Dim> &V, int src,
+                          int64_t src_off, int dst, int64_t dst_off, bool same_buf)
 {
-    Builder b;
-    b.p = p;
-    const Problem &pr = p->prob;
-    p->passes.clear();
-    if (pr.empty) return MFFT_OK;
-    const int prec = pr.prec;
+    PlanImpl *p = b.p;
+    const int prec = p->prob.prec;
     const int eb = elem_bytes(prec);
-    const Dim d = pr.N[0];
-    const int64_t n = d.n, H = pr.howmany;
-    const int dst = pr.inplace ? BUF_IN : BUF_OUT;
-    const bool fwd = pr.kind == 1;
+    const int64_t n = d.n;
+    int64_t H = 1;
+    for (const Dim &v : V) H *= v.n;
     bool pack = n % 2 == 0 && (fwd ? d.is == 1 : d.os == 1);
-    for (const Dim &v : pr.V) pack &= (fwd ? v.is : v.os) % 2 == 0;
+    for (const Dim &v : V) pack &= (fwd ? v.is : v.os) % 2 == 0;
     if (pack) {
         const int64_t h = n / 2;
         void *tw = table_alloc(p, (size_t)(h / 2 + 1) * eb);
@@ -1048,18 +1048,17 @@ static int build_real_plan(PlanImpl *p)
         hipError_t e = launch_gen_roots(tw, prec, h / 2 + 1, n, p->stream);
         if (e != hipSuccess) return fail(MFFT_EHIP, std::string("twiddle kernel: ") + hipGetErrorString(e));
         // the real side viewed as complex: vector strides halve
-        std::vector<Dim> Vc = pr.V;
+        std::vector<Dim> Vc = V;
         for (Dim &v : Vc) (fwd ? v.is : v.os) /= 2;
         // one pass when the half-length transform is a specialized leaf: the
         // split (or combine) runs in its store (load) through LDS.  In place
         // only when each real row starts where its complex row does.
         bool same_rows = true;
-        for (const Dim &v : pr.V) same_rows &= fwd ? v.is == 2 * v.os : v.os == 2 * v.is;
-        if (leaf_supported(prec, h) && (fwd ? d.os == 1 : d.is == 1) &&
-            (!pr.inplace || same_rows)) {
+        for (const Dim &v : V) same_rows &= fwd ? v.is == 2 * v.os : v.os == 2 * v.is;
+        if (leaf_supported(prec, h) && (fwd ? d.os == 1 : d.is == 1) && (!same_buf || same_rows)) {
             const size_t before = p->passes.size();
             const int64_t top = b.scratch_top, hi = b.scratch_hi;
-            int rc = plan_line(b, Dim{h, 1, 1}, Vc, BUF_IN, dst, 0, 0, !fwd, !fwd);
+            int rc = plan_line(b, Dim{h, 1, 1}, Vc, src, dst, src_off, dst_off, !fwd, !fwd);
             if (rc) return rc;
             if (p->passes.size() == before + 1 && p->passes.back().kernel == 1) {
                 Pass &ps = p->passes.back();
@@ -1067,7 +1066,6 @@ static int build_real_plan(PlanImpl *p)
                 ps.a.post = tw;
                 if (!fwd) ps.variant &= ~1;   // the combine replaces the prefetch
                 ps.desc += fwd ? " +split" : " +combine";
-                p->scratch_bytes = (size_t)b.scratch_hi;
                 return MFFT_OK;
             }
             p->passes.resize(before);
@@ -1076,65 +1074,122 @@ static int build_real_plan(PlanImpl *p)
         }
         const int64_t off = b.scratch_take(H * h * eb) / eb;
         if (fwd) {
-            int src = BUF_IN;
-            int64_t src_off = 0;
-            std::vector<Dim> Vu = packed(pr.V, h, 0);   // untangle reads packed Z
-            int64_t zis = 1;
+            int zsrc = src;
+            int64_t zoff = src_off;
+            std::vector<Dim> Vu = packed(V, h, 0);   // untangle reads packed Z
             if (h > 1) {
-                int rc = plan_line(b, Dim{h, 1, 1}, packed(Vc, h, 1), BUF_IN, BUF_SCRATCH, 0, off,
+                int rc = plan_line(b, Dim{h, 1, 1}, packed(Vc, h, 1), src, BUF_SCRATCH, src_off, off,
                                    false, false);
                 if (rc) return rc;
-                src = BUF_SCRATCH;
-                src_off = off;
+                zsrc = BUF_SCRATCH;
+                zoff = off;
             } else {
                 for (size_t i = 0; i < Vu.size(); ++i) Vu[i].is = Vc[i].is;
             }
-            int rc = add_real_pass(b, RK_UNTANGLE, n, h / 2 + 1, zis, d.os, Vu, src, src_off, dst, 0,
-                                   tw, "untangle");
-            if (rc) return rc;
-        } else {
-            int rc = add_real_pass(b, RK_TANGLE, n, h / 2 + 1, d.is, 1, packed(pr.V, h, 1), BUF_IN, 0,
-                                   BUF_SCRATCH, off, tw, "tangle");
-            if (rc) return rc;
-            std::vector<Dim> Vi = packed(Vc, h, 0);
-            if (h > 1) {
-                rc = plan_line(b, Dim{h, 1, 1}, Vi, BUF_SCRATCH, dst, off, 0, true, true);
-            } else {
-                std::vector<Dim> all = Vi;
-                all.push_back({1, 1, 1});
-                rc = add_copy_pass(b, all, BUF_SCRATCH, dst, off, 0, "copy");
-            }
+            return add_real_pass(b, RK_UNTANGLE, n, h / 2 + 1, 1, d.os, Vu, zsrc, zoff, dst, dst_off,
+                                 tw, "untangle");
+        }
+        int rc = add_real_pass(b, RK_TANGLE, n, h / 2 + 1, d.is, 1, packed(V, h, 1), src, src_off,
+                               BUF_SCRATCH, off, tw, "tangle");
+        if (rc) return rc;
+        std::vector<Dim> Vi = packed(Vc, h, 0);
+        if (h > 1) return plan_line(b, Dim{h, 1, 1}, Vi, BUF_SCRATCH, dst, off, dst_off, true, true);
+        std::vector<Dim> all = Vi;
+        all.push_back({1, 1, 1});
+        return add_copy_pass(b, all, BUF_SCRATCH, dst, off, dst_off, "copy");
+    }
+    const int64_t o0 = b.scratch_take(H * n * eb) / eb;
+    const int64_t o1 = n > 1 ? b.scratch_take(H * n * eb) / eb : o0;
+    std::vector<Dim> Vp = packed(packed(V, n, 0), n, 1);
+    if (fwd) {
+        int rc = add_real_pass(b, RK_WIDEN, n, n, d.is, 1, packed(V, n, 1), src, src_off,
+                               BUF_SCRATCH, o0, nullptr, "widen");
+        if (rc) return rc;
+        if (n > 1) {
+            rc = plan_line(b, Dim{n, 1, 1}, Vp, BUF_SCRATCH, BUF_SCRATCH, o0, o1, false, false);
             if (rc) return rc;
         }
+        std::vector<Dim> all = packed(V, n, 0);
+        all.push_back({n / 2 + 1, 1, d.os});
+        return add_copy_pass(b, all, BUF_SCRATCH, dst, o1, dst_off, "half spectrum");
+    }
+    int rc = add_real_pass(b, RK_HERM, n, n, d.is, 1, packed(V, n, 1), src, src_off, BUF_SCRATCH,
+                           o0, nullptr, "symmetric extension");
+    if (rc) return rc;
+    if (n > 1) {
+        rc = plan_line(b, Dim{n, 1, 1}, Vp, BUF_SCRATCH, BUF_SCRATCH, o0, o1, true, true);
+        if (rc) return rc;
+    }
+    return add_real_pass(b, RK_REAL, n, n, 1, d.os, packed(V, n, 0), BUF_SCRATCH, o1, dst, dst_off,
+                         nullptr, "real part");
+}
+
+// Rank-r real transforms (the last dimension is the halved one): forward, the
+// real step along the last dimension (the others join the vector loops), then
+// complex steps along the others in place on the output; inverse, complex
+// steps along the others from the input into packed scratch (the input is
+// not modified), then the real step into the output.
+static int build_real_plan(PlanImpl *p)
+{
+    Builder b;
+    b.p = p;
+    const Problem &pr = p->prob;
+    p->passes.clear();
+    if (pr.empty) return MFFT_OK;
+    const int eb = elem_bytes(pr.prec);
+    const bool fwd = pr.kind == 1;
+    const int dst = pr.inplace ? BUF_IN : BUF_OUT;
+    const Dim d = pr.N.back();
+    const int64_t hc = d.n / 2 + 1;   // complex points along the halved dimension
+    std::vector<Dim> others(pr.N.begin(), pr.N.end() - 1);
+    std::vector<Dim> V1 = pr.V;
+    V1.insert(V1.end(), others.begin(), others.end());
+    int rc = MFFT_OK;
+    if (fwd) {
+        rc = plan_real_line(b, true, d, V1, BUF_IN, 0, dst, 0, pr.inplace);
+        for (size_t j = 0; j < others.size() && rc == MFFT_OK; ++j) {
+            std::vector<Dim> Vj = copy_o(pr.V);
+            for (size_t k = 0; k < others.size(); ++k)
+                if (k != j) Vj.push_back({others[k].n, others[k].os, others[k].os});
+            Vj.push_back({hc, d.os, d.os});
+            rc = plan_line(b, Dim{others[j].n, others[j].os, others[j].os}, Vj, dst, dst, 0, 0,
+                           false, false);
+        }
+    } else if (others.empty()) {
+        rc = plan_real_line(b, false, d, pr.V, BUF_IN, 0, dst, 0, pr.inplace);
     } else {
-        const int64_t o0 = b.scratch_take(H * n * eb) / eb;
-        const int64_t o1 = n > 1 ? b.scratch_take(H * n * eb) / eb : o0;
-        std::vector<Dim> Vp = packed(packed(pr.V, n, 0), n, 1);
-        if (fwd) {
-            int rc = add_real_pass(b, RK_WIDEN, n, n, d.is, 1, packed(pr.V, n, 1), BUF_IN, 0,
-                                   BUF_SCRATCH, o0, nullptr, "widen");
-            if (rc) return rc;
-            if (n > 1) {
-                rc = plan_line(b, Dim{n, 1, 1}, Vp, BUF_SCRATCH, BUF_SCRATCH, o0, o1, false, false);
-                if (rc) return rc;
+        // complex half-spectrum tensor in packed scratch: [V..., others..., hc]
+        std::vector<Dim> all = pr.V;
+        all.insert(all.end(), others.begin(), others.end());
+        all.push_back({hc, d.is, d.is});
+        const std::vector<Dim> pk = packed(all, 1, 1);   // os: packed strides
+        int64_t total = 1;
+        for (const Dim &x : all) total *= x.n;
+        const int64_t S = b.scratch_take(total * eb) / eb;
+        const size_t nv = pr.V.size();
+        for (size_t j = 0; j < others.size() && rc == MFFT_OK; ++j) {
+            const bool first = j == 0;
+            std::vector<Dim> Vj;
+            for (size_t i = 0; i < all.size(); ++i) {
+                if (i == nv + j) continue;
+                const int64_t is = first ? all[i].is : pk[i].os;
+                Vj.push_back({all[i].n, is, pk[i].os});
             }
-            std::vector<Dim> all = packed(pr.V, n, 0);
-            all.push_back({n / 2 + 1, 1, d.os});
-            rc = add_copy_pass(b, all, BUF_SCRATCH, dst, o1, 0, "half spectrum");
-            if (rc) return rc;
-        } else {
-            int rc = add_real_pass(b, RK_HERM, n, n, d.is, 1, packed(pr.V, n, 1), BUF_IN, 0,
-                                   BUF_SCRATCH, o0, nullptr, "symmetric extension");
-            if (rc) return rc;
-            if (n > 1) {
-                rc = plan_line(b, Dim{n, 1, 1}, Vp, BUF_SCRATCH, BUF_SCRATCH, o0, o1, true, true);
-                if (rc) return rc;
+            const Dim dj{others[j].n, first ? others[j].is : pk[nv + j].os, pk[nv + j].os};
+            rc = plan_line(b, dj, Vj, first ? BUF_IN : BUF_SCRATCH, BUF_SCRATCH, first ? 0 : S, S,
+                           true, true);
+        }
+        if (rc == MFFT_OK) {
+            // the real step reads the packed scratch, writes the user's layout
+            std::vector<Dim> Vr;
+            for (size_t i = 0; i + 1 < all.size(); ++i) {
+                const Dim &u = i < nv ? pr.V[i] : others[i - nv];
+                Vr.push_back({u.n, pk[i].os, u.os});
             }
-            rc = add_real_pass(b, RK_REAL, n, n, 1, d.os, packed(pr.V, n, 0), BUF_SCRATCH, o1, dst, 0,
-                               nullptr, "real part");
-            if (rc) return rc;
+            rc = plan_real_line(b, false, Dim{d.n, 1, d.os}, Vr, BUF_SCRATCH, S, dst, 0, false);
         }
     }
+    if (rc) return rc;
     p->scratch_bytes = (size_t)b.scratch_hi;
     return MFFT_OK;
 }

@@ -167,35 +167,44 @@ int canonicalize_real(int kind, int rank, const mfft_iodim *dims, int howmany_ra
                       const mfft_iodim *hdims, int inplace, int prec, Problem *out)
 {
     if (kind != 1 && kind != 2) return fail(MFFT_EINVAL, "unknown real transform kind");
-    if (rank < 0 || rank > 8) return fail(MFFT_EINVAL, "rank must be in [0, 8]");
-    if (rank != 1) return fail(MFFT_ENOTSUP, "real-data transforms are planned for rank 1");
+    if (rank < 1 || rank > 8) return fail(MFFT_EINVAL, "real transforms need rank in [1, 8]");
     if (!dims) return fail(MFFT_EINVAL, "dims is NULL");
     // the vector loops alone: validated, merged and ordered as for complex data
     Problem p;
     int rc = canonicalize(0, nullptr, howmany_rank, hdims, inplace, kind == 1 ? -1 : 1, prec, &p);
     if (rc) return rc;
-    const mfft_iodim d = dims[0];
-    if (d.n < 0) return fail(MFFT_EINVAL, "negative length");
-    if (d.n > ((int64_t)1 << 40)) return fail(MFFT_EINVAL, "length too large");
     p.kind = kind;
-    if (d.n == 0) p.empty = true;
+    std::vector<Dim> N;
+    for (int i = 0; i < rank; ++i) {
+        const mfft_iodim &d = dims[i];
+        if (d.n < 0) return fail(MFFT_EINVAL, "negative length");
+        if (d.n > ((int64_t)1 << 40)) return fail(MFFT_EINVAL, "length too large");
+        if (d.n == 0) p.empty = true;
+        if (mul_overflows(d.n, d.is) || mul_overflows(d.n, d.os))
+            return fail(MFFT_EINVAL, "stride * length overflows");
+        N.push_back({d.n, d.is, d.os});
+    }
     if (p.empty) {
         *out = p;
         return MFFT_OK;
     }
-    if (mul_overflows(d.n, d.is) || mul_overflows(d.n, d.os))
-        return fail(MFFT_EINVAL, "stride * length overflows");
-    // outputs: n/2+1 complex values (forward) or n real values (inverse) per line
-    const int64_t nout = kind == 1 ? d.n / 2 + 1 : d.n;
+    // outputs: the last dimension holds n/2+1 complex values (forward) or n real
+    // values (inverse); the others their full length
     std::vector<Dim> all = p.V;
-    all.push_back({nout, d.is, d.os});
-    __int128 tot = nout;
+    __int128 tot = 1;
     for (const Dim &v : p.V) tot *= v.n;
+    for (int i = 0; i < rank; ++i) {
+        Dim x = N[i];
+        if (i == rank - 1 && kind == 1) x.n = x.n / 2 + 1;
+        all.push_back(x);
+        tot *= x.n;
+    }
     if (tot > ((__int128)1 << 40)) return fail(MFFT_EINVAL, "problem has more than 2^40 elements");
     if (!outputs_injective(all))
         return fail(MFFT_EINVAL, "two output elements share one address (aliasing output strides)");
-    p.N = {{d.n, d.is, d.os}};
-    p.n_total = d.n;
+    p.N = N;
+    p.n_total = 1;
+    for (const Dim &d : N) p.n_total *= d.n;
     *out = p;
     return MFFT_OK;
 }

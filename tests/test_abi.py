@@ -97,7 +97,9 @@ def test_wisdom_roundtrip_text():
     ("r2c", [(16, 1, 1)], [(4, 16, 9)], 0, 0, 0),
     ("c2r", [(16, 1, 1)], [(4, 9, 16)], 0, 1, 0),
     ("r2c", [(17, 1, 1)], [], 0, 0, 0),
-    ("r2c", [(8, 1, 1), (8, 8, 5)], [], 0, 0, -2),        # rank 2: not planned
+    ("r2c", [(8, 5, 5), (8, 1, 1)], [], 0, 0, 0),         # rank 2, last dim halved
+    ("r2c", [(8, 5, 4), (8, 1, 1)], [], 0, 0, -1),        # 5 outputs per row at distance 4
+    ("c2r", [], [], 0, 0, -1),                            # rank 0
     ("r2c", [(16, 1, 1)], [(4, 16, 4)], 0, 0, -1),        # 9 outputs per row at distance 4 alias
     ("c2r", [(16, 1, 1)], [(4, 9, 8)], 0, 0, -1),         # 16 real outputs at distance 8 alias
     ("r2c", [(-1, 1, 1)], [], 0, 0, -1),

@@ -204,3 +204,78 @@ def test_real_plans_in_a_batch():
     bt.destroy()
     for p in plans:
         p.destroy()
+
+
+def _row_major(shape):
+    st, s = [], 1
+    for n in reversed(shape):
+        st.append(s)
+        s *= n
+    return list(reversed(st)), s
+
+
+@pytest.mark.parametrize("shape", [(16, 32), (12, 10), (8, 6, 10), (3, 17), (256, 256),
+                                   (32, 8192), (5, 7, 9)])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_multidim(shape, prec):
+    """Rank > 1: the last dimension halved (n/2+1 complex values), the others
+    full; r2c against the oracle's rfftn, c2r of arbitrary half spectra
+    against its irfftn (inverse along the leading axes, then the real inverse)."""
+    import torch
+
+    import paper_2602_23525_amd as mfft
+    b = 2
+    hshape = tuple(shape[:-1]) + (shape[-1] // 2 + 1,)
+    rs, rtot = _row_major(shape)
+    cs, ctot = _row_major(hshape)
+    cdt = np.complex64 if prec == 0 else np.complex128
+    # forward
+    x = _real_seq(b * rtot, 40 + len(shape), prec)
+    dims = [(n, rs[i], cs[i]) for i, n in enumerate(shape)]
+    p = mfft.Plan(dims, [(b, rtot, ctot)], prec=prec, kind="r2c")
+    yt = torch.full((b * ctot,), float("nan"), dtype=torch.complex64 if prec == 0 else
+                    torch.complex128, device="cuda")
+    p.execute(_dev(x), yt)
+    torch.cuda.synchronize()
+    p.destroy()
+    ref = oracle.rfftn(x.astype(np.float64).reshape((b,) + shape), len(shape))
+    assert oracle.rel_rms(yt.cpu().numpy().reshape(ref.shape).astype(np.complex128),
+                          ref) <= TOL[prec]
+    # inverse, from an arbitrary half spectrum (the input must stay intact)
+    X = uniform_complex(b * ctot, seed=50 + len(shape), dtype=cdt)
+    dims = [(n, cs[i], rs[i]) for i, n in enumerate(shape)]
+    q = mfft.Plan(dims, [(b, ctot, rtot)], prec=prec, kind="c2r")
+    Xt = _dev(X)
+    zt = torch.full((b * rtot,), float("nan"), dtype=torch.float32 if prec == 0 else
+                    torch.float64, device="cuda")
+    q.execute(Xt, zt)
+    torch.cuda.synchronize()
+    q.destroy()
+    assert np.array_equal(Xt.cpu().numpy(), X)
+    ref = oracle.irfftn(X.astype(np.complex128).reshape((b,) + hshape), shape)
+    assert oracle.rel_rms(zt.cpu().numpy().reshape(ref.shape).astype(np.float64),
+                          ref) <= TOL[prec]
+
+
+def test_multidim_in_place():
+    """FFTW's in-place layout: real rows padded to 2(n/2+1) values."""
+    import torch
+
+    import paper_2602_23525_amd as mfft
+    n0, n1 = 24, 40
+    hc = n1 // 2 + 1
+    x = _real_seq(n0 * n1, 61, 0).reshape(n0, n1)
+    buf = torch.zeros(n0 * 2 * hc, dtype=torch.float32, device="cuda")
+    buf.view(n0, 2 * hc)[:, :n1] = _dev(x)
+    f = mfft.Plan([(n0, 2 * hc, hc), (n1, 1, 1)], [], inplace=True, kind="r2c")
+    f.execute(buf, buf)
+    torch.cuda.synchronize()
+    y = buf.view(torch.complex64).cpu().numpy().reshape(n0, hc)
+    assert oracle.rel_rms(y.astype(np.complex128), oracle.rfftn(x.astype(np.float64), 2)) <= 2e-6
+    g = mfft.Plan([(n0, hc, 2 * hc), (n1, 1, 1)], [], inplace=True, kind="c2r")
+    g.execute(buf, buf)
+    torch.cuda.synchronize()
+    z = buf.cpu().numpy().reshape(n0, 2 * hc)[:, :n1] / (n0 * n1)
+    assert oracle.rel_rms(z.astype(np.float64), x.astype(np.float64)) <= 4e-6
+    f.destroy()
+    g.destroy()

@@ -60,3 +60,19 @@ def test_irfft_ignores_imaginary_parts_of_self_conjugate_bins(n):
     if n % 2 == 0:
         y2[-1] -= 0.25j
     assert np.array_equal(oracle.irfft(y, n), oracle.irfft(y2, n))
+
+
+@pytest.mark.parametrize("shape", [(4, 6), (3, 5, 8), (7, 9)])
+def test_multidim_matches_numpy(shape):
+    x = np.random.default_rng(len(shape)).uniform(-1, 1, (2,) + shape)
+    axes = tuple(range(1, len(shape) + 1))
+    y = oracle.rfftn(x, len(shape))
+    assert oracle.rel_rms(y, np.fft.rfftn(x, axes=axes)) < 1e-14
+    z = oracle.irfftn(y, shape)
+    assert np.allclose(z, np.prod(shape) * x, atol=1e-11 * np.prod(shape))
+    # the inverse of an arbitrary (non-symmetric) half spectrum follows numpy's
+    # convention: inverse DFTs along the leading axes, then the real inverse
+    w = (np.random.default_rng(5).uniform(-1, 1, y.shape)
+         + 1j * np.random.default_rng(6).uniform(-1, 1, y.shape))
+    ref = np.fft.irfftn(w, s=shape, axes=axes) * np.prod(shape)
+    assert np.allclose(oracle.irfftn(w, shape), ref, atol=1e-11 * np.prod(shape))
