@@ -69,9 +69,9 @@ bool leaf_supported(int prec, int64_t n)
     return n >= 64 && n <= leaf_max_n(prec) && (n & (n - 1)) == 0;
 }
 
-// variant bits: 0 prefetch; 1 occupancy floor of 3 waves per SIMD (else 2);
-// 3 non-temporal stores; 4 non-temporal loads (only together with stores).
-// Floors of 4 waves force spills at these sizes and are not built.
+// variant bits: 0 prefetch; 1-2 occupancy floor (1: 3 waves per SIMD, 2: 4,
+// else 2; FP32 only); 3 non-temporal stores; 4 non-temporal loads (only
+// together with stores).
 template <typename T, int THREADS, bool PF, int WPE>
 static int run_nt(int kind, const PassArgs &a, int n, int nt, int grid, hipStream_t s,
                   hipError_t *e)
@@ -85,6 +85,7 @@ template <typename T, int THREADS, bool PF>
 static int run_wpe(int kind, const PassArgs &a, int n, int w, int nt, int grid, hipStream_t s,
                    hipError_t *e)
 {
+    if (w == 2) return run_nt<T, THREADS, PF, 4>(kind, a, n, nt, grid, s, e);
     if (w & 1) return run_nt<T, THREADS, PF, 3>(kind, a, n, nt, grid, s, e);
     return run_nt<T, THREADS, PF, 2>(kind, a, n, nt, grid, s, e);
 }
@@ -92,18 +93,19 @@ static int run_wpe(int kind, const PassArgs &a, int n, int w, int nt, int grid, 
 static int run(int kind, const PassArgs &a, int prec, int n, int variant, int grid,
                hipStream_t s, hipError_t *e)
 {
-    // real-data fusions: one configuration each (prefetch with a persistent
-    // grid for the long FP32 lines, as the plain default)
+    // real-data fusions: one configuration each, non-temporal loads and
+    // stores as the plain default (prefetch only for FP32 r2c, where it pays
+    // with a persistent grid)
     if (a.flags & (PF_R2C | PF_C2R)) {
         const bool pf = variant & 1;
         if (a.flags & PF_R2C) {
             if (prec == 0)
-                return pf ? dispatch<float, 256, true, 2, 0, 1>(kind, a, n, grid, s, e)
-                          : dispatch<float, 256, false, 2, 0, 1>(kind, a, n, grid, s, e);
-            return dispatch<double, 128, false, 2, 0, 1>(kind, a, n, grid, s, e);
+                return pf ? dispatch<float, 256, true, 2, 3, 1>(kind, a, n, grid, s, e)
+                          : dispatch<float, 256, false, 2, 3, 1>(kind, a, n, grid, s, e);
+            return dispatch<double, 128, false, 2, 3, 1>(kind, a, n, grid, s, e);
         }
-        if (prec == 0) return dispatch<float, 256, false, 2, 0, 2>(kind, a, n, grid, s, e);
-        return dispatch<double, 128, false, 2, 0, 2>(kind, a, n, grid, s, e);
+        if (prec == 0) return dispatch<float, 256, false, 2, 3, 2>(kind, a, n, grid, s, e);
+        return dispatch<double, 128, false, 2, 3, 2>(kind, a, n, grid, s, e);
     }
     const bool pf = variant & 1;
     const int w = (variant >> 1) & 3, nt = (variant >> 3) & 3;

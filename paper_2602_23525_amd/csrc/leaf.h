@@ -76,6 +76,19 @@ __device__ __forceinline__ void expand_tw(const cpx<T> *pin, cpx<T> (&w)[R])
     }
 }
 
+// Padded LDS slot of element b + k*STEP, k < 16, as one address plus a
+// compile-time offset: for STEP a multiple of 16 the padded index grows by
+// STEP + STEP/16 per step, and for STEP 1 with b % 16 + 15 inside one block of
+// 16 (b a multiple of a radix dividing 16 and k below that radix) by 1, so the
+// compiler keeps one address register instead of one per element.
+template <int STEP, typename T>
+__device__ __forceinline__ cpx<T> *lds_slot(cpx<T> *line, int b, int k)
+{
+    if constexpr (STEP % 16 == 0) return line + lds_pad(b) + k * (STEP + STEP / 16);
+    else if constexpr (STEP == 1) return line + lds_pad(b) + k;
+    else return line + lds_pad(b + k * STEP);
+}
+
 // One stage on registers: x[i + k*NB] is element k of butterfly i.
 template <typename T, int N, int TPT, int NS, int R, bool LAST>
 __device__ __forceinline__ void fast_stage(cpx<T> (&x)[16], const StageTw<T, R> &tw, cpx<T> *line,
@@ -103,7 +116,7 @@ __device__ __forceinline__ void fast_stage(cpx<T> (&x)[16], const StageTw<T, R> 
             const int q = b >> ilog2c(NS);
             const int base = q * NS * R + j;
 #pragma unroll
-            for (int k = 0; k < R; ++k) line[lds_pad(base + k * NS)] = v[k];
+            for (int k = 0; k < R; ++k) *lds_slot<NS>(line, base, k) = v[k];
         }
     }
 }
@@ -122,7 +135,7 @@ struct StageChain {
         fast_stage<T, N, TPT, NS, R, false>(x, tw, line, t);
         __syncthreads();
 #pragma unroll
-        for (int e = 0; e < 16; ++e) x[e] = line[lds_pad(t + e * TPT)];
+        for (int e = 0; e < 16; ++e) x[e] = *lds_slot<TPT>(line, t, e);
         __syncthreads();
         next.run(x, line, t);
     }
@@ -140,6 +153,29 @@ struct StageChain<T, N, TPT, NS, R> {
         fast_stage<T, N, TPT, NS, R, true>(x, tw, line, t);
     }
 };
+
+// Global loads and stores of one element, non-temporal when the pass does
+// not reuse what it reads (NT bit 1) or writes (NT bit 0).
+template <int NT, typename T>
+__device__ __forceinline__ cpx<T> ld_elem(const cpx<T> *p)
+{
+    if constexpr (NT & 2) {
+        return {__builtin_nontemporal_load(&p->re), __builtin_nontemporal_load(&p->im)};
+    } else {
+        return *p;
+    }
+}
+
+template <int NT, typename T>
+__device__ __forceinline__ void st_elem(cpx<T> *p, cpx<T> v)
+{
+    if constexpr (NT & 1) {
+        __builtin_nontemporal_store(v.re, &p->re);
+        __builtin_nontemporal_store(v.im, &p->im);
+    } else {
+        *p = v;
+    }
+}
 
 // RD: 0 plain; 1 the line is the transform of a packed real sequence, split
 // into the n+1 outputs of the real transform on store (PF_R2C); 2 the line is
@@ -174,25 +210,16 @@ __global__ __launch_bounds__(BT *N / 16) __attribute__((amdgpu_waves_per_eu(WPE)
             bi += idx * a.ois[d];
             bo += idx * a.oos[d];
         }
+        // a padding line of a partial last tile reads the last line (its
+        // results are never stored), so that every load is unconditional
         *ok = c < a.vn;
-        *ib = bi + c * a.vis;
+        *ib = bi + (*ok ? c : a.vn - 1) * a.vis;
         *obs = bo + c * a.vos;
     };
-    auto load_line = [&](cpx<T>(&x)[16], int64_t ib, bool ok) {
+    auto load_line = [&](cpx<T>(&x)[16], int64_t ib) {
         const cpx<T> *src = (const cpx<T> *)a.in + ib;
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            if constexpr (NT & 2) {
-                if (ok) {
-                    x[e].re = __builtin_nontemporal_load(&src[t + e * TPT].re);
-                    x[e].im = __builtin_nontemporal_load(&src[t + e * TPT].im);
-                } else {
-                    x[e] = cpx<T>{T(0), T(0)};
-                }
-            } else {
-                x[e] = ok ? src[t + e * TPT] : cpx<T>{T(0), T(0)};
-            }
-        }
+        for (int e = 0; e < 16; ++e) x[e] = ld_elem<NT>(&src[t + e * TPT]);
     };
 
     // Real-data fusions (one line = the n-point complex transform of a packed
@@ -204,14 +231,10 @@ __global__ __launch_bounds__(BT *N / 16) __attribute__((amdgpu_waves_per_eu(WPE)
     const cpx<T> *rtw = (const cpx<T> *)a.post;   // w_2n^k, k <= n/2
     // half spectrum X (n+1 values from ib) -> packed Z' in LDS, lane t taking
     // the pairs (k, n-k); ends with a barrier
-    auto combine_half_spectrum = [&](int64_t ib, bool ok) {
+    auto combine_half_spectrum = [&](int64_t ib) {
         const cpx<T> *X = (const cpx<T> *)a.in + ib;
         for (int k = t; k <= N / 2; k += TPT) {
-            cpx<T> A = {T(0), T(0)}, B = A;
-            if (ok) {
-                A = X[k];
-                B = X[N - k];
-            }
+            const cpx<T> A = ld_elem<NT>(&X[k]), B = ld_elem<NT>(&X[N - k]);
             if (k == 0) {   // bins 0 and n of the real transform are real
                 line[0] = {A.re + B.re, A.re - B.re};
                 continue;
@@ -228,7 +251,7 @@ __global__ __launch_bounds__(BT *N / 16) __attribute__((amdgpu_waves_per_eu(WPE)
     // real transform at ob; ends with a barrier so the next tile may reuse LDS
     auto split_to_half_spectrum = [&](const cpx<T>(&z)[16], int64_t ob, bool ok) {
 #pragma unroll
-        for (int e = 0; e < 16; ++e) line[lds_pad(t + e * TPT)] = z[e];
+        for (int e = 0; e < 16; ++e) *lds_slot<TPT>(line, t, e) = z[e];
         __syncthreads();
         if (ok) {
             cpx<T> *X = (cpx<T> *)a.out + ob;
@@ -236,16 +259,16 @@ __global__ __launch_bounds__(BT *N / 16) __attribute__((amdgpu_waves_per_eu(WPE)
             for (int k = t; k <= N / 2; k += TPT) {
                 const cpx<T> A = line[lds_pad(k)];
                 if (k == 0) {
-                    X[0] = {A.re + A.im, T(0)};
-                    X[N] = {A.re - A.im, T(0)};
+                    st_elem<NT>(&X[0], {A.re + A.im, T(0)});
+                    st_elem<NT>(&X[N], {A.re - A.im, T(0)});
                     continue;
                 }
                 const cpx<T> B = line[lds_pad(N - k)];
                 const cpx<T> E = {half * (A.re + B.re), half * (A.im - B.im)};
                 const cpx<T> O = {half * (A.im + B.im), half * (B.re - A.re)};
                 const cpx<T> wO = cmul(rtw[k], O);
-                X[k] = {E.re + wO.re, E.im + wO.im};
-                if (2 * k != N) X[N - k] = {E.re - wO.re, wO.im - E.im};
+                st_elem<NT>(&X[k], {E.re + wO.re, E.im + wO.im});
+                if (2 * k != N) st_elem<NT>(&X[N - k], {E.re - wO.re, wO.im - E.im});
             }
         }
         __syncthreads();
@@ -258,7 +281,7 @@ __global__ __launch_bounds__(BT *N / 16) __attribute__((amdgpu_waves_per_eu(WPE)
     bool ok;
     line_base(tile, &ib, &ob, &ok);
     cpx<T> x[16];
-    if constexpr (!c2r) load_line(x, ib, ok);
+    if constexpr (!c2r) load_line(x, ib);
     for (;;) {
         const int64_t next = tile + G;
         int64_t ib2 = 0, ob2 = 0;
@@ -267,13 +290,13 @@ __global__ __launch_bounds__(BT *N / 16) __attribute__((amdgpu_waves_per_eu(WPE)
         if constexpr (PF) {
             if (next < a.ntiles && !c2r) {
                 line_base(next, &ib2, &ob2, &ok2);
-                load_line(xn, ib2, ok2);
+                load_line(xn, ib2);
             }
         }
         if constexpr (c2r) {
-            combine_half_spectrum(ib, ok);
+            combine_half_spectrum(ib);
 #pragma unroll
-            for (int e = 0; e < 16; ++e) x[e] = line[lds_pad(t + e * TPT)];
+            for (int e = 0; e < 16; ++e) x[e] = *lds_slot<TPT>(line, t, e);
             __syncthreads();   // the first stage overwrites the line
         }
         if (cin) {
@@ -286,15 +309,7 @@ __global__ __launch_bounds__(BT *N / 16) __attribute__((amdgpu_waves_per_eu(WPE)
         } else if (ok) {
             cpx<T> *dst = (cpx<T> *)a.out + ob;
 #pragma unroll
-            for (int e = 0; e < 16; ++e) {
-                const cpx<T> y = cout ? conj(x[e]) : x[e];
-                if constexpr (NT & 1) {
-                    __builtin_nontemporal_store(y.re, &dst[t + e * TPT].re);
-                    __builtin_nontemporal_store(y.im, &dst[t + e * TPT].im);
-                } else {
-                    dst[t + e * TPT] = y;
-                }
-            }
+            for (int e = 0; e < 16; ++e) st_elem<NT>(&dst[t + e * TPT], cout ? conj(x[e]) : x[e]);
         }
         if (next >= a.ntiles) break;
         // no barrier needed here: every LDS read of this tile came before the
@@ -313,7 +328,7 @@ __global__ __launch_bounds__(BT *N / 16) __attribute__((amdgpu_waves_per_eu(WPE)
         }
         if (!prefetched) {
             line_base(tile, &ib, &ob, &ok);
-            if constexpr (!c2r) load_line(x, ib, ok);
+            if constexpr (!c2r) load_line(x, ib);
         }
     }
 }

@@ -262,14 +262,12 @@ static int fill_leaf(PlanImpl *p, const Leaf &L, PassArgs *a,
 // ------------------------------------------------------------ leaf variants
 
 // Estimate-mode choice of the leaf kernel variant (measured on MI355X over
-// batched unit-stride transforms): small lines gain from non-temporal stores,
-// lines of 2048 points and more (FP32) from a persistent grid that keeps the
-// next tile's loads in flight.
-LeafTune leaf_default(int prec, int n)
+// batched unit-stride transforms of 64 to 4096 points, both precisions): one
+// tile per workgroup with non-temporal loads and stores (neither the input
+// nor the output of the pass is reused by it) is fastest at every length.
+LeafTune leaf_default(int, int)
 {
-    if (n <= 256) return {8, 0};
-    if (prec == 0 && n >= 2048) return {25, 1};
-    return {0, 0};
+    return {24, 0};
 }
 
 void apply_leaf_tune(Pass *ps, const LeafTune &t)

@@ -33,7 +33,7 @@ static void pass_extent(const Pass &ps, int which, int64_t *lo, int64_t *hi)
     *hi = h;
 }
 
-static const int kCandVariants[] = {0, 8, 9, 25, 1, 2};
+static const int kCandVariants[] = {24, 25, 29, 8, 9, 0};
 
 int measure_plan(PlanImpl *p)
 {

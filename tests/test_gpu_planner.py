@@ -120,3 +120,36 @@ def test_fp32_twiddle_ablation_is_less_accurate():
     print(f"relRMS FP64-generated twiddles {e64:.3e}, FP32-evaluated twiddles {e32:.3e}")
     assert e64 <= 2e-6 and e32 <= 1e-5
     assert e64 <= 1.05 * e32
+
+
+# Every specialized leaf kernel variant (prefetch, occupancy floor of 2, 3 or 4
+# waves, non-temporal access) and grid kind, forced through stored choices,
+# on batches that leave a partial last tile and, with the persistent grid,
+# give workgroups more than one tile.
+LEAF_VARIANTS = [0, 1, 3, 5, 8, 9, 11, 13, 24, 25, 27, 29]
+
+
+@pytest.mark.parametrize("n,b,prec", [(64, 1000, 0), (256, 999, 0), (1024, 1001, 0),
+                                      (2048, 1003, 0), (4096, 1100, 0), (512, 777, 1),
+                                      (4096, 1029, 1)])
+def test_every_leaf_variant(n, b, prec):
+    import paper_2602_23525_amd as mfft
+    cdt = np.complex64 if prec == 0 else np.complex128
+    x = uniform_complex(n * b, seed=n + b, dtype=cdt)
+    ref = oracle.fft(x.astype(np.complex128).reshape(b, n))
+    tol = 2e-6 if prec == 0 else 1e-13
+    mfft.mfft_wisdom_forget()
+    p = mfft.Plan([(n, 1, 1)], [(b, n, n)], prec=prec, flags=mfft.MEASURE)
+    key = mfft.mfft_wisdom_export().strip().split("\n")[1].split(" => ")[0]
+    p.destroy()
+    for v in LEAF_VARIANTS:
+        for pe in (0, 1):
+            mfft.mfft_wisdom_forget()
+            mfft.mfft_wisdom_import(f"mfft-wisdom 1 {mfft.mfft_version()}\n{key} => 0:v{v}p{pe}\n")
+            p = mfft.Plan([(n, 1, 1)], [(b, n, n)], prec=prec, flags=mfft.WISDOM_ONLY)
+            assert "choices from wisdom" in p.info()["desc"]
+            y = _run(p, x)
+            p.destroy()
+            err = oracle.rel_rms(y.reshape(b, n), ref)
+            assert err <= tol, (n, b, prec, v, pe, err)
+    mfft.mfft_wisdom_forget()
