@@ -230,20 +230,42 @@ __global__ __launch_bounds__(BT *N / 16) __attribute__((amdgpu_waves_per_eu(WPE)
     constexpr bool r2c = RD == 1, c2r = RD == 2;
     const cpx<T> *rtw = (const cpx<T> *)a.post;   // w_2n^k, k <= n/2
     // half spectrum X (n+1 values from ib) -> packed Z' in LDS, lane t taking
-    // the pairs (k, n-k); ends with a barrier
+    // the pairs (k, n-k), k = t + j*TPT <= n/2 (j <= 8); the loads of a group
+    // of JC pairs (all nine in FP32, two groups in FP64 to bound registers)
+    // are issued before their first use; ends with a barrier
+    constexpr int J = N / 2 / TPT + 1;
+    constexpr int JC = sizeof(T) == 4 ? J : (J + 1) / 2;
     auto combine_half_spectrum = [&](int64_t ib) {
         const cpx<T> *X = (const cpx<T> *)a.in + ib;
-        for (int k = t; k <= N / 2; k += TPT) {
-            const cpx<T> A = ld_elem<NT>(&X[k]), B = ld_elem<NT>(&X[N - k]);
-            if (k == 0) {   // bins 0 and n of the real transform are real
-                line[0] = {A.re + B.re, A.re - B.re};
-                continue;
+        // an opaque copy of the lane index keeps the compiler from hoisting
+        // the J table and line addresses out of the tile loop
+        int tq = t;
+        __asm__ volatile("" : "+v"(tq));
+#pragma unroll
+        for (int j0 = 0; j0 < J; j0 += JC) {
+            cpx<T> A[JC], B[JC], W[JC];
+#pragma unroll
+            for (int q = 0; q < JC; ++q) {
+                const int k = min(tq + (j0 + q) * TPT, N / 2);
+                A[q] = ld_elem<NT>(&X[k]);
+                B[q] = ld_elem<NT>(&X[N - k]);
+                W[q] = rtw[k];
             }
-            const cpx<T> P = {A.re + B.re, A.im - B.im}, M = {A.re - B.re, A.im + B.im};
-            const cpx<T> wM = cmul(conj(rtw[k]), M);
-            const cpx<T> iwM = {-wM.im, wM.re};
-            line[lds_pad(k)] = {P.re + iwM.re, P.im + iwM.im};
-            if (2 * k != N) line[lds_pad(N - k)] = {P.re - iwM.re, iwM.im - P.im};
+#pragma unroll
+            for (int q = 0; q < JC; ++q) {
+                const int k = t + (j0 + q) * TPT;
+                if (j0 + q >= J || k > N / 2) break;
+                if (k == 0) {   // bins 0 and n of the real transform are real
+                    line[0] = {A[q].re + B[q].re, A[q].re - B[q].re};
+                    continue;
+                }
+                const cpx<T> P = {A[q].re + B[q].re, A[q].im - B[q].im};
+                const cpx<T> M = {A[q].re - B[q].re, A[q].im + B[q].im};
+                const cpx<T> wM = cmul(conj(W[q]), M);
+                const cpx<T> iwM = {-wM.im, wM.re};
+                line[lds_pad(k)] = {P.re + iwM.re, P.im + iwM.im};
+                if (2 * k != N) line[lds_pad(N - k)] = {P.re - iwM.re, iwM.im - P.im};
+            }
         }
         __syncthreads();
     };
@@ -256,7 +278,12 @@ __global__ __launch_bounds__(BT *N / 16) __attribute__((amdgpu_waves_per_eu(WPE)
         if (ok) {
             cpx<T> *X = (cpx<T> *)a.out + ob;
             const T half = T(0.5);
-            for (int k = t; k <= N / 2; k += TPT) {
+            int tq = t;   // opaque, as in the combine
+            __asm__ volatile("" : "+v"(tq));
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                const int k = tq + j * TPT;
+                if (k > N / 2) break;
                 const cpx<T> A = line[lds_pad(k)];
                 if (k == 0) {
                     st_elem<NT>(&X[0], {A.re + A.im, T(0)});
