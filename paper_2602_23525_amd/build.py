@@ -17,8 +17,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmfft.so")
 
 SOURCES = [
-    "k_c32_k0.hip", "k_c32_k1.hip", "k_c32_k3.hip", "k_c64_k0.hip", "k_c64_k1.hip",
-    "k_c64_k3.hip",
+    "k_c32_k0.hip", "k_c32_k1.hip", "k_c32_k5.hip", "k_c32_k7.hip", "k_c64_k0.hip",
+    "k_c64_k1.hip", "k_c64_k5.hip", "k_c64_k7.hip",
     "k_leaf.hip", "kernels.hip", "problem.cpp", "plan.cpp", "tune.cpp", "api.cpp", "batch.cpp", "server.cpp",
 ]
 

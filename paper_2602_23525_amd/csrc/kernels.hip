@@ -254,19 +254,23 @@ static inline unsigned blocks_for(int64_t count, int threads)
     int batch_blocks_per_cu_##P##_k##K(int block, size_t lds);
 MFFT_VARIANT(c32, 0)
 MFFT_VARIANT(c32, 1)
-MFFT_VARIANT(c32, 3)
+MFFT_VARIANT(c32, 5)
+MFFT_VARIANT(c32, 7)
 MFFT_VARIANT(c64, 0)
 MFFT_VARIANT(c64, 1)
-MFFT_VARIANT(c64, 3)
+MFFT_VARIANT(c64, 5)
+MFFT_VARIANT(c64, 7)
 #undef MFFT_VARIANT
 
-// Kernel kind needed by a pass: 0 plain, 1 Cooley-Tukey twiddles, 3 all features.
+// Kernel kind needed by a pass (bits of tile.h's K_*): 0 plain, 1 Cooley-Tukey
+// twiddles, 5 in-kernel convolution (with twiddles), 7 all features.
 int pass_kind(uint32_t flags)
 {
-    const uint32_t ext = PF_PRE_MUL | PF_GATHER | PF_CONV | PF_CONJ_A | PF_POST_MUL |
-                         PF_SCATTER | PF_RADER | PF_AUX_X0 | PF_AUX_A0 | PF_AUX_ADD;
+    const uint32_t ext = PF_PRE_MUL | PF_GATHER | PF_CONJ_A | PF_POST_MUL | PF_SCATTER |
+                         PF_RADER | PF_AUX_X0 | PF_AUX_ADD;
     // PF_XCD only changes the tile order and is handled by every kind
-    if (flags & ext) return 3;
+    if (flags & ext) return 7;
+    if (flags & (PF_CONV | PF_AUX_A0)) return 5;
     if (flags & PF_TW4) return 1;
     return 0;
 }
@@ -280,11 +284,13 @@ hipError_t launch_pass(const PassArgs &a, int prec, int emax, size_t lds_bytes, 
     if (prec == 0) {
         if (k == 0) return launch_pass_c32_k0(a, lds_bytes, s);
         if (k == 1) return launch_pass_c32_k1(a, lds_bytes, s);
-        return launch_pass_c32_k3(a, lds_bytes, s);
+        if (k == 5) return launch_pass_c32_k5(a, lds_bytes, s);
+        return launch_pass_c32_k7(a, lds_bytes, s);
     }
     if (k == 0) return launch_pass_c64_k0(a, lds_bytes, s);
     if (k == 1) return launch_pass_c64_k1(a, lds_bytes, s);
-    return launch_pass_c64_k3(a, lds_bytes, s);
+    if (k == 5) return launch_pass_c64_k5(a, lds_bytes, s);
+    return launch_pass_c64_k7(a, lds_bytes, s);
 }
 
 int batch_blocks_per_cu(int prec, int kind, int block, size_t lds)
@@ -292,11 +298,13 @@ int batch_blocks_per_cu(int prec, int kind, int block, size_t lds)
     if (prec == 0) {
         if (kind == 0) return batch_blocks_per_cu_c32_k0(block, lds);
         if (kind == 1) return batch_blocks_per_cu_c32_k1(block, lds);
-        return batch_blocks_per_cu_c32_k3(block, lds);
+        if (kind == 5) return batch_blocks_per_cu_c32_k5(block, lds);
+        return batch_blocks_per_cu_c32_k7(block, lds);
     }
     if (kind == 0) return batch_blocks_per_cu_c64_k0(block, lds);
     if (kind == 1) return batch_blocks_per_cu_c64_k1(block, lds);
-    return batch_blocks_per_cu_c64_k3(block, lds);
+    if (kind == 5) return batch_blocks_per_cu_c64_k5(block, lds);
+    return batch_blocks_per_cu_c64_k7(block, lds);
 }
 
 hipError_t launch_batch(const PassArgs *items_dev, const int64_t *prefix_dev, int nitems,
@@ -306,11 +314,13 @@ hipError_t launch_batch(const PassArgs *items_dev, const int64_t *prefix_dev, in
     if (prec == 0) {
         if (kind == 0) return launch_batch_c32_k0(items_dev, prefix_dev, nitems, counter, block, grid, lds_bytes, s);
         if (kind == 1) return launch_batch_c32_k1(items_dev, prefix_dev, nitems, counter, block, grid, lds_bytes, s);
-        return launch_batch_c32_k3(items_dev, prefix_dev, nitems, counter, block, grid, lds_bytes, s);
+        if (kind == 5) return launch_batch_c32_k5(items_dev, prefix_dev, nitems, counter, block, grid, lds_bytes, s);
+        return launch_batch_c32_k7(items_dev, prefix_dev, nitems, counter, block, grid, lds_bytes, s);
     }
     if (kind == 0) return launch_batch_c64_k0(items_dev, prefix_dev, nitems, counter, block, grid, lds_bytes, s);
     if (kind == 1) return launch_batch_c64_k1(items_dev, prefix_dev, nitems, counter, block, grid, lds_bytes, s);
-    return launch_batch_c64_k3(items_dev, prefix_dev, nitems, counter, block, grid, lds_bytes, s);
+    if (kind == 5) return launch_batch_c64_k5(items_dev, prefix_dev, nitems, counter, block, grid, lds_bytes, s);
+    return launch_batch_c64_k7(items_dev, prefix_dev, nitems, counter, block, grid, lds_bytes, s);
 }
 
 // Contiguous copy, 16-byte vectors, four per thread: the rank-0 plan of a

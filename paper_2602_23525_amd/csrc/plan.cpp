@@ -621,6 +621,33 @@ static int rader_tables(Builder &b, int64_t pr, int32_t **gather, int32_t **scat
                         void **spec);
 static int bluestein_tables(Builder &b, int64_t n, int64_t M, void **chirp, void **spec);
 
+// The middle pass of a three-pass convolution reads spectrum entry k1 + k2*m1
+// for element k2 of line k1; consecutive lanes work on consecutive k2, so the
+// pass reads a copy stored line by line (k1*r1 + k2), one coalesced run per
+// line instead of one cache line per element.
+static int spectrum_by_line(Builder &b, const void *spec, int64_t m1, int64_t r1, void **out)
+{
+    PlanImpl *p = b.p;
+    const int eb = elem_bytes(p->prob.prec);
+    *out = table_alloc(p, (size_t)(m1 * r1) * eb);
+    if (!*out) return fail(MFFT_ENOMEM, "spectrum table allocation failed");
+    CopyArgs c{};
+    c.in = spec;
+    c.out = *out;
+    c.rank = 2;
+    c.elem_bytes = eb;
+    c.total = m1 * r1;
+    c.n[0] = m1;   // k1
+    c.is[0] = 1;
+    c.os[0] = r1;
+    c.n[1] = r1;   // k2
+    c.is[1] = m1;
+    c.os[1] = 1;
+    hipError_t e = launch_copy(c, p->stream);
+    if (e != hipSuccess) return fail(MFFT_EHIP, hipGetErrorString(e));
+    return MFFT_OK;
+}
+
 static int plan_rader(Builder &b, Dim d, const std::vector<Dim> &V, int src, int dst,
                       int64_t src_off, int64_t dst_off, bool conj_in, bool conj_out)
 {
@@ -698,9 +725,12 @@ static int plan_rader(Builder &b, Dim d, const std::vector<Dim> &V, int src, int
     B.dst = BUF_SCRATCH;
     B.dst_off = s1;
     B.flags = PF_CONV | PF_TW4 | PF_AUX_A0;
-    B.conv = spec;
-    B.conv_c = 1;
-    B.conv_k = m1;
+    void *spec_lines = nullptr;
+    rc = spectrum_by_line(b, spec, m1, r1, &spec_lines);
+    if (rc) return rc;
+    B.conv = spec_lines;
+    B.conv_c = r1;
+    B.conv_k = 1;
     B.tw4_N = L;
     B.aux_off = aux;
     rc = add_line_pass(b, B);
@@ -819,9 +849,12 @@ static int plan_bluestein(Builder &b, Dim d, const std::vector<Dim> &V, int src,
     B.dst = BUF_SCRATCH;
     B.dst_off = s1;
     B.flags = PF_CONV | PF_TW4;
-    B.conv = spec;
-    B.conv_c = 1;
-    B.conv_k = m1;
+    void *spec_lines = nullptr;
+    rc = spectrum_by_line(b, spec, m1, r1, &spec_lines);
+    if (rc) return rc;
+    B.conv = spec_lines;
+    B.conv_c = r1;
+    B.conv_k = 1;
     B.tw4_N = M;
     rc = add_line_pass(b, B);
     if (rc) return rc;

@@ -26,8 +26,10 @@ namespace mfft {
 // Feature sets compiled into separate kernels so that plain leaf passes carry
 // no code (or registers) for the fused plan steps they do not use.
 enum : int {
-    K_TW4 = 1,   // Cooley-Tukey twiddles on store
-    K_EXT = 2,   // pre/post multiplies, gather/scatter, in-kernel convolution, Rader
+    K_TW4 = 1,    // Cooley-Tukey twiddles on store
+    K_EXT = 2,    // table-driven loads and stores: pre/post multiplies, gather/scatter,
+                  // Rader's per-transform terms
+    K_CONV = 4,   // in-kernel convolution between two transforms of the line
 };
 
 // ------------------------------------------------------------ tile context
@@ -66,7 +68,7 @@ __device__ __forceinline__ cpx<T> mul_d(cpx<T> y, double2 w)
     return cmul(y, wt);
 }
 
-// Elements per chunk of the table-driven (K_EXT) loads and stores.
+// Elements per chunk of the table-driven (K_EXT) stores.
 template <typename T>
 constexpr int ext_chunk() { return sizeof(T) == 4 ? 3 : 4; }
 
@@ -134,8 +136,11 @@ __device__ __forceinline__ void load_line(const PassArgs &a, const Tile<T> &tl, 
     const bool cj = (a.flags & PF_CONJ_IN) != 0;
     cpx<T> r[KMAX];
     if constexpr (KIND & K_EXT) {
-        // in chunks of CH elements to bound the registers held by the tables
-        constexpr int CH = ext_chunk<T>();
+        // one chunk: every index load of the lane, then every element and
+        // table load, so that a gathered tile costs two memory round trips
+        // (the load phase has registers to spare; the store side, which runs
+        // inside the stages, keeps small chunks)
+        constexpr int CH = KMAX;
         const uint32_t f = a.flags;
         const int64_t cl = c * a.li_c;
 #pragma unroll
@@ -293,7 +298,7 @@ __device__ __forceinline__ void stage(const PassArgs &a, const StageDesc &sd, Ti
             }
         }
     }
-    if constexpr (KIND & K_EXT) {
+    if constexpr (KIND & K_CONV) {
         if (fetch == F_LDS_CONV) {
             // in-kernel convolution: element idx of line c times the spectrum
             // entry conv[c*conv_c + idx*conv_k], conjugated (inverse by conjugation)
@@ -442,15 +447,17 @@ __device__ __forceinline__ void tile_body(const PassArgs &a, Tile<T> &tl, cpx<T>
     const int last_emit = a.store_mode == kModeCol ? E_LDS : E_GLOBAL;
 
     bool conv = false;
-    if constexpr (KIND & K_EXT) conv = (f & PF_CONV) != 0;
+    if constexpr (KIND & K_CONV) conv = (f & PF_CONV) != 0;
     if (conv) {
         run_fft<T, EMAX, KIND>(a, tl, first_fetch, E_LDS);   // ends with a barrier
-        if (f & PF_RADER) {
-            // x0 and the zero-frequency term of the permuted sequence, read
-            // before the second transform overwrites the line
-            tl.x0 = slots[2 * tl.tr];
-            tl.a0 = tl.my[0];
-            if (tl.act && tl.t == 0) slots[2 * tl.tr + 1] = tl.a0;
+        if constexpr (KIND & K_EXT) {
+            if (f & PF_RADER) {
+                // x0 and the zero-frequency term of the permuted sequence, read
+                // before the second transform overwrites the line
+                tl.x0 = slots[2 * tl.tr];
+                tl.a0 = tl.my[0];
+                if (tl.act && tl.t == 0) slots[2 * tl.tr + 1] = tl.a0;
+            }
         }
         if ((f & PF_AUX_A0) && tl.act && tl.t == 0 && tl.c0 + tl.tr == 0)
             ((cpx<T> *)a.aux)[2 * tl.o + 1] = tl.my[0];   // zero frequency of line 0
