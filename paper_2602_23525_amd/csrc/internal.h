@@ -44,6 +44,8 @@ enum : uint32_t {
     PF_XCD = 1u << 13,       // map consecutive tiles to one XCD (L2 locality of gathers)
     PF_R2C = 1u << 14,       // leaf kernel: split the packed real transform on store (n+1 out)
     PF_C2R = 1u << 15,       // leaf kernel: combine a half spectrum on load (n+1 in)
+    PF_NT_IN = 1u << 16,     // generic kernel: non-temporal element loads
+    PF_NT_OUT = 1u << 17,    // generic kernel: non-temporal element stores
 };
 
 // Workgroups are dispatched round-robin over the chip's 8 XCDs, each with its

@@ -180,6 +180,9 @@ static int line_lds_stride(int n)
     return s | 1;
 }
 
+// Dynamic LDS requested by scattering passes: at most two workgroups per CU.
+constexpr size_t kScatterLdsBytes = 64 * 1024;
+
 static size_t tile_lds_bytes(int n, int bt, int prec)
 {
     return ((size_t)bt * line_lds_stride(n) + 2 * (size_t)bt) * elem_bytes(prec);
@@ -436,6 +439,14 @@ static int add_line_pass(Builder &b, const LineSpec &ls)
     a.ntiles_inner = (a.vn + bt - 1) / bt;
     a.ntiles = a.ntiles_inner * nouter_total;
     ps.lds_bytes = tile_lds_bytes(L.n, bt, prec);
+    if ((ls.flags & PF_SCATTER) && (ls.flags & PF_XCD)) {
+        // A scattering pass fills each cache line of its output from many
+        // tiles; lines written back before they are full cost a partial
+        // write each (measured: 5x the output bytes at 4 workgroups per CU).
+        // Two workgroups per CU keep the partially written output of the
+        // tiles in flight on one XCD near 2 MB, within its 4 MB L2.
+        ps.lds_bytes = std::max<size_t>(ps.lds_bytes, kScatterLdsBytes);
+    }
 
     a.is = ls.line.is;
     a.os = ls.line.os;
@@ -747,7 +758,8 @@ static int plan_rader(Builder &b, Dim d, const std::vector<Dim> &V, int src, int
     D.src_off = s1;
     D.dst = dst;
     D.dst_off = dst_off;
-    D.flags = PF_CONJ_A | PF_AUX_ADD | PF_SCATTER | PF_XCD | (conj_out ? PF_CONJ_OUT : 0);
+    D.flags = PF_CONJ_A | PF_AUX_ADD | PF_SCATTER | PF_XCD | PF_NT_IN |
+              (conj_out ? PF_CONJ_OUT : 0);
     D.scatter = sct;
     D.lo_c = 1;
     D.lo_k = r1;

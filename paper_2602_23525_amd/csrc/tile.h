@@ -68,6 +68,19 @@ __device__ __forceinline__ cpx<T> mul_d(cpx<T> y, double2 w)
     return cmul(y, wt);
 }
 
+// Element access that marks the data as not reused (PF_NT_IN / PF_NT_OUT).
+template <typename T>
+__device__ __forceinline__ cpx<T> ld_nt(const cpx<T> *p)
+{
+    return {__builtin_nontemporal_load(&p->re), __builtin_nontemporal_load(&p->im)};
+}
+template <typename T>
+__device__ __forceinline__ void st_nt(cpx<T> *p, cpx<T> v)
+{
+    __builtin_nontemporal_store(v.re, &p->re);
+    __builtin_nontemporal_store(v.im, &p->im);
+}
+
 // Elements per chunk of the table-driven (K_EXT) stores.
 template <typename T>
 constexpr int ext_chunk() { return sizeof(T) == 4 ? 3 : 4; }
@@ -87,10 +100,18 @@ __device__ __forceinline__ void issue_plain(const PassArgs &a, const Tile<T> &tl
                        (int64_t)idx0 * a.is;
     const int64_t pst = (int64_t)step * a.is;
     const cpx<T> *p = p0;
+    if (a.flags & PF_NT_IN) {
 #pragma unroll
-    for (int k = 0; k < KMAX; ++k) {
-        r[k] = *(idx0 + k * step < n ? p : p0);
-        p += pst;
+        for (int k = 0; k < KMAX; ++k) {
+            r[k] = ld_nt(idx0 + k * step < n ? p : p0);
+            p += pst;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) {
+            r[k] = *(idx0 + k * step < n ? p : p0);
+            p += pst;
+        }
     }
 }
 
@@ -160,8 +181,13 @@ __device__ __forceinline__ void load_line(const PassArgs &a, const Tile<T> &tl, 
 #pragma unroll
                 for (int q = 0; q < CH; ++q) e[q] = a.gather[li[q]];
             }
+            if (f & PF_NT_IN) {
 #pragma unroll
-            for (int q = 0; q < CH; ++q) r[q] = in[(int64_t)e[q] * a.is];
+                for (int q = 0; q < CH; ++q) r[q] = ld_nt(&in[(int64_t)e[q] * a.is]);
+            } else {
+#pragma unroll
+                for (int q = 0; q < CH; ++q) r[q] = in[(int64_t)e[q] * a.is];
+            }
             if (f & PF_PRE_MUL) {
 #pragma unroll
                 for (int q = 0; q < CH; ++q) pm[q] = ((const cpx<T> *)a.pre)[li[q]];
@@ -227,7 +253,8 @@ __device__ __forceinline__ void store_run(const PassArgs &a, const Tile<T> &tl, 
                 if (f & PF_POST_MUL) v = cmul(v, pm[q]);
                 if (f & (PF_RADER | PF_AUX_ADD)) v = cadd(v, tl.x0);
                 if (f & PF_CONJ_OUT) v = conj(v);
-                out[(int64_t)e[q] * a.os] = v;
+                if (f & PF_NT_OUT) st_nt(&out[(int64_t)e[q] * a.os], v);
+                else out[(int64_t)e[q] * a.os] = v;
                 if ((f & (PF_RADER | PF_AUX_ADD)) && lo[q] == 0) {
                     cpx<T> y0 = cadd(tl.x0, tl.a0);
                     if (f & PF_CONJ_OUT) y0 = conj(y0);
@@ -240,10 +267,18 @@ __device__ __forceinline__ void store_run(const PassArgs &a, const Tile<T> &tl, 
             const bool cj = (f & PF_CONJ_OUT) != 0;
             const int64_t pst = (int64_t)ks * a.os;
             cpx<T> *p = out + (int64_t)k0 * a.os;
+            if (f & PF_NT_OUT) {
 #pragma unroll
-            for (int m = 0; m < M; ++m) {
-                if (!CHECK || k0 + m * ks < n) *p = cj ? conj(y[m]) : y[m];
-                p += pst;
+                for (int m = 0; m < M; ++m) {
+                    if (!CHECK || k0 + m * ks < n) st_nt(p, cj ? conj(y[m]) : y[m]);
+                    p += pst;
+                }
+            } else {
+#pragma unroll
+                for (int m = 0; m < M; ++m) {
+                    if (!CHECK || k0 + m * ks < n) *p = cj ? conj(y[m]) : y[m];
+                    p += pst;
+                }
             }
         }
     }
