@@ -129,8 +129,9 @@ int plan_internal(mfft_plan *out, int rank, const mfft_iodim *dims, int howmany_
     for (const Pass &ps : p->passes) {
         d << "  " << ps.desc;
         if (ps.kernel == 1)
-            d << " [leaf kernel v" << ps.variant << (ps.persistent ? " persistent" : "")
-              << " grid=" << ps.grid << "]";
+            d << " [leaf kernel" << ((ps.a.flags & PF_LEAF_COL) ? " columns" : "") << " v"
+              << ps.variant << (ps.persistent ? " persistent" : "") << " grid=" << ps.grid
+              << "]";
         d << "\n";
         p->bytes_passes += ps.bytes;
     }

@@ -46,6 +46,7 @@ enum : uint32_t {
     PF_C2R = 1u << 15,       // leaf kernel: combine a half spectrum on load (n+1 in)
     PF_NT_IN = 1u << 16,     // generic kernel: non-temporal element loads
     PF_NT_OUT = 1u << 17,    // generic kernel: non-temporal element stores
+    PF_LEAF_COL = 1u << 18,  // leaf kernel: tile of adjacent lines with strided elements
 };
 
 // Workgroups are dispatched round-robin over the chip's 8 XCDs, each with its

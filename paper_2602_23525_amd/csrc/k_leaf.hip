@@ -56,6 +56,50 @@ static int dispatch(int kind, const PassArgs &a, int n, int grid, hipStream_t s,
     return 0;
 }
 
+// Column tiles (PF_LEAF_COL): BT adjacent lines, so that each load and store
+// instruction of a wave moves runs of BT elements: 64 lines of 64 points up
+// to 16 of 256 (FP32; half as many in FP64, same bytes), then 16 / 8 (FP32)
+// and 8 / 4 (FP64) lines as the LDS allows.  One tile per workgroup,
+// non-temporal loads and stores, as the row default.
+constexpr int col_lines(int prec, int n)
+{
+    if (prec == 0) return n <= 256 ? 4096 / n : (n <= 512 ? 16 : 8);
+    return n <= 256 ? 2048 / n : (n <= 512 ? 8 : 4);
+}
+
+template <typename T>
+static int dispatch_cols(int kind, const PassArgs &a, int n, int grid, hipStream_t s,
+                         hipError_t *err)
+{
+    constexpr int P = sizeof(T) == 4 ? 0 : 1;
+#define COL_CASE(N, ...)                                                                  \
+    case N:                                                                               \
+        if (kind == 1) return occ<T, N, col_lines(P, N), false, 2, 3, 3, __VA_ARGS__>();  \
+        *err = go<T, N, col_lines(P, N), false, 2, 3, 3, __VA_ARGS__>(a, grid, s);        \
+        return 0;
+    switch (n) {
+        COL_CASE(64, 16, 4)
+        COL_CASE(128, 16, 8)
+        COL_CASE(256, 16, 16)
+        COL_CASE(512, 16, 16, 2)
+        COL_CASE(1024, 16, 16, 4)
+        COL_CASE(2048, 16, 16, 8)
+    default:
+        break;
+    }
+#undef COL_CASE
+    *err = hipErrorInvalidValue;
+    return 0;
+}
+
+int leaf_col_lines_per_tile(int prec, int n) { return col_lines(prec, n); }
+
+bool leaf_col_supported(int prec, int64_t n)
+{
+    (void)prec;
+    return n >= 64 && n <= 2048 && (n & (n - 1)) == 0;
+}
+
 int leaf_max_n(int) { return 4096; }
 
 int leaf_lines_per_tile(int prec, int n)
@@ -93,6 +137,10 @@ static int run_wpe(int kind, const PassArgs &a, int n, int w, int nt, int grid, 
 static int run(int kind, const PassArgs &a, int prec, int n, int variant, int grid,
                hipStream_t s, hipError_t *e)
 {
+    if (a.flags & PF_LEAF_COL) {
+        return prec == 0 ? dispatch_cols<float>(kind, a, n, grid, s, e)
+                         : dispatch_cols<double>(kind, a, n, grid, s, e);
+    }
     // real-data fusions: one configuration each, non-temporal loads and
     // stores as the plain default (prefetch only for FP32 r2c, where it pays
     // with a persistent grid)

@@ -69,9 +69,13 @@ hipError_t launch_zero_u64(unsigned long long *p, int count, hipStream_t s);
 }  // namespace mfft
 
 namespace mfft {
-// Specialized power-of-two leaf kernel (leaf.h): unit-stride lines only.
+// Specialized power-of-two leaf kernel (leaf.h): unit-stride lines, or tiles of
+// adjacent lines with strided elements.
 bool leaf_supported(int prec, int64_t n);
 int leaf_lines_per_tile(int prec, int n);
+// column tiles of the leaf kernel (PF_LEAF_COL): adjacent lines, strided elements
+bool leaf_col_supported(int prec, int64_t n);
+int leaf_col_lines_per_tile(int prec, int n);
 // variant bit 0: prefetch next tile; bit 1: lower occupancy floor (more VGPRs)
 int leaf_blocks_per_cu(int prec, int n, int variant);
 hipError_t launch_leaf(const PassArgs &a, int prec, int n, int variant, int grid, hipStream_t s);

@@ -179,7 +179,11 @@ __device__ __forceinline__ void st_elem(cpx<T> *p, cpx<T> v)
 
 // RD: 0 plain; 1 the line is the transform of a packed real sequence, split
 // into the n+1 outputs of the real transform on store (PF_R2C); 2 the line is
-// combined from n+1 values of a half spectrum on load (PF_C2R).
+// combined from n+1 values of a half spectrum on load (PF_C2R); 3 columns
+// (PF_LEAF_COL): the BT lines of a tile are adjacent in memory (unit vector
+// stride) and their elements strided, so consecutive lanes take consecutive
+// lines (runs of BT elements per load and store) and each line's thread index
+// t is the lane's rank among the lanes of its line.
 // WPE: occupancy floor in waves per SIMD (caps VGPRs at 512 / WPE).
 // NT: bit 0 streams the output with non-temporal stores, bit 1 the input with
 // non-temporal loads (neither is reused by this pass).
@@ -190,9 +194,12 @@ __global__ __launch_bounds__(BT *N / 16) __attribute__((amdgpu_waves_per_eu(WPE)
     constexpr int STRIDE = (lds_pad(N - 1) + 1) | 1;
     __shared__ cpx<T> lds[BT * STRIDE];
     const PassArgs &a = *(const PassArgs *)__builtin_amdgcn_kernarg_segment_ptr();
+    constexpr bool cols = RD == 3;
     const int tid = threadIdx.x;
-    const int tr = tid / TPT;
-    const int t = tid - tr * TPT;
+    const int tr = cols ? (tid & (BT - 1)) : tid / TPT;
+    const int t = cols ? tid / BT : tid - tr * TPT;
+    // element strides of the line (compile-time 1 for row lines)
+    const int64_t eis = cols ? a.is : 1, eos = cols ? a.os : 1;
     cpx<T> *line = lds + tr * STRIDE;
     const bool cin = (a.flags & PF_CONJ_IN) != 0, cout = (a.flags & PF_CONJ_OUT) != 0;
 
@@ -217,9 +224,9 @@ __global__ __launch_bounds__(BT *N / 16) __attribute__((amdgpu_waves_per_eu(WPE)
         *obs = bo + c * a.vos;
     };
     auto load_line = [&](cpx<T>(&x)[16], int64_t ib) {
-        const cpx<T> *src = (const cpx<T> *)a.in + ib;
+        const cpx<T> *src = (const cpx<T> *)a.in + ib + t * eis;
 #pragma unroll
-        for (int e = 0; e < 16; ++e) x[e] = ld_elem<NT>(&src[t + e * TPT]);
+        for (int e = 0; e < 16; ++e) x[e] = ld_elem<NT>(&src[e * TPT * eis]);
     };
 
     // Real-data fusions (one line = the n-point complex transform of a packed
@@ -334,9 +341,10 @@ __global__ __launch_bounds__(BT *N / 16) __attribute__((amdgpu_waves_per_eu(WPE)
         if constexpr (r2c) {
             split_to_half_spectrum(x, ob, ok);
         } else if (ok) {
-            cpx<T> *dst = (cpx<T> *)a.out + ob;
+            cpx<T> *dst = (cpx<T> *)a.out + ob + t * eos;
 #pragma unroll
-            for (int e = 0; e < 16; ++e) st_elem<NT>(&dst[t + e * TPT], cout ? conj(x[e]) : x[e]);
+            for (int e = 0; e < 16; ++e)
+                st_elem<NT>(&dst[e * TPT * eos], cout ? conj(x[e]) : x[e]);
         }
         if (next >= a.ntiles) break;
         // no barrier needed here: every LDS read of this tile came before the

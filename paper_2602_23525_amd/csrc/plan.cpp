@@ -480,6 +480,19 @@ static int add_line_pass(Builder &b, const LineSpec &ls)
         ps.lds_bytes = 0;
         LeafTune t = leaf_default(prec, (int)n);
         apply_leaf_tune(&ps, t);
+    } else if (!(ls.flags & ~plain) && !ls.conv_n && a.load_mode == kModeCol &&
+               a.store_mode == kModeCol && in_dim.is == 1 && in_dim.os == 1 &&
+               leaf_col_supported(prec, n)) {
+        // adjacent lines with strided elements (columns of a row-major array):
+        // the leaf kernel with column tiles
+        ps.kernel = 1;
+        a.flags |= PF_LEAF_COL;
+        a.bt = leaf_col_lines_per_tile(prec, (int)n);
+        a.bt_log2 = ilog2(a.bt);
+        a.ntiles_inner = (a.vn + a.bt - 1) / a.bt;
+        a.ntiles = a.ntiles_inner * nouter_total;
+        ps.lds_bytes = 0;
+        apply_leaf_tune(&ps, leaf_default(prec, (int)n));
     }
     ps.src = ls.src;
     ps.dst = ls.dst;

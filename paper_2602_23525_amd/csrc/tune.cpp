@@ -44,7 +44,8 @@ int measure_plan(PlanImpl *p)
         return fail(MFFT_EHIP, "event creation failed");
     int rc = MFFT_OK;
     for (Pass &ps : p->passes) {
-        if (ps.kind != 0 || ps.kernel != 1) continue;
+        // column tiles have one configuration
+        if (ps.kind != 0 || ps.kernel != 1 || (ps.a.flags & PF_LEAF_COL)) continue;
         int64_t ilo, ihi, olo, ohi;
         pass_extent(ps, 0, &ilo, &ihi);
         pass_extent(ps, 1, &olo, &ohi);

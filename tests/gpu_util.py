@@ -39,11 +39,11 @@ def note(msg: str):
 
 
 def run_case(dims, hdims=(), sign=-1, prec=0, inplace=False, seed=0, pad=3, check_guard=True,
-             method="auto", sample=None, tol=None, name=""):
+             method="auto", sample=None, tol=None, name="", expect=None):
     """Execute on the GPU and compare with the oracle; returns (relrms, maxerr).
 
     `sample`: list of vector multi-indices to compare (full-size runs); None =
-    the whole problem.
+    the whole problem.  `expect`: a substring the plan description must hold.
     """
     import torch
 
@@ -79,6 +79,9 @@ def run_case(dims, hdims=(), sign=-1, prec=0, inplace=False, seed=0, pad=3, chec
     y = yt.cpu().numpy().astype(np.complex128)
     info = plan.info()
     plan.destroy()
+    if expect is not None:
+        assert expect in info["desc"], f"plan lacks {expect!r}:\n{info['desc']}"
+
     x64 = x.astype(np.complex128)
     if not inplace:
         assert np.array_equal(xt.cpu().numpy(), x), "out-of-place transform modified its input"

@@ -79,6 +79,22 @@ def test_columns_and_rows_examples():
     run_case([(n1, n2, n2)], [(n2, 1, 1)], inplace=True, prec=1, seed=13, name="cols ip c64")
 
 
+@pytest.mark.parametrize("n", [64, 128, 256, 512, 1024, 2048])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_column_tiles(n, prec):
+    # columns of a row-major array (element stride = row length, adjacent
+    # lines): the leaf kernel with column tiles; row counts that leave a
+    # partial last tile, an outer loop, in place, and a wider row than the
+    # columns transformed
+    C = 37
+    run_case([(n, C, C)], [(C, 1, 1)], prec=prec, seed=n + 1, name=f"cols {n}",
+             expect="leaf kernel columns")
+    run_case([(n, C, C)], [(2, n * C, n * C), (C, 1, 1)], prec=prec, inplace=True,
+             seed=n + 2, name=f"cols ip outer {n}", expect="leaf kernel columns")
+    run_case([(n, 50, 40)], [(21, 1, 1)], prec=prec, sign=1, seed=n + 3,
+             name=f"cols strided {n}", expect="leaf kernel columns")
+
+
 def test_3d_inplace_small():
     n = 32
     dims = [(n, n * n, n * n), (n, n, n), (n, 1, 1)]
