@@ -129,7 +129,12 @@ int plan_internal(mfft_plan *out, int rank, const mfft_iodim *dims, int howmany_
     for (const Pass &ps : p->passes) {
         d << "  " << ps.desc;
         if (ps.kernel == 1)
-            d << " [leaf kernel" << ((ps.a.flags & PF_LEAF_COL) ? " columns" : "") << " v"
+            d << " [leaf kernel"
+              << ((ps.a.flags & PF_LEAF_COL)  ? " columns"
+                  : (ps.a.flags & PF_LEAF_CR) ? " columns->rows"
+                  : (ps.a.flags & PF_LEAF_RC) ? " rows->columns"
+                                              : "")
+              << " v"
               << ps.variant << (ps.persistent ? " persistent" : "") << " grid=" << ps.grid
               << "]";
         d << "\n";

@@ -47,6 +47,8 @@ enum : uint32_t {
     PF_NT_IN = 1u << 16,     // generic kernel: non-temporal element loads
     PF_NT_OUT = 1u << 17,    // generic kernel: non-temporal element stores
     PF_LEAF_COL = 1u << 18,  // leaf kernel: tile of adjacent lines with strided elements
+    PF_LEAF_CR = 1u << 19,   // leaf kernel: adjacent lines in, unit-stride lines out
+    PF_LEAF_RC = 1u << 20,   // leaf kernel: unit-stride lines in, adjacent lines out
 };
 
 // Workgroups are dispatched round-robin over the chip's 8 XCDs, each with its

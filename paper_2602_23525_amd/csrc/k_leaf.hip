@@ -67,19 +67,27 @@ constexpr int col_lines(int prec, int n)
     return n <= 256 ? 2048 / n : (n <= 512 ? 8 : 4);
 }
 
-template <typename T>
+// RD 3: columns in and out (64-2048 points); 4 / 5: columns in, rows out and
+// the reverse (256-2048 points, so that a row run is at least 16 lanes)
+template <typename T, int RD>
 static int dispatch_cols(int kind, const PassArgs &a, int n, int grid, hipStream_t s,
                          hipError_t *err)
 {
     constexpr int P = sizeof(T) == 4 ? 0 : 1;
-#define COL_CASE(N, ...)                                                                  \
-    case N:                                                                               \
-        if (kind == 1) return occ<T, N, col_lines(P, N), false, 2, 3, 3, __VA_ARGS__>();  \
-        *err = go<T, N, col_lines(P, N), false, 2, 3, 3, __VA_ARGS__>(a, grid, s);        \
+#define COL_CASE(N, ...)                                                                   \
+    case N:                                                                                \
+        if (kind == 1) return occ<T, N, col_lines(P, N), false, 2, 3, RD, __VA_ARGS__>();  \
+        *err = go<T, N, col_lines(P, N), false, 2, 3, RD, __VA_ARGS__>(a, grid, s);        \
         return 0;
+    if constexpr (RD == 3) {
+        switch (n) {
+            COL_CASE(64, 16, 4)
+            COL_CASE(128, 16, 8)
+        default:
+            break;
+        }
+    }
     switch (n) {
-        COL_CASE(64, 16, 4)
-        COL_CASE(128, 16, 8)
         COL_CASE(256, 16, 16)
         COL_CASE(512, 16, 16, 2)
         COL_CASE(1024, 16, 16, 4)
@@ -94,10 +102,10 @@ static int dispatch_cols(int kind, const PassArgs &a, int n, int grid, hipStream
 
 int leaf_col_lines_per_tile(int prec, int n) { return col_lines(prec, n); }
 
-bool leaf_col_supported(int prec, int64_t n)
+bool leaf_col_supported(int prec, int64_t n, bool transposing)
 {
     (void)prec;
-    return n >= 64 && n <= 2048 && (n & (n - 1)) == 0;
+    return n >= (transposing ? 256 : 64) && n <= 2048 && (n & (n - 1)) == 0;
 }
 
 int leaf_max_n(int) { return 4096; }
@@ -138,8 +146,16 @@ static int run(int kind, const PassArgs &a, int prec, int n, int variant, int gr
                hipStream_t s, hipError_t *e)
 {
     if (a.flags & PF_LEAF_COL) {
-        return prec == 0 ? dispatch_cols<float>(kind, a, n, grid, s, e)
-                         : dispatch_cols<double>(kind, a, n, grid, s, e);
+        return prec == 0 ? dispatch_cols<float, 3>(kind, a, n, grid, s, e)
+                         : dispatch_cols<double, 3>(kind, a, n, grid, s, e);
+    }
+    if (a.flags & PF_LEAF_CR) {
+        return prec == 0 ? dispatch_cols<float, 4>(kind, a, n, grid, s, e)
+                         : dispatch_cols<double, 4>(kind, a, n, grid, s, e);
+    }
+    if (a.flags & PF_LEAF_RC) {
+        return prec == 0 ? dispatch_cols<float, 5>(kind, a, n, grid, s, e)
+                         : dispatch_cols<double, 5>(kind, a, n, grid, s, e);
     }
     // real-data fusions: one configuration each, non-temporal loads and
     // stores as the plain default (prefetch only for FP32 r2c, where it pays

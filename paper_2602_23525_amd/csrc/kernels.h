@@ -73,8 +73,9 @@ namespace mfft {
 // adjacent lines with strided elements.
 bool leaf_supported(int prec, int64_t n);
 int leaf_lines_per_tile(int prec, int n);
-// column tiles of the leaf kernel (PF_LEAF_COL): adjacent lines, strided elements
-bool leaf_col_supported(int prec, int64_t n);
+// column tiles of the leaf kernel (PF_LEAF_COL, or transposing: PF_LEAF_CR /
+// PF_LEAF_RC): adjacent lines, strided elements
+bool leaf_col_supported(int prec, int64_t n, bool transposing);
 int leaf_col_lines_per_tile(int prec, int n);
 // variant bit 0: prefetch next tile; bit 1: lower occupancy floor (more VGPRs)
 int leaf_blocks_per_cu(int prec, int n, int variant);

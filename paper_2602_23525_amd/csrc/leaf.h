@@ -17,6 +17,7 @@
 #pragma once
 #include "butterfly.h"
 #include "internal.h"
+#include "twiddle4.h"
 
 namespace mfft {
 
@@ -183,7 +184,11 @@ __device__ __forceinline__ void st_elem(cpx<T> *p, cpx<T> v)
 // (PF_LEAF_COL): the BT lines of a tile are adjacent in memory (unit vector
 // stride) and their elements strided, so consecutive lanes take consecutive
 // lines (runs of BT elements per load and store) and each line's thread index
-// t is the lane's rank among the lanes of its line.
+// t is the lane's rank among the lanes of its line; 4 columns in, rows out and
+// 5 rows in, columns out (PF_LEAF_CR, PF_LEAF_RC): the loads use one
+// lane mapping, the stores the other, the results passing through LDS once
+// more, optionally times the Cooley-Tukey twiddle w_N^(c*k) of element k of
+// inner line c (PF_TW4).
 // WPE: occupancy floor in waves per SIMD (caps VGPRs at 512 / WPE).
 // NT: bit 0 streams the output with non-temporal stores, bit 1 the input with
 // non-temporal loads (neither is reused by this pass).
@@ -194,21 +199,31 @@ __global__ __launch_bounds__(BT *N / 16) __attribute__((amdgpu_waves_per_eu(WPE)
     constexpr int STRIDE = (lds_pad(N - 1) + 1) | 1;
     __shared__ cpx<T> lds[BT * STRIDE];
     const PassArgs &a = *(const PassArgs *)__builtin_amdgcn_kernarg_segment_ptr();
-    constexpr bool cols = RD == 3;
+    constexpr bool cols_in = RD == 3 || RD == 4, cols_out = RD == 3 || RD == 5;
+    constexpr bool xpose = cols_in != cols_out;
+    static_assert(!(xpose && PF), "transposing tiles are one tile per workgroup");
     const int tid = threadIdx.x;
-    const int tr = cols ? (tid & (BT - 1)) : tid / TPT;
-    const int t = cols ? tid / BT : tid - tr * TPT;
+    // lane -> (line, thread of the line) for the loads and the stages, and for
+    // the stores of a transposing tile
+    const int tr = cols_in ? (tid & (BT - 1)) : tid / TPT;
+    const int t = cols_in ? tid / BT : tid - tr * TPT;
+    const int trs = cols_out ? (tid & (BT - 1)) : tid / TPT;
+    const int ts = cols_out ? tid / BT : tid - trs * TPT;
     // element strides of the line (compile-time 1 for row lines)
-    const int64_t eis = cols ? a.is : 1, eos = cols ? a.os : 1;
+    const int64_t eis = cols_in ? a.is : 1, eos = cols_out ? a.os : 1;
     cpx<T> *line = lds + tr * STRIDE;
     const bool cin = (a.flags & PF_CONJ_IN) != 0, cout = (a.flags & PF_CONJ_OUT) != 0;
 
     StageChain<T, N, TPT, 1, Rs...> chain;
     chain.load((const cpx<T> *)a.tw, 0, t);
 
+    // store side of a transposing tile: inner index of the lane's store line
+    int64_t cst = 0;
     auto line_base = [&](int64_t tile, int64_t *ib, int64_t *obs, bool *ok) {
         const int64_t o = tile / a.ntiles_inner;
-        const int64_t c = (tile - o * a.ntiles_inner) * BT + tr;
+        const int64_t c0 = (tile - o * a.ntiles_inner) * BT;
+        const int64_t c = c0 + tr;
+        if constexpr (xpose) cst = c0 + trs;
         int64_t rem = o, bi = 0, bo = 0;
         for (int d = a.nouter - 1; d >= 0; --d) {
             const int64_t qd = rem / a.on[d];
@@ -219,9 +234,10 @@ __global__ __launch_bounds__(BT *N / 16) __attribute__((amdgpu_waves_per_eu(WPE)
         }
         // a padding line of a partial last tile reads the last line (its
         // results are never stored), so that every load is unconditional
-        *ok = c < a.vn;
-        *ib = bi + (*ok ? c : a.vn - 1) * a.vis;
-        *obs = bo + c * a.vos;
+        *ib = bi + (c < a.vn ? c : a.vn - 1) * a.vis;
+        const int64_t cs = xpose ? cst : c;
+        *ok = cs < a.vn;
+        *obs = bo + cs * a.vos;
     };
     auto load_line = [&](cpx<T>(&x)[16], int64_t ib) {
         const cpx<T> *src = (const cpx<T> *)a.in + ib + t * eis;
@@ -338,17 +354,40 @@ __global__ __launch_bounds__(BT *N / 16) __attribute__((amdgpu_waves_per_eu(WPE)
             for (int e = 0; e < 16; ++e) x[e] = conj(x[e]);
         }
         chain.run(x, line, t);
+        if constexpr (xpose) {
+            // results to LDS in the stage mapping, back in the store mapping
+#pragma unroll
+            for (int e = 0; e < 16; ++e) *lds_slot<TPT>(line, t, e) = x[e];
+            __syncthreads();
+            cpx<T> *sl = lds + trs * STRIDE;
+#pragma unroll
+            for (int e = 0; e < 16; ++e) x[e] = *lds_slot<TPT>(sl, ts, e);
+            if (a.flags & PF_TW4) {
+                // element k = ts + e*TPT of inner line c: w_N^(c*k), the powers
+                // of w_N^(c*TPT) by an FP64 recurrence from w_N^(c*ts)
+                const int64_t cw = ok ? cst : 0;
+                double2 w = tw4_root(a, cw * ts);
+                const double2 ws = tw4_root(a, cw * TPT);
+#pragma unroll
+                for (int e = 0; e < 16; ++e) {
+                    x[e] = mul_d(x[e], w);
+                    w = zmul(w, ws);
+                }
+            }
+        }
         if constexpr (r2c) {
             split_to_half_spectrum(x, ob, ok);
         } else if (ok) {
-            cpx<T> *dst = (cpx<T> *)a.out + ob + t * eos;
+            cpx<T> *dst = (cpx<T> *)a.out + ob + (xpose ? ts : t) * eos;
 #pragma unroll
             for (int e = 0; e < 16; ++e)
                 st_elem<NT>(&dst[e * TPT * eos], cout ? conj(x[e]) : x[e]);
         }
         if (next >= a.ntiles) break;
-        // no barrier needed here: every LDS read of this tile came before the
-        // barrier that ends the last exchange
+        // no barrier needed here (except after a transposing store): every
+        // LDS read of this tile came before the barrier that ends the last
+        // exchange
+        if constexpr (xpose) __syncthreads();
         tile = next;
         bool prefetched = false;
         if constexpr (PF) {

@@ -359,6 +359,24 @@ static std::string dims_str(const Dim &d) {
     return s.str();
 }
 
+// The leaf kernel takes a pass with column tiles when its lines are plain
+// (at most conjugation; Cooley-Tukey twiddles on a transposing tile), of a
+// supported length, adjacent (unit vector stride) on each column side and of
+// unit element stride on a row side.
+static bool leaf_col_fits(const LineSpec &ls, const PassArgs &a, const Dim &in_dim, int prec,
+                          int64_t n)
+{
+    const bool cin = a.load_mode == kModeCol, cout = a.store_mode == kModeCol;
+    if (!cin && !cout) return false;
+    const bool xp = cin != cout;
+    const uint32_t allowed = PF_CONJ_IN | PF_CONJ_OUT | (xp ? PF_TW4 : 0u);
+    if ((ls.flags & ~allowed) || ls.conv_n) return false;
+    if (!leaf_col_supported(prec, n, xp)) return false;
+    if (cin ? in_dim.is != 1 : ls.line.is != 1) return false;
+    if (cout ? in_dim.os != 1 : ls.line.os != 1) return false;
+    return true;
+}
+
 static int add_line_pass(Builder &b, const LineSpec &ls)
 {
     PlanImpl *p = b.p;
@@ -480,13 +498,12 @@ static int add_line_pass(Builder &b, const LineSpec &ls)
         ps.lds_bytes = 0;
         LeafTune t = leaf_default(prec, (int)n);
         apply_leaf_tune(&ps, t);
-    } else if (!(ls.flags & ~plain) && !ls.conv_n && a.load_mode == kModeCol &&
-               a.store_mode == kModeCol && in_dim.is == 1 && in_dim.os == 1 &&
-               leaf_col_supported(prec, n)) {
-        // adjacent lines with strided elements (columns of a row-major array):
-        // the leaf kernel with column tiles
+    } else if (leaf_col_fits(ls, a, in_dim, prec, n)) {
+        // adjacent lines with strided elements (columns of a row-major array)
+        // on one side or both: the leaf kernel with column tiles
+        const bool cin = a.load_mode == kModeCol, cout = a.store_mode == kModeCol;
         ps.kernel = 1;
-        a.flags |= PF_LEAF_COL;
+        a.flags |= cin && cout ? PF_LEAF_COL : (cin ? PF_LEAF_CR : PF_LEAF_RC);
         a.bt = leaf_col_lines_per_tile(prec, (int)n);
         a.bt_log2 = ilog2(a.bt);
         a.ntiles_inner = (a.vn + a.bt - 1) / a.bt;

@@ -95,6 +95,26 @@ def test_column_tiles(n, prec):
              name=f"cols strided {n}", expect="leaf kernel columns")
 
 
+@pytest.mark.parametrize("n", [256, 512, 1024, 2048])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_transposing_column_tiles(n, prec):
+    # one side adjacent lines, the other unit-stride lines: columns in and
+    # rows out, rows in and columns out (partial last tiles: 37 lines)
+    C = 37
+    run_case([(n, C, 1)], [(C, 1, n)], prec=prec, seed=n + 4, name=f"cols->rows {n}",
+             expect="leaf kernel columns->rows")
+    run_case([(n, 1, C)], [(C, n, 1)], prec=prec, sign=1, seed=n + 5,
+             name=f"rows->cols {n}", expect="leaf kernel rows->columns")
+
+
+@pytest.mark.parametrize("n", [65536, 131072, 1048576])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_two_pass_twiddled_column_tiles(n, prec):
+    # first Cooley-Tukey pass: columns in, rows out, times w_N^(c*k)
+    run_case([(n, 1, 1)], [(2, n, n)], prec=prec, seed=n + 6, name=f"ct {n}",
+             expect="leaf kernel columns->rows")
+
+
 def test_3d_inplace_small():
     n = 32
     dims = [(n, n * n, n * n), (n, n, n), (n, 1, 1)]
