@@ -25,7 +25,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 # sources of the specialized leaf kernel (the dominant kernel of the batched
 # power-of-two workloads)
 KERNEL_SOURCES = ["paper_2602_23525_amd/csrc/leaf.h", "paper_2602_23525_amd/csrc/k_leaf.hip",
-                  "paper_2602_23525_amd/csrc/butterfly.h", "paper_2602_23525_amd/csrc/internal.h"]
+                  "paper_2602_23525_amd/csrc/butterfly.h", "paper_2602_23525_amd/csrc/internal.h",
+                  "paper_2602_23525_amd/csrc/twiddle4.h"]
 
 
 def kernel_source_hash() -> str:
