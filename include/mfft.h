@@ -70,6 +70,18 @@ typedef enum { MFFT_C32 = 0, MFFT_C64 = 1 } mfft_prec;
  * cosine) instead of FP64 rounded once to FP32.  The index product is still
  * reduced exactly in integer arithmetic. */
 #define MFFT_FP32_TWIDDLES 8u
+/* In-place plans that need no scratch memory (Section 4.2's in-place plans):
+ * a transform along a dimension too long for one pass, n = q*q with q a leaf
+ * length, runs as columns (with the Cooley-Tukey twiddle), rows, and an
+ * in-place q x q transpose, all in the caller's buffer, instead of two passes
+ * through a scratch copy (one more pass over HBM, no scratch).  Planning fails
+ * with MFFT_ENOTSUP when the problem has no such plan (a multi-pass length
+ * that is not a square, prime sizes that need a convolution buffer, in-place
+ * problems whose input and output strides differ, and real-data transforms
+ * that need a packed copy).  Applies to in-place problems; out-of-place plans
+ * use no scratch anyway except for prime and real-data cases, which then also
+ * fail with MFFT_ENOTSUP. */
+#define MFFT_NO_SCRATCH 16u
 
 /* Optional device allocator (e.g. a framework's caching allocator).  alloc
  * returns NULL on failure.  NULL allocator = hipMalloc / hipFree. */
@@ -117,7 +129,8 @@ int mfft_problem_check(int rank, const mfft_iodim *dims, int howmany_rank,
  * steps chosen by the planner; here each step is one GPU pass).
  * Arguments as for mfft_problem_check, plus
  *   flags:      MFFT_ESTIMATE / MFFT_MEASURE / MFFT_WISDOM_ONLY | MFFT_NO_WISDOM
- *               (| MFFT_FP32_TWIDDLES for the accuracy ablation); other bits,
+ *               (| MFFT_FP32_TWIDDLES for the accuracy ablation,
+ *               | MFFT_NO_SCRATCH for plans without scratch); other bits,
  *               or MFFT_FP32_TWIDDLES with MFFT_C64, give EINVAL before any
  *               device work;
  *   alloc:      allocator for the plan's tables and scratch (NULL = hipMalloc);

@@ -18,7 +18,7 @@ __all__ = [
     "mfft_execute", "mfft_execute_scratch", "mfft_plan_dft_real", "mfft_problem_check_real", "mfft_plan_info", "mfft_plan_destroy",
     "mfft_wisdom_export", "mfft_wisdom_import", "mfft_wisdom_forget", "mfft_last_error",
     "mfft_version", "C32", "C64", "ESTIMATE", "MEASURE", "WISDOM_ONLY", "NO_WISDOM",
-    "FP32_TWIDDLES",
+    "FP32_TWIDDLES", "NO_SCRATCH",
     "header_functions", "LIB_PATH", "HEADER_PATH", "Batch", "BATCH_GRAPH", "Server", "Request",
 ]
 
@@ -27,7 +27,7 @@ LIB_PATH = os.path.join(HERE, "libmfft.so")
 HEADER_PATH = os.path.join(os.path.dirname(HERE), "include", "mfft.h")
 
 C32, C64 = 0, 1
-ESTIMATE, MEASURE, WISDOM_ONLY, NO_WISDOM, FP32_TWIDDLES = 0, 1, 2, 4, 8
+ESTIMATE, MEASURE, WISDOM_ONLY, NO_WISDOM, FP32_TWIDDLES, NO_SCRATCH = 0, 1, 2, 4, 8, 16
 
 STATUS = {0: "MFFT_OK", -1: "MFFT_EINVAL", -2: "MFFT_ENOTSUP", -3: "MFFT_ENOMEM",
           -4: "MFFT_EHIP", -5: "MFFT_EALIGN", -6: "MFFT_EBUDGET", -7: "MFFT_ESTATE",

@@ -98,7 +98,9 @@ int plan_internal(mfft_plan *out, int rank, const mfft_iodim *dims, int howmany_
     rc = build_plan(p);
     if (rc == MFFT_OK && !p->prob.empty) {
         // wisdom (stored choices) first, then measurement, else estimate defaults
-        const std::string key = problem_key(p->prob) + " " + g_arch;
+        // plans without scratch have other passes: their own wisdom entries
+        const std::string key = problem_key(p->prob) + " " + g_arch +
+                                ((flags & MFFT_NO_SCRATCH) ? " noscratch" : "");
         std::string val;
         const bool use_wisdom = !(flags & MFFT_NO_WISDOM);
         if (use_wisdom && wisdom_lookup(key, &val) && apply_choices(p, val)) {
@@ -158,7 +160,8 @@ const char *mfft_version(void) { return "mfft 0.1.0 (gfx950)"; }
 
 static int check_flags(unsigned flags, mfft_prec prec)
 {
-    const unsigned known = MFFT_MEASURE | MFFT_WISDOM_ONLY | MFFT_NO_WISDOM | MFFT_FP32_TWIDDLES;
+    const unsigned known = MFFT_MEASURE | MFFT_WISDOM_ONLY | MFFT_NO_WISDOM | MFFT_FP32_TWIDDLES |
+                           MFFT_NO_SCRATCH;
     if (flags & ~known) return fail(MFFT_EINVAL, "unknown planner flag bits");
     if ((flags & MFFT_FP32_TWIDDLES) && prec != MFFT_C32)
         return fail(MFFT_EINVAL, "MFFT_FP32_TWIDDLES applies to MFFT_C32 plans only");

@@ -64,6 +64,7 @@ int build_batch_layout(const std::vector<BatchItem> &items, BatchLayout *L)
     std::map<Key, size_t> fam_lds;
     std::map<int, std::vector<CopyArgs>> copies;
     std::map<int, std::vector<std::pair<RealArgs, int>>> reals;
+    std::map<int, std::vector<TransposeArgs>> transposes;
     std::map<int, std::vector<BatchStep>> leaves;
     int nphase = 0;
     for (const BatchItem &it : items) {
@@ -77,6 +78,10 @@ int build_batch_layout(const std::vector<BatchItem> &items, BatchLayout *L)
             }
             if (ps.kind == 2) {
                 reals[(int)k].push_back({resolve_real(p, ps, it.in, it.out, it.scratch), ps.prec});
+                continue;
+            }
+            if (ps.kind == 3) {
+                transposes[(int)k].push_back(resolve_transpose(p, ps, it.in, it.out, it.scratch));
                 continue;
             }
             PassArgs a = resolve_pass(p, ps, it.in, it.out, it.scratch);
@@ -160,6 +165,12 @@ int build_batch_layout(const std::vector<BatchItem> &items, BatchLayout *L)
             st.prec = rp.second;
             L->steps.push_back(st);
         }
+        for (const TransposeArgs &t : transposes[k]) {
+            BatchStep st;
+            st.transpose = true;
+            st.t = t;
+            L->steps.push_back(st);
+        }
         for (size_t gi = 0; gi < order.size(); ++gi)
             if (std::get<0>(order[gi].first) == k) {
                 BatchStep st;
@@ -182,6 +193,8 @@ int enqueue_batch_layout(const BatchLayout &L, char *dev, hipStream_t s)
             e = launch_copy(st.c, s);
         } else if (st.real) {
             e = launch_real(st.r, st.prec, s);
+        } else if (st.transpose) {
+            e = launch_transpose_sq(st.t, s);
         } else if (st.leaf) {
             e = launch_leaf(st.a, st.prec, st.a.n, st.leaf_variant, st.leaf_grid, s);
         } else {

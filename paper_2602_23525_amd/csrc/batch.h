@@ -23,11 +23,13 @@ struct BatchGroup {
     size_t items_off = 0, prefix_off = 0, counter_off = 0;   // offsets in the image
 };
 
-struct BatchStep {   // one launch: a group, a copy pass or a real-data step
+struct BatchStep {   // one launch: a group, a copy pass, a real-data step or a transpose
     bool copy = false;
     CopyArgs c{};
     bool real = false;
     RealArgs r{};
+    bool transpose = false;
+    TransposeArgs t{};
     bool leaf = false;   // a specialized leaf pass with a real-data fusion
     PassArgs a{};
     int leaf_variant = 0, leaf_grid = 0;

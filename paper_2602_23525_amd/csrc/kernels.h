@@ -54,6 +54,20 @@ hipError_t launch_batch(const PassArgs *items_dev, const int64_t *prefix_dev, in
 int pass_kind(uint32_t flags);
 int batch_blocks_per_cu(int prec, int kind, int block, size_t lds);
 hipError_t launch_copy(const CopyArgs &a, hipStream_t s);
+
+// In-place transpose of q x q blocks (the last step of an in-place two-pass
+// Cooley-Tukey plan without scratch): in every block, element (i, j) at
+// base + i*rs + j*cs trades places with (j, i); blocks at the offsets of up to
+// 8 outer loops (n[d], s[d]).  elem_bytes 8 or 16.
+struct TransposeArgs {
+    void *data;
+    int32_t elem_bytes;
+    int32_t rank;
+    int64_t q, rs, cs;
+    int64_t total;            // number of blocks (product of n[d])
+    int64_t n[8], s[8];
+};
+hipError_t launch_transpose_sq(const TransposeArgs &a, hipStream_t s);
 hipError_t launch_gen_stage_twiddles(void *out, int prec, int Ns, int R, hipStream_t s,
                                      bool fp32_math = false);
 hipError_t launch_gen_tw4(void *hi, int64_t nhi, void *lo, int64_t nlo, int shift, int64_t N,

@@ -338,6 +338,75 @@ __global__ __launch_bounds__(256) void copy_contig_kernel(const uint4 *__restric
         if (base + j * 256 < n16) out[base + j * 256] = v[j];
 }
 
+// ------------------------------------------------------------ in-place square transpose
+// One workgroup per pair of 32 x 32 tiles (ti <= tj) of one block: both tiles
+// are read into LDS (rows of 32 elements, coalesced), then each is written to
+// the other's place transposed; a diagonal tile is transposed onto itself.
+// Every element of the pair is read before the barrier and written after it,
+// and the pairs partition the block, so the transpose is race-free in place.
+constexpr int kTrTile = 32;
+
+template <typename E>
+__global__ __launch_bounds__(256) void transpose_sq_kernel(TransposeArgs a, int64_t pairs,
+                                                           int nt)
+{
+    __shared__ E ta[kTrTile][kTrTile + 1], tb[kTrTile][kTrTile + 1];
+    const int64_t g = blockIdx.x;
+    const int64_t blk = g / pairs;
+    int rem = (int)(g - blk * pairs);
+    // pair index -> (ti, tj), ti <= tj, row by row of the upper triangle
+    int ti = 0;
+    while (rem >= nt - ti) {
+        rem -= nt - ti;
+        ++ti;
+    }
+    const int tj = ti + rem;
+    int64_t base = 0, r = blk;
+    for (int d = a.rank - 1; d >= 0; --d) {
+        const int64_t qd = r / a.n[d];
+        base += (r - qd * a.n[d]) * a.s[d];
+        r = qd;
+    }
+    E *data = (E *)a.data + base;
+    const int x = threadIdx.x & (kTrTile - 1), y0 = threadIdx.x / kTrTile;
+    const int64_t q = a.q;
+    // tile A = rows ti*32.., columns tj*32..; tile B = rows tj*32.., columns ti*32..
+#pragma unroll
+    for (int y = y0; y < kTrTile; y += 256 / kTrTile) {
+        const int64_t ra = (int64_t)ti * kTrTile + y, ca = (int64_t)tj * kTrTile + x;
+        if (ra < q && ca < q) ta[y][x] = data[ra * a.rs + ca * a.cs];
+        const int64_t rb = (int64_t)tj * kTrTile + y, cb = (int64_t)ti * kTrTile + x;
+        if (ti != tj && rb < q && cb < q) tb[y][x] = data[rb * a.rs + cb * a.cs];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int y = y0; y < kTrTile; y += 256 / kTrTile) {
+        // B's place (rows tj.., columns ti..) gets A transposed
+        const int64_t rb = (int64_t)tj * kTrTile + y, cb = (int64_t)ti * kTrTile + x;
+        if (rb < q && cb < q) data[rb * a.rs + cb * a.cs] = ta[x][y];
+        if (ti != tj) {
+            const int64_t ra = (int64_t)ti * kTrTile + y, ca = (int64_t)tj * kTrTile + x;
+            if (ra < q && ca < q) data[ra * a.rs + ca * a.cs] = tb[x][y];
+        }
+    }
+}
+
+hipError_t launch_transpose_sq(const TransposeArgs &a, hipStream_t s)
+{
+    if (a.total <= 0 || a.q <= 1) return hipSuccess;
+    const int nt = (int)((a.q + kTrTile - 1) / kTrTile);
+    const int64_t pairs = (int64_t)nt * (nt + 1) / 2;
+    const int64_t grid = pairs * a.total;
+    if (grid > 0x7fffffffLL) return hipErrorInvalidValue;
+    if (a.elem_bytes == 8)
+        hipLaunchKernelGGL(transpose_sq_kernel<uint2>, dim3((unsigned)grid), dim3(256), 0, s, a,
+                           pairs, nt);
+    else
+        hipLaunchKernelGGL(transpose_sq_kernel<uint4>, dim3((unsigned)grid), dim3(256), 0, s, a,
+                           pairs, nt);
+    return hipGetLastError();
+}
+
 hipError_t launch_copy(const CopyArgs &a, hipStream_t s)
 {
     if (a.total <= 0) return hipSuccess;

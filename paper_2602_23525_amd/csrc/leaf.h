@@ -187,8 +187,8 @@ __device__ __forceinline__ void st_elem(cpx<T> *p, cpx<T> v)
 // t is the lane's rank among the lanes of its line; 4 columns in, rows out and
 // 5 rows in, columns out (PF_LEAF_CR, PF_LEAF_RC): the loads use one
 // lane mapping, the stores the other, the results passing through LDS once
-// more, optionally times the Cooley-Tukey twiddle w_N^(c*k) of element k of
-// inner line c (PF_TW4).
+// more.  Column tiles (3-5) may multiply element k of inner line c by the
+// Cooley-Tukey twiddle w_N^(c*k) on store (PF_TW4).
 // WPE: occupancy floor in waves per SIMD (caps VGPRs at 512 / WPE).
 // NT: bit 0 streams the output with non-temporal stores, bit 1 the input with
 // non-temporal loads (neither is reused by this pass).
@@ -217,13 +217,13 @@ __global__ __launch_bounds__(BT *N / 16) __attribute__((amdgpu_waves_per_eu(WPE)
     StageChain<T, N, TPT, 1, Rs...> chain;
     chain.load((const cpx<T> *)a.tw, 0, t);
 
-    // store side of a transposing tile: inner index of the lane's store line
+    // column tiles: inner index of the lane's store line (for the twiddle)
     int64_t cst = 0;
     auto line_base = [&](int64_t tile, int64_t *ib, int64_t *obs, bool *ok) {
         const int64_t o = tile / a.ntiles_inner;
         const int64_t c0 = (tile - o * a.ntiles_inner) * BT;
         const int64_t c = c0 + tr;
-        if constexpr (xpose) cst = c0 + trs;
+        if constexpr (cols_in || cols_out) cst = c0 + (xpose ? trs : tr);
         int64_t rem = o, bi = 0, bo = 0;
         for (int d = a.nouter - 1; d >= 0; --d) {
             const int64_t qd = rem / a.on[d];
@@ -362,11 +362,14 @@ __global__ __launch_bounds__(BT *N / 16) __attribute__((amdgpu_waves_per_eu(WPE)
             cpx<T> *sl = lds + trs * STRIDE;
 #pragma unroll
             for (int e = 0; e < 16; ++e) x[e] = *lds_slot<TPT>(sl, ts, e);
+        }
+        if constexpr (cols_in || cols_out) {
             if (a.flags & PF_TW4) {
-                // element k = ts + e*TPT of inner line c: w_N^(c*k), the powers
-                // of w_N^(c*TPT) by an FP64 recurrence from w_N^(c*ts)
+                // element k = k0 + e*TPT of inner line c (k0 the lane's store
+                // rank): w_N^(c*k), the powers of w_N^(c*TPT) by an FP64
+                // recurrence from w_N^(c*k0)
                 const int64_t cw = ok ? cst : 0;
-                double2 w = tw4_root(a, cw * ts);
+                double2 w = tw4_root(a, cw * (xpose ? ts : t));
                 const double2 ws = tw4_root(a, cw * TPT);
 #pragma unroll
                 for (int e = 0; e < 16; ++e) {

@@ -360,16 +360,16 @@ static std::string dims_str(const Dim &d) {
 }
 
 // The leaf kernel takes a pass with column tiles when its lines are plain
-// (at most conjugation; Cooley-Tukey twiddles on a transposing tile), of a
-// supported length, adjacent (unit vector stride) on each column side and of
-// unit element stride on a row side.
+// (at most conjugation and the Cooley-Tukey twiddle on store), of a supported
+// length, adjacent (unit vector stride) on each column side and of unit
+// element stride on a row side.
 static bool leaf_col_fits(const LineSpec &ls, const PassArgs &a, const Dim &in_dim, int prec,
                           int64_t n)
 {
     const bool cin = a.load_mode == kModeCol, cout = a.store_mode == kModeCol;
     if (!cin && !cout) return false;
     const bool xp = cin != cout;
-    const uint32_t allowed = PF_CONJ_IN | PF_CONJ_OUT | (xp ? PF_TW4 : 0u);
+    const uint32_t allowed = PF_CONJ_IN | PF_CONJ_OUT | PF_TW4;
     if ((ls.flags & ~allowed) || ls.conv_n) return false;
     if (!leaf_col_supported(prec, n, xp)) return false;
     if (cin ? in_dim.is != 1 : ls.line.is != 1) return false;
@@ -610,6 +610,73 @@ static int plan_leaf(Builder &b, Dim d, const std::vector<Dim> &V, int src, int 
 }
 
 // Cooley-Tukey DIT step, radix r = n/m (Section 4.2).
+static int add_transpose_pass(Builder &b, int buf, int64_t off, int64_t q, int64_t rs, int64_t cs,
+                              const std::vector<Dim> &V)
+{
+    Pass ps;
+    ps.kind = 3;
+    if (V.size() > 8) return fail(MFFT_ENOTSUP, "transpose over more than 8 loops");
+    ps.t.elem_bytes = elem_bytes(b.p->prob.prec);
+    ps.t.rank = (int)V.size();
+    ps.t.q = q;
+    ps.t.rs = rs;
+    ps.t.cs = cs;
+    ps.t.total = 1;
+    for (size_t i = 0; i < V.size(); ++i) {
+        ps.t.n[i] = V[i].n;
+        ps.t.s[i] = V[i].is;
+        ps.t.total *= V[i].n;
+    }
+    ps.src = ps.dst = buf;
+    ps.src_off = ps.dst_off = off;
+    ps.prec = b.p->prob.prec;
+    ps.bytes = 2.0 * (double)(q * q) * ps.t.total * ps.t.elem_bytes;
+    std::ostringstream d;
+    d << "transpose q=" << q << " in place x" << ps.t.total;
+    ps.desc = d.str();
+    b.p->passes.push_back(ps);
+    return MFFT_OK;
+}
+
+// In-place Cooley-Tukey step without scratch (Section 4.2's in-place plans)
+// for n = q*q: columns j (elements l*q + j, l < q) transformed in place with
+// the twiddle w_n^(j*k1) on store, then rows k1 (elements k1*q + j) in place,
+// which leaves Y[k1 + k2*q] at k1*q + k2, then an in-place q x q transpose.
+// Every pass reads a tile's elements before writing them and tiles are
+// disjoint, so no pass needs a copy of its input.
+static int plan_ct_square_inplace(Builder &b, Dim d, const std::vector<Dim> &V, int buf,
+                                  int64_t off, bool conj_in, bool conj_out)
+{
+    const int prec = b.p->prob.prec;
+    const int64_t n = d.n;
+    int64_t q = (int64_t)std::llround(std::sqrt((double)n));
+    while (q * q > n) --q;
+    while ((q + 1) * (q + 1) <= n) ++q;
+    if (q * q != n || !leaf_fits(q, prec, prec ? 4 : 8))
+        return fail(MFFT_ENOTSUP, "in place without scratch needs n = q*q with q one pass");
+    if (d.is != d.os) return fail(MFFT_ENOTSUP, "in place without scratch needs equal strides");
+    for (const Dim &v : V)
+        if (v.is != v.os) return fail(MFFT_ENOTSUP, "in place without scratch needs equal strides");
+    const int64_t s = d.is;
+    LineSpec A;
+    A.what = "ctA";
+    A.line = {q, q * s, q * s};
+    A.V = V;
+    A.V.push_back({q, s, s});
+    A.inner = (int)A.V.size() - 1;
+    A.src = A.dst = buf;
+    A.src_off = A.dst_off = off;
+    A.flags = PF_TW4 | (conj_in ? PF_CONJ_IN : 0);
+    A.tw4_N = n;
+    int rc = add_line_pass(b, A);
+    if (rc) return rc;
+    std::vector<Dim> VB = V;
+    VB.push_back({q, q * s, q * s});
+    rc = plan_line(b, Dim{q, s, s}, VB, buf, buf, off, off, false, conj_out);
+    if (rc) return rc;
+    return add_transpose_pass(b, buf, off, q, q * s, s, V);
+}
+
 static int plan_ct(Builder &b, Dim d, const std::vector<Dim> &V, int src, int dst,
                    int64_t src_off, int64_t dst_off, bool conj_in, bool conj_out, Split sp)
 {
@@ -636,6 +703,10 @@ static int plan_ct(Builder &b, Dim d, const std::vector<Dim> &V, int src, int ds
         std::vector<Dim> VB = copy_o(V);
         VB.push_back({m, d.os, d.os});
         return plan_line(b, dB, VB, dst, dst, dst_off, dst_off, false, conj_out);
+    }
+    if (b.p->flags & MFFT_NO_SCRATCH) {
+        if (oop) return fail(MFFT_ENOTSUP, "no plan without scratch memory for this problem");
+        return plan_ct_square_inplace(b, d, V, src, src_off, conj_in, conj_out);
     }
     // in place: pass A into packed scratch (transform v at v*n, element l2*m + k1)
     const int64_t H = vprod(V);
@@ -1197,6 +1268,14 @@ static int plan_real_line(Builder &b, bool fwd, Dim d, const std::vector<Dim> &V
                          nullptr, "real part");
 }
 
+// MFFT_NO_SCRATCH: a plan that still needs scratch has no form without it.
+static int no_scratch_check(const PlanImpl *p)
+{
+    if ((p->flags & MFFT_NO_SCRATCH) && p->scratch_bytes)
+        return fail(MFFT_ENOTSUP, "no plan without scratch memory for this problem");
+    return MFFT_OK;
+}
+
 // Rank-r real transforms (the last dimension is the halved one): forward, the
 // real step along the last dimension (the others join the vector loops), then
 // complex steps along the others in place on the output; inverse, complex
@@ -1264,7 +1343,7 @@ static int build_real_plan(PlanImpl *p)
     }
     if (rc) return rc;
     p->scratch_bytes = (size_t)b.scratch_hi;
-    return MFFT_OK;
+    return no_scratch_check(p);
 }
 
 int build_plan(PlanImpl *p)
@@ -1301,7 +1380,7 @@ int build_plan(PlanImpl *p)
             if (rc) return rc;
         }
         p->scratch_bytes = (size_t)b.scratch_hi;
-        return MFFT_OK;
+        return no_scratch_check(p);
     }
 
     int64_t persistent = 0;
@@ -1348,7 +1427,7 @@ int build_plan(PlanImpl *p)
         }
     }
     p->scratch_bytes = (size_t)b.scratch_hi;
-    return MFFT_OK;
+    return no_scratch_check(p);
 }
 
 // ------------------------------------------------------------ execution
@@ -1386,6 +1465,14 @@ RealArgs resolve_real(const PlanImpl *p, const Pass &ps, const void *in, void *o
     return r;
 }
 
+TransposeArgs resolve_transpose(const PlanImpl *p, const Pass &ps, const void *in, void *out,
+                                void *scratch)
+{
+    TransposeArgs t = ps.t;
+    t.data = resolve_buf(p, ps.dst, ps.dst_off, in, out, scratch);
+    return t;
+}
+
 size_t generic_lds_bytes(const Pass &ps)
 {
     return tile_lds_bytes(ps.a.n, ps.a.bt, ps.prec);
@@ -1399,6 +1486,8 @@ int run_plan(const PlanImpl *p, const void *in, void *out, void *scratch, hipStr
             e = launch_copy(resolve_copy(p, ps, in, out, scratch), s);
         } else if (ps.kind == 2) {
             e = launch_real(resolve_real(p, ps, in, out, scratch), p->prob.prec, s);
+        } else if (ps.kind == 3) {
+            e = launch_transpose_sq(resolve_transpose(p, ps, in, out, scratch), s);
         } else {
             const PassArgs a = resolve_pass(p, ps, in, out, scratch);
             if (ps.kernel == 1)

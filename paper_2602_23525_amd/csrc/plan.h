@@ -47,10 +47,12 @@ std::string problem_key(const Problem &p);
 enum : int { BUF_IN = 0, BUF_OUT = 1, BUF_SCRATCH = 2 };
 
 struct Pass {
-    int kind = 0;            // 0 = FFT tile pass, 1 = rank-0 copy, 2 = real-data step
+    int kind = 0;            // 0 = FFT tile pass, 1 = rank-0 copy, 2 = real-data step,
+                             // 3 = in-place square transpose
     PassArgs a{};            // pointers filled at execute time (except tables)
     CopyArgs c{};
     RealArgs r{};
+    TransposeArgs t{};
     int src = BUF_IN, dst = BUF_OUT;
     int64_t src_off = 0, dst_off = 0;       // complex elements (scratch: region offset)
     int64_t aux_off = -1;                    // bytes into scratch for Rader aux, or -1
@@ -124,6 +126,8 @@ int run_plan(const PlanImpl *p, const void *in, void *out, void *scratch, hipStr
 PassArgs resolve_pass(const PlanImpl *p, const Pass &ps, const void *in, void *out, void *scratch);
 CopyArgs resolve_copy(const PlanImpl *p, const Pass &ps, const void *in, void *out, void *scratch);
 RealArgs resolve_real(const PlanImpl *p, const Pass &ps, const void *in, void *out, void *scratch);
+TransposeArgs resolve_transpose(const PlanImpl *p, const Pass &ps, const void *in, void *out,
+                                void *scratch);
 // LDS bytes the generic tile kernel needs for a pass.
 size_t generic_lds_bytes(const Pass &ps);
 

@@ -39,11 +39,13 @@ def note(msg: str):
 
 
 def run_case(dims, hdims=(), sign=-1, prec=0, inplace=False, seed=0, pad=3, check_guard=True,
-             method="auto", sample=None, tol=None, name="", expect=None):
+             method="auto", sample=None, tol=None, name="", expect=None, flags=0,
+             check_info=None):
     """Execute on the GPU and compare with the oracle; returns (relrms, maxerr).
 
     `sample`: list of vector multi-indices to compare (full-size runs); None =
-    the whole problem.  `expect`: a substring the plan description must hold.
+    the whole problem.  `expect`: a substring the plan description must hold;
+    `check_info`: a callable given the plan info; `flags`: planner flags.
     """
     import torch
 
@@ -72,7 +74,7 @@ def run_case(dims, hdims=(), sign=-1, prec=0, inplace=False, seed=0, pad=3, chec
         yt = xt
     else:
         yt = torch.full((out_len,), complex(float("nan"), float("nan")), dtype=tdt, device=dev)
-    plan = mfft.Plan(dims, hdims, inplace=inplace, sign=sign, prec=prec)
+    plan = mfft.Plan(dims, hdims, inplace=inplace, sign=sign, prec=prec, flags=flags)
     eb = 8 if prec == 0 else 16
     plan.execute(xt.data_ptr() + eb * in_off, yt.data_ptr() + eb * out_off)
     torch.cuda.synchronize()
@@ -81,6 +83,8 @@ def run_case(dims, hdims=(), sign=-1, prec=0, inplace=False, seed=0, pad=3, chec
     plan.destroy()
     if expect is not None:
         assert expect in info["desc"], f"plan lacks {expect!r}:\n{info['desc']}"
+    if check_info is not None:
+        check_info(info)
 
     x64 = x.astype(np.complex128)
     if not inplace:

@@ -72,7 +72,7 @@ def test_plan_without_gpu_fails_cleanly():
     assert e.value.code == -4      # MFFT_EHIP
 
 
-@pytest.mark.parametrize("flags,prec", [(16, 0), (1 << 31, 0), (8, 1)])
+@pytest.mark.parametrize("flags,prec", [(32, 0), (1 << 31, 0), (8, 1)])
 def test_plan_rejects_bad_flags_before_device_work(flags, prec):
     # unknown flag bits, and the FP32-twiddle ablation on an FP64 plan
     with pytest.raises(mfft.MfftError) as e:
@@ -107,3 +107,12 @@ def test_wisdom_roundtrip_text():
 ])
 def test_problem_check_real(kind, dims, hdims, inplace, prec, expect):
     assert mfft.mfft_problem_check_real(kind, dims, hdims, inplace, prec) == expect
+
+
+def test_flag_constants_match_header():
+    import re
+    text = open(mfft.HEADER_PATH).read()
+    for name in ("MEASURE", "WISDOM_ONLY", "NO_WISDOM", "FP32_TWIDDLES", "NO_SCRATCH"):
+        m = re.search(r"#define MFFT_%s +(\d+)u" % name, text)
+        assert m, name
+        assert int(m.group(1)) == getattr(mfft, name), name

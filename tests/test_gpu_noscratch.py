@@ -1,0 +1,93 @@
+"""GPU tests of in-place plans without scratch (MFFT_NO_SCRATCH; Section
+4.2's in-place plans): n = q*q as columns with the twiddle, rows, and an
+in-place q x q transpose, all in the caller's buffer, against the FP64
+oracle; problems without such a plan are refused."""
+import numpy as np
+import pytest
+
+import oracle
+from synth import uniform_complex
+from tests.gpu_util import run_case
+
+pytestmark = pytest.mark.gpu
+
+
+def _no_scratch(passes):
+    def check(info):
+        assert info["scratch_bytes"] == 0, info
+        assert info["n_passes"] == passes, info["desc"]
+        assert "transpose" in info["desc"], info["desc"]
+    return check
+
+
+# lengths that do not fit one pass: 128^2 (FP64 only), 256^2, 512^2, 1024^2
+@pytest.mark.parametrize("n,prec", [(65536, 0), (262144, 0), (1048576, 0), (16384, 1),
+                                    (65536, 1), (1048576, 1)])
+@pytest.mark.parametrize("sign", [-1, 1])
+def test_square_inplace_without_scratch(n, prec, sign):
+    import paper_2602_23525_amd as mfft
+    b = 3 if n <= 65536 else 2
+    run_case([(n, 1, 1)], [(b, n, n)], prec=prec, sign=sign, inplace=True, seed=n + b,
+             name=f"noscratch {n}", flags=mfft.NO_SCRATCH, check_info=_no_scratch(3),
+             expect="leaf kernel columns")
+
+
+def test_square_inplace_without_scratch_mixed_radix_and_strided():
+    import paper_2602_23525_amd as mfft
+    # 90000 = 300^2 (generic kernels), transforms at stride 2 interleaved with
+    # a second batch dimension
+    run_case([(90000, 1, 1)], [(2, 90000, 90000)], inplace=True, seed=5,
+             name="noscratch 300^2", flags=mfft.NO_SCRATCH, check_info=_no_scratch(3))
+    run_case([(65536, 2, 2)], [(2, 1, 1), (3, 131072, 131072)], inplace=True, seed=6,
+             name="noscratch strided", flags=mfft.NO_SCRATCH, check_info=_no_scratch(3))
+
+
+def test_multidim_inplace_without_scratch():
+    import paper_2602_23525_amd as mfft
+    # 2-D 5 x 65536 in place: the long dimension by the square plan, the other
+    # as one leaf pass
+    run_case([(5, 65536, 65536), (65536, 1, 1)], [], inplace=True, seed=7,
+             name="noscratch 2d", flags=mfft.NO_SCRATCH, check_info=_no_scratch(4))
+
+
+@pytest.mark.parametrize("dims,hdims", [
+    ([(32768, 1, 1)], [(2, 32768, 32768)]),          # not a square
+    ([(65537, 1, 1)], [(2, 65537, 65537)]),          # Rader needs a convolution buffer
+    ([(64, 1, 8)], [(8, 64, 1)]),                    # in place, different strides
+])
+def test_refused_without_scratch(dims, hdims):
+    import paper_2602_23525_amd as mfft
+    with pytest.raises(mfft.MfftError) as e:
+        mfft.Plan(dims, hdims, inplace=True, flags=mfft.NO_SCRATCH)
+    assert e.value.code == -2   # MFFT_ENOTSUP
+
+
+def test_out_of_place_needs_no_scratch():
+    import paper_2602_23525_amd as mfft
+    p = mfft.Plan([(65536, 1, 1)], [(2, 65536, 65536)], flags=mfft.NO_SCRATCH)
+    assert p.info()["scratch_bytes"] == 0 and p.info()["n_passes"] == 2
+    p.destroy()
+
+
+def test_batch_with_a_plan_without_scratch():
+    import torch
+
+    import paper_2602_23525_amd as mfft
+    n, b = 65536, 2
+    x1 = uniform_complex(n * b, seed=21, dtype=np.complex64)
+    x2 = uniform_complex(1000 * 3, seed=22, dtype=np.complex64)
+    t1 = torch.from_numpy(x1).cuda()
+    t2 = torch.from_numpy(x2).cuda()
+    y2 = torch.empty_like(t2)
+    p1 = mfft.Plan([(n, 1, 1)], [(b, n, n)], inplace=True, flags=mfft.NO_SCRATCH)
+    p2 = mfft.Plan([(1000, 1, 1)], [(3, 1000, 1000)])
+    bt = mfft.Batch([p1, p2], [t1, t2], [t1, y2], graph=True)
+    bt.execute()
+    torch.cuda.synchronize()
+    r1 = oracle.fft(x1.astype(np.complex128).reshape(b, n))
+    r2 = oracle.fft(x2.astype(np.complex128).reshape(3, 1000))
+    assert oracle.rel_rms(t1.cpu().numpy().reshape(b, n), r1) <= 2e-6
+    assert oracle.rel_rms(y2.cpu().numpy().reshape(3, 1000), r2) <= 2e-6
+    bt.destroy()
+    p1.destroy()
+    p2.destroy()
