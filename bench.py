@@ -96,7 +96,8 @@ def cpu_baseline(x, dims, hdims, sign, n_total, howmany, budget_s=30.0):
 
 def run_uneven(args):
     """Uneven batch: `items` 1-D FP32 transforms of log-uniform sizes 64..65536
-    (60% powers of two, 30% 7-smooth, 10% primes), batch 1..32 each, executed
+    (60% powers of two, 30% 7-smooth, 10% primes), batch 1..32 each, packed at
+    256-byte aligned offsets of one input and one output buffer, executed
     (a) as one batch (persistent launches, HIP graph) and (b) one plan per
     launch on one stream."""
     import numpy as np
@@ -106,10 +107,14 @@ def run_uneven(args):
     from synth import uneven_batch
 
     items = uneven_batch(count=args.items, seed=4)
+    # items at 256-byte aligned offsets (as separate allocations would be):
+    # column passes move 128-byte runs, which straddle two cache lines when
+    # an item starts off a line boundary
     offs, tot = [], 0
     for it in items:
         offs.append(tot)
         tot += it.n * it.batch
+        tot = (tot + 31) // 32 * 32
     dev = torch.device("cuda", 0)
     g = torch.Generator(device=dev)
     g.manual_seed(4)
@@ -128,7 +133,8 @@ def run_uneven(args):
     batch_s = time.perf_counter() - t0
     binfo = batch.info()
     flops = sum(5.0 * it.n * math.log2(it.n) * it.batch for it in items)
-    comp = 2.0 * 8 * tot
+    npts = sum(it.n * it.batch for it in items)
+    comp = 2.0 * 8 * npts
     stream = torch.cuda.current_stream()
 
     def timed(fn, reps):
@@ -169,7 +175,7 @@ def run_uneven(args):
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_batch, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"uneven_batch_{len(items)}", "points": tot,
+        "config": {"workload": f"uneven_batch_{len(items)}", "points": npts,
                    "plan_seconds": round(plan_s, 2), "batch_create_seconds": round(batch_s, 3),
                    "launches_per_step": binfo["launches"], "tiles": binfo["tiles"],
                    "plain_ms_per_step": round(ms_plain, 3),

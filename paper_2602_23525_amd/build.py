@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libmfft.so")
 SOURCES = [
     "k_c32_k0.hip", "k_c32_k1.hip", "k_c32_k5.hip", "k_c32_k7.hip", "k_c64_k0.hip",
     "k_c64_k1.hip", "k_c64_k5.hip", "k_c64_k7.hip",
-    "k_leaf.hip", "kernels.hip", "problem.cpp", "plan.cpp", "tune.cpp", "api.cpp", "batch.cpp", "server.cpp",
+    "k_leaf.hip", "k_leaf_batch.hip", "kernels.hip", "problem.cpp", "plan.cpp", "tune.cpp", "api.cpp", "batch.cpp", "server.cpp",
 ]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

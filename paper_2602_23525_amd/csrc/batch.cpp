@@ -66,6 +66,9 @@ int build_batch_layout(const std::vector<BatchItem> &items, BatchLayout *L)
     std::map<int, std::vector<std::pair<RealArgs, int>>> reals;
     std::map<int, std::vector<TransposeArgs>> transposes;
     std::map<int, std::vector<BatchStep>> leaves;
+    // specialized leaf passes: one launch per phase, precision, length and tile kind
+    using LKey = std::tuple<int, int, int, int>;   // phase, prec, n, mode
+    std::map<LKey, std::vector<PassArgs>> leaffam;
     int nphase = 0;
     for (const BatchItem &it : items) {
         const PlanImpl *p = it.plan;
@@ -97,6 +100,13 @@ int build_batch_layout(const std::vector<BatchItem> &items, BatchLayout *L)
                 leaves[(int)k].push_back(st);
                 continue;
             }
+            if (ps.kernel == 1 && a.vn >= a.bt) {
+                // full leaf tiles: the batched leaf launch (a pass with fewer
+                // lines than a leaf tile goes to the tile kernel, whose tiles
+                // shrink to the lines present)
+                leaffam[LKey{(int)k, ps.prec, (int)a.n, leaf_batch_mode(a.flags)}].push_back(a);
+                continue;
+            }
             size_t lds = 0;
             const int block = widen(ps, &a, &lds);
             const Key key{(int)k, p->prob.prec, pass_kind(a.flags), block};
@@ -111,6 +121,14 @@ int build_batch_layout(const std::vector<BatchItem> &items, BatchLayout *L)
                          [](const Item &x, const Item &y) { return x.n > y.n; });
         bytes += kv.second.size() * sizeof(PassArgs) + 256;
         bytes += (kv.second.size() + 1) * sizeof(int64_t) + 256;
+    }
+    for (auto &kv : leaffam) {
+        bytes += kv.second.size() * sizeof(PassArgs) + 256;
+        bytes += (kv.second.size() + 1) * sizeof(int64_t) + 256;
+        int64_t t = 0;
+        for (const PassArgs &a : kv.second) t += a.ntiles;
+        if (t > 0x7fffffffLL) return fail(MFFT_ENOTSUP, "batched leaf launch too large");
+        bytes += (size_t)t * sizeof(int32_t) + 256;
     }
     L->host.assign(bytes, 0);
     size_t off = 0;
@@ -149,6 +167,32 @@ int build_batch_layout(const std::vector<BatchItem> &items, BatchLayout *L)
         g.grid = (int)std::max<int64_t>(1, std::min<int64_t>(g.tiles, resident));
         L->groups.push_back(g);
     }
+    std::map<int, std::vector<int>> leaf_groups;   // phase -> group indices
+    for (auto &kv : leaffam) {
+        BatchGroup g;
+        g.items_off = take(kv.second.size() * sizeof(PassArgs));
+        g.prefix_off = take((kv.second.size() + 1) * sizeof(int64_t));
+        PassArgs *dst = (PassArgs *)(L->host.data() + g.items_off);
+        int64_t *prefix = (int64_t *)(L->host.data() + g.prefix_off);
+        prefix[0] = 0;
+        for (size_t j = 0; j < kv.second.size(); ++j) {
+            dst[j] = kv.second[j];
+            prefix[j + 1] = prefix[j] + kv.second[j].ntiles;
+        }
+        g.prec = std::get<1>(kv.first);
+        g.leaf_n = std::get<2>(kv.first);
+        g.leaf_mode = std::get<3>(kv.first);
+        g.nitems = (int)kv.second.size();
+        g.tiles = prefix[g.nitems];
+        g.grid = (int)g.tiles;
+        g.owner_off = take((size_t)g.tiles * sizeof(int32_t));
+        int32_t *owner = (int32_t *)(L->host.data() + g.owner_off);
+        for (int j = 0; j < g.nitems; ++j)
+            for (int64_t t = prefix[j]; t < prefix[j + 1]; ++t) owner[t] = j;
+        L->tiles += g.tiles;
+        leaf_groups[std::get<0>(kv.first)].push_back((int)L->groups.size());
+        L->groups.push_back(g);
+    }
     L->bytes = off;
     for (int k = 0; k < nphase; ++k) {
         for (const CopyArgs &c : copies[k]) {
@@ -169,6 +213,11 @@ int build_batch_layout(const std::vector<BatchItem> &items, BatchLayout *L)
             BatchStep st;
             st.transpose = true;
             st.t = t;
+            L->steps.push_back(st);
+        }
+        for (int gi : leaf_groups[k]) {
+            BatchStep st;
+            st.group = gi;
             L->steps.push_back(st);
         }
         for (size_t gi = 0; gi < order.size(); ++gi)
@@ -197,6 +246,12 @@ int enqueue_batch_layout(const BatchLayout &L, char *dev, hipStream_t s)
             e = launch_transpose_sq(st.t, s);
         } else if (st.leaf) {
             e = launch_leaf(st.a, st.prec, st.a.n, st.leaf_variant, st.leaf_grid, s);
+        } else if (L.groups[st.group].leaf_n > 0) {
+            const BatchGroup &g = L.groups[st.group];
+            e = launch_leaf_batch((const PassArgs *)(dev + g.items_off),
+                                  (const int64_t *)(dev + g.prefix_off),
+                                  (const int32_t *)(dev + g.owner_off), g.tiles, g.prec, g.leaf_n,
+                                  g.leaf_mode, s);
         } else {
             const BatchGroup &g = L.groups[st.group];
             e = launch_batch((const PassArgs *)(dev + g.items_off),

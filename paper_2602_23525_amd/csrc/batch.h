@@ -15,12 +15,14 @@ struct BatchItem {
 };
 
 struct BatchGroup {
+    int leaf_n = 0, leaf_mode = 0;   // leaf_n > 0: a batched leaf launch (one tile per workgroup)
     int prec = 0, kind = 0, block = 0;
     size_t lds = 0;
     int grid = 0;
     int nitems = 0;
     int64_t tiles = 0;
     size_t items_off = 0, prefix_off = 0, counter_off = 0;   // offsets in the image
+    size_t owner_off = 0;   // batched leaf: the item of each tile (int32)
 };
 
 struct BatchStep {   // one launch: a group, a copy pass, a real-data step or a transpose

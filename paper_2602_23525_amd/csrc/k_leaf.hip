@@ -56,16 +56,10 @@ static int dispatch(int kind, const PassArgs &a, int n, int grid, hipStream_t s,
     return 0;
 }
 
-// Column tiles (PF_LEAF_COL): BT adjacent lines, so that each load and store
-// instruction of a wave moves runs of BT elements: 64 lines of 64 points up
-// to 16 of 256 (FP32; half as many in FP64, same bytes), then 16 / 8 (FP32)
-// and 8 / 4 (FP64) lines as the LDS allows.  One tile per workgroup,
-// non-temporal loads and stores, as the row default.
-constexpr int col_lines(int prec, int n)
-{
-    if (prec == 0) return n <= 256 ? 4096 / n : (n <= 512 ? 16 : 8);
-    return n <= 256 ? 2048 / n : (n <= 512 ? 8 : 4);
-}
+// Column tiles (PF_LEAF_COL, ...): leaf_col_lines adjacent lines, so that each
+// load and store instruction of a wave moves runs of that many elements.  One
+// tile per workgroup, non-temporal loads and stores, as the row default.
+constexpr int col_lines(int prec, int n) { return leaf_col_lines(prec, n); }
 
 // RD 3: columns in and out (64-2048 points); 4 / 5: columns in, rows out and
 // the reverse (256-2048 points, so that a row run is at least 16 lanes)
@@ -110,11 +104,7 @@ bool leaf_col_supported(int prec, int64_t n, bool transposing)
 
 int leaf_max_n(int) { return 4096; }
 
-int leaf_lines_per_tile(int prec, int n)
-{
-    const int lines = (prec == 0 ? 256 : 128) * 16 / n;
-    return lines > 0 ? lines : 1;
-}
+int leaf_lines_per_tile(int prec, int n) { return leaf_row_lines(prec, n); }
 
 bool leaf_supported(int prec, int64_t n)
 {

@@ -94,4 +94,11 @@ int leaf_col_lines_per_tile(int prec, int n);
 // variant bit 0: prefetch next tile; bit 1: lower occupancy floor (more VGPRs)
 int leaf_blocks_per_cu(int prec, int n, int variant);
 hipError_t launch_leaf(const PassArgs &a, int prec, int n, int variant, int grid, hipStream_t s);
+// Leaf passes of one length and tile kind (mode: 0 rows, 3 columns, 4 columns
+// in / rows out, 5 rows in / columns out; leaf_batch_mode of the pass flags)
+// from many plans in one launch: items[i] with prefix[i] = tiles before item
+// i, owner[t] = the item of tile t.
+int leaf_batch_mode(uint32_t flags);
+hipError_t launch_leaf_batch(const PassArgs *items, const int64_t *prefix, const int32_t *owner,
+                             int64_t tiles, int prec, int n, int mode, hipStream_t s);
 }  // namespace mfft

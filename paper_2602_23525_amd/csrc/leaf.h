@@ -192,13 +192,31 @@ __device__ __forceinline__ void st_elem(cpx<T> *p, cpx<T> v)
 // WPE: occupancy floor in waves per SIMD (caps VGPRs at 512 / WPE).
 // NT: bit 0 streams the output with non-temporal stores, bit 1 the input with
 // non-temporal loads (neither is reused by this pass).
-template <typename T, int N, int BT, bool PF, int WPE, int NT, int RD, int... Rs>
-__global__ __launch_bounds__(BT *N / 16) __attribute__((amdgpu_waves_per_eu(WPE))) void leaf_kernel(PassArgs)
+template <int N>
+constexpr int leaf_lds_stride() { return (lds_pad(N - 1) + 1) | 1; }
+
+// Lines per tile.  Row tiles: 256 threads (FP32) or 128 (FP64) of 16 elements,
+// at least one line (n = 4096 FP64: one line of 256 threads).  Column tiles:
+// 64 lines of 64 points up to 16 of 256 (FP32; half as many in FP64, same
+// bytes), then 16 / 8 (FP32) and 8 / 4 (FP64) lines as the LDS allows.
+constexpr int leaf_row_lines(int prec, int n)
+{
+    return (prec == 0 ? 4096 : 2048) / n > 0 ? (prec == 0 ? 4096 : 2048) / n : 1;
+}
+constexpr int leaf_col_lines(int prec, int n)
+{
+    if (prec == 0) return n <= 256 ? 4096 / n : (n <= 512 ? 16 : 8);
+    return n <= 256 ? 2048 / n : (n <= 512 ? 8 : 4);
+}
+
+// The leaf pass from tile `tile` on, every G-th tile, with the tile's LDS at
+// lds (BT lines of leaf_lds_stride<N>() elements).
+template <typename T, int N, int BT, bool PF, int NT, int RD, int... Rs>
+__device__ __forceinline__ void leaf_body(const PassArgs &a, cpx<T> *lds, int64_t tile,
+                                          const int64_t G)
 {
     constexpr int TPT = N / 16;
-    constexpr int STRIDE = (lds_pad(N - 1) + 1) | 1;
-    __shared__ cpx<T> lds[BT * STRIDE];
-    const PassArgs &a = *(const PassArgs *)__builtin_amdgcn_kernarg_segment_ptr();
+    constexpr int STRIDE = leaf_lds_stride<N>();
     constexpr bool cols_in = RD == 3 || RD == 4, cols_out = RD == 3 || RD == 5;
     constexpr bool xpose = cols_in != cols_out;
     static_assert(!(xpose && PF), "transposing tiles are one tile per workgroup");
@@ -324,8 +342,6 @@ __global__ __launch_bounds__(BT *N / 16) __attribute__((amdgpu_waves_per_eu(WPE)
         __syncthreads();
     };
 
-    const int64_t G = gridDim.x;
-    int64_t tile = blockIdx.x;
     if (tile >= a.ntiles) return;
     int64_t ib, ob;
     bool ok;
@@ -408,6 +424,31 @@ __global__ __launch_bounds__(BT *N / 16) __attribute__((amdgpu_waves_per_eu(WPE)
             if constexpr (!c2r) load_line(x, ib);
         }
     }
+}
+
+template <typename T, int N, int BT, bool PF, int WPE, int NT, int RD, int... Rs>
+__global__ __launch_bounds__(BT *N / 16) __attribute__((amdgpu_waves_per_eu(WPE))) void leaf_kernel(PassArgs)
+{
+    __shared__ cpx<T> lds[BT * leaf_lds_stride<N>()];
+    const PassArgs &a = *(const PassArgs *)__builtin_amdgcn_kernarg_segment_ptr();
+    leaf_body<T, N, BT, PF, NT, RD, Rs...>(a, lds, blockIdx.x, gridDim.x);
+}
+
+// Leaf passes of one length and tile kind from many plans in one launch (a
+// batch across plans): one tile per workgroup, tiles numbered pass by pass
+// (prefix[i] = tiles of passes before i, owner[t] = the pass of tile t, so a
+// workgroup finds its pass with one load instead of a search); the workgroup
+// runs that pass's tile with the pass's own arguments.  Non-temporal loads and
+// stores, as the one-pass default.
+template <typename T, int N, int BT, int RD, int... Rs>
+__global__ __launch_bounds__(BT *N / 16) __attribute__((amdgpu_waves_per_eu(2))) void leaf_batch_kernel(
+    const PassArgs *__restrict__ items, const int64_t *__restrict__ prefix,
+    const int32_t *__restrict__ owner)
+{
+    __shared__ cpx<T> lds[BT * leaf_lds_stride<N>()];
+    const int64_t tile = blockIdx.x;
+    const int i = owner[tile];
+    leaf_body<T, N, BT, false, 3, RD, Rs...>(items[i], lds, tile - prefix[i], int64_t(1) << 62);
 }
 
 }  // namespace mfft

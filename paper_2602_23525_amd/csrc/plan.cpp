@@ -578,8 +578,11 @@ static bool choose_split(int64_t n, int prec, Split *sp)
         if (n % m) continue;
         const int64_t r = n / m;
         if (!leaf_fits(m, prec, btmin) || !leaf_fits(r, prec, btmin)) continue;
+        // most balanced split; of two mirror splits the one with the longer
+        // first pass (a power-of-two first pass of 256 points or more runs in
+        // the leaf kernel's transposing tiles)
         const double cost = std::fabs(std::log((double)m) - std::log((double)r));
-        if (cost < best) {
+        if (cost <= best) {
             best = cost;
             best_m = m;
         }

@@ -78,17 +78,20 @@ __device__ __forceinline__ void issue_plain(const PassArgs &a, const Tile<T> &tl
     const cpx<T> *p0 = (const cpx<T> *)a.in + tl.ob_in + (c < a.vn ? c : tl.c0) * a.vis +
                        (int64_t)idx0 * a.is;
     const int64_t pst = (int64_t)step * a.is;
+    // slots past ceil(n / step) hold no element of any lane: skipped by a
+    // uniform branch rather than loaded from p0
+    const int kn = (n + step - 1) / step;
     const cpx<T> *p = p0;
     if (a.flags & PF_NT_IN) {
 #pragma unroll
         for (int k = 0; k < KMAX; ++k) {
-            r[k] = ld_nt(idx0 + k * step < n ? p : p0);
+            if (k < kn) r[k] = ld_nt(idx0 + k * step < n ? p : p0);
             p += pst;
         }
     } else {
 #pragma unroll
         for (int k = 0; k < KMAX; ++k) {
-            r[k] = *(idx0 + k * step < n ? p : p0);
+            if (k < kn) r[k] = *(idx0 + k * step < n ? p : p0);
             p += pst;
         }
     }
