@@ -193,6 +193,63 @@ def run_uneven(args):
     print(json.dumps(out), flush=True)
 
 
+def run_planner(args):
+    """Estimate vs measure (Section 4.3): for each workload, time the plan the
+    estimate mode picks and the one measure mode picks (both on the same
+    resident buffers), and report the estimate's time penalty."""
+    import torch
+
+    import paper_2602_23525_amd as mfft
+
+    cases = [(64, 262144, 0), (256, 65536, 0), (1024, 16384, 0), (4096, 4096, 0),
+             (1000, 16384, 0), (2187, 8192, 0), (14175, 1024, 0), (65536, 256, 0),
+             (65537, 256, 0), (4096, 2048, 1), (1024, 8192, 1)]
+    dev = torch.device("cuda", 0)
+    rows = []
+
+    def timed(fn, reps):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    for n, b, prec in cases:
+        dt = torch.complex64 if prec == 0 else torch.complex128
+        x = torch.zeros(n * b, dtype=dt, device=dev)
+        y = torch.empty_like(x)
+        res = {}
+        for name, flags in (("estimate", mfft.ESTIMATE | mfft.NO_WISDOM),
+                            ("measure", mfft.MEASURE | mfft.NO_WISDOM)):
+            t0 = time.perf_counter()
+            p = mfft.Plan([(n, 1, 1)], [(b, n, n)], prec=prec, flags=flags)
+            plan_s = time.perf_counter() - t0
+            ms = timed(lambda: p.execute(x, y), max(5, args.steps // 5))
+            res[name] = (ms, plan_s, p.info()["desc"])
+            p.destroy()
+        rows.append({"n": n, "batch": b, "prec": "c32" if prec == 0 else "c64",
+                     "estimate_ms": round(res["estimate"][0], 4),
+                     "measure_ms": round(res["measure"][0], 4),
+                     "penalty": round(res["estimate"][0] / res["measure"][0], 3),
+                     "measure_plan_s": round(res["measure"][1], 3),
+                     "same_plan": res["estimate"][2] == res["measure"][2]})
+        print(f"planner: {rows[-1]}", file=sys.stderr, flush=True)
+        del x, y
+    pen = [r["penalty"] for r in rows]
+    out = {"metric": "estimate-mode time / measure-mode time", "value": round(max(pen), 3),
+           "unit": "ratio (max over workloads)", "n_gpus": 1, "steps": args.steps,
+           "warmup": 2, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32+f64", "data": "synthetic",
+           "config": {"workload": "planner_estimate_vs_measure", "cases": rows}}
+    print(json.dumps(out))
+
+
 def run_serve(args):
     """Serving: a seeded Poisson trace of FFT requests (rank 1-3, 2^8..2^22
     points, batch 1..64, FP32/FP64 80/20, forward/inverse 50/50) replayed
@@ -355,6 +412,8 @@ def main():
     if args.workload == "serve":
         args.items = args.items or 2000
         return run_serve(args)
+    if args.workload == "planner":
+        return run_planner(args)
 
     import numpy as np
     import torch

@@ -265,12 +265,14 @@ static int fill_leaf(PlanImpl *p, const Leaf &L, PassArgs *a,
 // ------------------------------------------------------------ leaf variants
 
 // Estimate-mode choice of the leaf kernel variant (measured on MI355X over
-// batched unit-stride transforms of 64 to 4096 points, both precisions): one
-// tile per workgroup with non-temporal loads and stores (neither the input
-// nor the output of the pass is reused by it) is fastest at every length.
-LeafTune leaf_default(int, int)
+// batched unit-stride transforms of 64 to 4096 points, both precisions, 16 MB
+// to 512 MB per buffer, executed repeatedly on the same buffers): one tile
+// per workgroup; stores non-temporal, loads too once a buffer exceeds the
+// 256 MB last-level cache (a smaller input is usually still there from the
+// kernel that wrote it, and cached loads then run 5-15% faster).
+LeafTune leaf_default(int, int, double in_bytes)
 {
-    return {24, 0};
+    return {in_bytes > 256.0 * 1024 * 1024 ? 24 : 8, 0};
 }
 
 void apply_leaf_tune(Pass *ps, const LeafTune &t)
@@ -496,7 +498,7 @@ static int add_line_pass(Builder &b, const LineSpec &ls)
         a.ntiles_inner = (a.vn + a.bt - 1) / a.bt;
         a.ntiles = a.ntiles_inner * nouter_total;
         ps.lds_bytes = 0;
-        LeafTune t = leaf_default(prec, (int)n);
+        LeafTune t = leaf_default(prec, (int)n, (double)a.vn * nouter_total * n * elem_bytes(prec));
         apply_leaf_tune(&ps, t);
     } else if (leaf_col_fits(ls, a, in_dim, prec, n)) {
         // adjacent lines with strided elements (columns of a row-major array)
@@ -509,7 +511,7 @@ static int add_line_pass(Builder &b, const LineSpec &ls)
         a.ntiles_inner = (a.vn + a.bt - 1) / a.bt;
         a.ntiles = a.ntiles_inner * nouter_total;
         ps.lds_bytes = 0;
-        apply_leaf_tune(&ps, leaf_default(prec, (int)n));
+        apply_leaf_tune(&ps, leaf_default(prec, (int)n, (double)a.vn * nouter_total * n * elem_bytes(prec)));
     }
     ps.src = ls.src;
     ps.dst = ls.dst;

@@ -110,7 +110,7 @@ void dev_free(PlanImpl *p, void *ptr, size_t bytes);
 
 // Build the pass list and tables of a plan (Section 4.2 plan steps).
 int build_plan(PlanImpl *p);
-LeafTune leaf_default(int prec, int n);
+LeafTune leaf_default(int prec, int n, double in_bytes);
 void apply_leaf_tune(Pass *ps, const LeafTune &t);
 
 // Planner rigor (Section 4.3): time the candidate kernel variants of every
