@@ -47,17 +47,11 @@ struct Tile {
     cpx<T> x0, a0;      // Rader: x[0] and the zero-frequency sum of the permuted input
 };
 
-// Element access that marks the data as not reused (PF_NT_IN / PF_NT_OUT).
+// Element load that marks the data as not reused (PF_NT_IN).
 template <typename T>
 __device__ __forceinline__ cpx<T> ld_nt(const cpx<T> *p)
 {
     return {__builtin_nontemporal_load(&p->re), __builtin_nontemporal_load(&p->im)};
-}
-template <typename T>
-__device__ __forceinline__ void st_nt(cpx<T> *p, cpx<T> v)
-{
-    __builtin_nontemporal_store(v.re, &p->re);
-    __builtin_nontemporal_store(v.im, &p->im);
 }
 
 // Elements per chunk of the table-driven (K_EXT) stores.
@@ -235,8 +229,7 @@ __device__ __forceinline__ void store_run(const PassArgs &a, const Tile<T> &tl, 
                 if (f & PF_POST_MUL) v = cmul(v, pm[q]);
                 if (f & (PF_RADER | PF_AUX_ADD)) v = cadd(v, tl.x0);
                 if (f & PF_CONJ_OUT) v = conj(v);
-                if (f & PF_NT_OUT) st_nt(&out[(int64_t)e[q] * a.os], v);
-                else out[(int64_t)e[q] * a.os] = v;
+                out[(int64_t)e[q] * a.os] = v;
                 if ((f & (PF_RADER | PF_AUX_ADD)) && lo[q] == 0) {
                     cpx<T> y0 = cadd(tl.x0, tl.a0);
                     if (f & PF_CONJ_OUT) y0 = conj(y0);
@@ -249,18 +242,10 @@ __device__ __forceinline__ void store_run(const PassArgs &a, const Tile<T> &tl, 
             const bool cj = (f & PF_CONJ_OUT) != 0;
             const int64_t pst = (int64_t)ks * a.os;
             cpx<T> *p = out + (int64_t)k0 * a.os;
-            if (f & PF_NT_OUT) {
 #pragma unroll
-                for (int m = 0; m < M; ++m) {
-                    if (!CHECK || k0 + m * ks < n) st_nt(p, cj ? conj(y[m]) : y[m]);
-                    p += pst;
-                }
-            } else {
-#pragma unroll
-                for (int m = 0; m < M; ++m) {
-                    if (!CHECK || k0 + m * ks < n) *p = cj ? conj(y[m]) : y[m];
-                    p += pst;
-                }
+            for (int m = 0; m < M; ++m) {
+                if (!CHECK || k0 + m * ks < n) *p = cj ? conj(y[m]) : y[m];
+                p += pst;
             }
         }
     }
