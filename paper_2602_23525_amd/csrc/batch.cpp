@@ -6,8 +6,8 @@
 // kernel family (precision, feature kind, workgroup-size class) become one
 // launch of the persistent tile kernel over a device descriptor list.  Tiles
 // are numbered item by item, items ordered by line length, largest first, and
-// workgroups pop tile indices from a counter, so long lines start early and
-// short ones fill the tail.  Phases run in order on the stream, so pass k+1 of
+// workgroups pop tile indices from a counter (and find the tile's item in a
+// tile-to-item table), so long lines start early and short ones fill the tail.  Phases run in order on the stream, so pass k+1 of
 // a plan always sees pass k complete.  Counters are cleared by a kernel (not a
 // memset) so that the whole sequence can be captured in a HIP graph.
 #include <hip/hip_runtime.h>
@@ -121,6 +121,10 @@ int build_batch_layout(const std::vector<BatchItem> &items, BatchLayout *L)
                          [](const Item &x, const Item &y) { return x.n > y.n; });
         bytes += kv.second.size() * sizeof(PassArgs) + 256;
         bytes += (kv.second.size() + 1) * sizeof(int64_t) + 256;
+        int64_t t = 0;
+        for (const Item &it : kv.second) t += it.a.ntiles;
+        if (t > 0x7fffffffLL) return fail(MFFT_ENOTSUP, "batched launch too large");
+        bytes += (size_t)t * sizeof(int32_t) + 256;
     }
     for (auto &kv : leaffam) {
         bytes += kv.second.size() * sizeof(PassArgs) + 256;
@@ -161,6 +165,10 @@ int build_batch_layout(const std::vector<BatchItem> &items, BatchLayout *L)
         g.lds = fam_lds[kv.first];
         g.nitems = (int)kv.second.size();
         g.tiles = prefix[g.nitems];
+        g.owner_off = take((size_t)g.tiles * sizeof(int32_t));
+        int32_t *owner = (int32_t *)(L->host.data() + g.owner_off);
+        for (int j = 0; j < g.nitems; ++j)
+            for (int64_t t = prefix[j]; t < prefix[j + 1]; ++t) owner[t] = j;
         L->tiles += g.tiles;
         const int64_t resident =
             (int64_t)batch_blocks_per_cu(g.prec, g.kind, g.block, g.lds) * g_num_cus;
@@ -255,7 +263,8 @@ int enqueue_batch_layout(const BatchLayout &L, char *dev, hipStream_t s)
         } else {
             const BatchGroup &g = L.groups[st.group];
             e = launch_batch((const PassArgs *)(dev + g.items_off),
-                             (const int64_t *)(dev + g.prefix_off), g.nitems,
+                             (const int64_t *)(dev + g.prefix_off),
+                             (const int32_t *)(dev + g.owner_off), g.tiles,
                              (unsigned long long *)(dev + g.counter_off), g.prec, g.kind, g.block,
                              g.grid, g.lds, s);
             if (e != hipSuccess)

@@ -22,7 +22,7 @@ struct BatchGroup {
     int nitems = 0;
     int64_t tiles = 0;
     size_t items_off = 0, prefix_off = 0, counter_off = 0;   // offsets in the image
-    size_t owner_off = 0;   // batched leaf: the item of each tile (int32)
+    size_t owner_off = 0;   // the item of each tile (int32)
 };
 
 struct BatchStep {   // one launch: a group, a copy pass, a real-data step or a transpose

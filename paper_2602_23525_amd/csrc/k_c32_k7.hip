@@ -18,9 +18,9 @@ hipError_t launch_pass_c32_k7(const PassArgs &a, size_t lds, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_batch_c32_k7(const PassArgs *items, const int64_t *prefix, int nitems,
-                                unsigned long long *counter, int block, int grid, size_t lds,
-                                hipStream_t s)
+hipError_t launch_batch_c32_k7(const PassArgs *items, const int64_t *prefix, const int32_t *owner,
+                                int64_t total, unsigned long long *counter, int block, int grid,
+                                size_t lds, hipStream_t s)
 {
     static size_t big = 65536;
     if (lds > big) {
@@ -29,7 +29,7 @@ hipError_t launch_batch_c32_k7(const PassArgs *items, const int64_t *prefix, int
         big = lds;
     }
     hipLaunchKernelGGL((batch_kernel<float, 16, 7>), dim3(grid), dim3(block), lds, s, items,
-                       prefix, nitems, counter);
+                       prefix, owner, total, counter);
     return hipGetLastError();
 }
 

@@ -48,9 +48,9 @@ hipError_t launch_real(const RealArgs &a, int prec, hipStream_t s);
 hipError_t launch_gen_roots(void *out, int prec, int64_t count, int64_t N, hipStream_t s);
 
 hipError_t launch_pass(const PassArgs &a, int prec, int emax, size_t lds_bytes, hipStream_t s);
-hipError_t launch_batch(const PassArgs *items_dev, const int64_t *prefix_dev, int nitems,
-                        unsigned long long *counter, int prec, int kind, int block, int grid,
-                        size_t lds_bytes, hipStream_t s);
+hipError_t launch_batch(const PassArgs *items_dev, const int64_t *prefix_dev,
+                        const int32_t *owner_dev, int64_t total, unsigned long long *counter,
+                        int prec, int kind, int block, int grid, size_t lds_bytes, hipStream_t s);
 int pass_kind(uint32_t flags);
 int batch_blocks_per_cu(int prec, int kind, int block, size_t lds);
 hipError_t launch_copy(const CopyArgs &a, hipStream_t s);

@@ -249,8 +249,9 @@ static inline unsigned blocks_for(int64_t count, int threads)
 #define MFFT_VARIANT(P, K)                                                                   \
     hipError_t launch_pass_##P##_k##K(const PassArgs &a, size_t lds, hipStream_t s);          \
     hipError_t launch_batch_##P##_k##K(const PassArgs *items, const int64_t *prefix,         \
-                                       int nitems, unsigned long long *counter, int block,    \
-                                       int grid, size_t lds, hipStream_t s);     \
+                                       const int32_t *owner, int64_t total,                   \
+                                       unsigned long long *counter, int block, int grid,      \
+                                       size_t lds, hipStream_t s);                            \
     int batch_blocks_per_cu_##P##_k##K(int block, size_t lds);
 MFFT_VARIANT(c32, 0)
 MFFT_VARIANT(c32, 1)
@@ -307,20 +308,22 @@ int batch_blocks_per_cu(int prec, int kind, int block, size_t lds)
     return batch_blocks_per_cu_c64_k7(block, lds);
 }
 
-hipError_t launch_batch(const PassArgs *items_dev, const int64_t *prefix_dev, int nitems,
-                        unsigned long long *counter, int prec, int kind, int block, int grid,
-                        size_t lds_bytes, hipStream_t s)
+hipError_t launch_batch(const PassArgs *items_dev, const int64_t *prefix_dev,
+                        const int32_t *owner_dev, int64_t total, unsigned long long *counter,
+                        int prec, int kind, int block, int grid, size_t lds_bytes, hipStream_t s)
 {
+#define MFFT_BATCH_ARGS items_dev, prefix_dev, owner_dev, total, counter, block, grid, lds_bytes, s
     if (prec == 0) {
-        if (kind == 0) return launch_batch_c32_k0(items_dev, prefix_dev, nitems, counter, block, grid, lds_bytes, s);
-        if (kind == 1) return launch_batch_c32_k1(items_dev, prefix_dev, nitems, counter, block, grid, lds_bytes, s);
-        if (kind == 5) return launch_batch_c32_k5(items_dev, prefix_dev, nitems, counter, block, grid, lds_bytes, s);
-        return launch_batch_c32_k7(items_dev, prefix_dev, nitems, counter, block, grid, lds_bytes, s);
+        if (kind == 0) return launch_batch_c32_k0(MFFT_BATCH_ARGS);
+        if (kind == 1) return launch_batch_c32_k1(MFFT_BATCH_ARGS);
+        if (kind == 5) return launch_batch_c32_k5(MFFT_BATCH_ARGS);
+        return launch_batch_c32_k7(MFFT_BATCH_ARGS);
     }
-    if (kind == 0) return launch_batch_c64_k0(items_dev, prefix_dev, nitems, counter, block, grid, lds_bytes, s);
-    if (kind == 1) return launch_batch_c64_k1(items_dev, prefix_dev, nitems, counter, block, grid, lds_bytes, s);
-    if (kind == 5) return launch_batch_c64_k5(items_dev, prefix_dev, nitems, counter, block, grid, lds_bytes, s);
-    return launch_batch_c64_k7(items_dev, prefix_dev, nitems, counter, block, grid, lds_bytes, s);
+    if (kind == 0) return launch_batch_c64_k0(MFFT_BATCH_ARGS);
+    if (kind == 1) return launch_batch_c64_k1(MFFT_BATCH_ARGS);
+    if (kind == 5) return launch_batch_c64_k5(MFFT_BATCH_ARGS);
+    return launch_batch_c64_k7(MFFT_BATCH_ARGS);
+#undef MFFT_BATCH_ARGS
 }
 
 // Contiguous copy, 16-byte vectors, four per thread: the rank-0 plan of a

@@ -511,7 +511,7 @@ static int add_line_pass(Builder &b, const LineSpec &ls)
         a.ntiles_inner = (a.vn + a.bt - 1) / a.bt;
         a.ntiles = a.ntiles_inner * nouter_total;
         ps.lds_bytes = 0;
-        apply_leaf_tune(&ps, leaf_default(prec, (int)n, (double)a.vn * nouter_total * n * elem_bytes(prec)));
+        apply_leaf_tune(&ps, {24, 0});   // the one configuration of column tiles
     }
     ps.src = ls.src;
     ps.dst = ls.dst;

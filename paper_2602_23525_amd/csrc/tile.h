@@ -586,16 +586,17 @@ __global__ __launch_bounds__(max_block<T>()) void pass_kernel(PassArgs a)
 }
 
 // Persistent batched kernel: workgroups pop tiles from a shared counter until
-// the list is exhausted.  items[i] covers tiles [prefix[i], prefix[i+1]).
+// the list is exhausted.  items[i] covers tiles [prefix[i], prefix[i+1]);
+// owner[t] is the item of tile t, total the number of tiles.
 template <typename T, int EMAX, int KIND>
 __global__ __launch_bounds__(max_block<T>()) void batch_kernel(const PassArgs *__restrict__ items,
-                                                     const int64_t *__restrict__ prefix, int nitems,
-                                                     unsigned long long *counter)
+                                                     const int64_t *__restrict__ prefix,
+                                                     const int32_t *__restrict__ owner,
+                                                     int64_t total, unsigned long long *counter)
 {
     extern __shared__ unsigned char smem[];
     cpx<T> *lds = (cpx<T> *)smem;
     __shared__ long long next;
-    const int64_t total = prefix[nitems];
     for (;;) {
         if (threadIdx.x == 0) next = (long long)atomicAdd(counter, 1ull);
         __syncthreads();
@@ -607,14 +608,9 @@ __global__ __launch_bounds__(max_block<T>()) void batch_kernel(const PassArgs *_
                                     (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)gv));
         __syncthreads();
         if (g >= total) break;
-        // binary search for the item holding tile g
-        int lo = 0, hi = nitems - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (prefix[mid] <= g) lo = mid;
-            else hi = mid - 1;
-        }
-        run_tile<T, EMAX, KIND>(items[lo], g - prefix[lo], lds);
+        // the item holding tile g, from the tile-to-item table
+        const int i = owner[g];
+        run_tile<T, EMAX, KIND>(items[i], g - prefix[i], lds);
     }
 }
 
