@@ -23,6 +23,10 @@ def _items():
         out.append(([(n, 1, 1)], [(b, n, n)] if b > 1 else [], prec, sign, False))
     out.append(([(24, 40, 40), (40, 1, 1)], [], 0, -1, True))            # 2-D in place
     out.append(([(32, 1, 32), (32, 32, 1)], [], 1, -1, False))            # transposed out
+    # leaf-kernel passes with column and transposing tiles, both precisions
+    out.append(([(65536, 1, 1)], [(2, 65536, 65536)], 1, -1, False))
+    out.append(([(64, 4096, 4096), (64, 64, 64), (64, 1, 1)], [], 0, 1, True))   # 3-D in place
+    out.append(([(256, 512, 1), (512, 1, 256)], [], 1, -1, False))        # transposed out
     return out
 
 
@@ -111,3 +115,35 @@ def test_uneven_batch_sample_matches_oracle():
         ref = oracle.fft(x.astype(np.complex128).reshape(it.batch, it.n))
         assert oracle.rel_rms(y.cpu().numpy().reshape(it.batch, it.n), ref) <= 2e-6, it
     b.destroy()
+
+
+def test_batched_leaf_passes_bitwise_equal_alone():
+    """Plans whose passes all run in the leaf kernel with full tiles (rows,
+    columns, columns to rows with the twiddle) give the same bits in a batch
+    (batched leaf launches) as alone."""
+    import torch
+
+    import paper_2602_23525_amd as mfft
+    specs = [([(4096, 1, 1)], [(3, 4096, 4096)], 0), ([(1024, 1, 1)], [(40, 1024, 1024)], 1),
+             ([(65536, 1, 1)], [(2, 65536, 65536)], 0), ([(65536, 1, 1)], [], 1),
+             ([(256, 1, 16)], [(16, 256, 1)], 0)]
+    plans, xs, ys = [], [], []
+    for i, (dims, hd, prec) in enumerate(specs):
+        tot = int(np.prod([d[0] for d in dims + hd]))
+        cdt = np.complex64 if prec == 0 else np.complex128
+        xs.append(torch.from_numpy(uniform_complex(tot, seed=700 + i, dtype=cdt)).cuda())
+        ys.append(torch.full_like(xs[-1], float("nan")))
+        plans.append(mfft.Plan(dims, hd, prec=prec))
+        desc = plans[-1].info()["desc"]
+        assert desc.count("leaf kernel") == plans[-1].info()["n_passes"], desc
+    b = mfft.Batch(plans, xs, ys, graph=True)
+    b.execute()
+    torch.cuda.synchronize()
+    for p, x, y in zip(plans, xs, ys):
+        alone = torch.full_like(x, float("nan"))
+        p.execute(x, alone)
+        torch.cuda.synchronize()
+        assert np.array_equal(alone.cpu().numpy(), y.cpu().numpy())
+    b.destroy()
+    for p in plans:
+        p.destroy()
