@@ -91,3 +91,39 @@ def test_batch_with_a_plan_without_scratch():
     bt.destroy()
     p1.destroy()
     p2.destroy()
+
+
+def test_real_in_place_without_scratch():
+    """r2c then c2r in place (rows padded to 2(n/2+1) reals) with the split and
+    combine fused into the leaf kernel: no scratch either way."""
+    import torch
+
+    import paper_2602_23525_amd as mfft
+    n, b = 8192, 3
+    h = n // 2 + 1
+    rng = np.random.default_rng(31)
+    x = rng.uniform(-1, 1, (b, n)).astype(np.float32)
+    buf = torch.zeros(b * 2 * h, dtype=torch.float32, device="cuda")
+    buf.view(b, 2 * h)[:, :n] = torch.from_numpy(x).cuda()
+    f = mfft.Plan([(n, 1, 1)], [(b, 2 * h, h)], inplace=True, kind="r2c", flags=mfft.NO_SCRATCH)
+    g = mfft.Plan([(n, 1, 1)], [(b, h, 2 * h)], inplace=True, kind="c2r", flags=mfft.NO_SCRATCH)
+    assert f.info()["scratch_bytes"] == 0 and g.info()["scratch_bytes"] == 0
+    f.execute(buf, buf)
+    torch.cuda.synchronize()
+    y = buf.view(torch.complex64).cpu().numpy().reshape(b, h)
+    assert oracle.rel_rms(y.astype(np.complex128), oracle.rfft(x.astype(np.float64))) <= 2e-6
+    g.execute(buf, buf)
+    torch.cuda.synchronize()
+    z = buf.cpu().numpy().reshape(b, 2 * h)[:, :n] / n
+    assert oracle.rel_rms(z.astype(np.float64), x.astype(np.float64)) <= 4e-6
+    f.destroy()
+    g.destroy()
+
+
+def test_real_refused_without_scratch():
+    import paper_2602_23525_amd as mfft
+    # the inverse of a 2-D real transform runs its complex steps through a
+    # packed copy (the input is not overwritten)
+    with pytest.raises(mfft.MfftError) as e:
+        mfft.Plan([(24, 21, 40), (40, 1, 1)], [], kind="c2r", flags=mfft.NO_SCRATCH)
+    assert e.value.code == -2
