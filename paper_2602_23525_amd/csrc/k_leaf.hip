@@ -51,6 +51,21 @@ static int dispatch(int kind, const PassArgs &a, int n, int grid, hipStream_t s,
         *err = go<T, 4096, 1, PF, WPE, NT, RD, 16, 16, 16>(a, grid, s);
         return 0;
     }
+    if constexpr (!PF && RD == 0) {
+        // one line of 512 (8192 points) or 1024 threads (16384, FP32 only)
+        if (n == 8192) {
+            if (kind == 1) return occ<T, 8192, 1, PF, WPE, NT, RD, 16, 16, 16, 2>();
+            *err = go<T, 8192, 1, PF, WPE, NT, RD, 16, 16, 16, 2>(a, grid, s);
+            return 0;
+        }
+        if constexpr (sizeof(T) == 4) {
+            if (n == 16384) {
+                if (kind == 1) return occ<T, 16384, 1, PF, WPE, NT, RD, 16, 16, 16, 4>();
+                *err = go<T, 16384, 1, PF, WPE, NT, RD, 16, 16, 16, 4>(a, grid, s);
+                return 0;
+            }
+        }
+    }
 #undef LEAF_CASE
     *err = hipErrorInvalidValue;
     return 0;
@@ -102,7 +117,8 @@ bool leaf_col_supported(int prec, int64_t n, bool transposing)
     return n >= (transposing ? 256 : 64) && n <= 2048 && (n & (n - 1)) == 0;
 }
 
-int leaf_max_n(int) { return 4096; }
+// 16384 points (FP32) and 8192 (FP64) fill the LDS of one CU with one line
+int leaf_max_n(int prec) { return prec == 0 ? 16384 : 8192; }
 
 int leaf_lines_per_tile(int prec, int n) { return leaf_row_lines(prec, n); }
 
@@ -161,7 +177,8 @@ static int run(int kind, const PassArgs &a, int prec, int n, int variant, int gr
         if (prec == 0) return dispatch<float, 256, false, 2, 3, 2>(kind, a, n, grid, s, e);
         return dispatch<double, 128, false, 2, 3, 2>(kind, a, n, grid, s, e);
     }
-    const bool pf = variant & 1;
+    // lines above 4096 points are one tile per workgroup (no prefetch variant)
+    const bool pf = (variant & 1) && n <= 4096;
     const int w = (variant >> 1) & 3, nt = (variant >> 3) & 3;
     if (prec == 0) {
         if (pf) return run_wpe<float, 256, true>(kind, a, n, w, nt, grid, s, e);

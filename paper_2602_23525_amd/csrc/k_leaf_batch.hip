@@ -18,8 +18,8 @@ static hipError_t gob(const PassArgs *items, const int64_t *prefix, const int32_
     return hipGetLastError();
 }
 
-// RD 0 rows (64-4096 points), 3 columns (64-2048), 4 / 5 transposing column
-// tiles (256-2048)
+// RD 0 rows (64-16384 points FP32, 64-8192 FP64), 3 columns (64-2048), 4 / 5
+// transposing column tiles (256-2048)
 template <typename T, int RD>
 static hipError_t dispatch_b(const PassArgs *items, const int64_t *prefix, const int32_t *owner,
                              int64_t tiles, int n, hipStream_t s)
@@ -30,6 +30,10 @@ static hipError_t dispatch_b(const PassArgs *items, const int64_t *prefix, const
     }
     if constexpr (RD == 0) {
         if (n == 4096) return gob<T, 4096, RD, 16, 16, 16>(items, prefix, owner, tiles, s);
+        if (n == 8192) return gob<T, 8192, RD, 16, 16, 16, 2>(items, prefix, owner, tiles, s);
+        if constexpr (sizeof(T) == 4) {
+            if (n == 16384) return gob<T, 16384, RD, 16, 16, 16, 4>(items, prefix, owner, tiles, s);
+        }
     }
     switch (n) {
     case 256: return gob<T, 256, RD, 16, 16>(items, prefix, owner, tiles, s);

@@ -1204,7 +1204,9 @@ static int plan_real_line(Builder &b, bool fwd, Dim d, const std::vector<Dim> &V
         // only when each real row starts where its complex row does.
         bool same_rows = true;
         for (const Dim &v : V) same_rows &= fwd ? v.is == 2 * v.os : v.os == 2 * v.is;
-        if (leaf_supported(prec, h) && (fwd ? d.os == 1 : d.is == 1) && (!same_buf || same_rows)) {
+        // (the fused split and combine exist for half-lengths up to 4096)
+        if (leaf_supported(prec, h) && h <= 4096 && (fwd ? d.os == 1 : d.is == 1) &&
+            (!same_buf || same_rows)) {
             const size_t before = p->passes.size();
             const int64_t top = b.scratch_top, hi = b.scratch_hi;
             int rc = plan_line(b, Dim{h, 1, 1}, Vc, src, dst, src_off, dst_off, !fwd, !fwd);

@@ -131,7 +131,8 @@ LEAF_VARIANTS = [0, 1, 3, 5, 8, 9, 11, 13, 24, 25, 27, 29]
 
 @pytest.mark.parametrize("n,b,prec", [(64, 1000, 0), (256, 999, 0), (1024, 1001, 0),
                                       (2048, 1003, 0), (4096, 1100, 0), (512, 777, 1),
-                                      (4096, 1029, 1)])
+                                      (4096, 1029, 1), (8192, 600, 0), (16384, 300, 0),
+                                      (8192, 301, 1)])
 def test_every_leaf_variant(n, b, prec):
     import paper_2602_23525_amd as mfft
     cdt = np.complex64 if prec == 0 else np.complex128
