@@ -71,12 +71,14 @@ typedef enum { MFFT_C32 = 0, MFFT_C64 = 1 } mfft_prec;
  * reduced exactly in integer arithmetic. */
 #define MFFT_FP32_TWIDDLES 8u
 /* In-place plans that need no scratch memory (Section 4.2's in-place plans):
- * a transform along a dimension too long for one pass, n = q*q with q a leaf
- * length, runs as columns (with the Cooley-Tukey twiddle), rows, and an
- * in-place q x q transpose, all in the caller's buffer, instead of two passes
- * through a scratch copy (one more pass over HBM, no scratch).  Planning fails
- * with MFFT_ENOTSUP when the problem has no such plan (a multi-pass length
- * that is not a square, prime sizes that need a convolution buffer, in-place
+ * a transform along a dimension too long for one pass, n = q*q or n = 2*q*q
+ * with q (and 2q) one pass, runs as columns (with the Cooley-Tukey twiddle),
+ * rows, an in-place q x q transpose (of both halves for 2*q*q) and, for
+ * 2*q*q, an in-place interleave of the halves' rows, all in the caller's
+ * buffer, instead of two passes through a scratch copy (one or two more
+ * passes over HBM, no scratch).  Planning fails with MFFT_ENOTSUP when the
+ * problem has no such plan (a multi-pass length of another form, prime sizes
+ * that need a convolution buffer, in-place
  * problems whose input and output strides differ, and real-data transforms
  * that need a packed copy).  Applies to in-place problems; out-of-place plans
  * use no scratch anyway except for prime and real-data cases, which then also

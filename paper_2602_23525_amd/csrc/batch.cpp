@@ -65,6 +65,7 @@ int build_batch_layout(const std::vector<BatchItem> &items, BatchLayout *L)
     std::map<int, std::vector<CopyArgs>> copies;
     std::map<int, std::vector<std::pair<RealArgs, int>>> reals;
     std::map<int, std::vector<TransposeArgs>> transposes;
+    std::map<int, std::vector<PermuteArgs>> permutes;
     std::map<int, std::vector<BatchStep>> leaves;
     // specialized leaf passes: one launch per phase, precision, length and tile kind
     using LKey = std::tuple<int, int, int, int>;   // phase, prec, n, mode
@@ -85,6 +86,10 @@ int build_batch_layout(const std::vector<BatchItem> &items, BatchLayout *L)
             }
             if (ps.kind == 3) {
                 transposes[(int)k].push_back(resolve_transpose(p, ps, it.in, it.out, it.scratch));
+                continue;
+            }
+            if (ps.kind == 4) {
+                permutes[(int)k].push_back(resolve_permute(p, ps, it.in, it.out, it.scratch));
                 continue;
             }
             PassArgs a = resolve_pass(p, ps, it.in, it.out, it.scratch);
@@ -223,6 +228,12 @@ int build_batch_layout(const std::vector<BatchItem> &items, BatchLayout *L)
             st.t = t;
             L->steps.push_back(st);
         }
+        for (const PermuteArgs &pa : permutes[k]) {
+            BatchStep st;
+            st.permute = true;
+            st.pm = pa;
+            L->steps.push_back(st);
+        }
         for (int gi : leaf_groups[k]) {
             BatchStep st;
             st.group = gi;
@@ -252,6 +263,8 @@ int enqueue_batch_layout(const BatchLayout &L, char *dev, hipStream_t s)
             e = launch_real(st.r, st.prec, s);
         } else if (st.transpose) {
             e = launch_transpose_sq(st.t, s);
+        } else if (st.permute) {
+            e = launch_permute_items(st.pm, s);
         } else if (st.leaf) {
             e = launch_leaf(st.a, st.prec, st.a.n, st.leaf_variant, st.leaf_grid, s);
         } else if (L.groups[st.group].leaf_n > 0) {

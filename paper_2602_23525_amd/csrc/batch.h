@@ -32,6 +32,8 @@ struct BatchStep {   // one launch: a group, a copy pass, a real-data step or a 
     RealArgs r{};
     bool transpose = false;
     TransposeArgs t{};
+    bool permute = false;
+    PermuteArgs pm{};
     bool leaf = false;   // a specialized leaf pass with a real-data fusion
     PassArgs a{};
     int leaf_variant = 0, leaf_grid = 0;

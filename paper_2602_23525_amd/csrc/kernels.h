@@ -68,6 +68,23 @@ struct TransposeArgs {
     int64_t n[8], s[8];
 };
 hipError_t launch_transpose_sq(const TransposeArgs &a, hipStream_t s);
+
+// In-place permutation of equal runs (items) of a block: item x (len elements
+// at base + x*xs, element stride es) moves to item next[x].  The permutation's
+// cycles of length >= 2 start at starts[0 .. ncycles); blocks at the offsets of
+// up to 8 outer loops (n[d], s[d]).  len <= 2048, elem_bytes 8 or 16.
+struct PermuteArgs {
+    void *data;
+    int32_t elem_bytes;
+    int32_t rank;
+    int64_t len, es, xs;
+    const int32_t *next, *starts;
+    int32_t ncycles;
+    int32_t nitems;           // items per block (bounds every cycle's length)
+    int64_t total;            // number of blocks (product of n[d])
+    int64_t n[8], s[8];
+};
+hipError_t launch_permute_items(const PermuteArgs &a, hipStream_t s);
 hipError_t launch_gen_stage_twiddles(void *out, int prec, int Ns, int R, hipStream_t s,
                                      bool fp32_math = false);
 hipError_t launch_gen_tw4(void *hi, int64_t nhi, void *lo, int64_t nlo, int shift, int64_t N,

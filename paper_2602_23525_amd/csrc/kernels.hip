@@ -410,6 +410,83 @@ hipError_t launch_transpose_sq(const TransposeArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------ in-place item permutation
+// One workgroup per (cycle, block): the item at the cycle's start is read,
+// then along the cycle each item is read before the previous one is written
+// into its place.  A lane always handles the same elements of every item
+// (element t + 256*j), so lanes need no synchronization.  Elements move as W
+// 8-byte words (W = 1 FP32 complex, 2 FP64 complex); local arrays of 64-bit
+// words stay in registers.
+constexpr int kPermMax = 8;   // elements per lane: items up to 2048 elements
+
+template <int W>
+__global__ __launch_bounds__(256) void permute_items_kernel(PermuteArgs a)
+{
+    using U = unsigned long long;
+    const int64_t g = blockIdx.x;
+    const int64_t blk = g / a.ncycles;
+    const int c = (int)(g - blk * a.ncycles);
+    int64_t base = 0, r = blk;
+    for (int d = a.rank - 1; d >= 0; --d) {
+        const int64_t qd = r / a.n[d];
+        base += (r - qd * a.n[d]) * a.s[d];
+        r = qd;
+    }
+    U *data = (U *)a.data + base * W;
+    const int t = threadIdx.x;
+    const int x0 = a.starts[c];
+    U cur[kPermMax * W], nxt[kPermMax * W];
+#pragma unroll
+    for (int j = 0; j < kPermMax; ++j) {
+        const int64_t e = t + 256 * j;
+        if (e < a.len) {
+            const U *src = data + (x0 * a.xs + e * a.es) * W;
+#pragma unroll
+            for (int w = 0; w < W; ++w) cur[j * W + w] = src[w];
+        }
+    }
+    int x = x0;
+    for (int step = 0; step < a.nitems; ++step) {   // a cycle has at most nitems steps
+        const int y = a.next[x];
+        U *item = data + (int64_t)y * a.xs * W;
+        if (y != x0) {
+#pragma unroll
+            for (int j = 0; j < kPermMax; ++j) {
+                const int64_t e = t + 256 * j;
+                if (e < a.len) {
+#pragma unroll
+                    for (int w = 0; w < W; ++w) nxt[j * W + w] = item[e * a.es * W + w];
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kPermMax; ++j) {
+            const int64_t e = t + 256 * j;
+            if (e < a.len) {
+#pragma unroll
+                for (int w = 0; w < W; ++w) item[e * a.es * W + w] = cur[j * W + w];
+            }
+        }
+        if (y == x0) break;
+#pragma unroll
+        for (int k = 0; k < kPermMax * W; ++k) cur[k] = nxt[k];
+        x = y;
+    }
+}
+
+hipError_t launch_permute_items(const PermuteArgs &a, hipStream_t s)
+{
+    if (a.total <= 0 || a.ncycles <= 0) return hipSuccess;
+    if (a.len > 256 * kPermMax) return hipErrorInvalidValue;
+    const int64_t grid = (int64_t)a.ncycles * a.total;
+    if (grid > 0x7fffffffLL) return hipErrorInvalidValue;
+    if (a.elem_bytes == 8)
+        hipLaunchKernelGGL(permute_items_kernel<1>, dim3((unsigned)grid), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(permute_items_kernel<2>, dim3((unsigned)grid), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_copy(const CopyArgs &a, hipStream_t s)
 {
     if (a.total <= 0) return hipSuccess;

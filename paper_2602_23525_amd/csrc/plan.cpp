@@ -643,6 +643,64 @@ static int add_transpose_pass(Builder &b, int buf, int64_t off, int64_t q, int64
     return MFFT_OK;
 }
 
+// In-place perfect shuffle of the 2q runs of q elements of each block (run x
+// at x*q*s): run x goes to 2x mod (2q - 1), the last run stays.  The cycles
+// of the permutation are found on the host; a table of run destinations and
+// one start per cycle go to the device.
+static int add_shuffle_pass(Builder &b, int buf, int64_t off, int64_t q, int64_t s,
+                            const std::vector<Dim> &V)
+{
+    PlanImpl *p = b.p;
+    if (V.size() > 8) return fail(MFFT_ENOTSUP, "permutation over more than 8 loops");
+    const int64_t items = 2 * q;
+    std::vector<int32_t> next(items), starts;
+    for (int64_t x = 0; x < items; ++x) next[x] = (int32_t)(x == items - 1 ? x : (2 * x) % (items - 1));
+    std::vector<char> seen(items, 0);
+    for (int64_t x = 0; x < items; ++x) {
+        if (seen[x]) continue;
+        int64_t len = 0;
+        for (int64_t y = x; !seen[y]; y = next[y]) {
+            seen[y] = 1;
+            ++len;
+        }
+        if (len > 1) starts.push_back((int32_t)x);
+    }
+    int32_t *dnext = (int32_t *)table_alloc(p, (size_t)items * 4);
+    int32_t *dstarts = (int32_t *)table_alloc(p, std::max<size_t>(starts.size(), 1) * 4);
+    if (!dnext || !dstarts) return fail(MFFT_ENOMEM, "permutation table allocation failed");
+    hipError_t e = hipMemcpy(dnext, next.data(), (size_t)items * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess && !starts.empty())
+        e = hipMemcpy(dstarts, starts.data(), starts.size() * 4, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return fail(MFFT_EHIP, hipGetErrorString(e));
+    Pass ps;
+    ps.kind = 4;
+    ps.pm.elem_bytes = elem_bytes(p->prob.prec);
+    ps.pm.rank = (int)V.size();
+    ps.pm.len = q;
+    ps.pm.es = s;
+    ps.pm.xs = q * s;
+    ps.pm.next = dnext;
+    ps.pm.starts = dstarts;
+    ps.pm.ncycles = (int32_t)starts.size();
+    ps.pm.nitems = (int32_t)items;
+    ps.pm.total = 1;
+    for (size_t i = 0; i < V.size(); ++i) {
+        ps.pm.n[i] = V[i].n;
+        ps.pm.s[i] = V[i].is;
+        ps.pm.total *= V[i].n;
+    }
+    ps.src = ps.dst = buf;
+    ps.src_off = ps.dst_off = off;
+    ps.prec = p->prob.prec;
+    ps.bytes = 2.0 * (double)(items * q) * ps.pm.total * ps.pm.elem_bytes;
+    std::ostringstream d;
+    d << "shuffle 2x" << q << " runs in place x" << ps.pm.total << " (" << starts.size()
+      << " cycles)";
+    ps.desc = d.str();
+    p->passes.push_back(ps);
+    return MFFT_OK;
+}
+
 // In-place Cooley-Tukey step without scratch (Section 4.2's in-place plans)
 // for n = q*q: columns j (elements l*q + j, l < q) transformed in place with
 // the twiddle w_n^(j*k1) on store, then rows k1 (elements k1*q + j) in place,
@@ -654,20 +712,33 @@ static int plan_ct_square_inplace(Builder &b, Dim d, const std::vector<Dim> &V, 
 {
     const int prec = b.p->prob.prec;
     const int64_t n = d.n;
-    int64_t q = (int64_t)std::llround(std::sqrt((double)n));
-    while (q * q > n) --q;
-    while ((q + 1) * (q + 1) <= n) ++q;
-    if (q * q != n || !leaf_fits(q, prec, prec ? 4 : 8))
-        return fail(MFFT_ENOTSUP, "in place without scratch needs n = q*q with q one pass");
+    const int bt = prec ? 4 : 8;
+    // n = q*q (square), or n = 2*q*q: m = 2q rows of r = q columns
+    int64_t q = 0, m = 0;
+    for (const int64_t f : {int64_t(1), int64_t(2)}) {
+        if (n % f) continue;
+        int64_t c = (int64_t)std::llround(std::sqrt((double)(n / f)));
+        while (c * c > n / f) --c;
+        while ((c + 1) * (c + 1) <= n / f) ++c;
+        if (c * c == n / f && c <= 2048 && leaf_fits(c, prec, bt) && leaf_fits(f * c, prec, bt)) {
+            q = c;
+            m = f * c;
+            break;
+        }
+    }
+    if (!q)
+        return fail(MFFT_ENOTSUP,
+                    "in place without scratch needs n = q*q or 2*q*q with q one pass");
     if (d.is != d.os) return fail(MFFT_ENOTSUP, "in place without scratch needs equal strides");
     for (const Dim &v : V)
         if (v.is != v.os) return fail(MFFT_ENOTSUP, "in place without scratch needs equal strides");
-    const int64_t s = d.is;
+    const int64_t s = d.is, r = q;
+    // columns j < r: elements l*r + j, l < m, in place, times w_n^(j*k1)
     LineSpec A;
     A.what = "ctA";
-    A.line = {q, q * s, q * s};
+    A.line = {m, r * s, r * s};
     A.V = V;
-    A.V.push_back({q, s, s});
+    A.V.push_back({r, s, s});
     A.inner = (int)A.V.size() - 1;
     A.src = A.dst = buf;
     A.src_off = A.dst_off = off;
@@ -675,11 +746,20 @@ static int plan_ct_square_inplace(Builder &b, Dim d, const std::vector<Dim> &V, 
     A.tw4_N = n;
     int rc = add_line_pass(b, A);
     if (rc) return rc;
+    // rows k1 < m: elements k1*r + j, in place; Y[k1 + m*k2] lands at k1*r + k2
     std::vector<Dim> VB = V;
-    VB.push_back({q, q * s, q * s});
-    rc = plan_line(b, Dim{q, s, s}, VB, buf, buf, off, off, false, conj_out);
+    VB.push_back({m, r * s, r * s});
+    rc = plan_line(b, Dim{r, s, s}, VB, buf, buf, off, off, false, conj_out);
     if (rc) return rc;
-    return add_transpose_pass(b, buf, off, q, q * s, s, V);
+    if (m == q) return add_transpose_pass(b, buf, off, q, q * s, s, V);
+    // m = 2q: transpose the two q x q halves in place, then interleave their
+    // rows (row i of the result is row i of the first half, then row i of the
+    // second)
+    std::vector<Dim> VT = V;
+    VT.push_back({2, q * q * s, q * q * s});
+    rc = add_transpose_pass(b, buf, off, q, q * s, s, VT);
+    if (rc) return rc;
+    return add_shuffle_pass(b, buf, off, q, s, V);
 }
 
 static int plan_ct(Builder &b, Dim d, const std::vector<Dim> &V, int src, int dst,
@@ -1480,6 +1560,14 @@ TransposeArgs resolve_transpose(const PlanImpl *p, const Pass &ps, const void *i
     return t;
 }
 
+PermuteArgs resolve_permute(const PlanImpl *p, const Pass &ps, const void *in, void *out,
+                            void *scratch)
+{
+    PermuteArgs a = ps.pm;
+    a.data = resolve_buf(p, ps.dst, ps.dst_off, in, out, scratch);
+    return a;
+}
+
 size_t generic_lds_bytes(const Pass &ps)
 {
     return tile_lds_bytes(ps.a.n, ps.a.bt, ps.prec);
@@ -1495,6 +1583,8 @@ int run_plan(const PlanImpl *p, const void *in, void *out, void *scratch, hipStr
             e = launch_real(resolve_real(p, ps, in, out, scratch), p->prob.prec, s);
         } else if (ps.kind == 3) {
             e = launch_transpose_sq(resolve_transpose(p, ps, in, out, scratch), s);
+        } else if (ps.kind == 4) {
+            e = launch_permute_items(resolve_permute(p, ps, in, out, scratch), s);
         } else {
             const PassArgs a = resolve_pass(p, ps, in, out, scratch);
             if (ps.kernel == 1)

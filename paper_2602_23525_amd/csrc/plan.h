@@ -48,11 +48,12 @@ enum : int { BUF_IN = 0, BUF_OUT = 1, BUF_SCRATCH = 2 };
 
 struct Pass {
     int kind = 0;            // 0 = FFT tile pass, 1 = rank-0 copy, 2 = real-data step,
-                             // 3 = in-place square transpose
+                             // 3 = in-place square transpose, 4 = in-place item permutation
     PassArgs a{};            // pointers filled at execute time (except tables)
     CopyArgs c{};
     RealArgs r{};
     TransposeArgs t{};
+    PermuteArgs pm{};
     int src = BUF_IN, dst = BUF_OUT;
     int64_t src_off = 0, dst_off = 0;       // complex elements (scratch: region offset)
     int64_t aux_off = -1;                    // bytes into scratch for Rader aux, or -1
@@ -128,6 +129,8 @@ CopyArgs resolve_copy(const PlanImpl *p, const Pass &ps, const void *in, void *o
 RealArgs resolve_real(const PlanImpl *p, const Pass &ps, const void *in, void *out, void *scratch);
 TransposeArgs resolve_transpose(const PlanImpl *p, const Pass &ps, const void *in, void *out,
                                 void *scratch);
+PermuteArgs resolve_permute(const PlanImpl *p, const Pass &ps, const void *in, void *out,
+                            void *scratch);
 // LDS bytes the generic tile kernel needs for a pass.
 size_t generic_lds_bytes(const Pass &ps);
 

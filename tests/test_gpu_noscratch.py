@@ -1,7 +1,8 @@
 """GPU tests of in-place plans without scratch (MFFT_NO_SCRATCH; Section
 4.2's in-place plans): n = q*q as columns with the twiddle, rows, and an
-in-place q x q transpose, all in the caller's buffer, against the FP64
-oracle; problems without such a plan are refused."""
+in-place q x q transpose (n = 2*q*q: also an in-place shuffle of rows), all
+in the caller's buffer, against the FP64 oracle; problems without such a plan
+are refused."""
 import numpy as np
 import pytest
 
@@ -32,6 +33,23 @@ def test_square_inplace_without_scratch(n, prec, sign):
              expect="leaf kernel columns")
 
 
+# n = 2*q*q: columns of 2q points, rows of q, the two q x q halves transposed,
+# then their rows interleaved (an in-place perfect shuffle of 2q runs)
+@pytest.mark.parametrize("n,b,prec", [(32768, 3, 0), (32768, 2, 1), (131072, 2, 0),
+                                      (2097152, 1, 0), (20000, 3, 0), (131072, 1, 1)])
+@pytest.mark.parametrize("sign", [-1, 1])
+def test_double_square_inplace_without_scratch(n, b, prec, sign):
+    import paper_2602_23525_amd as mfft
+
+    def check(info):
+        assert info["scratch_bytes"] == 0, info
+        assert info["n_passes"] == 4, info["desc"]
+        assert "transpose" in info["desc"] and "shuffle" in info["desc"], info["desc"]
+    hd = [(b, n, n)] if b > 1 else []
+    run_case([(n, 1, 1)], hd, prec=prec, sign=sign, inplace=True, seed=n + b + 1,
+             name=f"noscratch 2q^2 {n}", flags=mfft.NO_SCRATCH, check_info=check)
+
+
 def test_square_inplace_without_scratch_mixed_radix_and_strided():
     import paper_2602_23525_amd as mfft
     # 90000 = 300^2 (generic kernels), transforms at stride 2 interleaved with
@@ -51,7 +69,7 @@ def test_multidim_inplace_without_scratch():
 
 
 @pytest.mark.parametrize("dims,hdims", [
-    ([(32768, 1, 1)], [(2, 32768, 32768)]),          # not a square
+    ([(49152, 1, 1)], [(2, 49152, 49152)]),          # neither q*q nor 2*q*q
     ([(65537, 1, 1)], [(2, 65537, 65537)]),          # Rader needs a convolution buffer
     ([(64, 1, 8)], [(8, 64, 1)]),                    # in place, different strides
 ])
