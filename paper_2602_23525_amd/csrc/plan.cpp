@@ -598,6 +598,92 @@ static bool choose_split(int64_t n, int prec, Split *sp)
 static int plan_line(Builder &b, Dim d, std::vector<Dim> V, int src, int dst, int64_t src_off,
                      int64_t dst_off, bool conj_in, bool conj_out);
 
+// ------------------------------------------------------------ convolution lengths
+// Estimate-mode costs of the cyclic convolutions behind prime sizes.  Each
+// stage of the generic tile kernel costs about the same per point for the
+// radices 2, 4, 8 and 16 (the LDS exchange dominates); the others cost more
+// per point, most for 11, 13 and 15, whose butterflies keep many more values
+// live.  The figures are relative to a power-of-two stage and were measured
+// on MI355X (FP32) over convolutions of lengths 1050 to 131072 whose radices
+// differ; they rank candidates, they do not predict times.
+static double stage_cost(int R)
+{
+    switch (R) {
+    case 2: case 4: case 8: case 16: return 1.0;
+    case 3: case 12: case 14: return 1.15;
+    case 5: case 7: case 9: case 10: return 1.65;
+    case 6: return 1.7;
+    case 13: return 2.85;
+    case 11: return 3.3;
+    default: return 3.8;   // 15
+    }
+}
+
+// A convolution that does not fit one tile adds three passes over HBM.
+constexpr double kConvPassesCost = 2.4;
+// Rader's index-table gather and scatter: inside one tile, and as the
+// random 8-byte accesses of the outer passes when the length is split.
+constexpr double kRaderTileCost = 1.0;
+constexpr double kRaderSplitCost = 4.4;
+
+// Estimated cost of a length-M convolution (forward transform, product,
+// inverse transform), in units of one power-of-two stage over M points;
+// infinite when M has no plan.
+static double conv_cost(int64_t M, int prec, bool rader)
+{
+    Leaf L;
+    if (leaf_fits(M, prec, 1) && make_leaf_shape(M, 16, max_threads(prec), &L)) {
+        double c = rader ? kRaderTileCost : 0.0;
+        for (int R : L.rad) c += stage_cost(R);
+        return c * (double)M;
+    }
+    Split sp;
+    if (!choose_split(M, prec, &sp)) return HUGE_VAL;
+    const int bt = prec ? 4 : 8;
+    Leaf A, B;
+    if (!make_leaf_shape(sp.m, 16, max_threads(prec) / bt, &A) ||
+        !make_leaf_shape(sp.r, 16, max_threads(prec) / bt, &B))
+        return HUGE_VAL;
+    double c = kConvPassesCost + (rader ? kRaderSplitCost : 0.0);
+    for (int R : A.rad) c += stage_cost(R);
+    for (int R : B.rad) c += stage_cost(R);
+    return c * (double)M;
+}
+
+// Bluestein's convolution length: any M >= 2n-1 gives the same result.  The
+// candidates are the smallest smooth M and the smallest of each form 2^a*k
+// with odd k <= 15 (power-of-two stages and at most one other), up to the
+// smallest power of two; the cheapest by conv_cost wins, ties to the shorter.
+static int64_t bluestein_length(int64_t n, int prec, double *cost)
+{
+    const int64_t lo = 2 * n - 1;
+    int64_t p2 = 1;
+    while (p2 < lo) p2 <<= 1;
+    std::vector<int64_t> cand;
+    for (int64_t c = lo; c <= p2; ++c)
+        if (is_smooth(c)) {
+            cand.push_back(c);
+            break;
+        }
+    for (int64_t k = 1; k <= 15; k += 2) {
+        int64_t c = k;
+        while (c < lo) c <<= 1;
+        if (c <= p2 && is_smooth(c)) cand.push_back(c);
+    }
+    std::sort(cand.begin(), cand.end());
+    int64_t best = 0;
+    double bc = HUGE_VAL;
+    for (int64_t c : cand) {
+        const double k = conv_cost(c, prec, false);
+        if (k < bc) {
+            bc = k;
+            best = c;
+        }
+    }
+    *cost = bc;
+    return best;
+}
+
 // Leaf: one pass.
 static int plan_leaf(Builder &b, Dim d, const std::vector<Dim> &V, int src, int dst,
                      int64_t src_off, int64_t dst_off, bool conj_in, bool conj_out)
@@ -962,27 +1048,10 @@ static int plan_bluestein(Builder &b, Dim d, const std::vector<Dim> &V, int src,
     const int64_t n = d.n;
     const int prec = b.p->prob.prec;
     const int eb = elem_bytes(prec);
-    // smallest smooth M >= 2n-1 that is a leaf, else one with a two-pass split
-    int64_t M = 0;
-    bool single = false;
-    for (int64_t c = 2 * n - 1; c <= 4 * n + 64; ++c) {
-        if (!is_smooth(c)) continue;
-        if (leaf_fits(c, prec, 1)) {
-            M = c;
-            single = true;
-        }
-        break;
-    }
-    if (!M) {
-        for (int64_t c = 2 * n - 1; c <= 4 * n + 64; ++c) {
-            Split sp;
-            if (is_smooth(c) && choose_split(c, prec, &sp)) {
-                M = c;
-                break;
-            }
-        }
-    }
-    if (!M) return fail(MFFT_ENOTSUP, "no Bluestein length");
+    double cost;
+    const int64_t M = bluestein_length(n, prec, &cost);
+    if (!M || cost == HUGE_VAL) return fail(MFFT_ENOTSUP, "no Bluestein length");
+    const bool single = leaf_fits(M, prec, 1);
     void *chirp, *spec;
     int rc = bluestein_tables(b, n, M, &chirp, &spec);
     if (rc) return rc;
@@ -1100,8 +1169,15 @@ static int plan_line(Builder &b, Dim d, std::vector<Dim> V, int src, int dst, in
         }
         return plan_ct(b, d, V, src, dst, src_off, dst_off, conj_in, conj_out, sp);
     }
-    if (smallest_prime_factor(n) == n && is_smooth(n - 1))
-        return plan_rader(b, d, V, src, dst, src_off, dst_off, conj_in, conj_out);
+    // Rader's convolution has the fixed length p-1; above 4096 points
+    // Bluestein's, at least twice as long, wins when p-1 needs costly radices
+    // (both estimated by conv_cost; the costs were measured on that range)
+    if (smallest_prime_factor(n) == n && is_smooth(n - 1)) {
+        double blue = HUGE_VAL;
+        if (n > 4096) (void)bluestein_length(n, prec, &blue);
+        if (n <= 4096 || conv_cost(n - 1, prec, true) <= blue)
+            return plan_rader(b, d, V, src, dst, src_off, dst_off, conj_in, conj_out);
+    }
     return plan_bluestein(b, d, V, src, dst, src_off, dst_off, conj_in, conj_out);
 }
 

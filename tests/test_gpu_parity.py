@@ -61,11 +61,24 @@ def test_bluestein_single_kernel(n, prec):
     run_case([(n, 1, 1)], [(5, n, n)], sign=1, prec=prec, seed=n + 1, name=f"bluestein {n} inv")
 
 
-@pytest.mark.parametrize("n,prec", [(65537, 0), (65537, 1), (12289, 0), (65521, 0), (8191, 1),
-                                    (8009, 1), (5281, 0), (65519, 0)])
-def test_prime_multi_pass(n, prec):
-    run_case([(n, 1, 1)], [(2, n, n)], sign=-1, prec=prec, seed=n, name=f"prime {n}")
+@pytest.mark.parametrize("n,prec,algo", [
+    (65537, 0, "raderA"), (65537, 1, "raderA"), (39937, 0, "raderA"),   # p-1 = 2^10*3*13
+    (12289, 0, "rader n=12288"), (39937, 1, None), (65521, 0, None),
+    # p-1 smooth but with costly radices (13, 11, 15): Bluestein is cheaper
+    (5281, 0, "bluestein n=12288"), (8191, 0, "bluestein"), (8191, 1, "bluesteinA n=128"),
+    (8009, 1, "bluesteinA n=128"), (65519, 0, "bluesteinA n=512")])
+def test_prime_multi_pass(n, prec, algo):
+    run_case([(n, 1, 1)], [(2, n, n)], sign=-1, prec=prec, seed=n, name=f"prime {n}",
+             expect=algo)
     run_case([(n, 1, 1)], [(2, n, n)], sign=1, prec=prec, seed=n + 1, name=f"prime {n} inv")
+
+
+@pytest.mark.parametrize("n,algo", [(4093, "bluestein n=8192"), (1213, "bluestein"),
+                                    (3011, "bluestein")])
+def test_bluestein_length_choice(n, algo):
+    # the convolution length is the cheapest candidate, not the shortest:
+    # 8190 = 15*14*13*3 loses to 8192
+    run_case([(n, 1, 1)], [(3, n, n)], sign=-1, seed=n, name=f"bluestein {n}", expect=algo)
 
 
 # ---------------------------------------------------------------- strides, ranks, in-place
