@@ -604,13 +604,15 @@ static int plan_line(Builder &b, Dim d, std::vector<Dim> V, int src, int dst, in
                      int64_t dst_off, bool conj_in, bool conj_out);
 
 // ------------------------------------------------------------ convolution lengths
-// Estimate-mode costs of the cyclic convolutions behind prime sizes.  Each
-// stage of the generic tile kernel costs about the same per point for the
-// radices 2, 4, 8 and 16 (the LDS exchange dominates); the others cost more
-// per point, most for 11, 13 and 15, whose butterflies keep many more values
-// live.  The figures are relative to a power-of-two stage and were measured
-// on MI355X (FP32) over convolutions of lengths 1050 to 131072 whose radices
-// differ; they rank candidates, they do not predict times.
+// Estimate-mode costs of the cyclic convolutions behind prime sizes: the
+// relative cost per point of one stage of radix R inside a convolution (two
+// transforms and the spectrum product in the generic tile kernel), fitted to
+// convolutions of lengths 1050 to 131072 whose radices differ, measured on
+// MI355X (FP32).  Powers of two cost about the same per stage; lengths with
+// 11, 13 and 15 ran much slower per point.  The figures rank convolution
+// lengths only: in plain transforms the same radices are not slow (3375 =
+// 15^3 runs at the rate of a power of two, and choosing the radices of
+// plain leaves by these figures made them slower).
 static double stage_cost(int R)
 {
     switch (R) {
