@@ -81,6 +81,21 @@ def test_bluestein_length_choice(n, algo):
     run_case([(n, 1, 1)], [(3, n, n)], sign=-1, seed=n, name=f"bluestein {n}", expect=algo)
 
 
+@pytest.mark.parametrize("n,prec,inplace,algo", [
+    (17 * 4096, 0, False, "bluestein n=70"), (31 * 1024, 0, True, "rader n=30"),
+    (1009 * 16, 0, False, "rader n=1008"), (17 * 1024, 1, False, "rader n=16"),
+    (23 * 2048, 1, True, "rader n=22"),
+    (4099 * 8, 0, False, "bluesteinA")])   # second pass too long: Bluestein over n
+def test_composite_with_one_large_prime(n, prec, inplace, algo):
+    # one prime factor above 13: a Cooley-Tukey step whose second pass is a
+    # one-tile prime-size plan (Rader, or Bluestein for 2*17), not Bluestein
+    # over the whole length
+    run_case([(n, 1, 1)], [(2, n, n)], prec=prec, inplace=inplace, seed=n, name=f"ct+prime {n}",
+             expect=algo)
+    run_case([(n, 1, 1)], [(2, n, n)], prec=prec, inplace=inplace, sign=1, seed=n + 1,
+             name=f"ct+prime {n} inv")
+
+
 # ---------------------------------------------------------------- strides, ranks, in-place
 
 def test_columns_and_rows_examples():
