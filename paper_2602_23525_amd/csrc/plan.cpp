@@ -16,7 +16,10 @@
 //     (Section 4.2 reduces rank > 1 to rank-1 problems);
 //   - prime sizes: Rader's algorithm when p-1 factors into the supported
 //     radices, Bluestein's chirp-z otherwise (Section 4.2, "Plans for prime
-//     sizes"), each one kernel when the convolution fits a leaf;
+//     sizes"), each one kernel when the convolution fits a leaf; Bluestein's
+//     length, and above 4096 points the choice between the two, by estimated
+//     cost; a composite length with one large prime factor as a Cooley-Tukey
+//     step whose second pass is such a prime-size plan;
 //   - rank 0: a copy (Section 4.2, "Rank-0 plans").
 #include <algorithm>
 #include <array>
