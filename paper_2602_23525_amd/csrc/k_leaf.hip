@@ -77,7 +77,8 @@ static int dispatch(int kind, const PassArgs &a, int n, int grid, hipStream_t s,
 constexpr int col_lines(int prec, int n) { return leaf_col_lines(prec, n); }
 
 // RD 3: columns in and out (64-2048 points); 4 / 5: columns in, rows out and
-// the reverse (256-2048 points, so that a row run is at least 16 lanes)
+// the reverse (256-2048 points, so that a row run is at least 16 lanes); 6 / 7:
+// 4 / 5 with Bluestein's chirp products
 template <typename T, int RD>
 static int dispatch_cols(int kind, const PassArgs &a, int n, int grid, hipStream_t s,
                          hipError_t *err)
@@ -156,10 +157,16 @@ static int run(int kind, const PassArgs &a, int prec, int n, int variant, int gr
                          : dispatch_cols<double, 3>(kind, a, n, grid, s, e);
     }
     if (a.flags & PF_LEAF_CR) {
+        if (a.flags & PF_PRE_MUL)   // Bluestein's first pass
+            return prec == 0 ? dispatch_cols<float, 6>(kind, a, n, grid, s, e)
+                             : dispatch_cols<double, 6>(kind, a, n, grid, s, e);
         return prec == 0 ? dispatch_cols<float, 4>(kind, a, n, grid, s, e)
                          : dispatch_cols<double, 4>(kind, a, n, grid, s, e);
     }
     if (a.flags & PF_LEAF_RC) {
+        if (a.flags & PF_POST_MUL)   // Bluestein's last pass
+            return prec == 0 ? dispatch_cols<float, 7>(kind, a, n, grid, s, e)
+                             : dispatch_cols<double, 7>(kind, a, n, grid, s, e);
         return prec == 0 ? dispatch_cols<float, 5>(kind, a, n, grid, s, e)
                          : dispatch_cols<double, 5>(kind, a, n, grid, s, e);
     }

@@ -188,7 +188,13 @@ __device__ __forceinline__ void st_elem(cpx<T> *p, cpx<T> v)
 // 5 rows in, columns out (PF_LEAF_CR, PF_LEAF_RC): the loads use one
 // lane mapping, the stores the other, the results passing through LDS once
 // more.  Column tiles (3-5) may multiply element k of inner line c by the
-// Cooley-Tukey twiddle w_N^(c*k) on store (PF_TW4).
+// Cooley-Tukey twiddle w_N^(c*k) on store (PF_TW4).  The outer passes of a
+// three-pass Bluestein convolution, compiled apart so that the plain column
+// tiles keep their registers: RD 6 is RD 4 loading element l of line c as
+// x[j] * pre[j], j = c*li_c + l*li_l, zero for j >= li_lim (the chirp product
+// and the zero padding); RD 7 is RD 5 storing element k of line c only for
+// g = c*lo_c + k*lo_k < lo_lim, as conj(y) * post[g] (PF_CONJ_A) or
+// y * post[g].
 // WPE: occupancy floor in waves per SIMD (caps VGPRs at 512 / WPE).
 // NT: bit 0 streams the output with non-temporal stores, bit 1 the input with
 // non-temporal loads (neither is reused by this pass).
@@ -217,7 +223,8 @@ __device__ __forceinline__ void leaf_body(const PassArgs &a, cpx<T> *lds, int64_
 {
     constexpr int TPT = N / 16;
     constexpr int STRIDE = leaf_lds_stride<N>();
-    constexpr bool cols_in = RD == 3 || RD == 4, cols_out = RD == 3 || RD == 5;
+    constexpr bool cols_in = RD == 3 || RD == 4 || RD == 6;
+    constexpr bool cols_out = RD == 3 || RD == 5 || RD == 7;
     constexpr bool xpose = cols_in != cols_out;
     static_assert(!(xpose && PF), "transposing tiles are one tile per workgroup");
     const int tid = threadIdx.x;
@@ -235,13 +242,16 @@ __device__ __forceinline__ void leaf_body(const PassArgs &a, cpx<T> *lds, int64_
     StageChain<T, N, TPT, 1, Rs...> chain;
     chain.load((const cpx<T> *)a.tw, 0, t);
 
-    // column tiles: inner index of the lane's store line (for the twiddle)
-    int64_t cst = 0;
+    // column tiles: inner index of the lane's store line (for the twiddle),
+    // and of its load line, clamped to the vector loop (for the pre product)
+    int64_t cst = 0, lc = 0;
+    constexpr bool pre = RD == 6;
     auto line_base = [&](int64_t tile, int64_t *ib, int64_t *obs, bool *ok) {
         const int64_t o = tile / a.ntiles_inner;
         const int64_t c0 = (tile - o * a.ntiles_inner) * BT;
         const int64_t c = c0 + tr;
         if constexpr (cols_in || cols_out) cst = c0 + (xpose ? trs : tr);
+        if constexpr (pre) lc = c < a.vn ? c : a.vn - 1;
         int64_t rem = o, bi = 0, bo = 0;
         for (int d = a.nouter - 1; d >= 0; --d) {
             const int64_t qd = rem / a.on[d];
@@ -259,6 +269,25 @@ __device__ __forceinline__ void leaf_body(const PassArgs &a, cpx<T> *lds, int64_
     };
     auto load_line = [&](cpx<T>(&x)[16], int64_t ib) {
         const cpx<T> *src = (const cpx<T> *)a.in + ib + t * eis;
+        if constexpr (pre) {
+            // elements past li_lim read element 0 of the line (in range) and
+            // become zero
+            const cpx<T> *pm = (const cpx<T> *)a.pre;
+            const int64_t j0 = lc * a.li_c + (int64_t)t * a.li_l, js = (int64_t)TPT * a.li_l;
+#pragma unroll
+            for (int e = 0; e < 16; ++e)
+                x[e] = ld_elem<NT>(j0 + e * js < a.li_lim ? &src[e * TPT * eis]
+                                                          : (const cpx<T> *)a.in + ib);
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int64_t j = j0 + e * js;
+                const bool v = j < a.li_lim;
+                const cpx<T> w = pm[v ? j : 0];
+                const cpx<T> y = cin ? conj(x[e]) : x[e];
+                x[e] = v ? cmul(y, w) : cpx<T>{T(0), T(0)};
+            }
+            return;
+        }
 #pragma unroll
         for (int e = 0; e < 16; ++e) x[e] = ld_elem<NT>(&src[e * TPT * eis]);
     };
@@ -365,7 +394,7 @@ __device__ __forceinline__ void leaf_body(const PassArgs &a, cpx<T> *lds, int64_
             for (int e = 0; e < 16; ++e) x[e] = *lds_slot<TPT>(line, t, e);
             __syncthreads();   // the first stage overwrites the line
         }
-        if (cin) {
+        if (cin && !pre) {
 #pragma unroll
             for (int e = 0; e < 16; ++e) x[e] = conj(x[e]);
         }
@@ -394,7 +423,22 @@ __device__ __forceinline__ void leaf_body(const PassArgs &a, cpx<T> *lds, int64_
                 }
             }
         }
-        if constexpr (r2c) {
+        if constexpr (RD == 7) {
+            if (ok) {
+                cpx<T> *dst = (cpx<T> *)a.out + ob + ts * eos;
+                const cpx<T> *pm = (const cpx<T> *)a.post;
+                const bool ca = (a.flags & PF_CONJ_A) != 0;
+                const int64_t g0 = cst * a.lo_c + (int64_t)ts * a.lo_k, gs = (int64_t)TPT * a.lo_k;
+#pragma unroll
+                for (int e = 0; e < 16; ++e) {
+                    const int64_t g = g0 + e * gs;
+                    if (g < a.lo_lim) {
+                        const cpx<T> y = cmul(ca ? conj(x[e]) : x[e], pm[g]);
+                        st_elem<NT>(&dst[e * TPT * eos], cout ? conj(y) : y);
+                    }
+                }
+            }
+        } else if constexpr (r2c) {
             split_to_half_spectrum(x, ob, ok);
         } else if (ok) {
             cpx<T> *dst = (cpx<T> *)a.out + ob + (xpose ? ts : t) * eos;

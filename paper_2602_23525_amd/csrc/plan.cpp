@@ -379,7 +379,11 @@ static bool leaf_col_fits(const LineSpec &ls, const PassArgs &a, const Dim &in_d
     const bool cin = a.load_mode == kModeCol, cout = a.store_mode == kModeCol;
     if (!cin && !cout) return false;
     const bool xp = cin != cout;
-    const uint32_t allowed = PF_CONJ_IN | PF_CONJ_OUT | PF_TW4;
+    // Bluestein's outer passes: the chirp product (and zero padding) on the
+    // loads of a columns-in tile, the chirp product (and truncation) on the
+    // stores of a columns-out tile
+    const uint32_t allowed = PF_CONJ_IN | PF_CONJ_OUT | PF_TW4 |
+                             (xp && cin ? PF_PRE_MUL : 0) | (xp && cout ? PF_POST_MUL | PF_CONJ_A : 0);
     if ((ls.flags & ~allowed) || ls.conv_n) return false;
     if (!leaf_col_supported(prec, n, xp)) return false;
     if (cin ? in_dim.is != 1 : ls.line.is != 1) return false;
