@@ -78,7 +78,7 @@ constexpr int col_lines(int prec, int n) { return leaf_col_lines(prec, n); }
 
 // RD 3: columns in and out (64-2048 points); 4 / 5: columns in, rows out and
 // the reverse (256-2048 points, so that a row run is at least 16 lanes); 6 / 7:
-// 4 / 5 with Bluestein's chirp products
+// 4 / 5 with Bluestein's chirp products; 8: 3 with Bluestein's convolution
 template <typename T, int RD>
 static int dispatch_cols(int kind, const PassArgs &a, int n, int grid, hipStream_t s,
                          hipError_t *err)
@@ -89,7 +89,7 @@ static int dispatch_cols(int kind, const PassArgs &a, int n, int grid, hipStream
         if (kind == 1) return occ<T, N, col_lines(P, N), false, 2, 3, RD, __VA_ARGS__>();  \
         *err = go<T, N, col_lines(P, N), false, 2, 3, RD, __VA_ARGS__>(a, grid, s);        \
         return 0;
-    if constexpr (RD == 3) {
+    if constexpr (RD == 3 || RD == 8) {
         switch (n) {
             COL_CASE(64, 16, 4)
             COL_CASE(128, 16, 8)
@@ -153,6 +153,9 @@ static int run(int kind, const PassArgs &a, int prec, int n, int variant, int gr
                hipStream_t s, hipError_t *e)
 {
     if (a.flags & PF_LEAF_COL) {
+        if (a.flags & PF_CONV)   // Bluestein's middle pass
+            return prec == 0 ? dispatch_cols<float, 8>(kind, a, n, grid, s, e)
+                             : dispatch_cols<double, 8>(kind, a, n, grid, s, e);
         return prec == 0 ? dispatch_cols<float, 3>(kind, a, n, grid, s, e)
                          : dispatch_cols<double, 3>(kind, a, n, grid, s, e);
     }

@@ -20,12 +20,12 @@ static hipError_t gob(const PassArgs *items, const int64_t *prefix, const int32_
 
 // RD 0 rows (64-16384 points FP32, 64-8192 FP64), 3 columns (64-2048), 4 / 5
 // transposing column tiles (256-2048), 6 / 7 the same with Bluestein's chirp
-// products
+// products, 8 columns with Bluestein's convolution
 template <typename T, int RD>
 static hipError_t dispatch_b(const PassArgs *items, const int64_t *prefix, const int32_t *owner,
                              int64_t tiles, int n, hipStream_t s)
 {
-    if constexpr (RD == 0 || RD == 3) {
+    if constexpr (RD == 0 || RD == 3 || RD == 8) {
         if (n == 64) return gob<T, 64, RD, 16, 4>(items, prefix, owner, tiles, s);
         if (n == 128) return gob<T, 128, RD, 16, 8>(items, prefix, owner, tiles, s);
     }
@@ -58,13 +58,14 @@ static hipError_t dispatch_mode(const PassArgs *items, const int64_t *prefix,
     case 5: return dispatch_b<T, 5>(items, prefix, owner, tiles, n, s);
     case 6: return dispatch_b<T, 6>(items, prefix, owner, tiles, n, s);
     case 7: return dispatch_b<T, 7>(items, prefix, owner, tiles, n, s);
+    case 8: return dispatch_b<T, 8>(items, prefix, owner, tiles, n, s);
     default: return hipErrorInvalidValue;
     }
 }
 
 int leaf_batch_mode(uint32_t flags)
 {
-    if (flags & PF_LEAF_COL) return 3;
+    if (flags & PF_LEAF_COL) return (flags & PF_CONV) ? 8 : 3;
     if (flags & PF_LEAF_CR) return (flags & PF_PRE_MUL) ? 6 : 4;
     if (flags & PF_LEAF_RC) return (flags & PF_POST_MUL) ? 7 : 5;
     return 0;

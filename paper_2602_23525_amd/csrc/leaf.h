@@ -194,7 +194,9 @@ __device__ __forceinline__ void st_elem(cpx<T> *p, cpx<T> v)
 // x[j] * pre[j], j = c*li_c + l*li_l, zero for j >= li_lim (the chirp product
 // and the zero padding); RD 7 is RD 5 storing element k of line c only for
 // g = c*lo_c + k*lo_k < lo_lim, as conj(y) * post[g] (PF_CONJ_A) or
-// y * post[g].
+// y * post[g]; RD 8 is RD 3 running the convolution of Bluestein's middle
+// pass: transform, product with conj, conj(y * conv[c*conv_c + k*conv_k]),
+// transform again (the inverse by conjugation).
 // WPE: occupancy floor in waves per SIMD (caps VGPRs at 512 / WPE).
 // NT: bit 0 streams the output with non-temporal stores, bit 1 the input with
 // non-temporal loads (neither is reused by this pass).
@@ -223,8 +225,8 @@ __device__ __forceinline__ void leaf_body(const PassArgs &a, cpx<T> *lds, int64_
 {
     constexpr int TPT = N / 16;
     constexpr int STRIDE = leaf_lds_stride<N>();
-    constexpr bool cols_in = RD == 3 || RD == 4 || RD == 6;
-    constexpr bool cols_out = RD == 3 || RD == 5 || RD == 7;
+    constexpr bool cols_in = RD == 3 || RD == 4 || RD == 6 || RD == 8;
+    constexpr bool cols_out = RD == 3 || RD == 5 || RD == 7 || RD == 8;
     constexpr bool xpose = cols_in != cols_out;
     static_assert(!(xpose && PF), "transposing tiles are one tile per workgroup");
     const int tid = threadIdx.x;
@@ -251,7 +253,7 @@ __device__ __forceinline__ void leaf_body(const PassArgs &a, cpx<T> *lds, int64_
         const int64_t c0 = (tile - o * a.ntiles_inner) * BT;
         const int64_t c = c0 + tr;
         if constexpr (cols_in || cols_out) cst = c0 + (xpose ? trs : tr);
-        if constexpr (pre) lc = c < a.vn ? c : a.vn - 1;
+        if constexpr (pre || RD == 8) lc = c < a.vn ? c : a.vn - 1;
         int64_t rem = o, bi = 0, bo = 0;
         for (int d = a.nouter - 1; d >= 0; --d) {
             const int64_t qd = rem / a.on[d];
@@ -399,6 +401,15 @@ __device__ __forceinline__ void leaf_body(const PassArgs &a, cpx<T> *lds, int64_
             for (int e = 0; e < 16; ++e) x[e] = conj(x[e]);
         }
         chain.run(x, line, t);
+        if constexpr (RD == 8) {
+            // every LDS read of the first transform came before its last
+            // barrier, so the second may start at once
+            const cpx<T> *cv = (const cpx<T> *)a.conv + lc * a.conv_c + (int64_t)t * a.conv_k;
+            const int64_t cks = (int64_t)TPT * a.conv_k;
+#pragma unroll
+            for (int e = 0; e < 16; ++e) x[e] = conj(cmul(x[e], cv[e * cks]));
+            chain.run(x, line, t);
+        }
         if constexpr (xpose) {
             // results to LDS in the stage mapping, back in the store mapping
 #pragma unroll

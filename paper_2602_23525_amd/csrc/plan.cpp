@@ -306,6 +306,10 @@ struct LineSpec {
     int64_t lo_c = 0, lo_k = 1, lo_lim = -1;
     int64_t tw4_N = 0;
     const void *pre = nullptr, *post = nullptr, *conv = nullptr;
+    // the spectrum as a column tile reads it (entry c*conv_cols_c + k*conv_cols_k
+    // for element k of line c), when the pass may run in the leaf kernel
+    const void *conv_cols = nullptr;
+    int64_t conv_cols_c = 0, conv_cols_k = 0;
     const int32_t *gather = nullptr, *scatter = nullptr;
     int64_t aux_off = -1;
     int64_t conv_n = 0;        // leaf length when it differs from line.n (Bluestein / Rader)
@@ -383,7 +387,8 @@ static bool leaf_col_fits(const LineSpec &ls, const PassArgs &a, const Dim &in_d
     // loads of a columns-in tile, the chirp product (and truncation) on the
     // stores of a columns-out tile
     const uint32_t allowed = PF_CONJ_IN | PF_CONJ_OUT | PF_TW4 |
-                             (xp && cin ? PF_PRE_MUL : 0) | (xp && cout ? PF_POST_MUL | PF_CONJ_A : 0);
+                             (xp && cin ? PF_PRE_MUL : 0) | (xp && cout ? PF_POST_MUL | PF_CONJ_A : 0) |
+                             (!xp && ls.conv_cols ? PF_CONV : 0);
     if ((ls.flags & ~allowed) || ls.conv_n) return false;
     if (!leaf_col_supported(prec, n, xp)) return false;
     if (cin ? in_dim.is != 1 : ls.line.is != 1) return false;
@@ -518,6 +523,11 @@ static int add_line_pass(Builder &b, const LineSpec &ls)
         const bool cin = a.load_mode == kModeCol, cout = a.store_mode == kModeCol;
         ps.kernel = 1;
         a.flags |= cin && cout ? PF_LEAF_COL : (cin ? PF_LEAF_CR : PF_LEAF_RC);
+        if (ls.flags & PF_CONV) {
+            a.conv = ls.conv_cols;
+            a.conv_c = ls.conv_cols_c;
+            a.conv_k = ls.conv_cols_k;
+        }
         a.bt = leaf_col_lines_per_tile(prec, (int)n);
         a.bt_log2 = ilog2(a.bt);
         a.ntiles_inner = (a.vn + a.bt - 1) / a.bt;
@@ -1136,6 +1146,9 @@ static int plan_bluestein(Builder &b, Dim d, const std::vector<Dim> &V, int src,
     B.conv = spec_lines;
     B.conv_c = r1;
     B.conv_k = 1;
+    B.conv_cols = spec;   // entry k1 + k2*m1: line k1, element k2
+    B.conv_cols_c = 1;
+    B.conv_cols_k = m1;
     B.tw4_N = M;
     rc = add_line_pass(b, B);
     if (rc) return rc;
