@@ -51,7 +51,7 @@ static int dispatch(int kind, const PassArgs &a, int n, int grid, hipStream_t s,
         *err = go<T, 4096, 1, PF, WPE, NT, RD, 16, 16, 16>(a, grid, s);
         return 0;
     }
-    if constexpr (!PF && RD == 0) {
+    if constexpr (!PF && (RD == 0 || RD == 9)) {
         // one line of 512 (8192 points) or 1024 threads (16384, FP32 only)
         if (n == 8192) {
             if (kind == 1) return occ<T, 8192, 1, PF, WPE, NT, RD, 16, 16, 16, 2>();
@@ -187,6 +187,10 @@ static int run(int kind, const PassArgs &a, int prec, int n, int variant, int gr
         if (prec == 0) return dispatch<float, 256, false, 2, 3, 2>(kind, a, n, grid, s, e);
         return dispatch<double, 128, false, 2, 3, 2>(kind, a, n, grid, s, e);
     }
+    // Bluestein in one tile: one configuration, as the column tiles
+    if (a.flags & PF_CONV)
+        return prec == 0 ? dispatch<float, 256, false, 2, 3, 9>(kind, a, n, grid, s, e)
+                         : dispatch<double, 128, false, 2, 3, 9>(kind, a, n, grid, s, e);
     // lines above 4096 points are one tile per workgroup (no prefetch variant)
     const bool pf = (variant & 1) && n <= 4096;
     const int w = (variant >> 1) & 3, nt = (variant >> 3) & 3;

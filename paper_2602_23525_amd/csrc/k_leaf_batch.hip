@@ -11,7 +11,7 @@ static hipError_t gob(const PassArgs *items, const int64_t *prefix, const int32_
                       int64_t tiles, hipStream_t s)
 {
     constexpr int P = sizeof(T) == 4 ? 0 : 1;
-    constexpr int BT = RD == 0 ? leaf_row_lines(P, N) : leaf_col_lines(P, N);
+    constexpr int BT = (RD == 0 || RD == 9) ? leaf_row_lines(P, N) : leaf_col_lines(P, N);
     constexpr int THREADS = BT * N / 16;
     hipLaunchKernelGGL((leaf_batch_kernel<T, N, BT, RD, Rs...>), dim3((unsigned)tiles),
                        dim3(THREADS), 0, s, items, prefix, owner);
@@ -20,16 +20,17 @@ static hipError_t gob(const PassArgs *items, const int64_t *prefix, const int32_
 
 // RD 0 rows (64-16384 points FP32, 64-8192 FP64), 3 columns (64-2048), 4 / 5
 // transposing column tiles (256-2048), 6 / 7 the same with Bluestein's chirp
-// products, 8 columns with Bluestein's convolution
+// products, 8 columns with Bluestein's convolution, 9 rows with a whole
+// Bluestein convolution
 template <typename T, int RD>
 static hipError_t dispatch_b(const PassArgs *items, const int64_t *prefix, const int32_t *owner,
                              int64_t tiles, int n, hipStream_t s)
 {
-    if constexpr (RD == 0 || RD == 3 || RD == 8) {
+    if constexpr (RD == 0 || RD == 3 || RD == 8 || RD == 9) {
         if (n == 64) return gob<T, 64, RD, 16, 4>(items, prefix, owner, tiles, s);
         if (n == 128) return gob<T, 128, RD, 16, 8>(items, prefix, owner, tiles, s);
     }
-    if constexpr (RD == 0) {
+    if constexpr (RD == 0 || RD == 9) {
         if (n == 4096) return gob<T, 4096, RD, 16, 16, 16>(items, prefix, owner, tiles, s);
         if (n == 8192) return gob<T, 8192, RD, 16, 16, 16, 2>(items, prefix, owner, tiles, s);
         if constexpr (sizeof(T) == 4) {
@@ -59,6 +60,7 @@ static hipError_t dispatch_mode(const PassArgs *items, const int64_t *prefix,
     case 6: return dispatch_b<T, 6>(items, prefix, owner, tiles, n, s);
     case 7: return dispatch_b<T, 7>(items, prefix, owner, tiles, n, s);
     case 8: return dispatch_b<T, 8>(items, prefix, owner, tiles, n, s);
+    case 9: return dispatch_b<T, 9>(items, prefix, owner, tiles, n, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -68,6 +70,7 @@ int leaf_batch_mode(uint32_t flags)
     if (flags & PF_LEAF_COL) return (flags & PF_CONV) ? 8 : 3;
     if (flags & PF_LEAF_CR) return (flags & PF_PRE_MUL) ? 6 : 4;
     if (flags & PF_LEAF_RC) return (flags & PF_POST_MUL) ? 7 : 5;
+    if (flags & PF_CONV) return 9;
     return 0;
 }
 

@@ -196,7 +196,10 @@ __device__ __forceinline__ void st_elem(cpx<T> *p, cpx<T> v)
 // g = c*lo_c + k*lo_k < lo_lim, as conj(y) * post[g] (PF_CONJ_A) or
 // y * post[g]; RD 8 is RD 3 running the convolution of Bluestein's middle
 // pass: transform, product with conj, conj(y * conv[c*conv_c + k*conv_k]),
-// transform again (the inverse by conjugation).
+// transform again (the inverse by conjugation); RD 9 is RD 0 running a whole
+// Bluestein convolution of length N in one tile: the chirp product and zero
+// padding of RD 6 on load, the convolution of RD 8, the chirp product and
+// truncation of RD 7 on store.
 // WPE: occupancy floor in waves per SIMD (caps VGPRs at 512 / WPE).
 // NT: bit 0 streams the output with non-temporal stores, bit 1 the input with
 // non-temporal loads (neither is reused by this pass).
@@ -247,13 +250,15 @@ __device__ __forceinline__ void leaf_body(const PassArgs &a, cpx<T> *lds, int64_
     // column tiles: inner index of the lane's store line (for the twiddle),
     // and of its load line, clamped to the vector loop (for the pre product)
     int64_t cst = 0, lc = 0;
-    constexpr bool pre = RD == 6;
+    constexpr bool pre = RD == 6 || RD == 9, conv = RD == 8 || RD == 9;
+    constexpr bool post = RD == 7 || RD == 9;
+    static_assert(!(PF && (pre || conv)), "lc belongs to the tile being computed");
     auto line_base = [&](int64_t tile, int64_t *ib, int64_t *obs, bool *ok) {
         const int64_t o = tile / a.ntiles_inner;
         const int64_t c0 = (tile - o * a.ntiles_inner) * BT;
         const int64_t c = c0 + tr;
         if constexpr (cols_in || cols_out) cst = c0 + (xpose ? trs : tr);
-        if constexpr (pre || RD == 8) lc = c < a.vn ? c : a.vn - 1;
+        if constexpr (pre || conv) lc = c < a.vn ? c : a.vn - 1;
         int64_t rem = o, bi = 0, bo = 0;
         for (int d = a.nouter - 1; d >= 0; --d) {
             const int64_t qd = rem / a.on[d];
@@ -401,7 +406,7 @@ __device__ __forceinline__ void leaf_body(const PassArgs &a, cpx<T> *lds, int64_
             for (int e = 0; e < 16; ++e) x[e] = conj(x[e]);
         }
         chain.run(x, line, t);
-        if constexpr (RD == 8) {
+        if constexpr (conv) {
             // every LDS read of the first transform came before its last
             // barrier, so the second may start at once
             const cpx<T> *cv = (const cpx<T> *)a.conv + lc * a.conv_c + (int64_t)t * a.conv_k;
@@ -434,12 +439,16 @@ __device__ __forceinline__ void leaf_body(const PassArgs &a, cpx<T> *lds, int64_
                 }
             }
         }
-        if constexpr (RD == 7) {
+        if constexpr (post) {
             if (ok) {
-                cpx<T> *dst = (cpx<T> *)a.out + ob + ts * eos;
+                // the store line and the lane's rank in it (row tiles: the
+                // load line, in range when ok)
+                const int64_t sc = xpose ? cst : lc;
+                const int sr = xpose ? ts : t;
+                cpx<T> *dst = (cpx<T> *)a.out + ob + sr * eos;
                 const cpx<T> *pm = (const cpx<T> *)a.post;
                 const bool ca = (a.flags & PF_CONJ_A) != 0;
-                const int64_t g0 = cst * a.lo_c + (int64_t)ts * a.lo_k, gs = (int64_t)TPT * a.lo_k;
+                const int64_t g0 = sc * a.lo_c + (int64_t)sr * a.lo_k, gs = (int64_t)TPT * a.lo_k;
 #pragma unroll
                 for (int e = 0; e < 16; ++e) {
                     const int64_t g = g0 + e * gs;

@@ -505,10 +505,16 @@ static int add_line_pass(Builder &b, const LineSpec &ls)
         rc = tw4_tables(b, ls.tw4_N, &a);
         if (rc) return rc;
     }
-    // unit-stride plain lines of a power-of-two length: the specialized leaf kernel
+    // unit-stride plain lines of a power-of-two length: the specialized leaf
+    // kernel; so too Bluestein in one tile over a power-of-two convolution
     const uint32_t plain = PF_CONJ_IN | PF_CONJ_OUT;
-    if (!(ls.flags & ~plain) && !ls.conv_n && ls.line.is == 1 && ls.line.os == 1 &&
-        a.load_mode == kModeRow && a.store_mode == kModeRow && leaf_supported(prec, n)) {
+    const uint32_t blue1 = PF_CONV | PF_PRE_MUL | PF_POST_MUL | PF_CONJ_A;
+    const bool leaf_blue = ls.conv_n && (ls.flags & ~plain) == blue1 && ls.li_c == 0 &&
+                           ls.li_l == 1 && ls.lo_c == 0 && ls.lo_k == 1 && ls.conv_c == 0 &&
+                           ls.conv_k == 1;
+    if ((leaf_blue || (!(ls.flags & ~plain) && !ls.conv_n)) && ls.line.is == 1 &&
+        ls.line.os == 1 && a.load_mode == kModeRow && a.store_mode == kModeRow &&
+        leaf_supported(prec, n)) {
         ps.kernel = 1;
         a.bt = leaf_lines_per_tile(prec, (int)n);
         a.bt_log2 = ilog2(a.bt);
@@ -643,18 +649,37 @@ static double stage_cost(int R)
     }
 }
 
-// A convolution that does not fit one tile adds three passes over HBM.
-constexpr double kConvPassesCost = 2.4;
-// Rader's index-table gather and scatter: inside one tile, and as the
-// random 8-byte accesses of the outer passes when the length is split.
+// A convolution split in three passes: each pass of the generic kernel
+// costs kPassCost per point plus its stages (the outer passes one transform
+// of the first factor, the middle pass two of the second); a pass that runs
+// in the leaf kernel's column tiles (Bluestein only; outer factor a power of
+// two in 256..2048, middle factor in 64..2048) costs kLeafPassCost.  Rader's
+// index-table gather and scatter add kRaderTileCost per point inside a tile
+// and kRaderSplitCost in the outer passes (random 8-byte accesses).  Fitted
+// to three-pass convolutions of lengths 18432 to 131072 measured on MI355X.
+constexpr double kPassCost = 1.3;
+constexpr double kLeafPassCost = 1.26;
 constexpr double kRaderTileCost = 1.0;
-constexpr double kRaderSplitCost = 4.4;
+constexpr double kRaderSplitCost = 2.5;
+
+static bool pow2_in(int64_t n, int64_t lo, int64_t hi)
+{
+    return (n & (n - 1)) == 0 && n >= lo && n <= hi;
+}
 
 // Estimated cost of a length-M convolution (forward transform, product,
-// inverse transform), in units of one power-of-two stage over M points;
-// infinite when M has no plan.
+// inverse transform), in units of one power-of-two stage of the generic
+// kernel over M points; infinite when M has no plan.
 static double conv_cost(int64_t M, int prec, bool rader)
 {
+    // Bluestein over a power-of-two length in one tile runs in the
+    // specialized leaf kernel, whose stages cost about half as much
+    // (measured: 12288 generic 0.70 ms, 16384 leaf 0.46 ms, 5582 x 6011)
+    if (!rader && leaf_supported(prec, M)) {
+        int st = 0;
+        for (int64_t m = 1; m < M; m *= 16) ++st;
+        return 0.5 * st * (double)M;
+    }
     Leaf L;
     if (leaf_fits(M, prec, 1) && make_leaf_shape(M, 16, max_threads(prec), &L)) {
         double c = rader ? kRaderTileCost : 0.0;
@@ -668,10 +693,12 @@ static double conv_cost(int64_t M, int prec, bool rader)
     if (!make_leaf_shape(sp.m, 16, max_threads(prec) / bt, &A) ||
         !make_leaf_shape(sp.r, 16, max_threads(prec) / bt, &B))
         return HUGE_VAL;
-    double c = kConvPassesCost + (rader ? kRaderSplitCost : 0.0);
-    for (int R : A.rad) c += stage_cost(R);
-    for (int R : B.rad) c += stage_cost(R);
-    return c * (double)M;
+    double sa = 0, sb = 0;
+    for (int R : A.rad) sa += stage_cost(R);
+    for (int R : B.rad) sb += stage_cost(R);
+    const double outer = !rader && pow2_in(sp.m, 256, 2048) ? kLeafPassCost : kPassCost + 0.41 * sa;
+    const double mid = !rader && pow2_in(sp.r, 64, 2048) ? kLeafPassCost : kPassCost + 0.81 * sb;
+    return (2 * outer + mid + (rader ? kRaderSplitCost : 0.0)) * (double)M;
 }
 
 // Bluestein's convolution length: any M >= 2n-1 gives the same result.  The

@@ -65,7 +65,7 @@ def test_bluestein_single_kernel(n, prec):
     (65537, 0, "raderA"), (65537, 1, "raderA"), (39937, 0, "raderA"),   # p-1 = 2^10*3*13
     (12289, 0, "rader n=12288"), (39937, 1, None), (65521, 0, None),
     # p-1 smooth but with costly radices (13, 11, 15): Bluestein is cheaper
-    (5281, 0, "bluestein n=12288"), (8191, 0, "bluestein"), (8191, 1, "bluesteinA n=128"),
+    (5281, 0, "bluestein n=16384"), (8191, 0, "bluestein"), (8191, 1, "bluesteinA n=128"),
     (8009, 1, "bluesteinA n=128"), (65519, 0, "bluesteinA n=512")])
 def test_prime_multi_pass(n, prec, algo):
     run_case([(n, 1, 1)], [(2, n, n)], sign=-1, prec=prec, seed=n, name=f"prime {n}",
@@ -82,7 +82,7 @@ def test_bluestein_length_choice(n, algo):
 
 
 @pytest.mark.parametrize("n,prec,inplace,algo", [
-    (17 * 4096, 0, False, "bluestein n=70"), (31 * 1024, 0, True, "rader n=30"),
+    (17 * 4096, 0, False, "bluestein n=128"), (31 * 1024, 0, True, "rader n=30"),
     (1009 * 16, 0, False, "rader n=1008"), (17 * 1024, 1, False, "rader n=16"),
     (23 * 2048, 1, True, "rader n=22"),
     (4099 * 8, 0, False, "bluesteinA")])   # second pass too long: Bluestein over n
