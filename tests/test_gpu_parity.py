@@ -50,7 +50,12 @@ def test_cooley_tukey_two_pass(n, prec):
                                23, 53, 79, 157, 859])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_rader_single_kernel(n, prec):
-    run_case([(n, 1, 1)], [(5, n, n)], sign=-1, prec=prec, seed=n, name=f"rader {n}")
+    # 11 and 13 are radices (one butterfly); up to 257 points Rader in one
+    # tile; above, Bluestein over a power of two in one leaf-kernel tile is
+    # cheaper (same results)
+    algo = None if n <= 13 else ("rader n=" if n <= 257 else "bluestein n=")
+    run_case([(n, 1, 1)], [(5, n, n)], sign=-1, prec=prec, seed=n, name=f"rader {n}",
+             expect=algo)
     run_case([(n, 1, 1)], [(5, n, n)], sign=1, prec=prec, seed=n + 1, name=f"rader {n} inv")
 
 
@@ -83,7 +88,7 @@ def test_bluestein_length_choice(n, algo):
 
 @pytest.mark.parametrize("n,prec,inplace,algo", [
     (17 * 4096, 0, False, "bluestein n=128"), (31 * 1024, 0, True, "rader n=30"),
-    (1009 * 16, 0, False, "rader n=1008"), (17 * 1024, 1, False, "rader n=16"),
+    (1009 * 16, 0, False, "bluestein n=2048"), (17 * 1024, 1, False, "rader n=16"),
     (23 * 2048, 1, True, "rader n=22"),
     (4099 * 8, 0, False, "bluesteinA")])   # second pass too long: Bluestein over n
 def test_composite_with_one_large_prime(n, prec, inplace, algo):
