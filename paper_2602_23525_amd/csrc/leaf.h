@@ -247,8 +247,9 @@ __device__ __forceinline__ void leaf_body(const PassArgs &a, cpx<T> *lds, int64_
     StageChain<T, N, TPT, 1, Rs...> chain;
     chain.load((const cpx<T> *)a.tw, 0, t);
 
-    // column tiles: inner index of the lane's store line (for the twiddle),
-    // and of its load line, clamped to the vector loop (for the pre product)
+    // column tiles: inner index of the lane's store line (for the twiddle);
+    // Bluestein modes: index of the lane's load line clamped to the vector
+    // loop (for the chirp, spectrum and, in row tiles, the store tables)
     int64_t cst = 0, lc = 0;
     constexpr bool pre = RD == 6 || RD == 9, conv = RD == 8 || RD == 9;
     constexpr bool post = RD == 7 || RD == 9;
