@@ -597,20 +597,26 @@ __global__ __launch_bounds__(max_block<T>()) void batch_kernel(const PassArgs *_
     extern __shared__ unsigned char smem[];
     cpx<T> *lds = (cpx<T> *)smem;
     __shared__ long long next;
+    if (threadIdx.x == 0) next = (long long)atomicAdd(counter, 1ull);
+    __syncthreads();
     for (;;) {
-        if (threadIdx.x == 0) next = (long long)atomicAdd(counter, 1ull);
-        __syncthreads();
         // the popped index is the same for the whole workgroup: make it a
         // scalar so the descriptor reads below are scalar loads
         const uint64_t gv = (uint64_t)next;
         const int64_t g = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane(
                                          (int)(gv >> 32)) << 32) |
                                     (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)gv));
-        __syncthreads();
         if (g >= total) break;
+        // pop the following tile now: the atomic's round trip overlaps this
+        // tile's loads instead of preceding the next tile's (past the end of
+        // the batch it pops an index no tile has; the counter is reset per launch)
+        unsigned long long popped = 0;
+        if (threadIdx.x == 0) popped = atomicAdd(counter, 1ull);
         // the item holding tile g, from the tile-to-item table
         const int i = owner[g];
-        run_tile<T, EMAX, KIND>(items[i], g - prefix[i], lds);
+        run_tile<T, EMAX, KIND>(items[i], g - prefix[i], lds);   // ends with a barrier
+        if (threadIdx.x == 0) next = (long long)popped;
+        __syncthreads();
     }
 }
 
