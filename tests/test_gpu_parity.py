@@ -101,6 +101,26 @@ def test_composite_with_one_large_prime(n, prec, inplace, algo):
              name=f"ct+prime {n} inv")
 
 
+@pytest.mark.parametrize("n,prec,inplace,hd,algo", [
+    (4093, 0, True, (3, 4093, 4093), "bluestein n=8192"),        # one leaf tile, in place
+    (4093, 0, False, (5, 4100, 4111), "bluestein n=8192"),       # padded distances
+    (2039, 1, False, (7, 2047, 2040), "bluestein n=4096"),       # FP64, 3.5 lines per tile
+    (65519, 1, False, (2, 65519, 65519), "bluesteinA n=512"),    # FP64, three leaf passes
+    (65519, 0, True, (3, 65519, 65519), "bluesteinA n=512"),     # in place through scratch
+    (50021, 0, False, (3, 50030, 50025), "bluesteinA n=512"),    # padded distances
+])
+def test_bluestein_in_leaf_kernel(n, prec, inplace, hd, algo):
+    # Bluestein convolutions over a power of two run in the leaf kernel: the
+    # chirp products with zero padding and truncation, the spectrum product
+    # between two transforms, in one tile or three column-tile passes
+    if inplace:
+        hd = (hd[0], hd[1], hd[1])
+    run_case([(n, 1, 1)], [hd], prec=prec, inplace=inplace, seed=n + hd[0], name=f"bl {n}",
+             expect=algo)
+    run_case([(n, 1, 1)], [hd], prec=prec, inplace=inplace, sign=1, seed=n + hd[0] + 1,
+             name=f"bl {n} inv")
+
+
 # ---------------------------------------------------------------- strides, ranks, in-place
 
 def test_columns_and_rows_examples():
