@@ -48,6 +48,22 @@ WORKLOADS = {
     "c2r_1d_n8192_b16384_c32": ([(8192, 1, 1)], [(16384, 4097, 8192)], 0, 1, False, "c2r"),
 }
 DEFAULT = "c2c_1d_n4096_b16384_c32"
+# sources of the specialized leaf kernel (the dominant kernel of the batched
+# power-of-two workloads): a counter summary applies while their hash matches
+LEAF_SOURCES = ["paper_2602_23525_amd/csrc/leaf.h", "paper_2602_23525_amd/csrc/k_leaf.hip",
+                "paper_2602_23525_amd/csrc/butterfly.h", "paper_2602_23525_amd/csrc/internal.h",
+                "paper_2602_23525_amd/csrc/twiddle4.h"]
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in LEAF_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def counter_traffic(workload: str, plan_desc: str):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3
     --pmc summary (FETCH_SIZE / WRITE_SIZE, scaled by the copy-kernel factor),
@@ -57,7 +73,6 @@ def counter_traffic(workload: str, plan_desc: str):
         return None
     with open(path) as fh:
         d = json.load(fh)
-    from paper_2602_23525_amd.rocprof_summary import kernel_source_hash
     if d.get("source_hash") != kernel_source_hash() or d.get("plan") != plan_desc:
         return None
     return d.get("traffic_bytes_per_launch")

@@ -1,0 +1,195 @@
+"""GPU parity at the workloads' own shapes, element by element against the
+FP64 oracle on the same seeded inputs:
+
+  * 4096-point transforms x 16384 (FP32), forward and inverse, every output;
+  * 256^3 FP32 in place and 2048^2 FP64 with transposed output strides, every
+    output (Section 4.1's I/O tensors: rank 3 in place, rank 2 with the output
+    strides of the transpose);
+  * 1000, 2187, 3^4*5^2*7, 1009 and 65537 points x 512 in both precisions
+    (every output, or 10 whole rows including the first and last for 65537);
+  * 2^22 points FP32 and 2^21 FP64 against the mixed-radix recursion (eq. ct);
+  * a seeded slice of the serving trace (2^8..2^22 points, rank 1-3, batch up
+    to 64, 20% FP64) with every response checked (sampled rows of the largest).
+
+Each case prints its relative RMS and max error (max |y - y*| / rms(y*)).
+Bounds: relative RMS <= 2e-6 (FP32), <= 1e-13 (FP64, n <= 2^20; scaled by
+log2(n)/20 above); the max error is bounded by 30x the RMS bound, far above
+the ~5x a normal error distribution reaches over these sizes, and far below
+what one wrong element (an error of order 1) gives."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import Request, serve_trace, split_smooth
+from tests.gpu_util import note, run_case, tol_for
+
+pytestmark = pytest.mark.gpu
+
+MAXERR_FACTOR = 30.0
+
+
+def _check_max(prec, ntot, me):
+    assert me <= MAXERR_FACTOR * tol_for(prec, ntot), me
+
+
+@pytest.mark.parametrize("sign", [-1, 1])
+def test_batched_4096_x16384_fp32_full(sign):
+    n, b = 4096, 16384
+    rr, me = run_case([(n, 1, 1)], [(b, n, n)], sign=sign, prec=0, seed=40 + (sign > 0),
+                      name=f"4096x16384 c32 sign {sign}")
+    _check_max(0, n, me)
+
+
+def test_batched_4096_x16384_fp64_sampled():
+    n, b = 4096, 16384
+    rows = [(0,), (1,), (4095,), (8191,), (12000,), (16383,)]
+    rr, me = run_case([(n, 1, 1)], [(b, n, n)], prec=1, seed=42, sample=rows,
+                      name="4096x16384 c64 sampled")
+    _check_max(1, n, me)
+
+
+@pytest.mark.parametrize("sign", [-1, 1])
+def test_3d_256cubed_fp32_inplace_full(sign):
+    dims = [(256, 65536, 65536), (256, 256, 256), (256, 1, 1)]
+    rr, me = run_case(dims, inplace=True, sign=sign, prec=0, seed=43 + (sign > 0),
+                      name=f"256^3 c32 in place sign {sign}")
+    _check_max(0, 1 << 24, me)
+
+
+@pytest.mark.parametrize("sign", [-1, 1])
+def test_2d_2048sq_fp64_transposed_full(sign):
+    rr, me = run_case([(2048, 2048, 1), (2048, 1, 2048)], prec=1, sign=sign,
+                      seed=45 + (sign > 0), name=f"2048^2 c64 transposed sign {sign}")
+    _check_max(1, 1 << 22, me)
+
+
+@pytest.mark.parametrize("n", [1000, 2187, 14175, 1009, 65537])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_config_sizes_batch_512(n, prec):
+    b = 512
+    sample = None
+    if n == 65537:
+        rng = np.random.default_rng(n + prec)
+        mid = sorted(int(v) for v in rng.choice(np.arange(1, b - 1), 8, replace=False))
+        sample = [(0,)] + [(v,) for v in mid] + [(b - 1,)]
+    for sign in (-1, 1):
+        rr, me = run_case([(n, 1, 1)], [(b, n, n)], prec=prec, sign=sign,
+                          seed=n * 3 + prec * 2 + (sign > 0), sample=sample,
+                          name=f"{n}x512 c{32 if prec == 0 else 64} sign {sign}")
+        _check_max(prec, n, me)
+
+
+@pytest.mark.parametrize("n,prec,b", [(1 << 22, 0, 2), (1 << 21, 1, 2)])
+def test_large_pow2_elementwise_vs_recursion(n, prec, b):
+    rr, me = run_case([(n, 1, 1)], [(b, n, n)], prec=prec, seed=n + prec, method="recursive",
+                      name=f"2^{int(math.log2(n))} c{32 if prec == 0 else 64}")
+    _check_max(prec, n, me)
+
+
+# ---------------------------------------------------------------- serving slice
+
+def _contig(dims):
+    out, s = [], 1
+    for n in reversed(dims):
+        out.append((n, s, s))
+        s *= n
+    return list(reversed(out))
+
+
+def _read(ptr, count, prec):
+    """Copy `count` elements of server-owned device memory to the host (through
+    the HIP runtime the library itself is linked against)."""
+    import ctypes
+
+    import torch
+
+    import paper_2602_23525_amd as mfft
+    dt = torch.complex64 if prec == 0 else torch.complex128
+    t = torch.empty(count, dtype=dt, device="cuda")
+    hip_memcpy = mfft.lib().hipMemcpy
+    hip_memcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    hip_memcpy.restype = ctypes.c_int
+    assert hip_memcpy(t.data_ptr(), ptr, count * (8 if prec == 0 else 16), 3) == 0
+    return t.cpu().numpy().astype(np.complex128)
+
+
+def _serve_slice():
+    """30 requests of the serving recipe (seeded), with the extremes forced in:
+    one of 2^22 points, one of batch 64, and every fifth in FP64."""
+    trace = serve_trace(30, rate_hz=400.0, seed=21)
+    out = []
+    for i, r in enumerate(trace):
+        dims, batch, prec = r.dims, r.batch, r.prec
+        # cap the other requests so the slice stays a few GB
+        while int(np.prod(dims)) * batch > (1 << 23) and batch > 1:
+            batch = max(1, batch // 2)
+        if i == 4:
+            dims, batch = split_smooth(1 << 22, 2), 2          # 2048 x 2048, two of them
+        if i == 9:
+            dims, batch = split_smooth(1 << 22, 1), 1          # 1-D 2^22
+        if i == 13:
+            dims, batch = [4096], 64                           # batch 64
+        prec = "c64" if i % 5 == 2 else ("c32" if prec == "c64" else prec)
+        out.append(Request(arrival=r.arrival, dims=list(dims), batch=batch, prec=prec,
+                           sign=r.sign, seed=r.seed))
+    return out
+
+
+def test_serving_slice_every_response_matches_oracle():
+    import time
+
+    import torch
+
+    import paper_2602_23525_amd as mfft
+    trace = _serve_slice()
+    assert max(int(np.prod(r.dims)) for r in trace) == 1 << 22
+    assert max(r.batch for r in trace) == 64
+    assert sum(r.prec == "c64" for r in trace) >= len(trace) // 5
+    need = {0: 1, 1: 1}
+    for r in trace:
+        p = 0 if r.prec == "c32" else 1
+        need[p] = max(need[p], r.points)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(21)
+    pools = {0: (torch.rand(2 * need[0], generator=g, device="cuda") * 2 - 1
+                 ).view(torch.complex64),
+             1: (torch.rand(2 * need[1], generator=g, device="cuda", dtype=torch.float64) * 2 - 1
+                 ).view(torch.complex128)}
+    torch.cuda.synchronize()   # the inputs are complete before any submission
+    srv = mfft.Server(budget_bytes=16 << 30, max_inflight=16, n_streams=4)
+    t0 = time.monotonic()
+    sub = []
+    for r in trace:
+        while time.monotonic() - t0 < r.arrival:
+            pass
+        prec = 0 if r.prec == "c32" else 1
+        ntot = int(np.prod(r.dims))
+        dims = _contig(r.dims)
+        hd = [(r.batch, ntot, ntot)] if r.batch > 1 else []
+        t = srv.submit(dims, hd, pools[prec], None, sign=r.sign, prec=prec, arrival=t0 + r.arrival)
+        sub.append((t, r, prec, dims, ntot))
+    worst = {0: 0.0, 1: 0.0}
+    for t, r, prec, dims, ntot in sub:
+        assert srv.wait(t, 120000) == 0
+        eb = 8 if prec == 0 else 16
+        # whole response, or the first and last transform of the batch for the
+        # largest responses
+        rows = list(range(r.batch)) if r.points <= (1 << 20) else [0, r.batch - 1]
+        for v in rows:
+            x = pools[prec][v * ntot:(v + 1) * ntot].cpu().numpy().astype(np.complex128)
+            y = _read(srv.output(t) + v * ntot * eb, ntot, prec)
+            ref = np.zeros(ntot, np.complex128)
+            oracle.dft(x, ref, dims, [], sign=r.sign)
+            rr, me = oracle.rel_rms(y, ref), oracle.max_err(y, ref)
+            worst[prec] = max(worst[prec], rr)
+            assert rr <= tol_for(prec, ntot), (r, v, rr)
+            assert me <= MAXERR_FACTOR * tol_for(prec, ntot), (r, v, me)
+        srv.release(t)
+    st = srv.stats()
+    note(f"    serving slice: {len(trace)} requests, worst relrms c32 {worst[0]:.3e} "
+         f"c64 {worst[1]:.3e}, p50 {st['p50_ms']:.2f} ms p99 {st['p99_ms']:.2f} ms")
+    assert st["completed"] == len(trace) and st["failed"] == 0
+    assert st["bytes_in_use"] == 0
+    srv.destroy()
