@@ -200,6 +200,23 @@ int mfft_execute(mfft_plan plan, const void *in, void *out, void *hip_stream);
 int mfft_execute_scratch(mfft_plan plan, const void *in, void *out, void *scratch,
                          void *hip_stream);
 
+/*
+ * For callers that cannot allocate device memory at execution time (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): as
+ * mfft_execute_scratch, with the scratch taken from a fixed array of
+ * MFFT_STATIC_SCRATCH_BYTES that the library reserves on each GPU it runs on
+ * (held until the process ends).  The call allocates and frees nothing.
+ * The plan's device must be current.  A plan whose info.scratch_bytes exceeds
+ * MFFT_STATIC_SCRATCH_BYTES is refused with MFFT_ENOMEM before any launch;
+ * a plan without scratch runs as with mfft_execute.  Every call on one GPU
+ * shares that GPU's array, and the array keeps the last call's contents (no
+ * plan reads scratch it has not written in the same call): calls that overlap
+ * in time on one GPU, on any streams, race and must be ordered by the caller.
+ * Other arguments and errors as for mfft_execute.
+ */
+#define MFFT_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+int mfft_execute_static_scratch(mfft_plan plan, const void *in, void *out, void *hip_stream);
+
 /* Fill *info for a plan. */
 int mfft_plan_info(mfft_plan plan, mfft_plan_info_t *info);
 

@@ -15,7 +15,7 @@ import re
 
 __all__ = [
     "lib", "IoDim", "PlanInfo", "MfftError", "Plan", "mfft_problem_check", "mfft_plan_dft",
-    "mfft_execute", "mfft_execute_scratch", "mfft_plan_dft_real", "mfft_problem_check_real", "mfft_plan_info", "mfft_plan_destroy",
+    "mfft_execute", "mfft_execute_scratch", "mfft_execute_static_scratch", "mfft_plan_dft_real", "mfft_problem_check_real", "mfft_plan_info", "mfft_plan_destroy",
     "mfft_wisdom_export", "mfft_wisdom_import", "mfft_wisdom_forget", "mfft_last_error",
     "mfft_version", "C32", "C64", "ESTIMATE", "MEASURE", "WISDOM_ONLY", "NO_WISDOM",
     "FP32_TWIDDLES", "NO_SCRATCH",
@@ -95,6 +95,7 @@ def lib():
         f.restype = ctypes.c_int
     L.mfft_execute.argtypes = [p, p, p, p]
     L.mfft_execute_scratch.argtypes = [p, p, p, p, p]
+    L.mfft_execute_static_scratch.argtypes = [p, p, p, p]
     L.mfft_plan_info.argtypes = [p, ctypes.POINTER(PlanInfo)]
     L.mfft_plan_destroy.argtypes = [p]
     L.mfft_wisdom_export.argtypes = [ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_size_t)]
@@ -126,6 +127,7 @@ def lib():
     L.mfft_last_error.restype = ctypes.c_char_p
     L.mfft_version.restype = ctypes.c_char_p
     for name in ("mfft_problem_check", "mfft_plan_dft", "mfft_execute", "mfft_execute_scratch",
+                 "mfft_execute_static_scratch",
                  "mfft_plan_info", "mfft_plan_destroy", "mfft_wisdom_export",
                  "mfft_wisdom_import", "mfft_wisdom_forget"):
         getattr(L, name).restype = ctypes.c_int
@@ -227,6 +229,14 @@ def mfft_execute_scratch(plan: int, x, y, scratch, stream=None):
            "mfft_execute_scratch")
 
 
+def mfft_execute_static_scratch(plan: int, x, y, stream=None):
+    _check(lib().mfft_execute_static_scratch(plan, _ptr(x), _ptr(y), _stream(stream)),
+           "mfft_execute_static_scratch")
+
+
+STATIC_SCRATCH_BYTES = 64 << 20
+
+
 def mfft_plan_info(plan: int) -> dict:
     info = PlanInfo()
     _check(lib().mfft_plan_info(plan, ctypes.byref(info)), "mfft_plan_info")
@@ -308,6 +318,11 @@ class Plan:
 
     def execute_scratch(self, x, y, scratch, stream=None):
         mfft_execute_scratch(self.handle, x, y, scratch, stream)
+        return y
+
+    def execute_static_scratch(self, x, y=None, stream=None):
+        y = x if y is None else y
+        mfft_execute_static_scratch(self.handle, x, y, stream)
         return y
 
     def info(self) -> dict:

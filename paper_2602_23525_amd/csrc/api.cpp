@@ -21,6 +21,32 @@ static std::mutex g_plan_mutex;
 static bool g_inited = false;
 static std::string g_arch = "unknown";
 
+// Scratch of mfft_execute_static_scratch: a fixed device array the loader
+// places on every GPU the library runs on, held until the process ends, so
+// that executing a plan that needs scratch allocates nothing.  In host code
+// `scratch` names a host-side stand-in; the device address comes from
+// hipGetSymbolAddress, resolved once per device and kept in g_static_ptr.
+static __device__ __align__(256) unsigned char scratch[MFFT_STATIC_SCRATCH_BYTES];
+constexpr int kMaxDevices = 64;
+static std::mutex g_static_mutex;
+static void *g_static_ptr[kMaxDevices];
+
+// Device address of `scratch` on device `dev` (which must be current).
+static int static_scratch_ptr(int dev, void **ptr)
+{
+    if (dev < 0 || dev >= kMaxDevices) return fail(MFFT_EINVAL, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_static_mutex);
+    if (!g_static_ptr[dev]) {
+        void *q = nullptr;
+        hipError_t e = hipGetSymbolAddress(&q, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !q)
+            return fail(MFFT_EHIP, std::string("static scratch address: ") + hipGetErrorString(e));
+        g_static_ptr[dev] = q;
+    }
+    *ptr = g_static_ptr[dev];
+    return MFFT_OK;
+}
+
 static int init_device()
 {
     if (g_inited) return MFFT_OK;
@@ -36,6 +62,9 @@ static int init_device()
     // keep a little LDS for the batched kernel's static variables
     g_lds_budget = std::min<size_t>(lds, 163840) - 256;
     g_num_cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    void *q = nullptr;
+    int rc = static_scratch_ptr(dev, &q);
+    if (rc) return rc;
     g_inited = true;
     return MFFT_OK;
 }
@@ -229,6 +258,25 @@ int mfft_execute(mfft_plan plan, const void *in, void *out, void *hip_stream)
 {
     if (!plan) return fail(MFFT_EINVAL, "plan is NULL");
     return mfft_execute_scratch(plan, in, out, plan->impl.scratch, hip_stream);
+}
+
+int mfft_execute_static_scratch(mfft_plan plan, const void *in, void *out, void *hip_stream)
+{
+    if (!plan) return fail(MFFT_EINVAL, "plan is NULL");
+    const PlanImpl *p = &plan->impl;
+    if (p->scratch_bytes > MFFT_STATIC_SCRATCH_BYTES)
+        return fail(MFFT_ENOMEM, "plan needs " + std::to_string(p->scratch_bytes) +
+                                     " bytes of scratch; the static scratch holds " +
+                                     std::to_string((size_t)MFFT_STATIC_SCRATCH_BYTES));
+    void *s = nullptr;
+    if (p->scratch_bytes) {
+        int dev = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e != hipSuccess) return fail(MFFT_EHIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+        int rc = static_scratch_ptr(dev, &s);
+        if (rc) return rc;
+    }
+    return mfft_execute_scratch(plan, in, out, s, hip_stream);
 }
 
 int mfft_plan_info(mfft_plan plan, mfft_plan_info_t *info)
