@@ -110,24 +110,6 @@ static int dispatch_cols(int kind, const PassArgs &a, int n, int grid, hipStream
     return 0;
 }
 
-int leaf_col_lines_per_tile(int prec, int n) { return col_lines(prec, n); }
-
-bool leaf_col_supported(int prec, int64_t n, bool transposing)
-{
-    (void)prec;
-    return n >= (transposing ? 256 : 64) && n <= 2048 && (n & (n - 1)) == 0;
-}
-
-// 16384 points (FP32) and 8192 (FP64) fill the LDS of one CU with one line
-int leaf_max_n(int prec) { return prec == 0 ? 16384 : 8192; }
-
-int leaf_lines_per_tile(int prec, int n) { return leaf_row_lines(prec, n); }
-
-bool leaf_supported(int prec, int64_t n)
-{
-    return n >= 64 && n <= leaf_max_n(prec) && (n & (n - 1)) == 0;
-}
-
 // variant bits: 0 prefetch; 1-2 occupancy floor (1: 3 waves per SIMD, 2: 4,
 // else 2; FP32 only); 3 non-temporal stores; 4 non-temporal loads (only
 // together with stores).

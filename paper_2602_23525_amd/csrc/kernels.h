@@ -5,6 +5,7 @@
 #include <cstdint>
 
 #include "internal.h"
+#include "leaf_shape.h"
 
 namespace mfft {
 
@@ -101,13 +102,7 @@ hipError_t launch_zero_u64(unsigned long long *p, int count, hipStream_t s);
 
 namespace mfft {
 // Specialized power-of-two leaf kernel (leaf.h): unit-stride lines, or tiles of
-// adjacent lines with strided elements.
-bool leaf_supported(int prec, int64_t n);
-int leaf_lines_per_tile(int prec, int n);
-// column tiles of the leaf kernel (PF_LEAF_COL, or transposing: PF_LEAF_CR /
-// PF_LEAF_RC): adjacent lines, strided elements
-bool leaf_col_supported(int prec, int64_t n, bool transposing);
-int leaf_col_lines_per_tile(int prec, int n);
+// adjacent lines with strided elements (shapes in leaf_shape.h).
 // variant bit 0: prefetch next tile; bit 1: lower occupancy floor (more VGPRs)
 int leaf_blocks_per_cu(int prec, int n, int variant);
 hipError_t launch_leaf(const PassArgs &a, int prec, int n, int variant, int grid, hipStream_t s);

@@ -17,6 +17,7 @@
 #pragma once
 #include "butterfly.h"
 #include "internal.h"
+#include "leaf_shape.h"
 #include "twiddle4.h"
 
 namespace mfft {
@@ -205,20 +206,6 @@ __device__ __forceinline__ void st_elem(cpx<T> *p, cpx<T> v)
 // non-temporal loads (neither is reused by this pass).
 template <int N>
 constexpr int leaf_lds_stride() { return (lds_pad(N - 1) + 1) | 1; }
-
-// Lines per tile.  Row tiles: 256 threads (FP32) or 128 (FP64) of 16 elements,
-// at least one line (n = 4096 FP64: one line of 256 threads).  Column tiles:
-// 64 lines of 64 points up to 16 of 256 (FP32; half as many in FP64, same
-// bytes), then 16 / 8 (FP32) and 8 / 4 (FP64) lines as the LDS allows.
-constexpr int leaf_row_lines(int prec, int n)
-{
-    return (prec == 0 ? 4096 : 2048) / n > 0 ? (prec == 0 ? 4096 : 2048) / n : 1;
-}
-constexpr int leaf_col_lines(int prec, int n)
-{
-    if (prec == 0) return n <= 256 ? 4096 / n : (n <= 512 ? 16 : 8);
-    return n <= 256 ? 2048 / n : (n <= 512 ? 8 : 4);
-}
 
 // The leaf pass from tile `tile` on, every G-th tile, with the tile's LDS at
 // lds (BT lines of leaf_lds_stride<N>() elements).
@@ -428,15 +415,25 @@ __device__ __forceinline__ void leaf_body(const PassArgs &a, cpx<T> *lds, int64_
         if constexpr (cols_in || cols_out) {
             if (a.flags & PF_TW4) {
                 // element k = k0 + e*TPT of inner line c (k0 the lane's store
-                // rank): w_N^(c*k), the powers of w_N^(c*TPT) by an FP64
-                // recurrence from w_N^(c*k0)
+                // rank): w_N^(c*k).  FP32 data: the powers of w_N^(c*TPT) by an
+                // FP64 recurrence from w_N^(c*k0) (16 steps, far below FP32
+                // rounding); FP64 data: each twiddle from the two tables
+                // (Section 6: no recurrence where it would reach the data's
+                // precision)
                 const int64_t cw = ok ? cst : 0;
-                double2 w = tw4_root(a, cw * (xpose ? ts : t));
-                const double2 ws = tw4_root(a, cw * TPT);
+                const int64_t k0 = xpose ? ts : t;
+                if constexpr (sizeof(T) == 8) {
 #pragma unroll
-                for (int e = 0; e < 16; ++e) {
-                    x[e] = mul_d(x[e], w);
-                    w = zmul(w, ws);
+                    for (int e = 0; e < 16; ++e)
+                        x[e] = mul_d(x[e], tw4_root(a, cw * (k0 + e * TPT)));
+                } else {
+                    double2 w = tw4_root(a, cw * k0);
+                    const double2 ws = tw4_root(a, cw * TPT);
+#pragma unroll
+                    for (int e = 0; e < 16; ++e) {
+                        x[e] = mul_d(x[e], w);
+                        w = zmul(w, ws);
+                    }
                 }
             }
         }

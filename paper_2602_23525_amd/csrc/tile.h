@@ -337,13 +337,20 @@ __device__ __forceinline__ void stage(const PassArgs &a, const StageDesc &sd, Ti
                 if constexpr (KIND & K_TW4) {
                     if (a.flags & PF_TW4) {
                         // element base + k*Ns of line c takes w_N^(c*(j + k*Ns)):
-                        // start w_N^(c*j), step w_N^(c*Ns), products in FP64
-                        double2 w = tw4_root(a, cs * j);
-                        const double2 ws = tw4_root(a, cs * Ns);
+                        // FP32 data: start w_N^(c*j), step w_N^(c*Ns), products
+                        // in FP64; FP64 data: every twiddle from the tables
+                        if constexpr (sizeof(T) == 8) {
 #pragma unroll
-                        for (int k = 0; k < R; ++k) {
-                            v[i][k] = mul_d(v[i][k], w);
-                            w = zmul(w, ws);
+                            for (int k = 0; k < R; ++k)
+                                v[i][k] = mul_d(v[i][k], tw4_root(a, cs * (j + k * Ns)));
+                        } else {
+                            double2 w = tw4_root(a, cs * j);
+                            const double2 ws = tw4_root(a, cs * Ns);
+#pragma unroll
+                            for (int k = 0; k < R; ++k) {
+                                v[i][k] = mul_d(v[i][k], w);
+                                w = zmul(w, ws);
+                            }
                         }
                     }
                 }
@@ -488,14 +495,18 @@ __device__ __forceinline__ void tile_body(const PassArgs &a, Tile<T> &tl, cpx<T>
             // this lane's elements idx + k*step of line c take the Cooley-Tukey
             // twiddle w_N^(c*idx) times powers of w_N^(c*step): two table
             // lookups per lane, FP64 products
+            // (FP64 data: every twiddle from the tables instead)
             double2 w = make_double2(1.0, 0.0), ws = w;
             bool tw = false;
+            int64_t cs = 0;
             if constexpr (KIND & K_TW4) {
                 tw = (f & PF_TW4) != 0;
                 if (tw) {
-                    const int64_t cs = okc ? c : tl.c0;   // padding lines: in-range tables
-                    w = tw4_root(a, (int64_t)idx * cs);
-                    ws = tw4_root(a, (int64_t)step * cs);
+                    cs = okc ? c : tl.c0;   // padding lines: in-range tables
+                    if constexpr (sizeof(T) != 8) {
+                        w = tw4_root(a, (int64_t)idx * cs);
+                        ws = tw4_root(a, (int64_t)step * cs);
+                    }
                 }
             }
             constexpr int CH = (KIND & K_EXT) ? ext_chunk<T>() : KMAX;
@@ -513,8 +524,12 @@ __device__ __forceinline__ void tile_body(const PassArgs &a, Tile<T> &tl, cpx<T>
                     const int pk = lin ? pidx + (k0 + q) * pstep : lds_pad(kk);
                     y[q] = kk < n ? src[pk] : cpx<T>{T(0), T(0)};
                     if (tw) {
-                        y[q] = mul_d(y[q], w);
-                        w = zmul(w, ws);
+                        if constexpr (sizeof(T) == 8) {
+                            if (kk < n) y[q] = mul_d(y[q], tw4_root(a, (int64_t)kk * cs));
+                        } else {
+                            y[q] = mul_d(y[q], w);
+                            w = zmul(w, ws);
+                        }
                     }
                 }
                 store_run<T, CH, KIND, true>(a, tq, c, okc, base, idx + k0 * step, step, y);

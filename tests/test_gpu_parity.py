@@ -78,6 +78,20 @@ def test_prime_multi_pass(n, prec, algo):
     run_case([(n, 1, 1)], [(2, n, n)], sign=1, prec=prec, seed=n + 1, name=f"prime {n} inv")
 
 
+@pytest.mark.parametrize("n,prec,algo", [(16633, 0, "raderB"), (8209, 0, "bluesteinB"),
+                                         (10369, 1, "raderB")])
+def test_three_pass_prime_with_partial_last_tile(n, prec, algo):
+    # regression for the padding-line over-read of the generic tile kernel: the
+    # middle pass tiles a column count that is not a multiple of its tile width
+    # (16632 = 126 * 132, 132 lines by 16; 18432 = 128 * 144, 144 lines by 32;
+    # 10368 = 96 * 108, 108 lines by 8, spectrum and twiddle tables), so the
+    # last tile's padding lines take an in-range line's tables (table bounds
+    # of every prime plan: the host planner test)
+    for sign in (-1, 1):
+        run_case([(n, 1, 1)], [(5, n, n)], sign=sign, prec=prec, seed=n + (sign > 0),
+                 name=f"three-pass prime {n} partial tile", expect=algo)
+
+
 @pytest.mark.parametrize("n,algo", [(4093, "bluestein n=8192"), (1213, "bluestein"),
                                     (3011, "bluestein")])
 def test_bluestein_length_choice(n, algo):

@@ -1,0 +1,110 @@
+"""The planner and the problem canonicalization compiled for the host with g++
+(tests/host_stub stands in for the HIP runtime: tables are address ranges,
+launches do nothing), so that every plan the library would make can be
+inspected on the CPU:
+
+  * table bounds: for each pass, the largest index any lane forms in each table
+    (gather/scatter, pre/post multipliers, convolution spectrum, two-level
+    twiddles, stage twiddles, Rader's per-transform terms), padding lines of a
+    partial last tile included, lies inside the table
+    (tests/plan_host_check.cpp), for every prime from 67 to 65521 in both
+    precisions -- the three-pass Rader / Bluestein plans whose column count is
+    not a multiple of the tile width among them, the case of the padding-line
+    over-read fixed in the generic tile kernel -- and for every length up to
+    4096 and sampled composite lengths above;
+  * the same planner (and the oracle's C code) under AddressSanitizer and
+    UndefinedBehaviorSanitizer, on prime ranges and seeded random problems
+    (strided, transposed, reversed, in place, aliasing)."""
+import os
+import re
+import shutil
+import subprocess
+
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(ROOT, "paper_2602_23525_amd", "csrc")
+SOURCES = [os.path.join(HERE, "plan_host_check.cpp"), os.path.join(CSRC, "plan.cpp"),
+           os.path.join(CSRC, "problem.cpp")]
+INC = ["-I", os.path.join(HERE, "host_stub"), "-I", CSRC, "-I", os.path.join(ROOT, "include")]
+SAN = ["-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all"]
+
+pytestmark = pytest.mark.skipif(shutil.which("g++") is None, reason="no host C++ compiler")
+
+
+@pytest.fixture(scope="module")
+def checker(tmp_path_factory):
+    exe = str(tmp_path_factory.mktemp("planhost") / "plan_host_check")
+    subprocess.run(["g++", "-std=c++17", "-O2", *INC, *SOURCES, "-o", exe], check=True)
+    return exe
+
+
+@pytest.fixture(scope="module")
+def checker_san(tmp_path_factory):
+    exe = str(tmp_path_factory.mktemp("planhost_san") / "plan_host_check")
+    subprocess.run(["g++", "-std=c++17", *SAN, *INC, *SOURCES, "-o", exe], check=True)
+    return exe
+
+
+def _run(exe, *args, env=None):
+    r = subprocess.run([exe, *map(str, args)], capture_output=True, text=True, env=env)
+    summary = r.stdout.strip().splitlines()[-1] if r.stdout.strip() else ""
+    print(summary)
+    assert r.returncode == 0, (r.stdout[-4000:], r.stderr[-4000:])
+    assert "VIOLATION" not in r.stdout and "runtime error" not in r.stderr, r.stderr[-4000:]
+    return r.stdout, dict((k, int(v)) for k, v in re.findall(r"(\w+)=(\d+)", summary))
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_prime_plans_stay_inside_their_tables(checker, prec):
+    out, s = _run(checker, "bounds", prec, 67, 65521, 2, "primes")
+    assert s["plans"] == 6524 and s["violations"] == 0 and s["failed"] == 0
+    # multi-pass prime plans with a partial last column tile exist, and their
+    # padding lines would read past the spectrum without the clamp
+    assert s["partial"] > 50 and s["guarded"] > 20
+    if prec == 0:
+        # p = 16633: Rader, L = 16632 = 126 * 132, the middle pass tiles 132
+        # lines by 16
+        assert re.search(r"GUARDED n=16633 c32: conv .*raderB", out)
+        # p = 8209: Bluestein, M = 18432 = 128 * 144, 144 lines by 32
+        assert re.search(r"GUARDED n=8209 c32: conv .*bluesteinB", out)
+    else:
+        # p = 10369: Rader, L = 10368 = 96 * 108, 108 lines by 8 (spectrum and
+        # two-level twiddles)
+        assert re.search(r"GUARDED n=10369 c64: tw4_hi .*raderB", out)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_every_length_to_4096_stays_inside_its_tables(checker, prec):
+    _, s = _run(checker, "bounds", prec, 1, 4096, 3, "all")
+    assert s["violations"] == 0 and s["failed"] == 0 and s["plans"] == 4096
+
+
+def test_sampled_composite_lengths_stay_inside_their_tables(checker):
+    for lo in (4097, 16000, 40000, 65530):
+        _, s = _run(checker, "bounds", 0, lo, lo + 400, 2, "composite")
+        assert s["violations"] == 0 and s["failed"] == 0
+
+
+def test_planner_under_address_and_ub_sanitizers(checker_san):
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=1",
+               UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1")
+    _, s = _run(checker_san, "bounds", 0, 67, 12000, 2, "primes", env=env)
+    assert s["violations"] == 0 and s["guarded"] > 0
+    _, s = _run(checker_san, "bounds", 1, 1, 2100, 3, "all", env=env)
+    assert s["violations"] == 0
+    _, s = _run(checker_san, "random", 3000, 11, env=env)
+    assert s["violations"] == 0 and s["planned"] > 1000
+
+
+def test_oracle_under_address_and_ub_sanitizers(tmp_path):
+    if shutil.which("gcc") is None:
+        pytest.skip("no gcc")
+    exe = str(tmp_path / "oracle_san")
+    subprocess.run(["gcc", "-std=gnu11", *SAN, "-pthread", os.path.join(ROOT, "oracle", "oracle.c"),
+                    os.path.join(HERE, "oracle_sanitize_check.c"), "-o", exe, "-lm"], check=True)
+    r = subprocess.run([exe], capture_output=True, text=True,
+                       env=dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=1"))
+    print(r.stdout)
+    assert r.returncode == 0 and "check ok" in r.stdout, (r.stdout, r.stderr[-4000:])
