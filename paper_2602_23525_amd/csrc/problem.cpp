@@ -37,26 +37,61 @@ static bool mul_overflows(int64_t a, int64_t b)
     return p > (__int128)INT64_MAX / 4 || p < -(__int128)INT64_MAX / 4;
 }
 
-// Injectivity of the output map over all dims with n > 1.  Sufficient test:
-// sorted by |os|, each |os| exceeds the span of all smaller dims.  When that
-// fails, an exact enumeration for problems of at most 2^22 elements.
+// Is v a sum of delta_j * |os_j| over the first k of the dims d (sorted by
+// |os|), |delta_j| < n_j?  span[i] is the largest such sum over the first i
+// dims.  Counts visited nodes against *budget (false once it runs out, with
+// *budget < 0).
+static bool in_difference_set(const std::vector<Dim> &d, const std::vector<int64_t> &span,
+                              size_t k, int64_t v, int64_t *budget)
+{
+    if (v == 0) return true;
+    if (k == 0 || --*budget < 0) return false;
+    const int64_t o = std::llabs(d[k - 1].os), m = d[k - 1].n - 1, s = span[k - 1];
+    if (std::llabs(v) > s + m * o) return false;
+    // delta * o within s of v
+    auto fdiv = [](int64_t a, int64_t q) { return a / q - ((a % q != 0) && ((a < 0) != (q < 0))); };
+    const int64_t lo = std::max(-m, -fdiv(-(v - s), o)), hi = std::min(m, fdiv(v + s, o));
+    for (int64_t delta = lo; delta <= hi; ++delta) {
+        if (in_difference_set(d, span, k - 1, v - delta * o, budget)) return true;
+        if (*budget < 0) return false;
+    }
+    return false;
+}
+
+// Injectivity of the output map over all dims with n > 1.  Two index tuples
+// collide exactly when some nonzero (delta_j), |delta_j| < n_j, has
+// sum delta_j * os_j = 0; taking the dim of largest |os| with delta_j != 0 as
+// the last, its multiple delta_k * |os_k| must be a difference of outputs of
+// the dims of smaller |os|, which only happens when it is at most their span
+// (so a layout where each |os| exceeds the span of the smaller ones is
+// injective at once).  Otherwise the multiples below that span are decided by
+// a bounded search over the smaller dims; past its budget, an enumeration of
+// every output for problems of at most 2^22 elements, else refused.
 static bool outputs_injective(const std::vector<Dim> &all)
 {
     std::vector<Dim> d;
     for (const Dim &x : all)
-        if (x.n > 1) d.push_back(x);
+        if (x.n > 1) {
+            if (x.os == 0) return false;
+            d.push_back(x);
+        }
     std::sort(d.begin(), d.end(),
               [](const Dim &a, const Dim &b) { return std::llabs(a.os) < std::llabs(b.os); });
-    int64_t span = 0;
-    bool ok = true;
-    for (const Dim &x : d) {
-        if (std::llabs(x.os) <= span) {
-            ok = false;
-            break;
+    std::vector<int64_t> span(d.size() + 1, 0);
+    for (size_t i = 0; i < d.size(); ++i) span[i + 1] = span[i] + (d[i].n - 1) * std::llabs(d[i].os);
+    int64_t budget = (int64_t)1 << 24;
+    bool decided = true;
+    for (size_t k = 1; k < d.size() && decided; ++k) {
+        const int64_t o = std::llabs(d[k].os);
+        for (int64_t delta = 1; delta < d[k].n && delta * o <= span[k]; ++delta) {
+            if (in_difference_set(d, span, k, delta * o, &budget)) return false;
+            if (budget < 0) {
+                decided = false;
+                break;
+            }
         }
-        span += (x.n - 1) * std::llabs(x.os);
     }
-    if (ok) return true;
+    if (decided) return true;
     int64_t total = 1;
     for (const Dim &x : d) {
         total *= x.n;

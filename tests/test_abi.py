@@ -46,6 +46,11 @@ def test_header_declares_extern_c_block():
     ([(1 << 41, 1, 1)], [], 0, -1, 0, EINVAL),             # too large
     ([(1 << 30, 1 << 40, 1)], [], 0, -1, 0, EINVAL),       # stride * length overflows
     ([(2, 1, 1)] * 9, [], 0, -1, 0, EINVAL),               # rank above 8
+    # above 2^22 elements, interleaved strides that fail the span test but
+    # never collide (5a + 2b < 16 for a < 2, b < 5): legal
+    ([(5, 2, 2), (2, 5, 5)], [(1 << 21, 16, 16)], 0, -1, 0, OK),
+    # the same size with a collision (3*2 = 2*3): aliasing
+    ([(4, 3, 3), (4, 2, 2)], [(1 << 20, 64, 64)], 0, -1, 0, EINVAL),
 ])
 def test_problem_check(dims, hdims, inplace, sign, prec, expect):
     assert mfft.mfft_problem_check(dims, hdims, inplace, sign, prec) == expect
@@ -116,3 +121,39 @@ def test_flag_constants_match_header():
         m = re.search(r"#define MFFT_%s +(\d+)u" % name, text)
         assert m, name
         assert int(m.group(1)) == getattr(mfft, name), name
+
+
+def _collides(dims):
+    seen = set()
+    idx = [0] * len(dims)
+    while True:
+        off = sum(i * d[2] for i, d in zip(idx, dims))
+        if off in seen:
+            return True
+        seen.add(off)
+        j = 0
+        while j < len(dims):
+            idx[j] += 1
+            if idx[j] < dims[j][0]:
+                break
+            idx[j] = 0
+            j += 1
+        if j == len(dims):
+            return False
+
+
+def test_aliasing_check_is_exact_on_random_layouts():
+    # small output layouts with arbitrary strides: the library's answer equals
+    # brute-force enumeration of every output address
+    import random
+    rng = random.Random(5)
+    seen_ok = seen_bad = 0
+    for _ in range(600):
+        k = rng.randint(1, 4)
+        dims = [(rng.randint(2, 6), 1, rng.choice([-1, 1]) * rng.randint(1, 12)) for _ in range(k)]
+        want = EINVAL if _collides(dims) else OK
+        got = mfft.mfft_problem_check(dims[:1], dims[1:], 0, -1, 0)
+        assert got == want, (dims, got, want)
+        seen_ok += want == OK
+        seen_bad += want == EINVAL
+    assert seen_ok > 100 and seen_bad > 100
