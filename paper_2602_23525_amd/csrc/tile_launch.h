@@ -1,0 +1,88 @@
+// Launchers of one variant (element type, kernel kind) of the generic tile
+// kernel: the single-pass launch, the persistent batched launch and its
+// occupancy query.  Each variant is instantiated by a translation unit of its
+// own (k_c{32,64}_k{0,1,5,7}.hip) so that the variants compile in parallel.
+#pragma once
+#include <mutex>
+
+#include "tile.h"
+
+namespace mfft {
+
+// Raise a kernel's dynamic-LDS limit to at least `lds` bytes (gfx950: up to
+// 160 KB per workgroup).  The limit only grows; calls from several host
+// threads are serialized so that a smaller request never lowers it.
+inline hipError_t allow_dynamic_lds(const void *fn, size_t lds, size_t *granted, std::mutex *m)
+{
+    std::lock_guard<std::mutex> lk(*m);
+    if (lds <= *granted) return hipSuccess;
+    const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e == hipSuccess) *granted = lds;
+    return e;
+}
+
+template <typename T, int KIND>
+struct TileLaunch {
+    static std::mutex &mu()
+    {
+        static std::mutex m;
+        return m;
+    }
+
+    static hipError_t pass(const PassArgs &a, size_t lds, hipStream_t s)
+    {
+        static size_t granted = 65536;
+        hipError_t e = allow_dynamic_lds((const void *)pass_kernel<T, 16, KIND>, lds, &granted, &mu());
+        if (e != hipSuccess) return e;
+        const int64_t grid = (a.flags & PF_XCD) ? (a.ntiles + kXcds - 1) / kXcds * kXcds : a.ntiles;
+        hipLaunchKernelGGL((pass_kernel<T, 16, KIND>), dim3((unsigned)grid), dim3(a.bt * a.tpt), lds,
+                           s, a);
+        return hipGetLastError();
+    }
+
+    static hipError_t batch(const PassArgs *items, const int64_t *prefix, const int32_t *owner,
+                            int64_t total, unsigned long long *counter, int block, int grid,
+                            size_t lds, hipStream_t s)
+    {
+        static size_t granted = 65536;
+        hipError_t e = allow_dynamic_lds((const void *)batch_kernel<T, 16, KIND>, lds, &granted, &mu());
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((batch_kernel<T, 16, KIND>), dim3(grid), dim3(block), lds, s, items,
+                           prefix, owner, total, counter);
+        return hipGetLastError();
+    }
+
+    static int blocks_per_cu(int block, size_t lds)
+    {
+        int b = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, batch_kernel<T, 16, KIND>, block, lds) !=
+            hipSuccess) {
+            (void)hipGetLastError();
+            return 1;
+        }
+        return b > 0 ? b : 1;
+    }
+};
+
+}  // namespace mfft
+
+// The three entry points of variant NAME (kernels.hip dispatches to them).
+#define MFFT_TILE_LAUNCHERS(T, NAME, KIND)                                                        \
+    namespace mfft {                                                                              \
+    hipError_t launch_pass_##NAME(const PassArgs &a, size_t lds, hipStream_t s)                   \
+    {                                                                                             \
+        return TileLaunch<T, KIND>::pass(a, lds, s);                                              \
+    }                                                                                             \
+    hipError_t launch_batch_##NAME(const PassArgs *items, const int64_t *prefix,                  \
+                                   const int32_t *owner, int64_t total,                           \
+                                   unsigned long long *counter, int block, int grid, size_t lds,  \
+                                   hipStream_t s)                                                 \
+    {                                                                                             \
+        return TileLaunch<T, KIND>::batch(items, prefix, owner, total, counter, block, grid, lds, \
+                                          s);                                                     \
+    }                                                                                             \
+    int batch_blocks_per_cu_##NAME(int block, size_t lds)                                         \
+    {                                                                                             \
+        return TileLaunch<T, KIND>::blocks_per_cu(block, lds);                                    \
+    }                                                                                             \
+    }
