@@ -259,15 +259,27 @@ int mfft_batch_destroy(mfft_batch batch);
  * and launches everything admitted since the last launch as one batch (see
  * mfft_batch_*) on the next of n_streams streams, so requests that arrive while
  * others run are admitted as memory frees and overlap on the device.  Plans and
- * their twiddle tables stay resident in a cache keyed by the problem.
+ * their twiddle tables stay resident in a cache keyed by the problem; a
+ * request whose plan is not cached is planned by a separate planner thread
+ * while the scheduler keeps admitting and retiring requests whose plans exist
+ * (admission is in arrival order among requests whose plan is ready; the
+ * first of them that does not fit the memory left blocks the others).
  *
- *   hbm_budget_bytes: device memory the server may hold for request outputs,
- *       scratch and launch descriptors (allocated once at creation).
+ *   hbm_budget_bytes: device memory the server may hold: request outputs and
+ *       scratch, launch descriptors and the cached plans' tables (the budget
+ *       is reserved once at creation; cached plans no request uses are evicted,
+ *       least recently used first, when memory is short).  Transient buffers of
+ *       planning itself (the FP64 sub-transforms that build prime-size tables)
+ *       come from hipMalloc and are freed before planning returns.
  *   max_inflight: admitted-but-unfinished request limit (>= 1); n_streams >= 1.
- *   alloc: reserved, pass NULL.
- * A request's input must stay valid until it completes.  If out is NULL the
- * server allocates the output inside the budget; read it with
- * mfft_server_output and give it back with mfft_server_release.
+ *   alloc: allocator for the budget's one reservation (NULL = hipMalloc);
+ *       called once at creation and once (free) at destruction.
+ * A request's input must stay valid until it completes.  If in_stream is not
+ * NULL, the request runs after the work enqueued on that stream before the
+ * submission (an event is recorded on it at submission); with NULL the input
+ * must be complete when submitted.  If out is NULL the server allocates the
+ * output inside the budget; read it with mfft_server_output and give it back
+ * with mfft_server_release.
  */
 typedef struct mfft_server_s *mfft_server;
 
@@ -281,6 +293,7 @@ typedef struct {
     const void *in;      /* device input tensor, element (0,...,0)              */
     void *out;           /* device output, or NULL = allocate in the budget      */
     double arrival;      /* steady-clock seconds of arrival (0 = at submission)  */
+    void *in_stream;     /* stream producing the input (hipStream_t), or NULL    */
 } mfft_request;
 
 typedef struct {
@@ -292,9 +305,11 @@ typedef struct {
     double flops;            /* nominal 5 N log2 N flops of completed requests     */
     double bytes;            /* compulsory bytes of completed requests             */
     size_t bytes_in_use, peak_bytes;   /* within the budget                        */
-    size_t plan_bytes;       /* resident plan tables and scratch (outside budget)  */
+    size_t plan_bytes;       /* resident plan tables (inside the budget, counted
+                              * in bytes_in_use and peak_bytes)                  */
     int plans_cached;
     int max_inflight_seen;
+    int plans_evicted;       /* cached plans dropped to make room                  */
 } mfft_server_stats_t;
 
 /* Request status reported by mfft_server_wait. */

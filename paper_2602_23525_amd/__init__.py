@@ -384,7 +384,8 @@ class Batch:
 class Request(ctypes.Structure):
     _fields_ = [("rank", ctypes.c_int), ("dims", IoDim * 8), ("howmany_rank", ctypes.c_int),
                 ("howmany_dims", IoDim * 8), ("sign", ctypes.c_int), ("prec", ctypes.c_int),
-                ("in_", ctypes.c_void_p), ("out", ctypes.c_void_p), ("arrival", ctypes.c_double)]
+                ("in_", ctypes.c_void_p), ("out", ctypes.c_void_p), ("arrival", ctypes.c_double),
+                ("in_stream", ctypes.c_void_p)]
 
 
 class ServerStats(ctypes.Structure):
@@ -394,7 +395,7 @@ class ServerStats(ctypes.Structure):
                                                "flops", "bytes")] + \
                [("bytes_in_use", ctypes.c_size_t), ("peak_bytes", ctypes.c_size_t),
                 ("plan_bytes", ctypes.c_size_t), ("plans_cached", ctypes.c_int),
-                ("max_inflight_seen", ctypes.c_int)]
+                ("max_inflight_seen", ctypes.c_int), ("plans_evicted", ctypes.c_int)]
 
 
 REQ_DONE, REQ_PENDING, REQ_RUNNING = 0, 1, 2
@@ -403,14 +404,19 @@ REQ_DONE, REQ_PENDING, REQ_RUNNING = 0, 1, 2
 class Server:
     """Request server with continuous batching (mfft_server_*)."""
 
-    def __init__(self, budget_bytes, max_inflight=64, n_streams=4):
+    def __init__(self, budget_bytes, max_inflight=64, n_streams=4, allocator=None):
         L = lib()
         h = ctypes.c_void_p()
+        self._alloc = allocator      # keeps the callbacks alive
+        al = ctypes.byref(allocator) if allocator is not None else None
         _check(L.mfft_server_create(ctypes.byref(h), int(budget_bytes), int(max_inflight),
-                                    int(n_streams), None), "mfft_server_create")
+                                    int(n_streams), al), "mfft_server_create")
         self.handle = h.value
 
-    def submit(self, dims, howmany_dims=(), x=None, y=None, sign=-1, prec=C32, arrival=0.0):
+    def submit(self, dims, howmany_dims=(), x=None, y=None, sign=-1, prec=C32, arrival=0.0,
+               in_stream="current"):
+        """in_stream: the stream whose work produces x ("current": torch's
+        current stream; None: x is complete already)."""
         r = Request()
         r.rank = len(dims)
         for i, d in enumerate(dims):
@@ -422,6 +428,8 @@ class Server:
         r.in_ = _ptr(x)
         r.out = _ptr(y) if y is not None else None
         r.arrival = float(arrival)
+        r.in_stream = None if in_stream is None else _stream(None if in_stream == "current"
+                                                             else in_stream)
         t = ctypes.c_uint64()
         _check(lib().mfft_server_submit(self.handle, ctypes.byref(r), ctypes.byref(t)),
                "mfft_server_submit")

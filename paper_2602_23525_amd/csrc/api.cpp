@@ -141,7 +141,7 @@ int plan_internal(mfft_plan *out, int rank, const mfft_iodim *dims, int howmany_
             if (rc == MFFT_OK && use_wisdom) wisdom_record(key, plan_choices(p));
         }
     }
-    if (rc == MFFT_OK && p->scratch_bytes) {
+    if (rc == MFFT_OK && p->scratch_bytes && !(flags & kPlanNoOwnScratch)) {
         p->scratch = dev_alloc(p, p->scratch_bytes);
         if (!p->scratch) rc = fail(MFFT_ENOMEM, "scratch allocation failed");
     }
@@ -150,6 +150,9 @@ int plan_internal(mfft_plan *out, int rank, const mfft_iodim *dims, int howmany_
         if (e != hipSuccess) rc = fail(MFFT_EHIP, std::string("table generation: ") + hipGetErrorString(e));
     }
     if (rc) {
+        // table kernels may still run on the stream: let them finish before
+        // their memory goes back to the allocator
+        (void)hipStreamSynchronize(stream);
         destroy_impl(p);
         delete pl;
         return rc;
@@ -175,6 +178,15 @@ int plan_internal(mfft_plan *out, int rank, const mfft_iodim *dims, int howmany_
     p->desc = d.str();
     *out = pl;
     return MFFT_OK;
+}
+
+int plan_dft_locked(mfft_plan *out, int rank, const mfft_iodim *dims, int howmany_rank,
+                    const mfft_iodim *hdims, int inplace, int sign, int prec, unsigned flags,
+                    const mfft_allocator *alloc, hipStream_t stream)
+{
+    std::lock_guard<std::mutex> lk(g_plan_mutex);
+    return plan_internal(out, rank, dims, howmany_rank, hdims, inplace, sign, prec, stream, flags,
+                         alloc);
 }
 
 }  // namespace mfft

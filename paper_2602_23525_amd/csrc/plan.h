@@ -138,6 +138,16 @@ size_t generic_lds_bytes(const Pass &ps);
 bool wisdom_lookup(const std::string &key, std::string *val);
 void wisdom_record(const std::string &key, const std::string &val);
 
+// Internal planner flag (never accepted from the C ABI): the plan allocates no
+// scratch of its own; its executions take scratch from the caller (the
+// request server allocates it per request inside its budget).
+constexpr unsigned kPlanNoOwnScratch = 1u << 30;
+
+// Plan under the global planner lock, with internal flags allowed.
+int plan_dft_locked(mfft_plan *out, int rank, const mfft_iodim *dims, int howmany_rank,
+                    const mfft_iodim *hdims, int inplace, int sign, int prec, unsigned flags,
+                    const mfft_allocator *alloc, hipStream_t stream);
+
 // Plan without taking the global planner lock (FP64 sub-plans for tables).
 int plan_internal(mfft_plan *out, int rank, const mfft_iodim *dims, int howmany_rank,
                   const mfft_iodim *hdims, int inplace, int sign, int prec, hipStream_t stream,

@@ -1,18 +1,22 @@
 // Request server with continuous batching (a systems layer on top of the
 // paper's method: the plans it runs are those of Section 4).
 //
-// One scheduler thread owns all GPU interaction:
-//   admit  -- pending requests, in arrival order, while the head fits the
-//             budget (output + scratch + descriptor image from an arena carved
-//             out of one allocation) and fewer than max_inflight are admitted;
+// A scheduler thread owns the launches:
+//   admit  -- pending requests whose plan is ready, in arrival order, while
+//             each fits the budget (output + scratch + descriptor image from
+//             an arena carved out of one reservation) and fewer than
+//             max_inflight are admitted; the first that does not fit blocks
+//             the ones behind it;
 //   launch -- everything admitted since the last launch becomes one batch
 //             (build_batch_layout) whose descriptor image is copied to the
-//             arena and launched on the next of n_streams streams; an event
-//             marks its end;
+//             arena and launched on the next of n_streams streams, after the
+//             requests' input events; an event marks its end;
 //   retire -- finished launches (event queries) complete their requests,
 //             return scratch and descriptors to the arena and wake waiters.
-// Plans live in a cache keyed by the canonical problem, with their tables
-// resident on the device.
+// A planner thread makes the plans of requests whose problem is not cached,
+// meanwhile the scheduler keeps going.  Cached plans keep their tables in the
+// arena (inside the budget); plans no request holds are evicted, least
+// recently used first, when memory is short.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -26,6 +30,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <set>
 #include <thread>
 #include <unordered_map>
 #include <vector>
@@ -50,26 +55,37 @@ static double now_s()
         .count();
 }
 
-// First-fit arena over one device allocation, 256-byte granules, coalescing.
+// First-fit arena over one device reservation, 256-byte granules, coalescing.
+// Thread safe (the planner thread allocates plan tables from it).
 class Arena {
   public:
-    bool init(size_t bytes)
+    bool init(size_t bytes, const mfft_allocator *alloc)
     {
         size_ = bytes / 256 * 256;
-        if (hipMalloc(&base_, size_) != hipSuccess) {
+        if (alloc && alloc->alloc) {
+            alloc_ = *alloc;
+            has_alloc_ = true;
+            base_ = alloc_.alloc(size_, nullptr, alloc_.ctx);
+        } else if (hipMalloc(&base_, size_) != hipSuccess) {
             (void)hipGetLastError();
             base_ = nullptr;
-            return false;
         }
+        if (!base_) return false;
         free_[0] = size_;
         return true;
     }
     ~Arena()
     {
-        if (base_) (void)hipFree(base_);
+        if (!base_) return;
+        if (has_alloc_) {
+            if (alloc_.free) alloc_.free(base_, nullptr, alloc_.ctx);
+        } else {
+            (void)hipFree(base_);
+        }
     }
     void *alloc(size_t n)
     {
+        std::lock_guard<std::mutex> lk(m_);
         n = std::max<size_t>(256, (n + 255) / 256 * 256);
         for (auto it = free_.begin(); it != free_.end(); ++it) {
             if (it->second >= n) {
@@ -87,6 +103,7 @@ class Arena {
     void release(void *p)
     {
         if (!p) return;
+        std::lock_guard<std::mutex> lk(m_);
         const size_t off = (char *)p - (char *)base_;
         auto s = sizes_.find(off);
         if (s == sizes_.end()) return;
@@ -111,21 +128,34 @@ class Arena {
         free_[start] = n;
     }
     size_t size() const { return size_; }
-    size_t used() const { return used_; }
-    size_t peak() const { return peak_; }
+    size_t used()
+    {
+        std::lock_guard<std::mutex> lk(m_);
+        return used_;
+    }
+    size_t peak()
+    {
+        std::lock_guard<std::mutex> lk(m_);
+        return peak_;
+    }
 
   private:
+    std::mutex m_;
     void *base_ = nullptr;
     size_t size_ = 0, used_ = 0, peak_ = 0;
     std::map<size_t, size_t> free_;
     std::unordered_map<size_t, size_t> sizes_;
+    mfft_allocator alloc_{};
+    bool has_alloc_ = false;
 };
 
 struct Req {
     uint64_t id = 0;
     mfft_request r{};
+    std::string key;                // canonical problem (plan cache key)
+    hipEvent_t ready = nullptr;     // recorded on r.in_stream at submission
     int state = MFFT_REQ_PENDING;   // or DONE (0) or a negative error
-    mfft_plan plan = nullptr;
+    mfft_plan plan = nullptr;       // held (counted in the cache entry's users)
     void *out = nullptr;
     bool own_out = false;
     void *scratch = nullptr;
@@ -133,6 +163,18 @@ struct Req {
     double t_arrival = 0, t_done = 0;
     double flops = 0, bytes = 0;
     bool cancelled = false;
+};
+
+struct CachedPlan {
+    mfft_plan plan = nullptr;
+    int users = 0;             // requests holding the plan (pending or admitted)
+    uint64_t last_use = 0;
+    size_t bytes = 0;          // its tables in the arena
+};
+
+struct PlanJob {
+    std::string key;
+    mfft_request r{};
 };
 
 struct Launch {
@@ -148,21 +190,25 @@ struct Launch {
 
 struct mfft_server_s {
     std::mutex mu;
-    std::condition_variable cv_work, cv_done;
-    std::thread worker;
+    std::condition_variable cv_work, cv_done, cv_plan;
+    std::thread worker, planner;
     bool stop = false;
-    mfft::Arena arena;   // request outputs and scratch
+    mfft::Arena arena;   // request outputs and scratch, plan tables
     mfft::Arena descs;   // launch descriptor images (part of the budget)
     int max_inflight = 1;
     std::vector<hipStream_t> streams;
     size_t next_stream = 0;
     uint64_t next_id = 1;
-    uint64_t wake_gen = 0;   // bumped when memory is released or a request is cancelled
+    uint64_t gen = 0;   // bumped by every event that may let a request be admitted
     std::deque<std::shared_ptr<mfft::Req>> pending;
     std::unordered_map<uint64_t, std::shared_ptr<mfft::Req>> reqs;
     std::deque<mfft::Launch> inflight;
     int admitted_open = 0;   // admitted, not yet finished
-    std::map<std::string, mfft_plan> plans;
+    std::map<std::string, mfft::CachedPlan> plans;
+    std::deque<mfft::PlanJob> plan_jobs;
+    std::set<std::string> planning;   // keys queued for or in the planner
+    uint64_t use_clock = 0;
+    mfft_allocator plan_alloc{};      // plan tables from the arena
     hipStream_t plan_stream = nullptr;
     int device = 0;
     // stats
@@ -171,19 +217,10 @@ struct mfft_server_s {
     std::vector<double> lat_ms;
     double busy_s = 0, busy_since = -1, flops = 0, bytes = 0;
     size_t plan_bytes = 0;
-    int max_inflight_seen = 0;
+    int max_inflight_seen = 0, plans_evicted = 0;
 };
 
 namespace mfft {
-
-static std::string req_key(const mfft_request &r)
-{
-    Problem p;
-    if (canonicalize(r.rank, r.dims, r.howmany_rank, r.howmany_dims, r.in == r.out, r.sign,
-                     (int)r.prec, &p) != MFFT_OK)
-        return std::string();
-    return problem_key(p);
-}
 
 // Output span (elements) of a request; its minimum offset must be 0 for a
 // server-allocated output.
@@ -206,6 +243,143 @@ static bool out_span(const mfft_request &r, int64_t *lo, int64_t *hi)
     return true;
 }
 
+// ------------------------------------------------------------ plan cache
+// (all with S->mu held)
+
+static void *arena_alloc_cb(size_t bytes, void *, void *ctx)
+{
+    return ((mfft_server_s *)ctx)->arena.alloc(bytes);
+}
+
+static void arena_free_cb(void *ptr, void *, void *ctx) { ((mfft_server_s *)ctx)->arena.release(ptr); }
+
+// Take a reference to the cached plan of q's problem, if there is one.
+static bool attach_plan(mfft_server_s *S, Req *q)
+{
+    if (q->plan) return true;
+    auto it = S->plans.find(q->key);
+    if (it == S->plans.end()) return false;
+    q->plan = it->second.plan;
+    it->second.users++;
+    it->second.last_use = ++S->use_clock;
+    return true;
+}
+
+static void drop_plan(mfft_server_s *S, Req *q)
+{
+    if (!q->plan) return;
+    auto it = S->plans.find(q->key);
+    if (it != S->plans.end() && it->second.plan == q->plan) {
+        it->second.users--;
+        it->second.last_use = ++S->use_clock;
+    }
+    q->plan = nullptr;
+}
+
+// Destroy the least recently used plan no request holds (its tables return
+// to the arena); false if there is none.
+static bool evict_one(mfft_server_s *S)
+{
+    auto victim = S->plans.end();
+    for (auto it = S->plans.begin(); it != S->plans.end(); ++it)
+        if (it->second.users == 0 && (victim == S->plans.end() || it->second.last_use < victim->second.last_use))
+            victim = it;
+    if (victim == S->plans.end()) return false;
+    mfft_plan_destroy(victim->second.plan);
+    S->plan_bytes -= victim->second.bytes;
+    S->plans.erase(victim);
+    S->plans_evicted++;
+    return true;
+}
+
+static void finish_request(mfft_server_s *S, Req *q)
+{
+    drop_plan(S, q);
+    if (q->ready) {
+        (void)hipEventDestroy(q->ready);
+        q->ready = nullptr;
+    }
+}
+
+static void wake(mfft_server_s *S)
+{
+    S->gen++;
+    S->cv_work.notify_one();
+    S->cv_plan.notify_one();
+}
+
+// Planner thread: plans the problems of pending requests that are not
+// cached, one at a time, with the plan tables in the arena; the scheduler
+// admits and retires other requests meanwhile.
+static void planner_loop(mfft_server_s *S)
+{
+    (void)hipSetDevice(S->device);
+    std::unique_lock<std::mutex> lk(S->mu);
+    for (;;) {
+        S->cv_plan.wait(lk, [&] { return S->stop || !S->plan_jobs.empty(); });
+        if (S->stop) break;
+        PlanJob job = S->plan_jobs.front();
+        S->plan_jobs.pop_front();
+        bool needed = false;
+        for (auto &q : S->pending)
+            if (q->key == job.key && !q->cancelled && q->state == MFFT_REQ_PENDING) needed = true;
+        if (!needed) {
+            S->planning.erase(job.key);
+            continue;
+        }
+        const mfft_request &r = job.r;
+        mfft_plan pl = nullptr;
+        lk.unlock();
+        int rc = plan_dft_locked(&pl, r.rank, r.dims, r.howmany_rank, r.howmany_dims,
+                                 r.in == r.out ? 1 : 0, r.sign, (int)r.prec,
+                                 MFFT_ESTIMATE | kPlanNoOwnScratch, &S->plan_alloc, S->plan_stream);
+        lk.lock();
+        if (rc == MFFT_ENOMEM) {
+            // make room: unused cached plans first, else wait for memory that
+            // requests still hold, unless none is held
+            bool evicted = false;
+            while (evict_one(S)) evicted = true;
+            if (evicted) {
+                S->plan_jobs.push_front(job);
+                continue;
+            }
+            // memory that requests hold (outputs, scratch, plans in use) comes
+            // back as they finish or are released
+            bool held = S->admitted_open > 0 || S->arena.used() > S->plan_bytes;
+            for (auto &kv : S->plans) held = held || kv.second.users > 0;
+            if (held && !S->stop) {
+                const uint64_t g = S->gen;
+                S->cv_plan.wait(lk, [&] { return S->stop || S->gen != g; });
+                S->plan_jobs.push_front(job);
+                continue;
+            }
+            rc = fail(MFFT_EBUDGET, "plan tables do not fit the server's HBM budget");
+        }
+        S->planning.erase(job.key);
+        if (rc) {
+            log_failure("planning", rc);
+            for (auto &q : S->pending)
+                if (q->key == job.key && !q->cancelled && q->state == MFFT_REQ_PENDING) {
+                    q->state = rc;
+                    if (rc == MFFT_EBUDGET) S->rejected++;
+                    else S->failed++;
+                }
+            S->cv_done.notify_all();
+            wake(S);
+            continue;
+        }
+        CachedPlan cp;
+        cp.plan = pl;
+        for (const DeviceAlloc &t : pl->impl.tables) cp.bytes += std::max<size_t>(256, (t.bytes + 255) / 256 * 256);
+        cp.last_use = ++S->use_clock;
+        S->plans[job.key] = cp;
+        S->plan_bytes += cp.bytes;
+        for (auto &q : S->pending)
+            if (q->key == job.key && !q->cancelled && q->state == MFFT_REQ_PENDING) attach_plan(S, q.get());
+        wake(S);
+    }
+}
+
 // Scheduler thread.
 static void server_loop(mfft_server_s *S)
 {
@@ -222,6 +396,7 @@ static void server_loop(mfft_server_s *S)
                     q->t_done = t;
                     S->arena.release(q->scratch);
                     q->scratch = nullptr;
+                    finish_request(S, q.get());
                     S->completed++;
                     S->lat_ms.push_back((t - q->t_arrival) * 1e3);
                     S->flops += q->flops;
@@ -240,7 +415,11 @@ static void server_loop(mfft_server_s *S)
             S->busy_s += now_s() - S->busy_since;
             S->busy_since = -1;
         }
-        if (progressed) S->cv_done.notify_all();
+        if (progressed) {
+            S->cv_done.notify_all();
+            S->gen++;
+            S->cv_plan.notify_one();   // a planner waiting for memory may retry
+        }
 
         // ---- on shutdown, requests not yet admitted are cancelled
         if (S->stop && !S->pending.empty()) {
@@ -249,48 +428,27 @@ static void server_loop(mfft_server_s *S)
                     q->state = MFFT_ECANCELED;
                     S->cancelled++;
                 }
+                finish_request(S, q.get());
             }
             S->pending.clear();
             S->cv_done.notify_all();
         }
 
-        // ---- admit
+        // ---- admit: requests whose plan is ready, in arrival order
+        const uint64_t gen = S->gen;
         std::vector<std::shared_ptr<Req>> tick;
         size_t desc_need = 512;   // upper bound of the tick's descriptor image
-        bool mem_blocked = false;   // the queue head waits for arena memory
-        while (!S->pending.empty() && S->admitted_open < S->max_inflight) {
-            std::shared_ptr<Req> q = S->pending.front();
-            if (q->cancelled) {
-                S->pending.pop_front();
+        for (auto it = S->pending.begin();
+             it != S->pending.end() && S->admitted_open < S->max_inflight;) {
+            std::shared_ptr<Req> q = *it;
+            if (q->cancelled || q->state != MFFT_REQ_PENDING) {   // cancelled or failed planning
+                finish_request(S, q.get());
+                it = S->pending.erase(it);
                 continue;
             }
-            if (!q->plan) {
-                const std::string key = req_key(q->r);
-                auto pit = S->plans.find(key);
-                if (pit != S->plans.end()) {
-                    q->plan = pit->second;
-                } else {
-                    mfft_plan pl = nullptr;
-                    lk.unlock();
-                    int rc = mfft_plan_dft(&pl, q->r.rank, q->r.dims, q->r.howmany_rank,
-                                           q->r.howmany_dims, q->r.in == q->r.out ? 1 : 0,
-                                           q->r.sign, q->r.prec, MFFT_ESTIMATE, nullptr,
-                                           (void *)S->plan_stream);
-                    lk.lock();
-                    if (rc) {
-                        log_failure("planning", rc);
-                        S->pending.pop_front();
-                        q->state = rc;
-                        S->failed++;
-                        S->cv_done.notify_all();
-                        continue;
-                    }
-                    mfft_plan_info_t info;
-                    mfft_plan_info(pl, &info);
-                    S->plan_bytes += info.table_bytes + info.scratch_bytes;
-                    S->plans[key] = pl;
-                    q->plan = pl;
-                }
+            if (!attach_plan(S, q.get())) {   // being planned: the ones behind may go first
+                ++it;
+                continue;
             }
             const PlanImpl *p = &q->plan->impl;
             // descriptor image bound: per pass one descriptor, a prefix entry and
@@ -298,45 +456,50 @@ static void server_loop(mfft_server_s *S)
             const size_t dneed = p->passes.size() * (sizeof(PassArgs) + 8 + 520) + 64;
             if (desc_need + dneed > S->descs.size() - S->descs.used()) {
                 if (tick.empty() && S->inflight.empty()) {
-                    S->pending.pop_front();
                     q->state = fail(MFFT_EBUDGET, "plan has too many passes for the descriptor area");
                     log_failure("admission", q->state);
+                    finish_request(S, q.get());
+                    it = S->pending.erase(it);
                     S->rejected++;
                     S->cv_done.notify_all();
                     continue;
                 }
                 break;
             }
-            if (q->out_bytes + p->scratch_bytes + 4096 > S->arena.size()) {
-                S->pending.pop_front();
+            const size_t tables = S->plans[q->key].bytes;
+            if (q->out_bytes + p->scratch_bytes + tables + 4096 > S->arena.size()) {
                 q->state = MFFT_EBUDGET;
+                finish_request(S, q.get());
+                it = S->pending.erase(it);
                 S->rejected++;
                 S->cv_done.notify_all();
                 continue;
             }
             void *out = q->r.out;
             void *scratch = nullptr;
-            if (!out && q->out_bytes) {
-                out = S->arena.alloc(q->out_bytes);
-                if (!out) {   // wait for memory (FIFO: the head blocks the queue)
-                    mem_blocked = true;
-                    break;
+            bool got = false;
+            for (;;) {
+                if (!out && q->out_bytes) out = S->arena.alloc(q->out_bytes);
+                if (out || !q->out_bytes) {
+                    if (p->scratch_bytes) scratch = S->arena.alloc(p->scratch_bytes);
+                    if (scratch || !p->scratch_bytes) {
+                        got = true;
+                        break;
+                    }
+                    if (!q->r.out) {
+                        S->arena.release(out);
+                        out = nullptr;
+                    }
                 }
+                if (!evict_one(S)) break;   // room from plans no request holds
             }
-            if (p->scratch_bytes) {
-                scratch = S->arena.alloc(p->scratch_bytes);
-                if (!scratch) {
-                    if (!q->r.out) S->arena.release(out);
-                    mem_blocked = true;
-                    break;
-                }
-            }
+            if (!got) break;   // wait for memory (the first ready request blocks the rest)
             desc_need += dneed;
             q->out = out;
             q->own_out = !q->r.out;
             q->scratch = scratch;
             q->state = MFFT_REQ_RUNNING;
-            S->pending.pop_front();
+            it = S->pending.erase(it);
             S->admitted++;
             S->admitted_open++;
             tick.push_back(q);
@@ -357,6 +520,10 @@ static void server_loop(mfft_server_s *S)
                                              std::to_string(desc_need) + ")");
             }
             hipStream_t s = S->streams[S->next_stream++ % S->streams.size()];
+            // inputs produced on the callers' streams
+            for (auto &q : tick)
+                if (rc == MFFT_OK && q->ready && hipStreamWaitEvent(s, q->ready, 0) != hipSuccess)
+                    rc = fail(MFFT_EHIP, "waiting for a request's input stream");
             if (rc == MFFT_OK &&
                 hipMemcpyAsync(L.desc, L.layout.host.data(), L.layout.bytes,
                                hipMemcpyHostToDevice, s) != hipSuccess)
@@ -374,6 +541,7 @@ static void server_loop(mfft_server_s *S)
                     S->arena.release(q->scratch);
                     if (q->own_out) S->arena.release(q->out);
                     q->out = nullptr;
+                    finish_request(S, q.get());
                     S->failed++;
                     S->admitted_open--;
                 }
@@ -397,12 +565,10 @@ static void server_loop(mfft_server_s *S)
             std::this_thread::sleep_for(std::chrono::microseconds(20));
             lk.lock();
         } else {
-            // idle, or the queue head waits for memory that only a client's
-            // release (or a cancel) can free: sleep until one of them happens
-            const uint64_t gen = S->wake_gen;
-            S->cv_work.wait(lk, [&] {
-                return S->stop || (!S->pending.empty() && (!mem_blocked || S->wake_gen != gen));
-            });
+            // idle, waiting for plans, or the first ready request waits for
+            // memory that only a client's release (or a cancel) can free:
+            // sleep until something changes
+            S->cv_work.wait(lk, [&] { return S->stop || S->gen != gen; });
         }
     }
 }
@@ -418,22 +584,28 @@ int mfft_server_create(mfft_server *out, size_t hbm_budget_bytes, int max_inflig
 {
     if (!out || max_inflight < 1 || n_streams < 1 || n_streams > 64 || hbm_budget_bytes < 4096)
         return fail(MFFT_EINVAL, "bad server arguments");
-    (void)alloc;
+    if (alloc && (!alloc->alloc || !alloc->free))
+        return fail(MFFT_EINVAL, "allocator needs both alloc and free");
     *out = nullptr;
     mfft_server_s *S = new (std::nothrow) mfft_server_s();
     if (!S) return fail(MFFT_ENOMEM, "host allocation failed");
     (void)hipGetDevice(&S->device);
-    // 1/16 of the budget (at most 16 MiB) holds launch descriptor images
+    // 1/16 of the budget (at most 16 MiB) holds launch descriptor images, in
+    // the same reservation as the rest
     const size_t dbytes = std::min<size_t>((size_t)16 << 20, hbm_budget_bytes / 16) / 256 * 256;
-    if (!S->descs.init(dbytes) || !S->arena.init(hbm_budget_bytes - dbytes)) {
+    if (!S->descs.init(dbytes, alloc) || !S->arena.init(hbm_budget_bytes - dbytes, alloc)) {
         delete S;
         return fail(MFFT_ENOMEM, "could not reserve the HBM budget");
     }
+    S->plan_alloc.alloc = arena_alloc_cb;
+    S->plan_alloc.free = arena_free_cb;
+    S->plan_alloc.ctx = S;
     S->max_inflight = max_inflight;
     for (int i = 0; i < n_streams + 1; ++i) {
         hipStream_t s;
         if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
             for (hipStream_t t : S->streams) (void)hipStreamDestroy(t);
+            if (S->plan_stream) (void)hipStreamDestroy(S->plan_stream);
             delete S;
             return fail(MFFT_EHIP, "stream creation failed");
         }
@@ -441,6 +613,7 @@ int mfft_server_create(mfft_server *out, size_t hbm_budget_bytes, int max_inflig
         else S->streams.push_back(s);
     }
     S->worker = std::thread(server_loop, S);
+    S->planner = std::thread(planner_loop, S);
     *out = S;
     return MFFT_OK;
 }
@@ -456,6 +629,7 @@ int mfft_server_submit(mfft_server S, const mfft_request *req, uint64_t *ticket)
     if (!p.empty && !r.in) return fail(MFFT_EINVAL, "NULL input");
     auto q = std::make_shared<Req>();
     q->r = r;
+    q->key = problem_key(p);
     const size_t eb = r.prec == MFFT_C64 ? 16 : 8;
     if (!r.out && !p.empty) {
         int64_t lo, hi;
@@ -466,14 +640,23 @@ int mfft_server_submit(mfft_server S, const mfft_request *req, uint64_t *ticket)
     const double N = (double)p.n_total;
     q->flops = (p.empty || N < 2) ? 0.0 : 5.0 * N * std::log2(N) * (double)p.howmany;
     q->bytes = p.empty ? 0.0 : 2.0 * eb * N * (double)p.howmany;
-    // a rough lower bound of what the request needs: output + two copies of
-    // the data for a multi-pass plan's scratch
-    const size_t need = q->out_bytes;
-    std::lock_guard<std::mutex> lk(S->mu);
-    if (S->stop) return fail(MFFT_ESTATE, "server is stopping");
-    if (need > S->arena.size()) {
+    // a lower bound of what the request needs: its output
+    if (q->out_bytes > S->arena.size()) {
+        std::lock_guard<std::mutex> lk(S->mu);
         S->rejected++;
         return fail(MFFT_EBUDGET, "request larger than the server's HBM budget");
+    }
+    if (r.in_stream && !p.empty) {
+        if (hipEventCreateWithFlags(&q->ready, hipEventDisableTiming) != hipSuccess ||
+            hipEventRecord(q->ready, (hipStream_t)r.in_stream) != hipSuccess) {
+            if (q->ready) (void)hipEventDestroy(q->ready);
+            return fail(MFFT_EHIP, "could not record an event on the input stream");
+        }
+    }
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (S->stop) {
+        if (q->ready) (void)hipEventDestroy(q->ready);
+        return fail(MFFT_ESTATE, "server is stopping");
     }
     q->id = S->next_id++;
     q->t_arrival = r.arrival > 0 ? r.arrival : now_s();
@@ -485,8 +668,12 @@ int mfft_server_submit(mfft_server S, const mfft_request *req, uint64_t *ticket)
         S->completed++;
         S->cv_done.notify_all();
     } else {
+        if (!attach_plan(S, q.get()) && !S->planning.count(q->key)) {
+            S->planning.insert(q->key);
+            S->plan_jobs.push_back({q->key, r});
+        }
         S->pending.push_back(q);
-        S->cv_work.notify_one();
+        wake(S);
     }
     *ticket = q->id;
     return MFFT_OK;
@@ -529,8 +716,7 @@ int mfft_server_release(mfft_server S, uint64_t ticket)
     if (q->own_out) S->arena.release(q->out);
     q->out = nullptr;
     S->reqs.erase(it);
-    S->wake_gen++;
-    S->cv_work.notify_one();   // memory may admit the next request
+    wake(S);   // memory may admit the next request
     return MFFT_OK;
 }
 
@@ -542,11 +728,13 @@ int mfft_server_cancel(mfft_server S, uint64_t ticket)
     if (it == S->reqs.end()) return fail(MFFT_ESTATE, "unknown ticket");
     std::shared_ptr<Req> q = it->second;
     if (q->state != MFFT_REQ_PENDING) return fail(MFFT_ESTATE, "request already admitted");
+    // the scheduler admits only requests still pending under this lock, so a
+    // cancelled request never runs (also when its plan is being made)
     q->cancelled = true;
     q->state = MFFT_ECANCELED;
+    finish_request(S, q.get());
     S->cancelled++;
-    S->wake_gen++;
-    S->cv_work.notify_one();
+    wake(S);
     S->cv_done.notify_all();
     return MFFT_OK;
 }
@@ -587,6 +775,7 @@ int mfft_server_stats(mfft_server S, mfft_server_stats_t *st)
     st->plan_bytes = S->plan_bytes;
     st->plans_cached = (int)S->plans.size();
     st->max_inflight_seen = S->max_inflight_seen;
+    st->plans_evicted = S->plans_evicted;
     return MFFT_OK;
 }
 
@@ -611,14 +800,18 @@ int mfft_server_destroy(mfft_server S)
         std::lock_guard<std::mutex> lk(S->mu);
         S->stop = true;
         S->cv_work.notify_all();
+        S->cv_plan.notify_all();
     }
     if (S->worker.joinable()) S->worker.join();
+    if (S->planner.joinable()) S->planner.join();
     for (hipStream_t s : S->streams) {
         (void)hipStreamSynchronize(s);
         (void)hipStreamDestroy(s);
     }
     if (S->plan_stream) (void)hipStreamDestroy(S->plan_stream);
-    for (auto &kv : S->plans) mfft_plan_destroy(kv.second);
+    for (auto &kv : S->plans) mfft_plan_destroy(kv.second.plan);
+    for (auto &kv : S->reqs)
+        if (kv.second->ready) (void)hipEventDestroy(kv.second->ready);
     delete S;
     return MFFT_OK;
 }

@@ -37,15 +37,20 @@ def _problem(req_dims, batch):
 
 
 def _read(ptr, count, prec):
+    """Copy `count` elements of server-owned device memory to the host, with
+    the hipMemcpy of the HIP runtime the library itself links."""
+    import ctypes
+
     import torch
+
+    import paper_2602_23525_amd as mfft
     dt = torch.complex64 if prec == 0 else torch.complex128
     t = torch.empty(count, dtype=dt, device="cuda")
     nbytes = count * (8 if prec == 0 else 16)
-    # copy from the server-owned output through torch's stream
-    import ctypes
-    hip = ctypes.CDLL("libamdhip64.so.7")
-    hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
-    assert hip.hipMemcpy(t.data_ptr(), ptr, nbytes, 3) == 0
+    hip_memcpy = mfft.lib().hipMemcpy
+    hip_memcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    hip_memcpy.restype = ctypes.c_int
+    assert hip_memcpy(t.data_ptr(), ptr, nbytes, 3) == 0
     return t.cpu().numpy()
 
 
@@ -71,7 +76,8 @@ def test_server_mixed_requests_match_oracle():
     st = srv.stats()
     assert st["completed"] == len(specs) and st["failed"] == 0
     assert st["launches"] >= 1 and st["p99_ms"] >= st["p50_ms"] > 0
-    assert st["bytes_in_use"] == 0 and st["peak_bytes"] > 0
+    # what stays in use are the cached plans' tables, inside the budget
+    assert st["bytes_in_use"] == st["plan_bytes"] > 0 and st["peak_bytes"] <= 2 << 30
     srv.destroy()
 
 
@@ -186,3 +192,160 @@ def test_memory_blocked_head_waits_for_release():
     st = srv.stats()
     assert st["completed"] == 5
     srv.destroy()                                           # t2[2] is cancelled
+
+
+def _is_prime(n):
+    return n > 1 and all(n % f for f in range(2, int(n ** 0.5) + 1))
+
+
+def _check_output(srv, t, x, dims, hd, prec, sign, rows=None):
+    """Compare a finished request's output with the oracle (whole, or the
+    given transforms of its batch)."""
+    ntot = int(np.prod([d[0] for d in dims]))
+    y = _read(srv.output(t), x.size, prec).astype(np.complex128)
+    if rows is None:
+        ref = np.zeros(x.size, np.complex128)
+        oracle.dft(x.astype(np.complex128), ref, dims, hd, sign=sign)
+        got = y
+    else:
+        got = np.concatenate([y[v * ntot:(v + 1) * ntot] for v in rows])
+        ref = np.concatenate([oracle.fft(x[v * ntot:(v + 1) * ntot].astype(np.complex128)[None],
+                                         sign=sign)[0] for v in rows])
+    rr = oracle.rel_rms(got, ref)
+    assert rr <= (2e-6 if prec == 0 else 1e-13), rr
+
+
+def test_cache_miss_planned_aside_does_not_delay_planned_requests():
+    """Requests whose plan is cached complete while other requests' plans are
+    still being made by the planner thread."""
+    import paper_2602_23525_amd as mfft
+    srv = mfft.Server(budget_bytes=4 << 30, max_inflight=32, n_streams=2)
+    xw, xwt = _mk((4096,), 4, 0, 501)
+    dw, hw = _problem((4096,), 4)
+    t = srv.submit(dw, hw, xwt, None)                 # warm the cache
+    assert srv.wait(t, 60000) == 0
+    srv.release(t)
+    cold = []
+    # six FP64 prime plans, made one after another by the planner thread
+    for i, n in enumerate([p for p in range(65521, 60000, -1) if _is_prime(p)][:6]):
+        x, xt = _mk((n,), 2, 1, 510 + i)
+        d, h = _problem((n,), 2)
+        cold.append((srv.submit(d, h, xt, None, prec=1), x, xt, d, h))
+    t = srv.submit(dw, hw, xwt, None)
+    assert srv.wait(t, 60000) == 0
+    # the cached request finished while a plan of the earlier ones was still
+    # being made (the last cold request is still pending)
+    assert srv.wait(cold[-1][0], 0) == mfft.REQ_PENDING
+    _check_output(srv, t, xw, dw, hw, 0, -1)
+    srv.release(t)
+    for tc, x, xt, d, h in cold:
+        assert srv.wait(tc, 60000) == 0
+        _check_output(srv, tc, x, d, h, 1, -1)
+        srv.release(tc)
+    st = srv.stats()
+    assert st["completed"] == 8 and st["failed"] == 0 and st["plans_cached"] == 7
+    srv.destroy()
+
+
+def test_cancel_while_planning_never_runs_and_frees_everything():
+    import paper_2602_23525_amd as mfft
+    srv = mfft.Server(budget_bytes=1 << 30, max_inflight=8, n_streams=2)
+    x, xt = _mk((65519,), 3, 1, 520)
+    d, h = _problem((65519,), 3)
+    tc = srv.submit(d, h, xt, None, prec=1)          # plan not cached: being planned
+    srv.cancel(tc)
+    assert srv.wait(tc, 0) == -9
+    srv.release(tc)
+    xw, xwt = _mk((1000,), 5, 0, 521)
+    dw, hw = _problem((1000,), 5)
+    t = srv.submit(dw, hw, xwt, None)
+    assert srv.wait(t, 60000) == 0
+    _check_output(srv, t, xw, dw, hw, 0, -1)
+    srv.release(t)
+    time.sleep(0.5)                                    # let the planner finish, if it started
+    st = srv.stats()
+    assert st["cancelled"] == 1 and st["failed"] == 0 and st["completed"] == 1
+    assert st["admitted"] == 1
+    assert st["bytes_in_use"] == st["plan_bytes"]       # only cached tables remain
+    srv.destroy()
+
+
+def test_plan_tables_count_against_the_budget_and_unused_plans_are_evicted():
+    """A budget too small for every plan's tables at once: cached plans no
+    request holds are evicted, every response still matches the oracle, and
+    outputs, scratch, descriptors and tables together stay within the budget."""
+    import paper_2602_23525_amd as mfft
+    budget = 40 << 20
+    srv = mfft.Server(budget_bytes=budget, max_inflight=4, n_streams=2)
+    primes = [p for p in range(65521, 60000, -1) if _is_prime(p)][:18]
+    for i, n in enumerate(primes):
+        x, xt = _mk((n,), 4, 0, 530 + i)
+        d, h = _problem((n,), 4)
+        t = srv.submit(d, h, xt, None, sign=(-1 if i % 2 else 1))
+        assert srv.wait(t, 60000) == 0
+        if i % 4 == 0:
+            _check_output(srv, t, x, d, h, 0, -1 if i % 2 else 1, rows=[0, 3])
+        srv.release(t)
+        st = srv.stats()
+        assert st["bytes_in_use"] == st["plan_bytes"] <= budget
+    st = srv.stats()
+    assert st["plans_evicted"] > 0 and st["peak_bytes"] <= budget
+    assert st["completed"] == len(primes) and st["failed"] == 0
+    srv.destroy()
+
+
+def test_budget_reserved_through_the_callers_allocator():
+    import torch
+
+    import paper_2602_23525_amd as mfft
+    calls = {"alloc": 0, "free": 0}
+    dev = torch.cuda.current_device()
+
+    @mfft.ALLOC_FN
+    def _alloc(nbytes, stream, ctx):
+        calls["alloc"] += 1
+        return torch.cuda.caching_allocator_alloc(int(nbytes), dev, stream or 0)
+
+    @mfft.FREE_FN
+    def _free(ptr, stream, ctx):
+        calls["free"] += 1
+        torch.cuda.caching_allocator_delete(ptr)
+
+    al = mfft.Allocator(_alloc, _free, None)
+    srv = mfft.Server(budget_bytes=256 << 20, max_inflight=4, n_streams=1, allocator=al)
+    assert calls["alloc"] == 2                          # the budget: request memory + descriptors
+    x, xt = _mk((4096,), 8, 0, 540)
+    d, h = _problem((4096,), 8)
+    t = srv.submit(d, h, xt, None)
+    assert srv.wait(t, 60000) == 0
+    _check_output(srv, t, x, d, h, 0, -1)
+    srv.release(t)
+    assert calls["alloc"] == 2                          # plans and outputs come from the budget
+    srv.destroy()
+    assert calls["free"] == 2
+
+
+def test_input_written_on_another_stream_is_waited_for():
+    """The request's input is produced by device work still queued on a side
+    stream at submission; the server orders its launch after that work."""
+    import torch
+
+    import paper_2602_23525_amd as mfft
+    n, b = 8192, 64
+    x = uniform_complex(n * b, seed=550, dtype=np.complex64)
+    src = torch.from_numpy(x).cuda()
+    dst = torch.zeros_like(src)
+    a = torch.randn(4096, 4096, device="cuda")
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    srv = mfft.Server(budget_bytes=1 << 30, max_inflight=4, n_streams=2)
+    d, h = _problem((n,), b)
+    with torch.cuda.stream(side):
+        for _ in range(6):                             # milliseconds of work ahead of the copy
+            a = torch.tanh(a @ a)
+        dst.copy_(src)
+        t = srv.submit(d, h, dst, None, in_stream=side)
+    assert srv.wait(t, 60000) == 0
+    _check_output(srv, t, x, d, h, 0, -1, rows=[0, 31, 63])
+    srv.release(t)
+    srv.destroy()
