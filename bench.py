@@ -52,7 +52,7 @@ DEFAULT = "c2c_1d_n4096_b16384_c32"
 # power-of-two workloads): a counter summary applies while their hash matches
 LEAF_SOURCES = ["paper_2602_23525_amd/csrc/leaf.h", "paper_2602_23525_amd/csrc/k_leaf.hip",
                 "paper_2602_23525_amd/csrc/butterfly.h", "paper_2602_23525_amd/csrc/internal.h",
-                "paper_2602_23525_amd/csrc/twiddle4.h"]
+                "paper_2602_23525_amd/csrc/twiddle4.h", "paper_2602_23525_amd/csrc/leaf_shape.h"]
 
 
 def kernel_source_hash() -> str:
@@ -76,6 +76,19 @@ def counter_traffic(workload: str, plan_desc: str):
     if d.get("source_hash") != kernel_source_hash() or d.get("plan") != plan_desc:
         return None
     return d.get("traffic_bytes_per_launch")
+
+
+def cpu_model() -> str:
+    """The host CPU's model name (as /proc/cpuinfo reports it)."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.lower().startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
 
 
 def cpu_baseline(x, dims, hdims, sign, n_total, howmany, budget_s=30.0):
@@ -104,12 +117,12 @@ def cpu_baseline(x, dims, hdims, sign, n_total, howmany, budget_s=30.0):
     t = time.perf_counter() - t0
     flops = 5.0 * n_total * math.log2(n_total) * sample
     return {"value": round(flops / t / 1e9, 3), "unit": "GFLOP/s", "cores": cores,
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": cpu_model(),
             "sample": f"{sample} of {n_items} transforms of n={n_total}, FP64 oracle "
                       f"(mixed-radix recursion), {t:.2f} s"}
 
 
-def run_uneven(args):
+def run_uneven(args, emit=True):
     """Uneven batch: `items` 1-D FP32 transforms of log-uniform sizes 64..65536
     (60% powers of two, 30% 7-smooth, 10% primes), batch 1..32 each, packed at
     256-byte aligned offsets of one input and one output buffer, executed
@@ -171,20 +184,24 @@ def run_uneven(args):
         for p, i, o in zip(plans, ins, outs):
             p.execute(i, o)
 
-    ms_plain = timed(plain, max(1, args.steps // 5))
-    # verify a seeded sample of items against the oracle
-    import oracle
-    batch.execute()
-    torch.cuda.synchronize()
-    rng = np.random.default_rng(1)
-    worst = 0.0
-    for k in rng.choice(len(items), size=min(24, len(items)), replace=False):
-        it = items[k]
-        cnt = it.n * it.batch
-        x = xin[offs[k]:offs[k] + cnt].cpu().numpy().astype(np.complex128)
-        y = yout[offs[k]:offs[k] + cnt].cpu().numpy()
-        ref = oracle.fft(x.reshape(it.batch, it.n))
-        worst = max(worst, oracle.rel_rms(y.reshape(it.batch, it.n), ref))
+    ms_plain = worst = worst_max = None
+    if not args.timing_only:
+        # the plain form (one plan per launch) and a seeded sample of items
+        # against the oracle; left out of profiler runs
+        ms_plain = timed(plain, max(1, args.steps // 5))
+        import oracle
+        batch.execute()
+        torch.cuda.synchronize()
+        rng = np.random.default_rng(1)
+        worst = worst_max = 0.0
+        for k in rng.choice(len(items), size=min(24, len(items)), replace=False):
+            it = items[k]
+            cnt = it.n * it.batch
+            x = xin[offs[k]:offs[k] + cnt].cpu().numpy().astype(np.complex128)
+            y = yout[offs[k]:offs[k] + cnt].cpu().numpy()
+            ref = oracle.fft(x.reshape(it.batch, it.n))
+            worst = max(worst, oracle.rel_rms(y.reshape(it.batch, it.n), ref))
+            worst_max = max(worst_max, oracle.max_err(y.reshape(it.batch, it.n), ref))
     out = {
         "metric": METRIC, "value": round(flops / (ms_batch * 1e-3) / 1e9, 2), "unit": "GFLOP/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -193,10 +210,10 @@ def run_uneven(args):
         "config": {"workload": f"uneven_batch_{len(items)}", "points": npts,
                    "plan_seconds": round(plan_s, 2), "batch_create_seconds": round(batch_s, 3),
                    "launches_per_step": binfo["launches"], "tiles": binfo["tiles"],
-                   "plain_ms_per_step": round(ms_plain, 3),
-                   "plain_gflops": round(flops / (ms_plain * 1e-3) / 1e9, 2),
-                   "batched_over_plain": round(ms_plain / ms_batch, 3),
-                   "sampled_relrms_max": worst},
+                   "plain_ms_per_step": ms_plain and round(ms_plain, 3),
+                   "plain_gflops": ms_plain and round(flops / (ms_plain * 1e-3) / 1e9, 2),
+                   "batched_over_plain": ms_plain and round(ms_plain / ms_batch, 3),
+                   "sampled_relrms_max": worst, "sampled_maxerr_max": worst_max},
         "roofline": {"bound": "hbm", "achieved": round(comp / (ms_batch * 1e-3) / 1e9, 1),
                      "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(comp / (ms_batch * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
@@ -205,7 +222,11 @@ def run_uneven(args):
     batch.destroy()
     for p in plans:
         p.destroy()
-    print(json.dumps(out), flush=True)
+    del xin, yout
+    torch.cuda.empty_cache()
+    if emit:
+        print(json.dumps(out), flush=True)
+    return out
 
 
 def run_planner(args):
@@ -265,7 +286,7 @@ def run_planner(args):
     print(json.dumps(out))
 
 
-def run_serve(args):
+def run_serve(args, emit=True, rhos=(0.5, 0.8, 1.2)):
     """Serving: a seeded Poisson trace of FFT requests (rank 1-3, 2^8..2^22
     points, batch 1..64, FP32/FP64 80/20, forward/inverse 50/50) replayed
     against the continuous-batching server and against sequential execution
@@ -381,7 +402,7 @@ def run_serve(args):
     mu = len(reqs) / seq_cap["wall_s"]
     res = {"sequential_capacity_req_per_s": round(mu, 1), "closed_loop_sequential": seq_cap}
     res["closed_loop_batched"] = replay(bat, None, "closed-loop batched")
-    for rho in (0.5, 0.8, 1.2):
+    for rho in rhos:
         # the trace has unit mean rate: stretch it to a mean rate of rho * mu
         sc = 1.0 / (rho * mu)
         res[f"rho{rho}_batched"] = replay(bat, sc, f"rho {rho} batched")
@@ -394,7 +415,11 @@ def run_serve(args):
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
            "data": "synthetic",
            "config": {"workload": f"serve_poisson_{len(reqs)}", "budget_bytes": budget, **res}}
-    print(json.dumps(out), flush=True)
+    del pool32, pool64
+    torch.cuda.empty_cache()
+    if emit:
+        print(json.dumps(out), flush=True)
+    return out
 
 
 def main():
@@ -414,6 +439,8 @@ def main():
     ap.add_argument("--batch", type=int, default=1, help="custom 1-D workload: batch")
     ap.add_argument("--prec", default="c32", choices=["c32", "c64"])
     ap.add_argument("--sign", type=int, default=-1)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="default workload: leave out the uneven-batch and serving legs")
     ap.add_argument("--items", type=int, default=None,
                     help="uneven_batch: items (default 10000); serve: requests (default 2000)")
     args = ap.parse_args()
@@ -576,18 +603,23 @@ def main():
         # sampled accuracy against the FP64 oracle (three whole transforms)
         import oracle
 
-        def sampled_relrms(y):
-            worst = 0.0
+        def sampled_errors(y):
+            worst = worst_max = 0.0
             for v in (0, howmany // 2, howmany - 1):
                 ref = np.zeros(n_total, np.complex128)
                 oracle.dft(x.astype(np.complex128), ref, [(n_total, 1, 1)], [], sign=sign,
                            in_off=v * n_total)
-                worst = max(worst, oracle.rel_rms(y[v * n_total:(v + 1) * n_total], ref))
-            return worst
+                got = y[v * n_total:(v + 1) * n_total]
+                worst = max(worst, oracle.rel_rms(got, ref))
+                worst_max = max(worst_max, oracle.max_err(got, ref))
+            return worst, worst_max
+
+        def sampled_relrms(y):
+            return sampled_errors(y)[0]
 
         plan.execute(xt, yt)
         torch.cuda.synchronize()
-        cfg["sampled_relrms"] = sampled_relrms(yt.cpu().numpy())
+        cfg["sampled_relrms"], cfg["sampled_maxerr"] = sampled_errors(yt.cpu().numpy())
         if prec == 0:
             # accuracy ablation: stage twiddles evaluated in FP32 arithmetic
             abl = mfft.Plan(dims, hdims, sign=sign, prec=prec,
@@ -624,6 +656,36 @@ def main():
         out["cpu_baseline"] = cpu_baseline(x, [(n_total, 1, 1)] if len(dims) == 1 else dims,
                                            hdims, sign, n_total, howmany)
     plan.destroy()
+    if extras and not args.no_extras:
+        # the rest of the metric on the same GPU: the uneven batch (one graph of
+        # persistent launches vs one plan per launch) and a bounded serving
+        # replay (p50/p99 at rho = 0.8 of the sequential capacity)
+        del xt, yt
+        torch.cuda.empty_cache()
+        ua = argparse.Namespace(**vars(args))
+        ua.items, ua.steps, ua.warmup = 10000, 5, 1
+        u = run_uneven(ua, emit=False)
+        out["uneven_batch"] = {
+            "workload": u["config"]["workload"], "gflops": u["value"],
+            "ms_per_step": u["ms_per_step"], "hbm_frac": u["roofline"]["frac"],
+            "plain_ms_per_step": u["config"]["plain_ms_per_step"],
+            "batched_over_plain": u["config"]["batched_over_plain"],
+            "launches_per_step": u["config"]["launches_per_step"],
+            "plan_seconds": u["config"]["plan_seconds"],
+            "sampled_relrms_max": u["config"]["sampled_relrms_max"],
+            "sampled_maxerr_max": u["config"]["sampled_maxerr_max"]}
+        sa = argparse.Namespace(**vars(args))
+        sa.items = 300
+        sv = run_serve(sa, emit=False, rhos=(0.8,))["config"]
+        out["serve"] = {
+            "workload": sv["workload"], "rho": 0.8,
+            "sequential_capacity_req_per_s": sv["sequential_capacity_req_per_s"],
+            "batched": {k: sv["rho0.8_batched"][k] for k in ("p50_ms", "p99_ms", "req_per_s",
+                                                             "gflops")},
+            "sequential": {k: sv["rho0.8_sequential"][k] for k in ("p50_ms", "p99_ms",
+                                                                   "req_per_s", "gflops")},
+            "closed_loop_batched_req_per_s": sv["closed_loop_batched"]["req_per_s"],
+            "closed_loop_sequential_req_per_s": sv["closed_loop_sequential"]["req_per_s"]}
     print(json.dumps(out), flush=True)
 
 

@@ -34,10 +34,19 @@ static int widen(const Pass &ps, PassArgs *a, size_t *lds)
     while (block < a->bt * a->tpt) block *= 2;
     Pass wide = ps;
     int bt = a->bt;
-    while (bt * 2 * a->tpt <= block && bt * 2 <= a->vn) {
-        wide.a.bt = bt * 2;
-        if (generic_lds_bytes(wide) > std::min<size_t>(g_lds_budget, 65536)) break;
-        bt *= 2;
+    if (a->load_mode == kModeRow && a->store_mode == kModeRow) {
+        // row tiles take any line count: as many as the class holds
+        while ((bt + 1) * a->tpt <= block && bt + 1 <= a->vn) {
+            wide.a.bt = bt + 1;
+            if (generic_lds_bytes(wide) > std::min<size_t>(g_lds_budget, 65536)) break;
+            ++bt;
+        }
+    } else {
+        while (bt * 2 * a->tpt <= block && bt * 2 <= a->vn) {
+            wide.a.bt = bt * 2;
+            if (generic_lds_bytes(wide) > std::min<size_t>(g_lds_budget, 65536)) break;
+            bt *= 2;
+        }
     }
     wide.a.bt = bt;
     if (bt != a->bt) {

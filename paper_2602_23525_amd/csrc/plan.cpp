@@ -396,6 +396,34 @@ static bool leaf_col_fits(const LineSpec &ls, const PassArgs &a, const Dim &in_d
     return true;
 }
 
+// Lines per tile of a row tile (lanes along the lines, so any count works):
+// the workgroup of bt * tpt threads should fill its waves and the 256-, 512-
+// or 1024-thread class that batched launches round it up to, with a tile of
+// at most 64 KB of LDS (two or more workgroups per CU) and no more lines than
+// the vector loop has.  Among the classes, the best filled; ties go to the
+// smaller.  (Powers of two alone left up to a quarter of the lanes idle, e.g.
+// 200 of 256 threads for 1000-point lines.)
+int row_lines_per_tile(int n, int tpt, int prec, int64_t lines)
+{
+    const int mt = max_threads(prec);
+    int best = 1;
+    double best_fill = -1;
+    for (int cls = 256; cls <= mt; cls *= 2) {
+        int bt = std::max(1, cls / tpt);
+        while (bt > 1 && tile_lds_bytes(n, bt, prec) > 65536) --bt;
+        while (bt > 1 && tile_lds_bytes(n, bt, prec) > g_lds_budget) --bt;
+        if (lines > 0) bt = (int)std::max<int64_t>(1, std::min<int64_t>(bt, lines));
+        int block = 256;
+        while (block < bt * tpt) block *= 2;
+        const double fill = (double)(bt * tpt) / block;
+        if (fill > best_fill + 1e-9) {
+            best_fill = fill;
+            best = bt;
+        }
+    }
+    return best;
+}
+
 static int add_line_pass(Builder &b, const LineSpec &ls)
 {
     PlanImpl *p = b.p;
@@ -462,13 +490,14 @@ static int add_line_pass(Builder &b, const LineSpec &ls)
     // Prefer tiles of at most 64 KB (several workgroups per CU); column tiles
     // may grow to the full LDS rather than drop below 64-byte runs.
     int bt;
-    if (col) bt = prec ? 8 : 16;
-    else bt = std::max(1, 256 / L.tpt);
-    bt = 1 << ilog2(bt);
-    if (bt > 1 && (1 << ilog2(bt)) != bt) bt >>= 1;
-    while (bt > bt_floor && (tile_lds_bytes(L.n, bt, prec) > 65536 || bt * L.tpt > mt)) bt >>= 1;
-    while (bt > 1 && (tile_lds_bytes(L.n, bt, prec) > g_lds_budget || bt * L.tpt > mt)) bt >>= 1;
-    while (bt > 1 && bt / 2 >= in_dim.n) bt >>= 1;   // no wider than the loop
+    if (col) {
+        bt = prec ? 8 : 16;
+        while (bt > bt_floor && (tile_lds_bytes(L.n, bt, prec) > 65536 || bt * L.tpt > mt)) bt >>= 1;
+        while (bt > 1 && (tile_lds_bytes(L.n, bt, prec) > g_lds_budget || bt * L.tpt > mt)) bt >>= 1;
+        while (bt > 1 && bt / 2 >= in_dim.n) bt >>= 1;   // no wider than the loop
+    } else {
+        bt = row_lines_per_tile(L.n, L.tpt, prec, in_dim.n);
+    }
     if (tile_lds_bytes(L.n, bt, prec) > g_lds_budget || bt * L.tpt > mt)
         return fail(MFFT_ENOTSUP, "leaf does not fit the LDS budget");
     a.bt = bt;

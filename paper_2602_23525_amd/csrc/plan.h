@@ -131,6 +131,8 @@ TransposeArgs resolve_transpose(const PlanImpl *p, const Pass &ps, const void *i
                                 void *scratch);
 PermuteArgs resolve_permute(const PlanImpl *p, const Pass &ps, const void *in, void *out,
                             void *scratch);
+// Lines per tile of a generic-kernel row tile (see plan.cpp).
+int row_lines_per_tile(int n, int tpt, int prec, int64_t lines);
 // LDS bytes the generic tile kernel needs for a pass.
 size_t generic_lds_bytes(const Pass &ps);
 
