@@ -150,8 +150,25 @@ def run_uneven(args, emit=True):
     xin = xin.view(torch.complex64)
     yout = torch.empty_like(xin)
     base_in, base_out = xin.data_ptr(), yout.data_ptr()
+    measure_s = None
+    flags = mfft.ESTIMATE
+    if getattr(args, "plan", "estimate") == "measure":
+        # measure mode once per distinct length (its structural choice is
+        # stored per length), then every item planned from wisdom alone
+        mfft.mfft_wisdom_forget()
+        t0 = time.perf_counter()
+        done = set()
+        for it in items:
+            if it.n in done:
+                continue
+            done.add(it.n)
+            mfft.Plan([(it.n, 1, 1)], [(it.batch, it.n, it.n)] if it.batch > 1 else [],
+                      flags=mfft.MEASURE).destroy()
+        measure_s = time.perf_counter() - t0
+        flags = mfft.WISDOM_ONLY
     t0 = time.perf_counter()
-    plans = [mfft.Plan([(it.n, 1, 1)], [(it.batch, it.n, it.n)] if it.batch > 1 else [])
+    plans = [mfft.Plan([(it.n, 1, 1)], [(it.batch, it.n, it.n)] if it.batch > 1 else [],
+                       flags=flags)
              for it in items]
     plan_s = time.perf_counter() - t0
     ins = [base_in + 8 * o for o in offs]
@@ -208,6 +225,9 @@ def run_uneven(args, emit=True):
         "ms_per_step": round(ms_batch, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"uneven_batch_{len(items)}", "points": npts,
+                   "plan_source": "estimate" if measure_s is None else
+                   "wisdom from measure mode (one problem per distinct length)",
+                   "measure_seconds": measure_s and round(measure_s, 1),
                    "plan_seconds": round(plan_s, 2), "batch_create_seconds": round(batch_s, 3),
                    "launches_per_step": binfo["launches"], "tiles": binfo["tiles"],
                    "plain_ms_per_step": ms_plain and round(ms_plain, 3),
@@ -439,6 +459,9 @@ def main():
     ap.add_argument("--batch", type=int, default=1, help="custom 1-D workload: batch")
     ap.add_argument("--prec", default="c32", choices=["c32", "c64"])
     ap.add_argument("--sign", type=int, default=-1)
+    ap.add_argument("--plan", default="estimate", choices=["estimate", "measure"],
+                    help="uneven_batch: plan every item by estimate, or measure each "
+                         "distinct length once and plan from the stored wisdom")
     ap.add_argument("--no-extras", action="store_true",
                     help="default workload: leave out the uneven-batch and serving legs")
     ap.add_argument("--items", type=int, default=None,
@@ -671,6 +694,7 @@ def main():
             "plain_ms_per_step": u["config"]["plain_ms_per_step"],
             "batched_over_plain": u["config"]["batched_over_plain"],
             "launches_per_step": u["config"]["launches_per_step"],
+            "plan_source": u["config"]["plan_source"],
             "plan_seconds": u["config"]["plan_seconds"],
             "sampled_relrms_max": u["config"]["sampled_relrms_max"],
             "sampled_maxerr_max": u["config"]["sampled_maxerr_max"]}

@@ -99,6 +99,69 @@ static void destroy_impl(PlanImpl *p)
     p->scratch = nullptr;
 }
 
+int rebuild_plan(PlanImpl *p)
+{
+    // table kernels of the previous build may still be queued
+    (void)hipStreamSynchronize(p->stream);
+    destroy_impl(p);
+    p->table_bytes = 0;
+    p->scratch_bytes = 0;
+    p->passes.clear();
+    return build_plan(p);
+}
+
+// Wisdom key of the structural choice for lines of one length (shared by
+// every problem with such lines, whatever its strides and vector loops).
+static std::string length_key(const PlanImpl *p, int64_t n, unsigned flags)
+{
+    return std::string("line c") + (p->prob.prec ? "64" : "32") + " n=" + std::to_string(n) + " " +
+           g_arch + ((flags & MFFT_NO_SCRATCH) ? " noscratch" : "");
+}
+
+// Stored choices for the problem: the problem's own entry (structure and
+// kernel variants), else one entry per transform length (structure).  True
+// when the plan is fully determined by them.
+static int apply_wisdom(PlanImpl *p, const std::string &key, unsigned flags, bool *found)
+{
+    *found = false;
+    std::string val;
+    if (wisdom_lookup(key, &val)) {
+        const size_t bar = val.find('|');
+        std::map<int64_t, StructChoice> st;
+        if (parse_structure(bar == std::string::npos ? "-" : val.substr(0, bar), &st)) {
+            int rc = MFFT_OK;
+            if (!st.empty()) {
+                p->overrides = st;
+                rc = rebuild_plan(p);
+                if (rc) return rc;
+            }
+            if (apply_choices(p, val)) {
+                *found = true;
+                return MFFT_OK;
+            }
+        }
+    }
+    if (p->prob.kind != 0) return MFFT_OK;
+    bool all = true;
+    std::map<int64_t, StructChoice> st;
+    for (const Dim &d : p->prob.N) {
+        int64_t n = 0;
+        StructChoice c;
+        if (wisdom_lookup(length_key(p, d.n, flags), &val) && parse_choice(val, &n, &c) && n == d.n) {
+            if (!c.empty()) st[d.n] = c;
+        } else {
+            all = false;
+        }
+    }
+    if (!st.empty()) {
+        p->overrides = st;
+        int rc = rebuild_plan(p);
+        if (rc) return rc;
+    }
+    *found = all;
+    return MFFT_OK;
+}
+
 // Plan without the global lock (used for the FP64 sub-transforms that build
 // Rader and Bluestein spectra while another plan is being made).
 int plan_internal(mfft_plan *out, int rank, const mfft_iodim *dims, int howmany_rank,
@@ -130,15 +193,35 @@ int plan_internal(mfft_plan *out, int rank, const mfft_iodim *dims, int howmany_
         // plans without scratch have other passes: their own wisdom entries
         const std::string key = problem_key(p->prob) + " " + g_arch +
                                 ((flags & MFFT_NO_SCRATCH) ? " noscratch" : "");
-        std::string val;
         const bool use_wisdom = !(flags & MFFT_NO_WISDOM);
-        if (use_wisdom && wisdom_lookup(key, &val) && apply_choices(p, val)) {
-            p->from_wisdom = true;
-        } else if (flags & MFFT_WISDOM_ONLY) {
-            rc = fail(MFFT_ENOWISDOM, "no stored plan for " + key);
-        } else if (flags & MFFT_MEASURE) {
-            rc = measure_plan(p);
-            if (rc == MFFT_OK && use_wisdom) wisdom_record(key, plan_choices(p));
+        bool found = false;
+        if (use_wisdom) rc = apply_wisdom(p, key, flags, &found);
+        if (rc) {
+            // a stored choice that no longer plans: fall back to the estimate
+            p->overrides.clear();
+            rc = rebuild_plan(p);
+            found = false;
+        }
+        if (rc == MFFT_OK) {
+            if (found) {
+                p->from_wisdom = true;
+            } else if (flags & MFFT_WISDOM_ONLY) {
+                rc = fail(MFFT_ENOWISDOM, "no stored plan for " + key);
+            } else if (flags & MFFT_MEASURE) {
+                rc = measure_structure(p);
+                if (rc == MFFT_OK) rc = measure_plan(p);
+                if (rc == MFFT_OK && use_wisdom) {
+                    wisdom_record(key, plan_choices(p));
+                    if (p->prob.kind == 0)
+                        for (const Dim &d : p->prob.N) {
+                            auto it = p->overrides.find(d.n);
+                            wisdom_record(length_key(p, d.n, flags),
+                                          choice_text(d.n, it == p->overrides.end()
+                                                               ? StructChoice{}
+                                                               : it->second));
+                        }
+                }
+            }
         }
     }
     if (rc == MFFT_OK && p->scratch_bytes && !(flags & kPlanNoOwnScratch)) {

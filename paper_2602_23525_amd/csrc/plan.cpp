@@ -191,11 +191,28 @@ static size_t tile_lds_bytes(int n, int bt, int prec)
     return ((size_t)bt * line_lds_stride(n) + 2 * (size_t)bt) * elem_bytes(prec);
 }
 
+static bool leaf_shape_from(int64_t n, int emax, int max_tpt, const std::vector<int> &rad, Leaf *L);
+
 static bool make_leaf_shape(int64_t n, int emax, int max_tpt, Leaf *L)
 {
     if (n < 2 || n > (1 << 20)) return false;
     std::vector<int> rad;
     if (!radices_for(n, emax, max_tpt, &rad)) return false;
+    return leaf_shape_from(n, emax, max_tpt, rad, L);
+}
+
+// The leaf shape of a given radix sequence (radices the tile kernel compiles,
+// product n, thread need within max_tpt), or false.
+static bool leaf_shape_from(int64_t n, int emax, int max_tpt, const std::vector<int> &rad, Leaf *L)
+{
+    if (n < 2 || n > (1 << 20) || rad.empty() || (int)rad.size() > kMaxStages) return false;
+    int64_t prod = 1;
+    for (int R : rad) {
+        if (R < 2 || R > 16) return false;   // every radix 2..16 is compiled
+        if (stage_threads(n, R, emax) > max_tpt) return false;
+        prod *= R;
+    }
+    if (prod != n) return false;
     int tpt = 1;
     for (int R : rad) tpt = std::max(tpt, stage_threads(n, R, emax));
     // the column loops unroll EMAX + 2 elements per thread
@@ -424,11 +441,18 @@ int row_lines_per_tile(int n, int tpt, int prec, int64_t lines)
     return best;
 }
 
+static const StructChoice *choice_for(const PlanImpl *p, int64_t n)
+{
+    auto it = p->overrides.find(n);
+    return it == p->overrides.end() ? nullptr : &it->second;
+}
+
 static int add_line_pass(Builder &b, const LineSpec &ls)
 {
     PlanImpl *p = b.p;
     const int prec = p->prob.prec;
     const int64_t n = ls.conv_n ? ls.conv_n : ls.line.n;
+    const StructChoice *ch = choice_for(p, n);
     Pass ps;
     PassArgs &a = ps.a;
     ps.prec = prec;
@@ -484,6 +508,11 @@ static int add_line_pass(Builder &b, const LineSpec &ls)
     Leaf L;
     if (!make_leaf_shape(n, 16, mt / bt_floor, &L) && !make_leaf_shape(n, 16, mt, &L))
         return fail(MFFT_ENOTSUP, "no leaf shape for n");
+    if (ch && !ch->rad.empty()) {
+        // a measured radix sequence (if it fits this pass's thread budget)
+        Leaf Lc;
+        if (leaf_shape_from(n, 16, mt / bt_floor, ch->rad, &Lc)) L = Lc;
+    }
     ps.emax = L.emax;
     int rc = fill_leaf(p, L, &a, &b.twcache);
     if (rc) return rc;
@@ -497,6 +526,9 @@ static int add_line_pass(Builder &b, const LineSpec &ls)
         while (bt > 1 && bt / 2 >= in_dim.n) bt >>= 1;   // no wider than the loop
     } else {
         bt = row_lines_per_tile(L.n, L.tpt, prec, in_dim.n);
+        if (ch && ch->bt > 0 && ch->bt * L.tpt <= mt &&
+            tile_lds_bytes(L.n, ch->bt, prec) <= g_lds_budget)
+            bt = (int)std::max<int64_t>(1, std::min<int64_t>(ch->bt, in_dim.n));
     }
     if (tile_lds_bytes(L.n, bt, prec) > g_lds_budget || bt * L.tpt > mt)
         return fail(MFFT_ENOTSUP, "leaf does not fit the LDS budget");
@@ -654,6 +686,23 @@ static bool choose_split(int64_t n, int prec, Split *sp)
 
 static int plan_line(Builder &b, Dim d, std::vector<Dim> V, int src, int dst, int64_t src_off,
                      int64_t dst_off, bool conj_in, bool conj_out);
+
+// The plan's split of a length: a measured one when it is a valid split,
+// else the estimate's.
+static bool split_for(const PlanImpl *p, int64_t n, int prec, Split *sp)
+{
+    if (const StructChoice *c = choice_for(p, n)) {
+        const int btmin = prec ? 4 : 8;
+        const int64_t m = c->split;
+        if (m > 1 && m < n && n % m == 0 && leaf_fits(m, prec, btmin) &&
+            leaf_fits(n / m, prec, btmin)) {
+            sp->m = m;
+            sp->r = n / m;
+            return true;
+        }
+    }
+    return choose_split(n, prec, sp);
+}
 
 // ------------------------------------------------------------ convolution lengths
 // Estimate-mode costs of the cyclic convolutions behind prime sizes: the
@@ -1043,7 +1092,7 @@ static int plan_rader(Builder &b, Dim d, const std::vector<Dim> &V, int src, int
         return add_line_pass(b, ls);
     }
     Split sp;
-    if (!choose_split(L, b.p->prob.prec, &sp)) return fail(MFFT_ENOTSUP, "Rader length too large");
+    if (!split_for(b.p, L, b.p->prob.prec, &sp)) return fail(MFFT_ENOTSUP, "Rader length too large");
     (void)btmin;
     const int64_t m1 = sp.m, r1 = sp.r;
     const int64_t H = vprod(V);
@@ -1129,7 +1178,16 @@ static int plan_bluestein(Builder &b, Dim d, const std::vector<Dim> &V, int src,
     const int prec = b.p->prob.prec;
     const int eb = elem_bytes(prec);
     double cost;
-    const int64_t M = bluestein_length(n, prec, &cost);
+    int64_t M = bluestein_length(n, prec, &cost);
+    if (const StructChoice *c = choice_for(b.p, n)) {
+        // a measured convolution length: any smooth M >= 2n-1 with a plan
+        Split t;
+        if (c->M >= 2 * n - 1 && is_smooth(c->M) &&
+            (leaf_fits(c->M, prec, 1) || choose_split(c->M, prec, &t))) {
+            M = c->M;
+            cost = 0;
+        }
+    }
     if (!M || cost == HUGE_VAL) return fail(MFFT_ENOTSUP, "no Bluestein length");
     const bool single = leaf_fits(M, prec, 1);
     void *chirp, *spec;
@@ -1157,7 +1215,7 @@ static int plan_bluestein(Builder &b, Dim d, const std::vector<Dim> &V, int src,
         return add_line_pass(b, ls);
     }
     Split sp;
-    choose_split(M, prec, &sp);
+    if (!split_for(b.p, M, prec, &sp)) return fail(MFFT_ENOTSUP, "no split of the Bluestein length");
     const int64_t m1 = sp.m, r1 = sp.r;
     const int64_t H = vprod(V);
     const int64_t s0 = b.scratch_take(H * M * eb) / eb;
@@ -1241,7 +1299,7 @@ static int plan_line(Builder &b, Dim d, std::vector<Dim> V, int src, int dst, in
                 return plan_leaf(b, d, V, src, dst, src_off, dst_off, conj_in, conj_out);
         }
         Split sp;
-        if (!choose_split(n, prec, &sp)) {
+        if (!split_for(b.p, n, prec, &sp)) {
             // three or more passes: peel the largest leaf factor and recurse
             int64_t best = 0;
             for (int64_t m = 2; m < n; ++m)
@@ -1258,10 +1316,14 @@ static int plan_line(Builder &b, Dim d, std::vector<Dim> V, int src, int dst, in
     // measured: 1009 Rader 0.45 ms, Bluestein 0.27 ms, 33254 transforms;
     // 97 Rader 0.27 ms, Bluestein 0.31 ms)
     if (smallest_prime_factor(n) == n && is_smooth(n - 1)) {
+        const StructChoice *c = choice_for(b.p, n);
+        if (c && c->prime == 1) return plan_rader(b, d, V, src, dst, src_off, dst_off, conj_in, conj_out);
         double blue = HUGE_VAL;
         if (n > 256) (void)bluestein_length(n, prec, &blue);
-        if (n <= 256 || conv_cost(n - 1, prec, true) <= blue)
+        if ((!c || c->prime != 2) && (n <= 256 || conv_cost(n - 1, prec, true) <= blue))
             return plan_rader(b, d, V, src, dst, src_off, dst_off, conj_in, conj_out);
+        if (c && c->prime == 2)
+            return plan_bluestein(b, d, V, src, dst, src_off, dst_off, conj_in, conj_out);
     }
     // A composite length whose only prime factor above 13 is p, once: one
     // Cooley-Tukey step (eq. ct) with smooth m-point transforms first (m the
@@ -1370,6 +1432,257 @@ static int bluestein_tables(Builder &b, int64_t n, int64_t M, void **chirp, void
     dev_free(p, vhat, (size_t)M * 16);
     if (e != hipSuccess) return fail(MFFT_EHIP, hipGetErrorString(e));
     return MFFT_OK;
+}
+
+// ------------------------------------------------------------ structural candidates
+// (measure mode: Section 4.3's planner times alternatives instead of trusting
+// the estimate)
+
+// Radix sequences of a one-pass leaf of length n: the multisets of compiled
+// radices with product n whose stages each fit the thread budget, with at most
+// one stage more than the fewest, ordered by stages then thread need; each
+// with its radices largest first, the estimate's sequence first of all, and the
+// smallest-first order of the two best.
+static std::vector<std::vector<int>> radix_candidates(int64_t n, int prec, size_t limit)
+{
+    static const int kRad[] = {16, 15, 14, 13, 12, 11, 10, 9, 8, 7, 6, 5, 4, 3, 2};
+    const int mt = max_threads(prec);
+    std::vector<std::vector<int>> all;
+    std::vector<int> cur;
+    std::function<void(int64_t, int)> rec = [&](int64_t rest, int from) {
+        if (all.size() > 400 || (int)cur.size() > kMaxStages) return;
+        if (rest == 1) {
+            if (!cur.empty()) all.push_back(cur);
+            return;
+        }
+        for (int i = from; i < 15; ++i) {
+            const int R = kRad[i];
+            if (rest % R || stage_threads(n, R, 16) > mt) continue;
+            cur.push_back(R);
+            rec(rest / R, i);
+            cur.pop_back();
+        }
+    };
+    rec(n, 0);
+    if (all.empty()) return {};
+    size_t fewest = SIZE_MAX;
+    for (auto &r : all) fewest = std::min(fewest, r.size());
+    auto need = [&](const std::vector<int> &r) {
+        int t = 0;
+        for (int R : r) t = std::max(t, stage_threads(n, R, 16));
+        return t;
+    };
+    std::vector<std::vector<int>> keep;
+    for (auto &r : all)
+        if (r.size() <= fewest + 1) keep.push_back(r);
+    std::stable_sort(keep.begin(), keep.end(), [&](const std::vector<int> &a, const std::vector<int> &b) {
+        if (a.size() != b.size()) return a.size() < b.size();
+        return need(a) < need(b);
+    });
+    std::vector<std::vector<int>> out;
+    std::vector<int> est;
+    if (radices_for(n, 16, mt, &est)) out.push_back(est);
+    for (auto &r : keep) {
+        if (out.size() >= limit) break;
+        if (std::find(out.begin(), out.end(), r) == out.end()) out.push_back(r);
+    }
+    const size_t base = out.size();
+    for (size_t i = 0; i < std::min<size_t>(2, base) && out.size() < limit + 2; ++i) {
+        std::vector<int> up(out[i].rbegin(), out[i].rend());
+        if (std::find(out.begin(), out.end(), up) == out.end()) out.push_back(up);
+    }
+    return out;
+}
+
+// The estimate's structural choice for lines of length n, spelled out (so
+// that stored wisdom keeps it even if the estimate changes).
+static StructChoice estimate_choice(const PlanImpl *p, int64_t n)
+{
+    const int prec = p->prob.prec;
+    StructChoice c;
+    if (n < 2) return c;
+    if (smallest_prime_factor(n) == n) {
+        if (n <= 13) return c;
+        double blue = HUGE_VAL;
+        const int64_t M = bluestein_length(n, prec, &blue);
+        if (is_smooth(n - 1) && (n <= 256 || conv_cost(n - 1, prec, true) <= blue)) {
+            c.prime = 1;
+        } else if (M) {
+            c.prime = 2;
+            c.M = M;
+        }
+        return c;
+    }
+    if (!is_smooth(n)) return c;
+    if (leaf_fits(n, prec, 1)) {
+        if (leaf_supported(prec, n)) return c;
+        Leaf L;
+        if (make_leaf_shape(n, 16, max_threads(prec), &L)) {
+            c.rad = L.rad;
+            c.bt = row_lines_per_tile(L.n, L.tpt, prec, 0);
+        }
+        return c;
+    }
+    Split sp;
+    if (choose_split(n, prec, &sp)) c.split = sp.m;
+    return c;
+}
+
+std::vector<StructChoice> structure_candidates(const PlanImpl *p, int64_t n)
+{
+    const int prec = p->prob.prec;
+    std::vector<StructChoice> out;
+    out.push_back(estimate_choice(p, n));   // the estimate's, first
+    if (n < 2) return out;
+    if (smallest_prime_factor(n) == n) {
+        if (n <= 13) return out;   // a radix: one butterfly
+        if (is_smooth(n - 1)) {
+            StructChoice c;
+            c.prime = 1;
+            out.push_back(c);
+        }
+        // Bluestein over each convolution length the estimate considers
+        const int64_t lo = 2 * n - 1;
+        int64_t p2 = 1;
+        while (p2 < lo) p2 <<= 1;
+        std::vector<int64_t> cand;
+        for (int64_t c = lo; c <= p2; ++c)
+            if (is_smooth(c)) {
+                cand.push_back(c);
+                break;
+            }
+        for (int64_t k = 1; k <= 15; k += 2) {
+            int64_t c = k;
+            while (c < lo) c <<= 1;
+            if (c <= p2 && is_smooth(c) && std::find(cand.begin(), cand.end(), c) == cand.end())
+                cand.push_back(c);
+        }
+        for (int64_t M : cand) {
+            Split t;
+            if (!leaf_fits(M, prec, 1) && !choose_split(M, prec, &t)) continue;
+            StructChoice c;
+            c.prime = 2;
+            c.M = M;
+            out.push_back(c);
+        }
+        return out;
+    }
+    if (!is_smooth(n)) return out;
+    if (leaf_fits(n, prec, 1)) {
+        // one pass; powers of two run in the specialized leaf kernel (fixed
+        // radices), the rest in the generic kernel
+        if (leaf_supported(prec, n)) return out;
+        const auto rads = radix_candidates(n, prec, 6);
+        for (size_t i = 0; i < rads.size(); ++i) {
+            StructChoice c;
+            c.rad = rads[i];
+            if (i > 0) {
+                out.push_back(c);
+                continue;
+            }
+            // the estimate's radices (first) with other line counts per tile
+            Leaf L;
+            if (!leaf_shape_from(n, 16, max_threads(prec), c.rad, &L)) continue;
+            const int bt = row_lines_per_tile(L.n, L.tpt, prec, 0);
+            for (int b2 : {bt / 2, bt * 2}) {
+                if (b2 < 1 || b2 == bt || b2 * L.tpt > max_threads(prec) ||
+                    tile_lds_bytes(L.n, b2, prec) > g_lds_budget)
+                    continue;
+                StructChoice cb = c;
+                cb.bt = b2;
+                out.push_back(cb);
+            }
+        }
+        return out;
+    }
+    // two passes: the splits whose factors are both column leaves, most
+    // balanced first
+    const int btmin = prec ? 4 : 8;
+    std::vector<std::pair<double, int64_t>> sp;
+    for (int64_t m = 2; m < n; ++m) {
+        if (n % m || !leaf_fits(m, prec, btmin) || !leaf_fits(n / m, prec, btmin)) continue;
+        sp.push_back({std::fabs(std::log((double)m) - std::log((double)(n / m))), m});
+    }
+    std::sort(sp.begin(), sp.end());
+    for (size_t i = 0; i < sp.size() && i < 6; ++i) {
+        StructChoice c;
+        c.split = sp[i].second;
+        out.push_back(c);
+    }
+    return out;
+}
+
+// "n=<length>[:r=<R>.<R>...][:b=<lines>][:s=<split>][:a=R|B][:M=<length>]"
+std::string choice_text(int64_t n, const StructChoice &c)
+{
+    std::ostringstream s;
+    s << "n=" << n;
+    if (!c.rad.empty()) {
+        s << ":r=";
+        for (size_t i = 0; i < c.rad.size(); ++i) s << (i ? "." : "") << c.rad[i];
+    }
+    if (c.bt) s << ":b=" << c.bt;
+    if (c.split) s << ":s=" << c.split;
+    if (c.prime) s << ":a=" << (c.prime == 1 ? "R" : "B");
+    if (c.M) s << ":M=" << c.M;
+    return s.str();
+}
+
+bool parse_choice(const std::string &text, int64_t *n, StructChoice *c)
+{
+    *c = StructChoice{};
+    std::istringstream s(text);
+    std::string f;
+    bool have_n = false;
+    while (std::getline(s, f, ':')) {
+        if (f.size() < 3 || f[1] != '=') return false;
+        const std::string v = f.substr(2);
+        char *end = nullptr;
+        switch (f[0]) {
+        case 'n':
+            *n = std::strtoll(v.c_str(), &end, 10);
+            have_n = *end == 0 && *n > 1;
+            break;
+        case 'r': {
+            std::istringstream rs(v);
+            std::string r;
+            while (std::getline(rs, r, '.')) {
+                char *rend = nullptr;
+                const long R = std::strtol(r.c_str(), &rend, 10);
+                if (*rend || R < 2 || R > 16) return false;
+                c->rad.push_back((int)R);
+            }
+            break;
+        }
+        case 'b': c->bt = (int)std::strtol(v.c_str(), &end, 10); break;
+        case 's': c->split = std::strtoll(v.c_str(), &end, 10); break;
+        case 'a':
+            if (v == "R") c->prime = 1;
+            else if (v == "B") c->prime = 2;
+            else return false;
+            break;
+        case 'M': c->M = std::strtoll(v.c_str(), &end, 10); break;
+        default: return false;
+        }
+        if (end && *end) return false;
+    }
+    return have_n && c->bt >= 0 && c->split >= 0 && c->M >= 0;
+}
+
+// The structural part of a choice string ("-" or "n=...;n=...").
+bool parse_structure(const std::string &text, std::map<int64_t, StructChoice> *out)
+{
+    out->clear();
+    if (text == "-" || text.empty()) return true;
+    std::istringstream s(text);
+    std::string item;
+    while (std::getline(s, item, ';')) {
+        int64_t n = 0;
+        StructChoice c;
+        if (!parse_choice(item, &n, &c)) return false;
+        (*out)[n] = c;
+    }
+    return true;
 }
 
 // ------------------------------------------------------------ whole problems

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -75,6 +76,17 @@ struct LeafTune {
     int persistent = 0;
 };
 
+// Structural choices for the lines of one length (what measure mode times and
+// wisdom stores besides kernel variants; zero / empty = the estimate's).
+struct StructChoice {
+    std::vector<int> rad;   // radix sequence of a generic-kernel leaf of this length
+    int bt = 0;             // lines per row tile of that leaf
+    int64_t split = 0;      // two-pass Cooley-Tukey: length of the first pass's lines
+    int prime = 0;          // prime length: 1 Rader, 2 Bluestein
+    int64_t M = 0;          // Bluestein's convolution length
+    bool empty() const { return rad.empty() && !bt && !split && !prime && !M; }
+};
+
 struct DeviceAlloc {
     void *ptr = nullptr;
     size_t bytes = 0;
@@ -95,6 +107,7 @@ struct PlanImpl {
     double bytes_passes = 0;
     int device = 0;
     bool from_wisdom = false;
+    std::map<int64_t, StructChoice> overrides;   // by line length
 };
 
 }  // namespace mfft
@@ -119,6 +132,16 @@ void apply_leaf_tune(Pass *ps, const LeafTune &t);
 int measure_plan(PlanImpl *p);
 std::string plan_choices(const PlanImpl *p);
 bool apply_choices(PlanImpl *p, const std::string &text);
+// Structural choices: the candidates for lines of length n (the estimate's
+// own first), measuring them (rebuilding the plan per candidate), and their
+// text form in wisdom ("n=1000:r=10.10.10:b=5", ...).
+std::vector<StructChoice> structure_candidates(const PlanImpl *p, int64_t n);
+int measure_structure(PlanImpl *p);
+std::string choice_text(int64_t n, const StructChoice &c);
+bool parse_choice(const std::string &text, int64_t *n, StructChoice *c);
+bool parse_structure(const std::string &text, std::map<int64_t, StructChoice> *out);
+// Free the plan's tables and passes and build it again (with p->overrides).
+int rebuild_plan(PlanImpl *p);
 
 // Enqueue the passes.
 int run_plan(const PlanImpl *p, const void *in, void *out, void *scratch, hipStream_t s);

@@ -16,6 +16,10 @@
 //     summary "checked plans=P passes=S partial=Q guarded=G violations=V".
 //   plan_host_check plan <prec> <n> <batch>
 //     prints the plan's pass list (as the library describes it).
+//   plan_host_check cands <prec> <n_lo> <n_hi> <batch> [print]
+//     every structural candidate measure mode would time for each length
+//     (radix sequences, lines per tile, splits, Rader / Bluestein lengths),
+//     planned with that choice and checked like the estimate's plan.
 //   plan_host_check random <count> <seed>
 //     seeded random problems (rank 1-3 with vector loops, contiguous,
 //     transposed or reversed strides, in place or not, both precisions, some
@@ -317,6 +321,50 @@ int main(int argc, char **argv)
             std::printf("%s vn=%lld bt=%d tiles=%lld\n", ps.desc.c_str(), (long long)ps.a.vn,
                         ps.a.bt, (long long)ps.a.ntiles);
         return 0;
+    }
+    if (argc >= 6 && !std::strcmp(argv[1], "cands")) {
+        const int prec = std::atoi(argv[2]);
+        const int64_t lo = std::atoll(argv[3]), hi = std::atoll(argv[4]), batch = std::atoll(argv[5]);
+        const bool print = argc >= 7;
+        int lengths = 0, cands = 0, planned = 0, violations = 0, failed = 0;
+        for (int64_t n = lo; n <= hi; ++n) {
+            mfft_plan_s base;
+            if (host_plan(&base.impl, prec, n, batch)) continue;
+            const auto cs = structure_candidates(&base.impl, n);
+            ++lengths;
+            for (size_t i = 0; i < cs.size(); ++i) {
+                mfft_plan_s pl;
+                PlanImpl *p = &pl.impl;
+                if (!cs[i].empty()) p->overrides[n] = cs[i];
+                ++cands;
+                // the wisdom text of the choice reads back as the same choice
+                int64_t n2 = 0;
+                StructChoice c2;
+                const std::string text = choice_text(n, cs[i]);
+                if (!parse_choice(text, &n2, &c2) || n2 != n || choice_text(n2, c2) != text) {
+                    std::printf("TEXT ROUND TRIP FAILED %s\n", text.c_str());
+                    ++failed;
+                }
+                const int rc = host_plan(p, prec, n, batch);
+                if (rc) {
+                    std::printf("CANDIDATE FAILED n=%lld %s rc=%d\n", (long long)n,
+                                choice_text(n, cs[i]).c_str(), rc);
+                    ++failed;
+                    continue;
+                }
+                ++planned;
+                if (print) {
+                    std::printf("%s\n", choice_text(n, cs[i]).c_str());
+                    for (const Pass &ps : p->passes) std::printf("    %s\n", ps.desc.c_str());
+                }
+                Checker ck{p, "n=" + std::to_string(n) + " " + choice_text(n, cs[i])};
+                for (const Pass &ps : p->passes) ck.check_pass(ps);
+                violations += ck.violations;
+            }
+        }
+        std::printf("checked lengths=%d candidates=%d planned=%d violations=%d failed=%d\n", lengths,
+                    cands, planned, violations, failed);
+        return violations || failed ? 1 : 0;
     }
     if (argc >= 4 && !std::strcmp(argv[1], "random")) {
         const int count = std::atoi(argv[2]);

@@ -154,3 +154,49 @@ def test_every_leaf_variant(n, b, prec):
             err = oracle.rel_rms(y.reshape(b, n), ref)
             assert err <= tol, (n, b, prec, v, pe, err)
     mfft.mfft_wisdom_forget()
+
+
+def _wisdom_lines():
+    import paper_2602_23525_amd as mfft
+    return dict(line.split(" => ") for line in mfft.mfft_wisdom_export().strip().split("\n")[1:])
+
+
+@pytest.mark.parametrize("n,b,prec,field", [(1000, 4096, 0, ":r="), (2187, 1024, 1, ":r="),
+                                            (65537, 64, 0, ":a="), (4099, 256, 0, ":a="),
+                                            (100000, 32, 0, ":s=")])
+def test_measured_structure_is_stored_and_reused(n, b, prec, field):
+    """Measure mode times structural alternatives (radix sequence and lines per
+    tile of a generic leaf, Cooley-Tukey split, Rader or Bluestein and its
+    length) and stores the winner per problem and per transform length; a
+    wisdom-only plan rebuilt from the text gives identical bits, also for
+    another batch count of the same length."""
+    import paper_2602_23525_amd as mfft
+    cdt = np.complex64 if prec == 0 else np.complex128
+    tol = 2e-6 if prec == 0 else 1e-13
+    x = uniform_complex(n * b, seed=n + 3, dtype=cdt)
+    rows = [0, b - 1]
+    ref = oracle.fft(x.astype(np.complex128).reshape(b, n)[rows])
+    mfft.mfft_wisdom_forget()
+    pm = mfft.Plan([(n, 1, 1)], [(b, n, n)], prec=prec, flags=mfft.MEASURE)
+    ym = _run(pm, x)
+    assert oracle.rel_rms(ym.reshape(b, n)[rows], ref) <= tol
+    w = _wisdom_lines()
+    line = [v for k, v in w.items() if k.startswith(f"line c{32 if prec == 0 else 64} n={n} ")]
+    assert len(line) == 1 and line[0].startswith(f"n={n}") and field in line[0], w
+    prob = [v for k, v in w.items() if not k.startswith("line ")]
+    assert len(prob) == 1 and field in prob[0].split("|")[0], w
+    text = mfft.mfft_wisdom_export()
+    mfft.mfft_wisdom_forget()
+    mfft.mfft_wisdom_import(text)
+    pw = mfft.Plan([(n, 1, 1)], [(b, n, n)], prec=prec, flags=mfft.WISDOM_ONLY)
+    assert "choices from wisdom" in pw.info()["desc"]
+    assert pw.info()["desc"].replace("  (choices from wisdom)\n", "") == pm.info()["desc"]
+    assert np.array_equal(_run(pw, x), ym), "stored structure must give identical bits"
+    # the per-length entry plans the same length with another batch count
+    b2 = 3
+    pb = mfft.Plan([(n, 1, 1)], [(b2, n, n)], prec=prec, flags=mfft.WISDOM_ONLY)
+    y2 = _run(pb, x[: n * b2])
+    assert oracle.rel_rms(y2.reshape(b2, n)[:1], ref[:1]) <= tol
+    for p in (pm, pw, pb):
+        p.destroy()
+    mfft.mfft_wisdom_forget()

@@ -12,9 +12,11 @@ inspected on the CPU:
     not a multiple of the tile width among them, the case of the padding-line
     over-read fixed in the generic tile kernel -- and for every length up to
     4096 and sampled composite lengths above;
+  * every structural alternative measure mode would time plans and stays in
+    bounds, and its wisdom text reads back unchanged;
   * the same planner (and the oracle's C code) under AddressSanitizer and
-    UndefinedBehaviorSanitizer, on prime ranges and seeded random problems
-    (strided, transposed, reversed, in place, aliasing)."""
+    UndefinedBehaviorSanitizer, on prime ranges, measure candidates and seeded
+    random problems (strided, transposed, reversed, in place, aliasing)."""
 import os
 import re
 import shutil
@@ -87,6 +89,15 @@ def test_sampled_composite_lengths_stay_inside_their_tables(checker):
         assert s["violations"] == 0 and s["failed"] == 0
 
 
+@pytest.mark.parametrize("prec,lo,hi", [(0, 2, 4096), (1, 2, 4096), (0, 60000, 65536)])
+def test_measure_candidates_plan_and_stay_inside_their_tables(checker, prec, lo, hi):
+    # every structural alternative measure mode times (radix sequences, lines
+    # per tile, Cooley-Tukey splits, Rader or Bluestein and its length) plans,
+    # keeps its table reads in bounds, and its wisdom text reads back the same
+    _, s = _run(checker, "cands", prec, lo, hi, 3)
+    assert s["violations"] == 0 and s["failed"] == 0 and s["candidates"] > s["lengths"]
+
+
 def test_planner_under_address_and_ub_sanitizers(checker_san):
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=1",
                UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1")
@@ -96,6 +107,8 @@ def test_planner_under_address_and_ub_sanitizers(checker_san):
     assert s["violations"] == 0
     _, s = _run(checker_san, "random", 3000, 11, env=env)
     assert s["violations"] == 0 and s["planned"] > 1000
+    _, s = _run(checker_san, "cands", 0, 2, 1200, 2, env=env)
+    assert s["violations"] == 0 and s["failed"] == 0
 
 
 def test_oracle_under_address_and_ub_sanitizers(tmp_path):
