@@ -858,42 +858,45 @@ static int add_transpose_pass(Builder &b, int buf, int64_t off, int64_t q, int64
     return MFFT_OK;
 }
 
-// In-place perfect shuffle of the 2q runs of q elements of each block (run x
-// at x*q*s): run x goes to 2x mod (2q - 1), the last run stays.  The cycles
-// of the permutation are found on the host; a table of run destinations and
-// one start per cycle go to the device.
-static int add_shuffle_pass(Builder &b, int buf, int64_t off, int64_t q, int64_t s,
-                            const std::vector<Dim> &V)
+// In-place transpose of a rows x cols matrix of runs (run x = row*cols + col,
+// `len` elements of stride s each, at x*len*s) into cols x rows: run x goes
+// to (x mod cols)*rows + x div cols.  The cycles of the permutation are
+// found on the host; a table of run destinations and one start per cycle go
+// to the device.
+static int add_run_transpose_pass(Builder &b, int buf, int64_t off, int64_t rows, int64_t cols,
+                                  int64_t len, int64_t s, const std::vector<Dim> &V)
 {
     PlanImpl *p = b.p;
     if (V.size() > 8) return fail(MFFT_ENOTSUP, "permutation over more than 8 loops");
-    const int64_t items = 2 * q;
+    if (len > 2048) return fail(MFFT_ENOTSUP, "runs of more than 2048 elements");
+    const int64_t items = rows * cols;
+    if (items > INT32_MAX) return fail(MFFT_ENOTSUP, "too many runs");
     std::vector<int32_t> next(items), starts;
-    for (int64_t x = 0; x < items; ++x) next[x] = (int32_t)(x == items - 1 ? x : (2 * x) % (items - 1));
+    for (int64_t x = 0; x < items; ++x) next[x] = (int32_t)((x % cols) * rows + x / cols);
     std::vector<char> seen(items, 0);
     for (int64_t x = 0; x < items; ++x) {
         if (seen[x]) continue;
-        int64_t len = 0;
+        int64_t clen = 0;
         for (int64_t y = x; !seen[y]; y = next[y]) {
             seen[y] = 1;
-            ++len;
+            ++clen;
         }
-        if (len > 1) starts.push_back((int32_t)x);
+        if (clen > 1) starts.push_back((int32_t)x);
     }
+    if (starts.empty()) return MFFT_OK;   // identity (a single row or column of runs)
     int32_t *dnext = (int32_t *)table_alloc(p, (size_t)items * 4);
-    int32_t *dstarts = (int32_t *)table_alloc(p, std::max<size_t>(starts.size(), 1) * 4);
+    int32_t *dstarts = (int32_t *)table_alloc(p, starts.size() * 4);
     if (!dnext || !dstarts) return fail(MFFT_ENOMEM, "permutation table allocation failed");
     hipError_t e = hipMemcpy(dnext, next.data(), (size_t)items * 4, hipMemcpyHostToDevice);
-    if (e == hipSuccess && !starts.empty())
-        e = hipMemcpy(dstarts, starts.data(), starts.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dstarts, starts.data(), starts.size() * 4, hipMemcpyHostToDevice);
     if (e != hipSuccess) return fail(MFFT_EHIP, hipGetErrorString(e));
     Pass ps;
     ps.kind = 4;
     ps.pm.elem_bytes = elem_bytes(p->prob.prec);
     ps.pm.rank = (int)V.size();
-    ps.pm.len = q;
+    ps.pm.len = len;
     ps.pm.es = s;
-    ps.pm.xs = q * s;
+    ps.pm.xs = len * s;
     ps.pm.next = dnext;
     ps.pm.starts = dstarts;
     ps.pm.ncycles = (int32_t)starts.size();
@@ -907,43 +910,47 @@ static int add_shuffle_pass(Builder &b, int buf, int64_t off, int64_t q, int64_t
     ps.src = ps.dst = buf;
     ps.src_off = ps.dst_off = off;
     ps.prec = p->prob.prec;
-    ps.bytes = 2.0 * (double)(items * q) * ps.pm.total * ps.pm.elem_bytes;
+    ps.bytes = 2.0 * (double)(items * len) * ps.pm.total * ps.pm.elem_bytes;
     std::ostringstream d;
-    d << "shuffle 2x" << q << " runs in place x" << ps.pm.total << " (" << starts.size()
-      << " cycles)";
+    d << "transpose " << rows << "x" << cols << " runs of " << len << " in place x" << ps.pm.total
+      << " (" << starts.size() << " cycles)";
     ps.desc = d.str();
     p->passes.push_back(ps);
     return MFFT_OK;
 }
 
 // In-place Cooley-Tukey step without scratch (Section 4.2's in-place plans)
-// for n = q*q: columns j (elements l*q + j, l < q) transformed in place with
-// the twiddle w_n^(j*k1) on store, then rows k1 (elements k1*q + j) in place,
-// which leaves Y[k1 + k2*q] at k1*q + k2, then an in-place q x q transpose.
-// Every pass reads a tile's elements before writing them and tiles are
-// disjoint, so no pass needs a copy of its input.
+// for n = k*q*q, viewed as m = k*q rows of r = q columns: columns j
+// (elements l*q + j, l < m) transformed in place with the twiddle
+// w_n^(j*k1) on store, then rows k1 (elements k1*q + j) in place, which
+// leaves Y[k1 + k2*m] at k1*q + k2 -- the m x q matrix whose transpose is the
+// result.  It is transposed in place as k q x q blocks (each transposed in
+// place) followed by a transpose of the k x q matrix of q-element runs
+// (permutation cycles).  Every pass reads a tile's elements before writing
+// them and tiles are disjoint, so no pass needs a copy of its input.
 static int plan_ct_square_inplace(Builder &b, Dim d, const std::vector<Dim> &V, int buf,
                                   int64_t off, bool conj_in, bool conj_out)
 {
     const int prec = b.p->prob.prec;
     const int64_t n = d.n;
     const int bt = prec ? 4 : 8;
-    // n = q*q (square), or n = 2*q*q: m = 2q rows of r = q columns
-    int64_t q = 0, m = 0;
-    for (const int64_t f : {int64_t(1), int64_t(2)}) {
+    // the smallest k with n = k*q*q, q <= 2048 and both q and k*q one pass
+    int64_t q = 0, m = 0, k = 0;
+    for (int64_t f = 1; f <= 64 && !q; ++f) {
         if (n % f) continue;
         int64_t c = (int64_t)std::llround(std::sqrt((double)(n / f)));
-        while (c * c > n / f) --c;
+        while (c > 0 && c * c > n / f) --c;
         while ((c + 1) * (c + 1) <= n / f) ++c;
-        if (c * c == n / f && c <= 2048 && leaf_fits(c, prec, bt) && leaf_fits(f * c, prec, bt)) {
+        if (c > 1 && c * c == n / f && c <= 2048 && leaf_fits(c, prec, bt) &&
+            leaf_fits(f * c, prec, bt)) {
             q = c;
             m = f * c;
-            break;
+            k = f;
         }
     }
     if (!q)
         return fail(MFFT_ENOTSUP,
-                    "in place without scratch needs n = q*q or 2*q*q with q one pass");
+                    "in place without scratch needs n = k*q*q with q and k*q one pass each");
     if (d.is != d.os) return fail(MFFT_ENOTSUP, "in place without scratch needs equal strides");
     for (const Dim &v : V)
         if (v.is != v.os) return fail(MFFT_ENOTSUP, "in place without scratch needs equal strides");
@@ -966,15 +973,61 @@ static int plan_ct_square_inplace(Builder &b, Dim d, const std::vector<Dim> &V, 
     VB.push_back({m, r * s, r * s});
     rc = plan_line(b, Dim{r, s, s}, VB, buf, buf, off, off, false, conj_out);
     if (rc) return rc;
-    if (m == q) return add_transpose_pass(b, buf, off, q, q * s, s, V);
-    // m = 2q: transpose the two q x q halves in place, then interleave their
-    // rows (row i of the result is row i of the first half, then row i of the
-    // second)
+    if (k == 1) return add_transpose_pass(b, buf, off, q, q * s, s, V);
+    // k blocks of q x q, each transposed in place: run i*q + c (c < q) then
+    // holds the results Y[c*m + i*q ...] that belong at run c*k + i
     std::vector<Dim> VT = V;
-    VT.push_back({2, q * q * s, q * q * s});
+    VT.push_back({k, q * q * s, q * q * s});
     rc = add_transpose_pass(b, buf, off, q, q * s, s, VT);
     if (rc) return rc;
-    return add_shuffle_pass(b, buf, off, q, s, V);
+    return add_run_transpose_pass(b, buf, off, k, q, q, s, V);
+}
+
+// In-place rank-0 transpose without scratch (Section 4.2, "Rank-0 plans":
+// the in-place transpose as a rank-0 problem with two vector dimensions): an
+// R x C matrix (rows of C elements of stride s) rewritten as its C x R
+// transpose, with C = k*R or R = k*C: the k square blocks transposed in
+// place, then a transpose of the matrix of runs (one shorter side each).
+// Other vector loops (is = os) repeat it.
+static int plan_rank0_transpose_inplace(Builder &b, const std::vector<Dim> &V)
+{
+    int ia = -1, ib = -1;
+    for (size_t i = 0; i < V.size(); ++i)
+        for (size_t j = 0; j < V.size(); ++j) {
+            if (i == j) continue;
+            const Dim &A = V[i], &B = V[j];   // A: rows (R), B: columns (C)
+            const int64_t st = B.is;
+            if (st > 0 && A.is == B.n * st && A.os == st && B.os == A.n * st) {
+                ia = (int)i;
+                ib = (int)j;
+            }
+        }
+    if (ia < 0) return fail(MFFT_ENOTSUP, "in place without scratch: rank-0 problem is not a transpose");
+    std::vector<Dim> outer;
+    for (size_t i = 0; i < V.size(); ++i) {
+        if ((int)i == ia || (int)i == ib) continue;
+        if (V[i].is != V[i].os) return fail(MFFT_ENOTSUP, "in place without scratch: other loops move");
+        outer.push_back(V[i]);
+    }
+    const int64_t R = V[ia].n, C = V[ib].n, st = V[ib].is;
+    const int64_t q = std::min(R, C), k = std::max(R, C) / q;
+    if (std::max(R, C) % q) return fail(MFFT_ENOTSUP, "in place without scratch: sides not multiples");
+    if (q > 2048) return fail(MFFT_ENOTSUP, "in place without scratch: shorter side above 2048");
+    std::vector<Dim> VT = outer;
+    if (C >= R) {
+        // blocks side by side: block i at columns i*q.. of every row
+        if (k > 1) VT.push_back({k, q * st, q * st});
+        int rc = add_transpose_pass(b, BUF_IN, 0, q, C * st, st, VT);
+        if (rc || k == 1) return rc;
+        // run a*k + i (row a, block i) holds output row i*q + a
+        return add_run_transpose_pass(b, BUF_IN, 0, R, k, q, st, outer);
+    }
+    // blocks stacked: block i = rows i*q.. (contiguous)
+    VT.push_back({k, q * C * st, q * C * st});
+    int rc = add_transpose_pass(b, BUF_IN, 0, q, C * st, st, VT);
+    if (rc) return rc;
+    // run i*q + c (block i, row c) holds part i of output row c
+    return add_run_transpose_pass(b, BUF_IN, 0, k, q, q, st, outer);
 }
 
 static int plan_ct(Builder &b, Dim d, const std::vector<Dim> &V, int src, int dst,
@@ -1966,6 +2019,12 @@ int build_plan(PlanImpl *p)
     if (N.empty()) {
         if (pr.inplace && same_layout) return MFFT_OK;   // copy onto itself
         std::vector<Dim> all = V;
+        if (pr.inplace && (p->flags & MFFT_NO_SCRATCH)) {
+            int rc = plan_rank0_transpose_inplace(b, V);
+            if (rc) return rc;
+            p->scratch_bytes = 0;
+            return MFFT_OK;
+        }
         if (pr.inplace) {
             const int64_t off = b.scratch_take(pr.howmany * eb) / eb;
             int rc = add_copy_pass(b, packed(all, 1, 1), BUF_IN, BUF_SCRATCH, 0, off, "snapshot");

@@ -1,8 +1,9 @@
 """GPU tests of in-place plans without scratch (MFFT_NO_SCRATCH; Section
-4.2's in-place plans): n = q*q as columns with the twiddle, rows, and an
-in-place q x q transpose (n = 2*q*q: also an in-place shuffle of rows), all
-in the caller's buffer, against the FP64 oracle; problems without such a plan
-are refused."""
+4.2's in-place plans): n = k*q*q as columns with the twiddle, rows, in-place
+q x q transposes and (k > 1) an in-place transpose of the k x q matrix of
+q-element runs, all in the caller's buffer, against the FP64 oracle; in-place
+rank-0 transposes (Section 4.2, "Rank-0 plans") the same way; problems
+without such a plan are refused."""
 import numpy as np
 import pytest
 
@@ -44,7 +45,7 @@ def test_double_square_inplace_without_scratch(n, b, prec, sign):
     def check(info):
         assert info["scratch_bytes"] == 0, info
         assert info["n_passes"] == 4, info["desc"]
-        assert "transpose" in info["desc"] and "shuffle" in info["desc"], info["desc"]
+        assert "transpose q=" in info["desc"] and "2x" in info["desc"], info["desc"]
     hd = [(b, n, n)] if b > 1 else []
     run_case([(n, 1, 1)], hd, prec=prec, sign=sign, inplace=True, seed=n + b + 1,
              name=f"noscratch 2q^2 {n}", flags=mfft.NO_SCRATCH, check_info=check)
@@ -68,8 +69,50 @@ def test_multidim_inplace_without_scratch():
              name="noscratch 2d", flags=mfft.NO_SCRATCH, check_info=_no_scratch(4))
 
 
+# n = k*q*q for k > 2: columns of k*q points, rows of q, k blocks of q x q
+# transposed, then the k x q matrix of q-element runs transposed
+@pytest.mark.parametrize("n,b,prec,k", [(49152, 2, 0, 3), (81920, 2, 0, 5), (12288, 3, 1, 3),
+                                        (25088, 2, 0, 2), (57344, 1, 0, 14)])
+@pytest.mark.parametrize("sign", [-1, 1])
+def test_k_square_inplace_without_scratch(n, b, prec, k, sign):
+    import paper_2602_23525_amd as mfft
+
+    def check(info):
+        assert info["scratch_bytes"] == 0, info
+        assert info["n_passes"] == 4, info["desc"]
+        assert f"transpose {k}x" in info["desc"], info["desc"]
+    hd = [(b, n, n)] if b > 1 else []
+    run_case([(n, 1, 1)], hd, prec=prec, sign=sign, inplace=True, seed=n + b + 2,
+             name=f"noscratch {k}q^2 {n}", flags=mfft.NO_SCRATCH, check_info=check)
+
+
+@pytest.mark.parametrize("R,C,outer,prec", [(24, 48, 1, 0), (48, 24, 1, 0), (96, 32, 3, 0),
+                                            (32, 96, 2, 1), (64, 64, 2, 0), (7, 21, 1, 1),
+                                            (2048, 4096, 1, 0), (1000, 10, 2, 0)])
+def test_rank0_transpose_inplace_without_scratch(R, C, outer, prec):
+    """An R x C matrix (optionally several) rewritten in place as its
+    transpose, with no scratch: square blocks transposed in place, then the
+    runs of the shorter side permuted along their cycles; the result is the
+    exact transpose."""
+    import torch
+
+    import paper_2602_23525_amd as mfft
+    cdt = np.complex64 if prec == 0 else np.complex128
+    x = uniform_complex(outer * R * C, seed=R * 7 + C, dtype=cdt)
+    hd = [(R, C, 1), (C, 1, R)] + ([(outer, R * C, R * C)] if outer > 1 else [])
+    p = mfft.Plan([], hd, inplace=True, prec=prec, flags=mfft.NO_SCRATCH)
+    info = p.info()
+    assert info["scratch_bytes"] == 0, info
+    t = torch.from_numpy(x).cuda()
+    p.execute(t, t)
+    torch.cuda.synchronize()
+    want = x.reshape(outer, R, C).transpose(0, 2, 1).reshape(-1)
+    assert np.array_equal(t.cpu().numpy(), want), info["desc"]
+    p.destroy()
+
+
 @pytest.mark.parametrize("dims,hdims", [
-    ([(49152, 1, 1)], [(2, 49152, 49152)]),          # neither q*q nor 2*q*q
+    ([(30030, 1, 1)], [(2, 30030, 30030)]),          # no k*q*q form with one-pass factors
     ([(65537, 1, 1)], [(2, 65537, 65537)]),          # Rader needs a convolution buffer
     ([(64, 1, 8)], [(8, 64, 1)]),                    # in place, different strides
 ])
@@ -78,6 +121,14 @@ def test_refused_without_scratch(dims, hdims):
     with pytest.raises(mfft.MfftError) as e:
         mfft.Plan(dims, hdims, inplace=True, flags=mfft.NO_SCRATCH)
     assert e.value.code == -2   # MFFT_ENOTSUP
+
+
+def test_rank0_transpose_refused_without_scratch():
+    import paper_2602_23525_amd as mfft
+    # 24 x 40: neither side a multiple of the other
+    with pytest.raises(mfft.MfftError) as e:
+        mfft.Plan([], [(24, 40, 1), (40, 1, 24)], inplace=True, flags=mfft.NO_SCRATCH)
+    assert e.value.code == -2
 
 
 def test_out_of_place_needs_no_scratch():
