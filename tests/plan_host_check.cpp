@@ -20,6 +20,12 @@
 //     every structural candidate measure mode would time for each length
 //     (radix sequences, lines per tile, splits, Rader / Bluestein lengths),
 //     planned with that choice and checked like the estimate's plan.
+//   plan_host_check steps <n> <R.R...>
+//     plans one n-point transform with the radix sequence forced (Stockham
+//     stages in execution order) and prints its stage descriptors, then the
+//     plan as the list of DFT steps it executes, in breadth-first order (each
+//     stage over the whole transform) and grouped depth-first (consecutive
+//     steps that run under the same loop count nested in one loop).
 //   plan_host_check random <count> <seed>
 //     seeded random problems (rank 1-3 with vector loops, contiguous,
 //     transposed or reversed strides, in place or not, both precisions, some
@@ -365,6 +371,56 @@ int main(int argc, char **argv)
         std::printf("checked lengths=%d candidates=%d planned=%d violations=%d failed=%d\n", lengths,
                     cands, planned, violations, failed);
         return violations || failed ? 1 : 0;
+    }
+    if (argc >= 4 && !std::strcmp(argv[1], "steps")) {
+        const int64_t n = std::atoll(argv[2]);
+        mfft_plan_s pl;
+        PlanImpl *p = &pl.impl;
+        int64_t n2 = 0;
+        StructChoice c;
+        if (!parse_choice("n=" + std::to_string(n) + ":r=" + argv[3], &n2, &c)) return 2;
+        p->overrides[n] = c;
+        if (host_plan(p, 1, n, 1) || p->passes.size() != 1 || p->passes[0].kernel != 0) return 1;
+        const PassArgs &a = p->passes[0].a;
+        struct Step {
+            bool direct;
+            int R;
+            int64_t vec, loop;
+        };
+        std::vector<Step> steps;
+        for (int st = 0; st < a.nst; ++st) {
+            const StageDesc &sd = a.st[st];
+            std::printf("stage R=%d Ns=%d nb=%d\n", sd.R, sd.Ns, sd.nb);
+            if (st == 0) {
+                // the first stage's butterflies have no twiddle: the direct
+                // DFTs of the innermost step, vector of the next radix
+                const int64_t v = a.nst > 1 ? a.st[1].R : 1;
+                steps.push_back({true, sd.R, v, n / (sd.R * v)});
+            } else {
+                steps.push_back({false, sd.R, sd.Ns, n / ((int64_t)sd.R * sd.Ns)});
+            }
+        }
+        auto one = [](const Step &t) {
+            return std::string(t.direct ? "direct " : "twiddle ") + std::to_string(t.R) + " x" +
+                   std::to_string(t.vec);
+        };
+        std::string br, de;
+        for (size_t i = 0; i < steps.size(); ++i) {
+            br += (i ? " ; " : "") + (steps[i].loop > 1 ? "loop " + std::to_string(steps[i].loop) +
+                                                              " {" + one(steps[i]) + "}"
+                                                        : one(steps[i]));
+        }
+        for (size_t i = 0; i < steps.size();) {
+            size_t j = i;
+            while (j + 1 < steps.size() && steps[j + 1].loop == steps[i].loop) ++j;
+            std::string body;
+            for (size_t k = i; k <= j; ++k) body += (k > i ? " ; " : "") + one(steps[k]);
+            de += (i ? " ; " : "") +
+                  (steps[i].loop > 1 ? "loop " + std::to_string(steps[i].loop) + " {" + body + "}" : body);
+            i = j + 1;
+        }
+        std::printf("breadth: %s\ndepth: %s\n", br.c_str(), de.c_str());
+        return 0;
     }
     if (argc >= 4 && !std::strcmp(argv[1], "random")) {
         const int count = std::atoi(argv[2]);

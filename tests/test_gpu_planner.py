@@ -200,3 +200,23 @@ def test_measured_structure_is_stored_and_reused(n, b, prec, field):
     for p in (pm, pw, pb):
         p.destroy()
     mfft.mfft_wisdom_forget()
+
+
+def test_forced_radices_of_fig3_compute_the_dft():
+    """The Fig. 3 plan of n = 30 (DIT radices 3, 2, 5; Stockham stages 5, 2, 3)
+    given as a stored structural choice computes the DFT (FP64)."""
+    import paper_2602_23525_amd as mfft
+    n, b = 30, 7
+    x = uniform_complex(n * b, seed=30, dtype=np.complex128)
+    ref = oracle.fft(x.reshape(b, n))
+    mfft.mfft_wisdom_forget()
+    mfft.Plan([(n, 1, 1)], [(b, n, n)], prec=1, flags=mfft.MEASURE).destroy()
+    key = [k for k in _wisdom_lines() if k.startswith("line c64 n=30 ")][0]
+    mfft.mfft_wisdom_forget()
+    mfft.mfft_wisdom_import(f"mfft-wisdom 1 {mfft.mfft_version()}\n{key} => n=30:r=5.2.3\n")
+    p = mfft.Plan([(n, 1, 1)], [(b, n, n)], prec=1, flags=mfft.WISDOM_ONLY)
+    assert "rad=5x2x3" in p.info()["desc"], p.info()["desc"]
+    y = _run(p, x)
+    assert oracle.rel_rms(y.reshape(b, n), ref) <= 1e-13
+    p.destroy()
+    mfft.mfft_wisdom_forget()

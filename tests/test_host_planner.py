@@ -98,6 +98,43 @@ def test_measure_candidates_plan_and_stay_inside_their_tables(checker, prec, lo,
     assert s["violations"] == 0 and s["failed"] == 0 and s["candidates"] > s["lengths"]
 
 
+def test_fig3_plan_of_30_with_radices_3_2_5(checker):
+    """Fig. 3 (Section 4.2, "Discussion"): n = 30 planned by DIT steps of radix
+    3, then 2, then 5.  Here the steps are Stockham stages, executed innermost
+    first (radix 5, then 2, then 3); forced through the planner's structural
+    choice, the stage descriptors and the steps they execute must be the
+    figure's: the size-5 DFTs without twiddles (vector 2, loop 3), the size-2
+    twiddle step (vector 5, loop 3), the size-3 twiddle step (vector 10) --
+    the breadth-first list, and grouped under the shared loop of 3, the
+    depth-first one."""
+    r = subprocess.run([checker, "steps", "30", "5.2.3"], capture_output=True, text=True)
+    assert r.returncode == 0, r.stdout + r.stderr
+    lines = r.stdout.strip().splitlines()
+    stages = [tuple(int(v) for v in re.findall(r"=(\d+)", ln)) for ln in lines if ln.startswith("stage")]
+    assert stages == [(5, 1, 6), (2, 5, 15), (3, 10, 10)]          # (R, Ns, butterflies)
+    steps = dict(ln.split(": ", 1) for ln in lines if ": " in ln)
+
+    def parse(text):
+        # "loop L {a ; b} ; c" -> [("loop", L, [a, b]), c] with a = (kind, R, vector)
+        out = []
+        for m in re.finditer(r"loop (\d+) \{([^}]*)\}|(direct|twiddle) (\d+) x(\d+)", text):
+            if m.group(1):
+                body = [(k, int(a), int(v)) for k, a, v in
+                        re.findall(r"(direct|twiddle) (\d+) x(\d+)", m.group(2))]
+                out.append(("loop", int(m.group(1)), body))
+            else:
+                out.append((m.group(3), int(m.group(4)), int(m.group(5))))
+        return out
+
+    # the figure's two step lists (tests/golden/fig3_plan_n30.txt)
+    with open(os.path.join(HERE, "golden", "fig3_plan_n30.txt")) as fh:
+        fig = dict(ln.strip().split(": ", 1) for ln in fh if ln.strip() and not ln.startswith("#"))
+    assert parse(fig["breadth"]) == [("loop", 3, [("direct", 5, 2)]),
+                                     ("loop", 3, [("twiddle", 2, 5)]), ("twiddle", 3, 10)]
+    assert parse(steps["breadth"]) == parse(fig["breadth"])
+    assert parse(steps["depth"]) == parse(fig["depth"])
+
+
 def test_planner_under_address_and_ub_sanitizers(checker_san):
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=1",
                UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1")
