@@ -18,7 +18,8 @@ LIB = os.path.join(HERE, "libmfft.so")
 
 SOURCES = [
     "k_c32_k0.hip", "k_c32_k1.hip", "k_c32_k5.hip", "k_c32_k7.hip", "k_c64_k0.hip",
-    "k_c64_k1.hip", "k_c64_k5.hip", "k_c64_k7.hip",
+    "k_c64_k1.hip", "k_c64_k5.hip", "k_c64_k7.hip", "k_c32_k0_e24.hip", "k_c32_k1_e24.hip",
+    "k_c64_k0_e24.hip", "k_c64_k1_e24.hip",
     "k_leaf.hip", "k_leaf_batch.hip", "kernels.hip", "problem.cpp", "plan.cpp", "tune.cpp", "api.cpp", "batch.cpp", "server.cpp",
 ]
 

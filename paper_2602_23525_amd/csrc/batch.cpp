@@ -29,7 +29,7 @@ extern size_t g_lds_budget;
 // more lines per tile so few lanes idle in the class (tiles kept <= 64 KB).
 static int widen(const Pass &ps, PassArgs *a, size_t *lds)
 {
-    const int maxb = ps.prec ? 512 : 1024;
+    const int maxb = ps.prec || ps.emax > 16 ? 512 : 1024;
     int block = std::min(256, maxb);
     while (block < a->bt * a->tpt) block *= 2;
     Pass wide = ps;
@@ -123,7 +123,8 @@ int build_batch_layout(const std::vector<BatchItem> &items, BatchLayout *L)
             }
             size_t lds = 0;
             const int block = widen(ps, &a, &lds);
-            const Key key{(int)k, p->prob.prec, pass_kind(a.flags), block};
+            const Key key{(int)k, p->prob.prec,
+                          pass_kind(a.flags) + (ps.emax > 16 ? kWideKind : 0), block};
             fam[key].push_back({a, (int64_t)a.n});
             fam_lds[key] = std::max(fam_lds[key], lds);
         }

@@ -53,6 +53,9 @@ hipError_t launch_batch(const PassArgs *items_dev, const int64_t *prefix_dev,
                         const int32_t *owner_dev, int64_t total, unsigned long long *counter,
                         int prec, int kind, int block, int grid, size_t lds_bytes, hipStream_t s);
 int pass_kind(uint32_t flags);
+// Batched-launch family of the variants with 24 elements per thread (lines
+// with radices 17, 19, 23): kWideKind + pass_kind, for kinds 0 and 1.
+constexpr int kWideKind = 16;
 int batch_blocks_per_cu(int prec, int kind, int block, size_t lds);
 hipError_t launch_copy(const CopyArgs &a, hipStream_t s);
 

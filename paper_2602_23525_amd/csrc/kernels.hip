@@ -261,6 +261,10 @@ MFFT_VARIANT(c64, 0)
 MFFT_VARIANT(c64, 1)
 MFFT_VARIANT(c64, 5)
 MFFT_VARIANT(c64, 7)
+MFFT_VARIANT(c32, 0_e24)
+MFFT_VARIANT(c32, 1_e24)
+MFFT_VARIANT(c64, 0_e24)
+MFFT_VARIANT(c64, 1_e24)
 #undef MFFT_VARIANT
 
 // Kernel kind needed by a pass (bits of tile.h's K_*): 0 plain, 1 Cooley-Tukey
@@ -278,10 +282,15 @@ int pass_kind(uint32_t flags)
 
 hipError_t launch_pass(const PassArgs &a, int prec, int emax, size_t lds_bytes, hipStream_t s)
 {
-    (void)emax;
     if (a.ntiles <= 0) return hipSuccess;
     if (a.ntiles > 0x7fffffffLL - kXcds) return hipErrorInvalidValue;
     const int k = pass_kind(a.flags);
+    if (emax > 16) {
+        // radices 17, 19, 23: plain and twiddled lines only
+        if (emax > 24 || k > 1) return hipErrorInvalidValue;
+        if (prec == 0) return k ? launch_pass_c32_k1_e24(a, lds_bytes, s) : launch_pass_c32_k0_e24(a, lds_bytes, s);
+        return k ? launch_pass_c64_k1_e24(a, lds_bytes, s) : launch_pass_c64_k0_e24(a, lds_bytes, s);
+    }
     if (prec == 0) {
         if (k == 0) return launch_pass_c32_k0(a, lds_bytes, s);
         if (k == 1) return launch_pass_c32_k1(a, lds_bytes, s);
@@ -296,6 +305,13 @@ hipError_t launch_pass(const PassArgs &a, int prec, int emax, size_t lds_bytes, 
 
 int batch_blocks_per_cu(int prec, int kind, int block, size_t lds)
 {
+    if (kind == kWideKind || kind == kWideKind + 1) {
+        if (prec == 0)
+            return kind == kWideKind ? batch_blocks_per_cu_c32_k0_e24(block, lds)
+                                     : batch_blocks_per_cu_c32_k1_e24(block, lds);
+        return kind == kWideKind ? batch_blocks_per_cu_c64_k0_e24(block, lds)
+                                 : batch_blocks_per_cu_c64_k1_e24(block, lds);
+    }
     if (prec == 0) {
         if (kind == 0) return batch_blocks_per_cu_c32_k0(block, lds);
         if (kind == 1) return batch_blocks_per_cu_c32_k1(block, lds);
@@ -313,6 +329,13 @@ hipError_t launch_batch(const PassArgs *items_dev, const int64_t *prefix_dev,
                         int prec, int kind, int block, int grid, size_t lds_bytes, hipStream_t s)
 {
 #define MFFT_BATCH_ARGS items_dev, prefix_dev, owner_dev, total, counter, block, grid, lds_bytes, s
+    if (kind == kWideKind || kind == kWideKind + 1) {
+        if (prec == 0)
+            return kind == kWideKind ? launch_batch_c32_k0_e24(MFFT_BATCH_ARGS)
+                                     : launch_batch_c32_k1_e24(MFFT_BATCH_ARGS);
+        return kind == kWideKind ? launch_batch_c64_k0_e24(MFFT_BATCH_ARGS)
+                                 : launch_batch_c64_k1_e24(MFFT_BATCH_ARGS);
+    }
     if (prec == 0) {
         if (kind == 0) return launch_batch_c32_k0(MFFT_BATCH_ARGS);
         if (kind == 1) return launch_batch_c32_k1(MFFT_BATCH_ARGS);

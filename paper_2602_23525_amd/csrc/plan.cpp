@@ -40,7 +40,8 @@ int g_num_cus = 256;           // compute units of the device
 
 static int elem_bytes(int prec) { return prec ? 16 : 8; }
 // workgroup size limit of the generic kernels (launch bounds in tile.h)
-static int max_threads(int prec) { return prec ? 512 : 1024; }
+// (512 also for FP32 lines with 24 elements per thread: radices 17, 19, 23)
+static int max_threads(int prec, int emax = 16) { return prec || emax > 16 ? 512 : 1024; }
 
 // ------------------------------------------------------------ memory
 
@@ -94,16 +95,21 @@ static int stage_threads(int64_t n, int R, int emax)
     return (int)((n / R + nbmax - 1) / nbmax);
 }
 
+// Elements per thread of a generic leaf of length n: 16, or 24 for lengths
+// that need a radix 17, 19 or 23 (the kernel variant that holds them).
+static int leaf_emax(int64_t n) { return is_smooth(n) ? 16 : 24; }
+
 // Radix sequence of a leaf of length n (smooth): the fewest stages over the
 // radices the tile kernel compiles whose thread need fits max_tpt (each stage
 // is one LDS exchange); among those, the smallest thread count, then larger
-// radices first.  A dynamic program over the exponents of 2, 3, 5, 7, 11, 13.
+// radices first.  A dynamic program over the exponents of 2, 3, ..., 23
+// (radices above 16 only with 24 elements per thread).
 static bool radices_for(int64_t n, int emax, int max_tpt, std::vector<int> *r)
 {
-    if (n < 2 || !is_smooth(n)) return false;
-    constexpr int NP = 6;
-    static const int kRad[] = {16, 15, 14, 13, 12, 11, 10, 9, 8, 7, 6, 5, 4, 3, 2};
-    static const int kPrime[NP] = {2, 3, 5, 7, 11, 13};
+    if (n < 2 || !(emax >= 24 ? is_smooth23(n) : is_smooth(n))) return false;
+    constexpr int NP = 9;
+    static const int kRad[] = {23, 19, 17, 16, 15, 14, 13, 12, 11, 10, 9, 8, 7, 6, 5, 4, 3, 2};
+    static const int kPrime[NP] = {2, 3, 5, 7, 11, 13, 17, 19, 23};
     using Ex = std::array<int, NP>;
     auto expo = [](int64_t v) {
         Ex e{};
@@ -208,7 +214,9 @@ static bool leaf_shape_from(int64_t n, int emax, int max_tpt, const std::vector<
     if (n < 2 || n > (1 << 20) || rad.empty() || (int)rad.size() > kMaxStages) return false;
     int64_t prod = 1;
     for (int R : rad) {
-        if (R < 2 || R > 16) return false;   // every radix 2..16 is compiled
+        // radices 2..16 are compiled, and 17, 19, 23 with 24 elements per thread
+        if (R < 2 || R > 23 || (R > 16 && (emax < 24 || (R != 17 && R != 19 && R != 23))))
+            return false;
         if (stage_threads(n, R, emax) > max_tpt) return false;
         prod *= R;
     }
@@ -230,8 +238,9 @@ static bool leaf_shape_from(int64_t n, int emax, int max_tpt, const std::vector<
 static bool leaf_fits(int64_t n, int prec, int bt)
 {
     Leaf L;
-    if (!make_leaf_shape(n, 16, max_threads(prec) / bt, &L)) return false;
-    return tile_lds_bytes((int)n, bt, prec) <= g_lds_budget && bt * L.tpt <= max_threads(prec);
+    const int mt = max_threads(prec, leaf_emax(n));
+    if (!make_leaf_shape(n, leaf_emax(n), mt / bt, &L)) return false;
+    return tile_lds_bytes((int)n, bt, prec) <= g_lds_budget && bt * L.tpt <= mt;
 }
 
 // Stage twiddle table for a leaf: stage s holds w_(Ns*R)^(j*k) for j < Ns,
@@ -422,7 +431,7 @@ static bool leaf_col_fits(const LineSpec &ls, const PassArgs &a, const Dim &in_d
 // 200 of 256 threads for 1000-point lines.)
 int row_lines_per_tile(int n, int tpt, int prec, int64_t lines)
 {
-    const int mt = max_threads(prec);
+    const int mt = max_threads(prec, leaf_emax(n));
     int best = 1;
     double best_fill = -1;
     for (int cls = 256; cls <= mt; cls *= 2) {
@@ -504,14 +513,17 @@ static int add_line_pass(Builder &b, const LineSpec &ls)
     // 256-thread workgroups.  Both bounded by the LDS budget.
     const bool col = a.load_mode == kModeCol || a.store_mode == kModeCol;
     const int bt_floor = col ? (prec ? 4 : 8) : 1;
-    const int mt = max_threads(prec);
+    const int emax = leaf_emax(n);
+    const int mt = max_threads(prec, emax);
     Leaf L;
-    if (!make_leaf_shape(n, 16, mt / bt_floor, &L) && !make_leaf_shape(n, 16, mt, &L))
+    if (emax > 16 && (ls.flags & ~(PF_CONJ_IN | PF_CONJ_OUT | PF_TW4 | PF_XCD)))
+        return fail(MFFT_ENOTSUP, "radices above 16 only in plain or twiddled lines");
+    if (!make_leaf_shape(n, emax, mt / bt_floor, &L) && !make_leaf_shape(n, emax, mt, &L))
         return fail(MFFT_ENOTSUP, "no leaf shape for n");
     if (ch && !ch->rad.empty()) {
         // a measured radix sequence (if it fits this pass's thread budget)
         Leaf Lc;
-        if (leaf_shape_from(n, 16, mt / bt_floor, ch->rad, &Lc)) L = Lc;
+        if (leaf_shape_from(n, emax, mt / bt_floor, ch->rad, &Lc)) L = Lc;
     }
     ps.emax = L.emax;
     int rc = fill_leaf(p, L, &a, &b.twcache);
@@ -1344,7 +1356,13 @@ static int plan_line(Builder &b, Dim d, std::vector<Dim> V, int src, int dst, in
 {
     const int prec = b.p->prob.prec;
     const int64_t n = d.n;
-    if (is_smooth(n)) {
+    // lengths with radices 17, 19, 23 take the plain Cooley-Tukey path too when
+    // they fit a leaf or split into two leaves (else the paths for large
+    // prime factors below)
+    Split wsp;
+    const bool wide_ok = !is_smooth(n) && is_smooth23(n) &&
+                         (leaf_fits(n, prec, 1) || split_for(b.p, n, prec, &wsp));
+    if (is_smooth(n) || wide_ok) {
         const bool strided = std::llabs(d.is) != 1 || std::llabs(d.os) != 1;
         if (leaf_fits(n, prec, strided ? (prec ? 4 : 8) : 1) || leaf_fits(n, prec, 1)) {
             const bool inplace = src == dst && src_off == dst_off;
@@ -1498,8 +1516,9 @@ static int bluestein_tables(Builder &b, int64_t n, int64_t M, void **chirp, void
 // smallest-first order of the two best.
 static std::vector<std::vector<int>> radix_candidates(int64_t n, int prec, size_t limit)
 {
-    static const int kRad[] = {16, 15, 14, 13, 12, 11, 10, 9, 8, 7, 6, 5, 4, 3, 2};
-    const int mt = max_threads(prec);
+    static const int kRad[] = {23, 19, 17, 16, 15, 14, 13, 12, 11, 10, 9, 8, 7, 6, 5, 4, 3, 2};
+    const int emax = leaf_emax(n);
+    const int mt = max_threads(prec, emax);
     std::vector<std::vector<int>> all;
     std::vector<int> cur;
     std::function<void(int64_t, int)> rec = [&](int64_t rest, int from) {
@@ -1508,9 +1527,9 @@ static std::vector<std::vector<int>> radix_candidates(int64_t n, int prec, size_
             if (!cur.empty()) all.push_back(cur);
             return;
         }
-        for (int i = from; i < 15; ++i) {
+        for (int i = from; i < 18; ++i) {
             const int R = kRad[i];
-            if (rest % R || stage_threads(n, R, 16) > mt) continue;
+            if (rest % R || stage_threads(n, R, emax) > mt) continue;
             cur.push_back(R);
             rec(rest / R, i);
             cur.pop_back();
@@ -1522,7 +1541,7 @@ static std::vector<std::vector<int>> radix_candidates(int64_t n, int prec, size_
     for (auto &r : all) fewest = std::min(fewest, r.size());
     auto need = [&](const std::vector<int> &r) {
         int t = 0;
-        for (int R : r) t = std::max(t, stage_threads(n, R, 16));
+        for (int R : r) t = std::max(t, stage_threads(n, R, emax));
         return t;
     };
     std::vector<std::vector<int>> keep;
@@ -1534,7 +1553,7 @@ static std::vector<std::vector<int>> radix_candidates(int64_t n, int prec, size_
     });
     std::vector<std::vector<int>> out;
     std::vector<int> est;
-    if (radices_for(n, 16, mt, &est)) out.push_back(est);
+    if (radices_for(n, emax, mt, &est)) out.push_back(est);
     for (auto &r : keep) {
         if (out.size() >= limit) break;
         if (std::find(out.begin(), out.end(), r) == out.end()) out.push_back(r);
@@ -1555,7 +1574,7 @@ static StructChoice estimate_choice(const PlanImpl *p, int64_t n)
     StructChoice c;
     if (n < 2) return c;
     if (smallest_prime_factor(n) == n) {
-        if (n <= 13) return c;
+        if (n <= 23) return c;   // a radix: one butterfly
         double blue = HUGE_VAL;
         const int64_t M = bluestein_length(n, prec, &blue);
         if (is_smooth(n - 1) && (n <= 256 || conv_cost(n - 1, prec, true) <= blue)) {
@@ -1566,11 +1585,11 @@ static StructChoice estimate_choice(const PlanImpl *p, int64_t n)
         }
         return c;
     }
-    if (!is_smooth(n)) return c;
+    if (!is_smooth23(n)) return c;
     if (leaf_fits(n, prec, 1)) {
         if (leaf_supported(prec, n)) return c;
         Leaf L;
-        if (make_leaf_shape(n, 16, max_threads(prec), &L)) {
+        if (make_leaf_shape(n, leaf_emax(n), max_threads(prec, leaf_emax(n)), &L)) {
             c.rad = L.rad;
             c.bt = row_lines_per_tile(L.n, L.tpt, prec, 0);
         }
@@ -1588,7 +1607,7 @@ std::vector<StructChoice> structure_candidates(const PlanImpl *p, int64_t n)
     out.push_back(estimate_choice(p, n));   // the estimate's, first
     if (n < 2) return out;
     if (smallest_prime_factor(n) == n) {
-        if (n <= 13) return out;   // a radix: one butterfly
+        if (n <= 23) return out;   // a radix: one butterfly
         if (is_smooth(n - 1)) {
             StructChoice c;
             c.prime = 1;
@@ -1620,7 +1639,7 @@ std::vector<StructChoice> structure_candidates(const PlanImpl *p, int64_t n)
         }
         return out;
     }
-    if (!is_smooth(n)) return out;
+    if (!is_smooth23(n)) return out;
     if (leaf_fits(n, prec, 1)) {
         // one pass; powers of two run in the specialized leaf kernel (fixed
         // radices), the rest in the generic kernel
@@ -1635,10 +1654,11 @@ std::vector<StructChoice> structure_candidates(const PlanImpl *p, int64_t n)
             }
             // the estimate's radices (first) with other line counts per tile
             Leaf L;
-            if (!leaf_shape_from(n, 16, max_threads(prec), c.rad, &L)) continue;
+            const int mt = max_threads(prec, leaf_emax(n));
+            if (!leaf_shape_from(n, leaf_emax(n), mt, c.rad, &L)) continue;
             const int bt = row_lines_per_tile(L.n, L.tpt, prec, 0);
             for (int b2 : {bt / 2, bt * 2}) {
-                if (b2 < 1 || b2 == bt || b2 * L.tpt > max_threads(prec) ||
+                if (b2 < 1 || b2 == bt || b2 * L.tpt > mt ||
                     tile_lds_bytes(L.n, b2, prec) > g_lds_budget)
                     continue;
                 StructChoice cb = c;
@@ -1702,7 +1722,7 @@ bool parse_choice(const std::string &text, int64_t *n, StructChoice *c)
             while (std::getline(rs, r, '.')) {
                 char *rend = nullptr;
                 const long R = std::strtol(r.c_str(), &rend, 10);
-                if (*rend || R < 2 || R > 16) return false;
+                if (*rend || R < 2 || R > 23) return false;
                 c->rad.push_back((int)R);
             }
             break;

@@ -180,6 +180,7 @@ int plan_internal(mfft_plan *out, int rank, const mfft_iodim *dims, int howmany_
 
 int64_t smallest_prime_factor(int64_t n);
 bool is_smooth(int64_t n);
+bool is_smooth23(int64_t n);
 int64_t primitive_root(int64_t p);
 void div_magic(uint32_t d, uint32_t *magic, int *shift);
 

@@ -275,6 +275,16 @@ bool is_smooth(int64_t n)
     return n == 1;
 }
 
+// Lengths the leaves with 24 elements per thread also factor: prime factors
+// up to 23 (radices 17, 19, 23 besides those of is_smooth).
+bool is_smooth23(int64_t n)
+{
+    if (n < 1) return false;
+    for (int64_t f : {2, 3, 5, 7, 11, 13, 17, 19, 23})
+        while (n % f == 0) n /= f;
+    return n == 1;
+}
+
 static int64_t powmod(int64_t b, int64_t e, int64_t m)
 {
     int64_t r = 1 % m;

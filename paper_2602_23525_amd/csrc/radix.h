@@ -1,7 +1,8 @@
 // Butterflies of the generic tile kernel: the radices of butterfly.h, the
 // composites 6, 9, 10, 12, 14 and 15, each one step of eq. ct with constant
 // twiddles (fewer LDS exchanges for sizes with factors 3, 5 and 7), and the
-// primes 11 and 13 by the definition with paired terms.
+// primes 11, 13, 17, 19 and 23 by the definition with paired terms (17 to 23
+// only in the kernel variant that holds 24 elements per thread).
 #pragma once
 #include <utility>
 
@@ -147,7 +148,7 @@ __device__ __forceinline__ void dftx(cpx<T> *v)
     else if constexpr (R == 12) dft_ab<T, 4, 3>(v);
     else if constexpr (R == 14) dft_ab<T, 7, 2>(v);
     else if constexpr (R == 15) dft_ab<T, 5, 3>(v);
-    else if constexpr (R == 11 || R == 13) dft_odd_prime<T, R>(v);
+    else if constexpr (R == 11 || R == 13 || R == 17 || R == 19 || R == 23) dft_odd_prime<T, R>(v);
     else dft<T, R>(v);
 }
 

@@ -392,6 +392,16 @@ __device__ __forceinline__ void run_fft(const PassArgs &a, Tile<T> &tl, int firs
         case 15: stage<T, 15, EMAX, KIND>(a, sd, tl, fetch, emit); break;
         case 11: stage<T, 11, EMAX, KIND>(a, sd, tl, fetch, emit); break;
         case 13: stage<T, 13, EMAX, KIND>(a, sd, tl, fetch, emit); break;
+        // primes above 16: only the variant with 24 elements per thread
+        case 17:
+            if constexpr (EMAX >= 17) stage<T, 17, EMAX, KIND>(a, sd, tl, fetch, emit);
+            break;
+        case 19:
+            if constexpr (EMAX >= 19) stage<T, 19, EMAX, KIND>(a, sd, tl, fetch, emit);
+            break;
+        case 23:
+            if constexpr (EMAX >= 23) stage<T, 23, EMAX, KIND>(a, sd, tl, fetch, emit);
+            break;
         default: stage<T, 16, EMAX, KIND>(a, sd, tl, fetch, emit); break;
         }
     }
@@ -576,13 +586,14 @@ __device__ __forceinline__ void run_tile(const PassArgs &a, int64_t tile, cpx<T>
     tile_body<T, EMAX, KIND>(a, tl, lds);
 }
 
-// Largest workgroup of the generic kernels: FP64 lines keep 512 threads so the
-// compiler may use up to 256 VGPRs without spilling.
+// Largest workgroup of the generic kernels: FP64 lines, and FP32 lines with 24
+// elements per thread, keep 512 threads so the compiler may use up to 256
+// VGPRs without spilling.
 template <typename T>
-constexpr int max_block() { return sizeof(T) == 8 ? 512 : 1024; }
+constexpr int max_block(int emax) { return sizeof(T) == 8 || emax > 16 ? 512 : 1024; }
 
 template <typename T, int EMAX, int KIND>
-__global__ __launch_bounds__(max_block<T>()) void pass_kernel(PassArgs a)
+__global__ __launch_bounds__(max_block<T>(EMAX)) void pass_kernel(PassArgs a)
 {
     extern __shared__ unsigned char smem[];
     cpx<T> *lds = (cpx<T> *)smem;
@@ -604,7 +615,7 @@ __global__ __launch_bounds__(max_block<T>()) void pass_kernel(PassArgs a)
 // the list is exhausted.  items[i] covers tiles [prefix[i], prefix[i+1]);
 // owner[t] is the item of tile t, total the number of tiles.
 template <typename T, int EMAX, int KIND>
-__global__ __launch_bounds__(max_block<T>()) void batch_kernel(const PassArgs *__restrict__ items,
+__global__ __launch_bounds__(max_block<T>(EMAX)) void batch_kernel(const PassArgs *__restrict__ items,
                                                      const int64_t *__restrict__ prefix,
                                                      const int32_t *__restrict__ owner,
                                                      int64_t total, unsigned long long *counter)

@@ -1,7 +1,9 @@
-// Launchers of one variant (element type, kernel kind) of the generic tile
-// kernel: the single-pass launch, the persistent batched launch and its
-// occupancy query.  Each variant is instantiated by a translation unit of its
-// own (k_c{32,64}_k{0,1,5,7}.hip) so that the variants compile in parallel.
+// Launchers of one variant (element type, kernel kind, elements per thread)
+// of the generic tile kernel: the single-pass launch, the persistent batched
+// launch and its occupancy query.  Each variant is instantiated by a
+// translation unit of its own (k_c{32,64}_k{0,1,5,7}.hip, and
+// k_c{32,64}_k{0,1}_e24.hip for lines with radices 17, 19, 23) so that the
+// variants compile in parallel.
 #pragma once
 #include <mutex>
 
@@ -21,7 +23,7 @@ inline hipError_t allow_dynamic_lds(const void *fn, size_t lds, size_t *granted,
     return e;
 }
 
-template <typename T, int KIND>
+template <typename T, int KIND, int EMAX = 16>
 struct TileLaunch {
     static std::mutex &mu()
     {
@@ -32,10 +34,10 @@ struct TileLaunch {
     static hipError_t pass(const PassArgs &a, size_t lds, hipStream_t s)
     {
         static size_t granted = 65536;
-        hipError_t e = allow_dynamic_lds((const void *)pass_kernel<T, 16, KIND>, lds, &granted, &mu());
+        hipError_t e = allow_dynamic_lds((const void *)pass_kernel<T, EMAX, KIND>, lds, &granted, &mu());
         if (e != hipSuccess) return e;
         const int64_t grid = (a.flags & PF_XCD) ? (a.ntiles + kXcds - 1) / kXcds * kXcds : a.ntiles;
-        hipLaunchKernelGGL((pass_kernel<T, 16, KIND>), dim3((unsigned)grid), dim3(a.bt * a.tpt), lds,
+        hipLaunchKernelGGL((pass_kernel<T, EMAX, KIND>), dim3((unsigned)grid), dim3(a.bt * a.tpt), lds,
                            s, a);
         return hipGetLastError();
     }
@@ -45,9 +47,9 @@ struct TileLaunch {
                             size_t lds, hipStream_t s)
     {
         static size_t granted = 65536;
-        hipError_t e = allow_dynamic_lds((const void *)batch_kernel<T, 16, KIND>, lds, &granted, &mu());
+        hipError_t e = allow_dynamic_lds((const void *)batch_kernel<T, EMAX, KIND>, lds, &granted, &mu());
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((batch_kernel<T, 16, KIND>), dim3(grid), dim3(block), lds, s, items,
+        hipLaunchKernelGGL((batch_kernel<T, EMAX, KIND>), dim3(grid), dim3(block), lds, s, items,
                            prefix, owner, total, counter);
         return hipGetLastError();
     }
@@ -55,7 +57,7 @@ struct TileLaunch {
     static int blocks_per_cu(int block, size_t lds)
     {
         int b = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, batch_kernel<T, 16, KIND>, block, lds) !=
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, batch_kernel<T, EMAX, KIND>, block, lds) !=
             hipSuccess) {
             (void)hipGetLastError();
             return 1;
@@ -67,22 +69,23 @@ struct TileLaunch {
 }  // namespace mfft
 
 // The three entry points of variant NAME (kernels.hip dispatches to them).
-#define MFFT_TILE_LAUNCHERS(T, NAME, KIND)                                                        \
+#define MFFT_TILE_LAUNCHERS(T, NAME, KIND) MFFT_TILE_LAUNCHERS_E(T, NAME, KIND, 16)
+#define MFFT_TILE_LAUNCHERS_E(T, NAME, KIND, EMAX)                                                \
     namespace mfft {                                                                              \
     hipError_t launch_pass_##NAME(const PassArgs &a, size_t lds, hipStream_t s)                   \
     {                                                                                             \
-        return TileLaunch<T, KIND>::pass(a, lds, s);                                              \
+        return TileLaunch<T, KIND, EMAX>::pass(a, lds, s);                                              \
     }                                                                                             \
     hipError_t launch_batch_##NAME(const PassArgs *items, const int64_t *prefix,                  \
                                    const int32_t *owner, int64_t total,                           \
                                    unsigned long long *counter, int block, int grid, size_t lds,  \
                                    hipStream_t s)                                                 \
     {                                                                                             \
-        return TileLaunch<T, KIND>::batch(items, prefix, owner, total, counter, block, grid, lds, \
+        return TileLaunch<T, KIND, EMAX>::batch(items, prefix, owner, total, counter, block, grid, lds, \
                                           s);                                                     \
     }                                                                                             \
     int batch_blocks_per_cu_##NAME(int block, size_t lds)                                         \
     {                                                                                             \
-        return TileLaunch<T, KIND>::blocks_per_cu(block, lds);                                    \
+        return TileLaunch<T, KIND, EMAX>::blocks_per_cu(block, lds);                                    \
     }                                                                                             \
     }

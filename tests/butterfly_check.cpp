@@ -41,7 +41,8 @@ int main()
 {
     const double w[] = {check<2>(), check<3>(), check<4>(),  check<5>(),  check<6>(),
                         check<7>(), check<8>(), check<9>(),  check<10>(), check<12>(),
-                        check<14>(), check<15>(), check<16>(), check<11>(), check<13>()};
+                        check<14>(), check<15>(), check<16>(), check<11>(), check<13>(),
+                        check<17>(), check<19>(), check<23>()};
     double m = 0;
     for (double e : w) m = std::fmax(m, e);
     return m < 1e-14 ? 0 : 1;

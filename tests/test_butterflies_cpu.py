@@ -1,6 +1,6 @@
 """The register butterflies of the tile kernel (radices 2-16, including the
 composites built by one eq. ct step with compile-time twiddles, and the primes
-11 and 13), compiled for the host with g++ and checked against the DFT
+11, 13, 17, 19 and 23), compiled for the host with g++ and checked against the DFT
 definition."""
 import os
 import shutil
@@ -20,4 +20,4 @@ def test_every_radix_matches_the_definition(tmp_path):
     out = subprocess.run([str(exe)], capture_output=True, text=True)
     print(out.stdout)
     assert out.returncode == 0, out.stdout
-    assert out.stdout.count("radix") == 15
+    assert out.stdout.count("radix") == 18

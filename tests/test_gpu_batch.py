@@ -19,7 +19,9 @@ def _items():
                              (16384, 2, 0, -1), (65536, 1, 0, 1), (97, 7, 0, -1),
                              (1009, 3, 1, 1), (65537, 1, 0, -1), (65521, 1, 0, -1),
                              (8191, 2, 1, -1), (256, 31, 1, 1), (14175, 2, 0, -1),
-                             (12, 50, 0, -1), (3125, 3, 0, 1)]:
+                             (12, 50, 0, -1), (3125, 3, 0, 1),
+                             # radices 17, 19, 23 (24 elements per thread), FP32 and FP64
+                             (1088, 5, 0, -1), (7429, 2, 1, 1), (69632, 1, 0, -1)]:
         out.append(([(n, 1, 1)], [(b, n, n)] if b > 1 else [], prec, sign, False))
     out.append(([(24, 40, 40), (40, 1, 1)], [], 0, -1, True))            # 2-D in place
     out.append(([(32, 1, 32), (32, 32, 1)], [], 1, -1, False))            # transposed out

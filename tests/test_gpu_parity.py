@@ -38,6 +38,34 @@ def test_leaf_sizes(n, prec):
     run_case([(n, 1, 1)], [(b, n, n)], sign=-1, prec=prec, seed=n, name=f"leaf {n}")
 
 
+def _has_wide_radix(info):
+    import re
+    rads = re.findall(r"rad=([0-9x]+)", info["desc"])
+    assert any(int(r) in (17, 19, 23) for rs in rads for r in rs.split("x")), info["desc"]
+
+
+# radices 17, 19, 23 (the butterflies by paired terms, in the kernel variant
+# with 24 elements per thread): one-pass leaves, and two-pass Cooley-Tukey
+# lengths whose factors need them
+@pytest.mark.parametrize("n", [17, 19, 23, 34, 51, 289, 361, 529, 1088, 2432, 5888, 7429,
+                               4 * 17 * 19, 69632, 12167])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_radices_17_19_23(n, prec):
+    b = max(1, min(19, 40000 // n))
+    run_case([(n, 1, 1)], [(b, n, n)], sign=-1, prec=prec, seed=n + 5, name=f"wide {n}",
+             check_info=_has_wide_radix)
+    run_case([(n, 1, 1)], [(b, n, n)], sign=1, prec=prec, seed=n + 6, name=f"wide {n} inv")
+
+
+def test_wide_radices_strided_and_in_place():
+    # columns of a row-major 289 x 96 array (column tiles), a 2-D 19 x 23
+    # transform in place, and a 1088-point batch in place
+    run_case([(289, 96, 96)], [(96, 1, 1)], seed=71, name="wide columns", check_info=_has_wide_radix)
+    run_case([(19, 23, 23), (23, 1, 1)], [(5, 437, 437)], inplace=True, prec=1, seed=72,
+             name="wide 2d in place")
+    run_case([(1088, 1, 1)], [(7, 1088, 1088)], inplace=True, seed=73, name="wide in place")
+
+
 @pytest.mark.parametrize("n", [8192, 14175, 16384, 65536, 100000])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_cooley_tukey_two_pass(n, prec):
@@ -50,10 +78,10 @@ def test_cooley_tukey_two_pass(n, prec):
                                23, 53, 79, 157, 859])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_rader_single_kernel(n, prec):
-    # 11 and 13 are radices (one butterfly); up to 257 points Rader in one
-    # tile; above, Bluestein over a power of two in one leaf-kernel tile is
-    # cheaper (same results)
-    algo = None if n <= 13 else ("rader n=" if n <= 257 else "bluestein n=")
+    # 11, 13, 17, 19, 23 are radices (one butterfly); up to 257 points Rader
+    # in one tile; above, Bluestein over a power of two in one leaf-kernel
+    # tile is cheaper (same results)
+    algo = None if n <= 23 else ("rader n=" if n <= 257 else "bluestein n=")
     run_case([(n, 1, 1)], [(5, n, n)], sign=-1, prec=prec, seed=n, name=f"rader {n}",
              expect=algo)
     run_case([(n, 1, 1)], [(5, n, n)], sign=1, prec=prec, seed=n + 1, name=f"rader {n} inv")
@@ -101,14 +129,14 @@ def test_bluestein_length_choice(n, algo):
 
 
 @pytest.mark.parametrize("n,prec,inplace,algo", [
-    (17 * 4096, 0, False, "bluestein n=128"), (31 * 1024, 0, True, "rader n=30"),
-    (1009 * 16, 0, False, "bluestein n=2048"), (17 * 1024, 1, False, "rader n=16"),
-    (23 * 2048, 1, True, "rader n=22"),
+    (37 * 4096, 0, False, "bluestein n=256"), (31 * 1024, 0, True, "rader n=30"),
+    (1009 * 16, 0, False, "bluestein n=2048"), (41 * 2048, 1, False, "rader n=40"),
+    (43 * 1024, 1, True, "rader n=42"), (47 * 2048, 0, False, "bluestein n=128"),
     (4099 * 8, 0, False, "bluesteinA")])   # second pass too long: Bluestein over n
 def test_composite_with_one_large_prime(n, prec, inplace, algo):
-    # one prime factor above 13: a Cooley-Tukey step whose second pass is a
-    # one-tile prime-size plan (Rader, or Bluestein for 2*17), not Bluestein
-    # over the whole length
+    # one prime factor above 23: a Cooley-Tukey step whose second pass is a
+    # one-tile prime-size plan (Rader, or Bluestein for 2*37 and 47), not
+    # Bluestein over the whole length
     run_case([(n, 1, 1)], [(2, n, n)], prec=prec, inplace=inplace, seed=n, name=f"ct+prime {n}",
              expect=algo)
     run_case([(n, 1, 1)], [(2, n, n)], prec=prec, inplace=inplace, sign=1, seed=n + 1,
