@@ -70,7 +70,10 @@ struct StageDesc {
 struct PassArgs {
     const void *in;
     void *out;
-    const void *tw;       // stage twiddles, element type of the pass
+    const void *tw;       // stage twiddles, element type of the pass (generic
+                          // kernel layout, offsets in st[].tw_off)
+    const void *tw_leaf;  // the same twiddles in the specialized leaf kernel's
+                          // layout (passes planned for that kernel)
     const void *tw4_hi;   // two-level Cooley-Tukey twiddle tables (FP64 pairs)
     const void *tw4_lo;
     const void *pre;      // pre-multiply table (element type)

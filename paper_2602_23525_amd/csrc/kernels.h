@@ -89,8 +89,10 @@ struct PermuteArgs {
     int64_t n[8], s[8];
 };
 hipError_t launch_permute_items(const PermuteArgs &a, hipStream_t s);
+// Stage table of Ns*R (k-major, leaf kernel) or Ns*(R-1) (j-major, generic
+// kernel) twiddles w_(Ns*R)^(j*k).
 hipError_t launch_gen_stage_twiddles(void *out, int prec, int Ns, int R, hipStream_t s,
-                                     bool fp32_math = false);
+                                     bool fp32_math, bool jmajor);
 hipError_t launch_gen_tw4(void *hi, int64_t nhi, void *lo, int64_t nlo, int shift, int64_t N,
                           hipStream_t s);
 hipError_t launch_gen_chirp(void *c, int64_t n, hipStream_t s);

@@ -70,24 +70,42 @@ __device__ double2 root_fp64(int64_t e, int64_t N)
     return make_double2(csign * c, -(ssign * s));
 }
 
+// Entry e of a stage table: (j, k) with the twiddle w_(Ns*R)^(j*k).
+// k-major (the specialized leaf kernel): e = k*Ns + j, k < R.
+// j-major (the generic tile kernel): e = j*(R-1) + k - 1, 1 <= k < R, so that
+// a butterfly's R-1 twiddles are consecutive.
+__device__ __forceinline__ void stage_entry(int64_t e, int32_t Ns, int32_t R, bool jmajor,
+                                            int64_t *j, int64_t *k)
+{
+    if (jmajor) {
+        *j = e / (R - 1);
+        *k = e % (R - 1) + 1;
+    } else {
+        *k = e / Ns;
+        *j = e % Ns;
+    }
+}
+
 template <typename T>
-__global__ void gen_stage_twiddles(cpx<T> *out, int32_t Ns, int32_t R)
+__global__ void gen_stage_twiddles(cpx<T> *out, int32_t Ns, int32_t R, bool jmajor)
 {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (int64_t)Ns * R) return;
-    const int64_t k = e / Ns, j = e % Ns;
+    if (e >= (int64_t)Ns * (jmajor ? R - 1 : R)) return;
+    int64_t j, k;
+    stage_entry(e, Ns, R, jmajor, &j, &k);
     const double2 w = root_fp64(j * k, (int64_t)Ns * R);
     out[e] = {T(w.x), T(w.y)};
 }
 
 // Accuracy ablation: the same FP32 table with the angle 2 pi m / N and its
 // sine and cosine evaluated in FP32 (m = j*k reduced exactly in integer).
-__global__ void gen_stage_twiddles_f32(cpx<float> *out, int32_t Ns, int32_t R)
+__global__ void gen_stage_twiddles_f32(cpx<float> *out, int32_t Ns, int32_t R, bool jmajor)
 {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t N = (int64_t)Ns * R;
-    if (e >= N) return;
-    const int64_t k = e / Ns, j = e % Ns;
+    if (e >= (int64_t)Ns * (jmajor ? R - 1 : R)) return;
+    int64_t j, k;
+    stage_entry(e, Ns, R, jmajor, &j, &k);
     const int64_t m = (j * k) % N;
     const float ang = -2.0f * 3.14159265358979f * (float)m / (float)N;
     float s, c;
@@ -526,19 +544,19 @@ hipError_t launch_copy(const CopyArgs &a, hipStream_t s)
 }
 
 hipError_t launch_gen_stage_twiddles(void *out, int prec, int Ns, int R, hipStream_t s,
-                                     bool fp32_math)
+                                     bool fp32_math, bool jmajor)
 {
-    const int64_t cnt = (int64_t)Ns * R;
+    const int64_t cnt = (int64_t)Ns * (jmajor ? R - 1 : R);
     if (cnt <= 0) return hipSuccess;
     if (prec == 0 && fp32_math)
         hipLaunchKernelGGL(gen_stage_twiddles_f32, dim3(blocks_for(cnt, 256)), dim3(256), 0, s,
-                           (cpx<float> *)out, Ns, R);
+                           (cpx<float> *)out, Ns, R, jmajor);
     else if (prec == 0)
         hipLaunchKernelGGL(gen_stage_twiddles<float>, dim3(blocks_for(cnt, 256)), dim3(256), 0, s,
-                           (cpx<float> *)out, Ns, R);
+                           (cpx<float> *)out, Ns, R, jmajor);
     else
         hipLaunchKernelGGL(gen_stage_twiddles<double>, dim3(blocks_for(cnt, 256)), dim3(256), 0,
-                           s, (cpx<double> *)out, Ns, R);
+                           s, (cpx<double> *)out, Ns, R, jmajor);
     return hipGetLastError();
 }
 

@@ -232,7 +232,7 @@ __device__ __forceinline__ void leaf_body(const PassArgs &a, cpx<T> *lds, int64_
     const bool cin = (a.flags & PF_CONJ_IN) != 0, cout = (a.flags & PF_CONJ_OUT) != 0;
 
     StageChain<T, N, TPT, 1, Rs...> chain;
-    chain.load((const cpx<T> *)a.tw, 0, t);
+    chain.load((const cpx<T> *)a.tw_leaf, 0, t);
 
     // column tiles: inner index of the lane's store line (for the twiddle);
     // Bluestein modes: index of the lane's load line clamped to the vector

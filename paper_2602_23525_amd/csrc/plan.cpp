@@ -243,15 +243,55 @@ static bool leaf_fits(int64_t n, int prec, int bt)
     return tile_lds_bytes((int)n, bt, prec) <= g_lds_budget && bt * L.tpt <= mt;
 }
 
-// Stage twiddle table for a leaf: stage s holds w_(Ns*R)^(j*k) for j < Ns,
-// 0 <= k < R at [tw_off + k*Ns + j] (k-major, so that the lanes of a wave,
-// which work on consecutive j, read consecutive entries).
-static int fill_leaf(PlanImpl *p, const Leaf &L, PassArgs *a,
-                     std::map<std::string, void *> *cache)
+// Stage twiddle tables of a leaf: stage s holds w_(Ns*R)^(j*k) for j < Ns.
+// k-major: 0 <= k < R at [off_s + k*Ns + j] (the lanes of a wave, which work
+// on consecutive j, read consecutive entries); j-major: 1 <= k < R at
+// [off_s + j*(R-1) + k-1] (a butterfly's twiddles are consecutive: one address
+// and immediate offsets).  The generic tile kernel reads FP32 tables j-major
+// (measured on MI355X, FP32: 1000 x 16384 83.6 -> 80.3 us, 6561 x 4096 213 ->
+// 199 us) and FP64 tables k-major (j-major 1000 x 8192 FP64: 70.7 -> 82.9 us:
+// rows of 16-byte twiddles spread a wave's load over too many cache lines),
+// at tw + st[s].tw_off; every pass has that table, since a batch may run any
+// pass in the generic kernel.  A pass planned for the specialized leaf kernel
+// also gets the k-major table it reads, in tw_leaf.
+static int stage_table(PlanImpl *p, const Leaf &L, bool jmajor, std::map<std::string, void *> *cache,
+                       const void **out)
 {
     std::ostringstream key;
-    key << p->prob.prec << ":" << L.n;
+    key << p->prob.prec << ":" << L.n << (jmajor ? "j" : "k");
     for (int R : L.rad) key << "," << R;
+    auto it = cache->find(key.str());
+    if (it != cache->end()) {
+        *out = it->second;
+        return MFFT_OK;
+    }
+    int64_t total = 0;
+    for (int64_t s = 0, Ns = 1; s < (int64_t)L.rad.size(); Ns *= L.rad[s], ++s)
+        total += Ns * (jmajor ? L.rad[s] - 1 : L.rad[s]);
+    const size_t eb = elem_bytes(p->prob.prec);
+    void *tw = table_alloc(p, (size_t)std::max<int64_t>(total, 1) * eb);
+    if (!tw) return fail(MFFT_ENOMEM, "twiddle table allocation failed");
+    int64_t off = 0;
+    for (int64_t s = 0, Ns = 1; s < (int64_t)L.rad.size(); Ns *= L.rad[s], ++s) {
+        const int R = L.rad[s];
+        if (Ns > 1) {
+            hipError_t e = launch_gen_stage_twiddles((char *)tw + (size_t)off * eb, p->prob.prec,
+                                                     (int)Ns, R, p->stream,
+                                                     (p->flags & MFFT_FP32_TWIDDLES) != 0, jmajor);
+            if (e != hipSuccess)
+                return fail(MFFT_EHIP, std::string("twiddle kernel: ") + hipGetErrorString(e));
+        }
+        off += Ns * (jmajor ? R - 1 : R);
+    }
+    (*cache)[key.str()] = tw;
+    *out = tw;
+    return MFFT_OK;
+}
+
+static int fill_leaf(PlanImpl *p, const Leaf &L, PassArgs *a,
+                     std::map<std::string, void *> *cache, bool leaf_kernel)
+{
+    const bool jmajor = p->prob.prec == 0;   // the generic kernel's layout
     int64_t off = 0;
     int Ns = 1;
     a->n = L.n;
@@ -265,28 +305,12 @@ static int fill_leaf(PlanImpl *p, const Leaf &L, PassArgs *a,
         div_magic((uint32_t)Ns, &sd.magic, &sd.shift);
         sd.tw_off = (int32_t)off;
         sd.nb = L.n / sd.R;
-        off += (int64_t)Ns * sd.R;
+        off += (int64_t)Ns * (jmajor ? sd.R - 1 : sd.R);
         Ns *= sd.R;
     }
-    auto it = cache->find(key.str());
-    if (it != cache->end()) {
-        a->tw = it->second;
-        return MFFT_OK;
-    }
-    const size_t eb = elem_bytes(p->prob.prec);
-    void *tw = table_alloc(p, (size_t)std::max<int64_t>(off, 1) * eb);
-    if (!tw) return fail(MFFT_ENOMEM, "twiddle table allocation failed");
-    for (size_t s = 0; s < L.rad.size(); ++s) {
-        const StageDesc &sd = a->st[s];
-        if (sd.Ns == 1) continue;
-        hipError_t e = launch_gen_stage_twiddles((char *)tw + (size_t)sd.tw_off * eb, p->prob.prec,
-                                                 sd.Ns, sd.R, p->stream,
-                                                 (p->flags & MFFT_FP32_TWIDDLES) != 0);
-        if (e != hipSuccess) return fail(MFFT_EHIP, std::string("twiddle kernel: ") + hipGetErrorString(e));
-    }
-    (*cache)[key.str()] = tw;
-    a->tw = tw;
-    return MFFT_OK;
+    int rc = stage_table(p, L, jmajor, cache, &a->tw);
+    if (rc == MFFT_OK && leaf_kernel) rc = stage_table(p, L, false, cache, &a->tw_leaf);
+    return rc;
 }
 
 // ------------------------------------------------------------ pass building
@@ -526,8 +550,8 @@ static int add_line_pass(Builder &b, const LineSpec &ls)
         if (leaf_shape_from(n, emax, mt / bt_floor, ch->rad, &Lc)) L = Lc;
     }
     ps.emax = L.emax;
-    int rc = fill_leaf(p, L, &a, &b.twcache);
-    if (rc) return rc;
+    a.n = L.n;   // the stage tables are filled once the kernel is chosen
+    int rc = MFFT_OK;
     // Prefer tiles of at most 64 KB (several workgroups per CU); column tiles
     // may grow to the full LDS rather than drop below 64-byte runs.
     int bt;
@@ -614,6 +638,8 @@ static int add_line_pass(Builder &b, const LineSpec &ls)
         ps.lds_bytes = 0;
         apply_leaf_tune(&ps, {24, 0});   // the one configuration of column tiles
     }
+    rc = fill_leaf(p, L, &a, &b.twcache, ps.kernel == 1);
+    if (rc) return rc;
     ps.src = ls.src;
     ps.dst = ls.dst;
     ps.src_off = ls.src_off;
@@ -1455,7 +1481,11 @@ static int rader_tables(Builder &b, int64_t pr, int32_t **gather, int32_t **scat
     // DFT of b in FP64 with this library, then scale by 1/(p-1) and round
     mfft_plan sub = nullptr;
     mfft_iodim dim{L, 1, 1};
-    int rc = plan_internal(&sub, 1, &dim, 0, nullptr, 0, -1, MFFT_C64, p->stream);
+    // the sub-plan takes its memory where this plan does (a caller's
+    // allocator: no hipMalloc / hipFree, which can stall other threads'
+    // launches, while a server plans beside its running requests)
+    int rc = plan_internal(&sub, 1, &dim, 0, nullptr, 0, -1, MFFT_C64, p->stream, 0,
+                           p->has_alloc ? &p->alloc : nullptr);
     if (rc) return rc;
     rc = mfft_execute(sub, bseq, bhat, (void *)p->stream);
     if (rc) {
@@ -1488,7 +1518,11 @@ static int bluestein_tables(Builder &b, int64_t n, int64_t M, void **chirp, void
     if (e != hipSuccess) return fail(MFFT_EHIP, hipGetErrorString(e));
     mfft_plan sub = nullptr;
     mfft_iodim dim{M, 1, 1};
-    int rc = plan_internal(&sub, 1, &dim, 0, nullptr, 0, -1, MFFT_C64, p->stream);
+    // the sub-plan takes its memory where this plan does (a caller's
+    // allocator: no hipMalloc / hipFree, which can stall other threads'
+    // launches, while a server plans beside its running requests)
+    int rc = plan_internal(&sub, 1, &dim, 0, nullptr, 0, -1, MFFT_C64, p->stream, 0,
+                           p->has_alloc ? &p->alloc : nullptr);
     if (rc) return rc;
     rc = mfft_execute(sub, v, vhat, (void *)p->stream);
     if (rc) {

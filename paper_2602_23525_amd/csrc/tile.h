@@ -326,10 +326,23 @@ __device__ __forceinline__ void stage(const PassArgs &a, const StageDesc &sd, Ti
             const int q = fast_div(b, sd.magic, sd.shift);
             const int j = b - q * Ns;
             if (Ns > 1) {
-                // k-major table: lanes with consecutive j read consecutive entries
-                const cpx<T> *w = tw + j;
+                if constexpr (sizeof(T) == 4) {
+                    // FP32: j-major table, the butterfly's R-1 twiddles are
+                    // consecutive (one address, immediate offsets, 16-byte loads)
+                    const cpx<T> *w = tw + (uint32_t)j * (uint32_t)(R - 1);
+                    cpx<T> wk[R - 1];
 #pragma unroll
-                for (int k = 1; k < R; ++k) v[i][k] = cmul(v[i][k], w[k * Ns]);
+                    for (int k = 1; k < R; ++k) wk[k - 1] = w[k - 1];
+#pragma unroll
+                    for (int k = 1; k < R; ++k) v[i][k] = cmul(v[i][k], wk[k - 1]);
+                } else {
+                    // FP64: k-major table, lanes with consecutive j read
+                    // consecutive entries (16-byte elements: wide rows of the
+                    // j-major form spread a wave's load over too many lines)
+                    const cpx<T> *w = tw + j;
+#pragma unroll
+                    for (int k = 1; k < R; ++k) v[i][k] = cmul(v[i][k], w[k * Ns]);
+                }
             }
             dftx<T, R>(v[i]);
             const int base = q * Ns * R + j;

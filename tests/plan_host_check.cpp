@@ -49,7 +49,10 @@ hipError_t launch_pass(const PassArgs &, int, int, size_t, hipStream_t) { return
 hipError_t launch_copy(const CopyArgs &, hipStream_t) { return hipSuccess; }
 hipError_t launch_transpose_sq(const TransposeArgs &, hipStream_t) { return hipSuccess; }
 hipError_t launch_permute_items(const PermuteArgs &, hipStream_t) { return hipSuccess; }
-hipError_t launch_gen_stage_twiddles(void *, int, int, int, hipStream_t, bool) { return hipSuccess; }
+hipError_t launch_gen_stage_twiddles(void *, int, int, int, hipStream_t, bool, bool)
+{
+    return hipSuccess;
+}
 hipError_t launch_gen_tw4(void *, int64_t, void *, int64_t, int, int64_t, hipStream_t)
 {
     return hipSuccess;
@@ -195,12 +198,22 @@ struct Checker {
             need(ps, "tw4_hi", a.tw4_hi, e >> a.tw4_shift, 16, eu >> a.tw4_shift);
             need(ps, "tw4_lo", a.tw4_lo, a.tw4_mask, 16, 0);
         }
+        // stage twiddles in the generic kernel's layout (every pass has them:
+        // a batch may run any pass in that kernel): FP32 j-major, entry
+        // tw_off + j*(R-1) + k-1 (j < Ns, 1 <= k < R); FP64 k-major, entry
+        // tw_off + k*Ns + j (k < R); leaf-kernel passes also the k-major table
+        for (int s = 0; s < a.nst; ++s) {
+            const StageDesc &sd = a.st[s];
+            if (sd.Ns > 1)
+                need(ps, "stage", a.tw,
+                     sd.tw_off + (int64_t)(ps.prec ? sd.R : sd.R - 1) * sd.Ns - 1, eb, 0);
+        }
+        if (leaf) {
+            int64_t total = 0;
+            for (int s = 0; s < a.nst; ++s) total += (int64_t)a.st[s].Ns * a.st[s].R;
+            need(ps, "stage (leaf layout)", a.tw_leaf, total - 1, eb, 0);
+        }
         if (!leaf) {
-            // stage twiddles of the generic kernel: entry tw_off + j + k*Ns
-            for (int s = 0; s < a.nst; ++s) {
-                const StageDesc &sd = a.st[s];
-                if (sd.Ns > 1) need(ps, "stage", a.tw, sd.tw_off + (int64_t)sd.R * sd.Ns - 1, eb, 0);
-            }
             // per-transform Rader terms in scratch: entries 2*o, 2*o + 1
             if (a.flags & (PF_AUX_X0 | PF_AUX_A0 | PF_AUX_ADD)) {
                 int64_t outer = 1;
