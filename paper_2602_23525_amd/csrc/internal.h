@@ -64,6 +64,16 @@ struct StageDesc {
     int32_t shift;
     int32_t tw_off;  // offset of this stage's twiddles in the stage table
     int32_t nb;      // butterflies of the stage, n / R
+    // LDS layouts (generic tile kernel).  The layout a stage writes puts one
+    // spare slot after every 2^wr_shift groups of Ns*R elements (none:
+    // wr_shift 31), so element q*Ns*R + j + k*Ns sits at
+    // q*Ns*R + j + (q >> wr_shift) + k*Ns.  The next stage reads element
+    // b + k*nb at b + (q >> rd_shift) + k*rd_stride (q = b / Ns), the period
+    // of the layout dividing nb.  Tile loads and the last stage's layout are
+    // unpadded.
+    int32_t rd_stride;
+    int16_t rd_shift;
+    int16_t wr_shift;
 };
 
 // Kernel argument block of one pass (also the descriptor of a batched item).
@@ -114,8 +124,9 @@ struct PassArgs {
     int64_t conv_c, conv_k;
 };
 
-// LDS index padding: one spare slot every 16 elements keeps radix-16 stride
-// writes free of bank conflicts.
+// LDS index padding of the specialized leaf kernel: one spare slot every 16
+// elements keeps radix-16 stride writes free of bank conflicts.  Lines of the
+// generic tile kernel hold up to lds_pad(n - 1) + 1 elements in every layout.
 __host__ __device__ constexpr int lds_pad(int i) { return i + (i >> 4); }
 
 }  // namespace mfft

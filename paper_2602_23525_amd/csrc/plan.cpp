@@ -288,6 +288,89 @@ static int stage_table(PlanImpl *p, const Leaf &L, bool jmajor, std::map<std::st
     return MFFT_OK;
 }
 
+// Bank-conflict cycles of one LDS access by a wave whose lane l touches
+// complex element addr[l] (eb bytes; negative: lane idle), summed over two
+// models of the LDS: 32 and 64 banks of 4 bytes, lanes served in groups that
+// cover the banks once.
+static int lds_access_cycles(const int (&addr)[64], int eb)
+{
+    int total = 0;
+    for (int banks : {32, 64}) {
+        const int group = std::max(1, banks * 4 / eb), words = eb / 4;
+        for (int l0 = 0; l0 < 64; l0 += group) {
+            int cnt[64] = {};
+            int worst = 0;
+            for (int l = l0; l < l0 + group && l < 64; ++l) {
+                if (addr[l] < 0) continue;
+                for (int w = 0; w < words; ++w) {
+                    const int bank = (int)(((int64_t)addr[l] * words + w) % banks);
+                    worst = std::max(worst, ++cnt[bank]);
+                }
+            }
+            total += worst;
+        }
+    }
+    return total;
+}
+
+// LDS layouts of a generic leaf's stages (StageDesc::rd_stride, rd_shift,
+// wr_shift): for each stage boundary, the padding period G*2^sh (G = Ns*R of
+// the writing stage) or none, among those of at least 16 elements (a line
+// then never needs more than lds_pad(n - 1) + 1 slots) that divide the next
+// stage's butterfly count (its reads stay affine), with the fewest modeled
+// bank-conflict cycles over the first wave's writes and the next stage's
+// reads; ties go to no padding, then to the longer period.
+void lds_layouts(int n, int nst, int tpt, int lds_stride, int emax, int eb, StageDesc *st)
+{
+    constexpr int kNone = 31;
+    auto lane_cost = [&](int s, int sh, bool write) {
+        const StageDesc &sd = st[s];
+        const int R = sd.R, Ns = sd.Ns, G = Ns * R, nbs = n / R;
+        int cost = 0;
+        for (int i = 0; i < emax / R; ++i)
+            for (int k = 0; k < R; ++k) {
+                int addr[64];
+                for (int l = 0; l < 64; ++l) {
+                    const int tr = l / tpt, t = l % tpt, b = t + i * tpt;
+                    const int q = b / Ns, j = b - q * Ns;
+                    addr[l] = b >= nbs ? -1
+                                       : tr * lds_stride +
+                                             (write ? q * G + j + (sh == kNone ? 0 : q >> sh) + k * Ns
+                                                    : b + (sh == kNone ? 0 : q >> sh) + k * sd.rd_stride);
+                }
+                cost += lds_access_cycles(addr, eb);
+            }
+        return cost;
+    };
+    st[0].rd_shift = kNone;
+    st[0].rd_stride = n / st[0].R;
+    for (int s = 0; s < nst; ++s) {
+        StageDesc &sd = st[s];
+        sd.wr_shift = kNone;
+        if (s + 1 == nst) break;   // the last layout is unpadded
+        StageDesc &nx = st[s + 1];
+        const int G = sd.Ns * sd.R, nbn = n / nx.R;
+        int best_cost = INT32_MAX, best = kNone;
+        for (int sh = kNone; sh >= 0; sh = sh == kNone ? 20 : sh - 1) {
+            int rstride = nbn;
+            if (sh != kNone) {
+                const int64_t per = (int64_t)G << sh;
+                if (per < 16 || per > nbn || nbn % per != 0) continue;
+                rstride = nbn + (int)(nbn / per);
+            }
+            nx.rd_stride = rstride;
+            const int cost = lane_cost(s, sh, true) + lane_cost(s + 1, sh, false);
+            if (cost < best_cost) {
+                best_cost = cost;
+                best = sh;
+            }
+        }
+        sd.wr_shift = (int16_t)best;
+        nx.rd_shift = (int16_t)best;
+        nx.rd_stride = best == kNone ? nbn : nbn + nbn / (G << best);
+    }
+}
+
 static int fill_leaf(PlanImpl *p, const Leaf &L, PassArgs *a,
                      std::map<std::string, void *> *cache, bool leaf_kernel)
 {
@@ -308,6 +391,7 @@ static int fill_leaf(PlanImpl *p, const Leaf &L, PassArgs *a,
         off += (int64_t)Ns * (jmajor ? sd.R - 1 : sd.R);
         Ns *= sd.R;
     }
+    lds_layouts(L.n, a->nst, L.tpt, L.lds_stride, L.emax, (int)elem_bytes(p->prob.prec), a->st);
     int rc = stage_table(p, L, jmajor, cache, &a->tw);
     if (rc == MFFT_OK && leaf_kernel) rc = stage_table(p, L, false, cache, &a->tw_leaf);
     return rc;

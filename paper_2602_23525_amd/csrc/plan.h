@@ -156,6 +156,9 @@ PermuteArgs resolve_permute(const PlanImpl *p, const Pass &ps, const void *in, v
                             void *scratch);
 // Lines per tile of a generic-kernel row tile (see plan.cpp).
 int row_lines_per_tile(int n, int tpt, int prec, int64_t lines);
+// LDS layouts of the generic kernel's stage boundaries (StageDesc rd_stride,
+// rd_shift, wr_shift) for a leaf of nst stages st[0..nst) with R, Ns, nb set.
+void lds_layouts(int n, int nst, int tpt, int lds_stride, int emax, int eb, StageDesc *st);
 // LDS bytes the generic tile kernel needs for a pass.
 size_t generic_lds_bytes(const Pass &ps);
 

@@ -97,22 +97,12 @@ __device__ __forceinline__ void commit_plain(const PassArgs &a, cpx<T> *lds, int
 {
     constexpr int KMAX = EMAX + 2;
     const int n = a.n, step = a.tpt;
-    cpx<T> *dst = lds + line * a.lds_stride;
+    // the tile load's layout is unpadded: element idx at idx
+    cpx<T> *d0 = lds + line * a.lds_stride + idx0;
     const bool cj = (a.flags & PF_CONJ_IN) != 0;
-    if ((step & 15) == 0) {
-        // padded LDS index of idx0 + k*step is linear in k
-        cpx<T> *d0 = dst + lds_pad(idx0);
-        const int ps = step + (step >> 4);
 #pragma unroll
-        for (int k = 0; k < KMAX; ++k)
-            if (idx0 + k * step < n) d0[k * ps] = cj ? conj(r[k]) : r[k];
-    } else {
-#pragma unroll
-        for (int k = 0; k < KMAX; ++k) {
-            const int idx = idx0 + k * step;
-            if (idx < n) dst[lds_pad(idx)] = cj ? conj(r[k]) : r[k];
-        }
-    }
+    for (int k = 0; k < KMAX; ++k)
+        if (idx0 + k * step < n) d0[k * step] = cj ? conj(r[k]) : r[k];
 }
 
 // Tile load of one lane: elements idx0 + k*tpt (k < EMAX + 2, below n) of
@@ -175,7 +165,7 @@ __device__ __forceinline__ void load_line(const PassArgs &a, const Tile<T> &tl, 
                     cpx<T> x = val[q] ? r[q] : cpx<T>{T(0), T(0)};
                     if (cj) x = conj(x);
                     if (f & PF_PRE_MUL) x = cmul(x, pm[q]);
-                    dst[lds_pad(idx)] = x;
+                    dst[idx] = x;
                 }
             }
         }
@@ -277,27 +267,18 @@ __device__ __forceinline__ void stage(const PassArgs &a, const StageDesc &sd, Ti
     // block) only take part in the barriers
     const int nbl = tl.act ? nb : 0;
     cpx<T> v[NB][R];
+    int qv[NB];
 
-    // padded LDS index of x + k*d is linear in k when d is a multiple of 16
-    if ((nb & 15) == 0) {
-        const int pnb = nb + (nb >> 4);
+    // butterfly b = q*Ns + j reads element b + k*nb of the previous layout
+    // (one address per butterfly, the k-th element rd_stride further)
 #pragma unroll
-        for (int i = 0; i < NB; ++i) {
-            const int b = tl.t + i * tpt;
-            if (b < nbl) {
-                const cpx<T> *src = tl.my + lds_pad(b);
+    for (int i = 0; i < NB; ++i) {
+        const int b = tl.t + i * tpt;
+        qv[i] = fast_div(b, sd.magic, sd.shift);
+        if (b < nbl) {
+            const cpx<T> *src = tl.my + b + (qv[i] >> sd.rd_shift);
 #pragma unroll
-                for (int k = 0; k < R; ++k) v[i][k] = src[k * pnb];
-            }
-        }
-    } else {
-#pragma unroll
-        for (int i = 0; i < NB; ++i) {
-            const int b = tl.t + i * tpt;
-            if (b < nbl) {
-#pragma unroll
-                for (int k = 0; k < R; ++k) v[i][k] = tl.my[lds_pad(b + k * nb)];
-            }
+            for (int k = 0; k < R; ++k) v[i][k] = src[k * sd.rd_stride];
         }
     }
     if constexpr (KIND & K_CONV) {
@@ -323,7 +304,7 @@ __device__ __forceinline__ void stage(const PassArgs &a, const StageDesc &sd, Ti
     for (int i = 0; i < NB; ++i) {
         const int b = tl.t + i * tpt;
         if (b < nbl) {
-            const int q = fast_div(b, sd.magic, sd.shift);
+            const int q = qv[i];
             const int j = b - q * Ns;
             if (Ns > 1) {
                 if constexpr (sizeof(T) == 4) {
@@ -368,14 +349,10 @@ __device__ __forceinline__ void stage(const PassArgs &a, const StageDesc &sd, Ti
                     }
                 }
                 store_run<T, R, KIND, false>(a, tl, c, ok, out_base, base, Ns, v[i]);
-            } else if ((Ns & 15) == 0) {
-                cpx<T> *dst = tl.my + lds_pad(base);
-                const int pns = Ns + (Ns >> 4);
-#pragma unroll
-                for (int k = 0; k < R; ++k) dst[k * pns] = v[i][k];
             } else {
+                cpx<T> *dst = tl.my + base + (q >> sd.wr_shift);
 #pragma unroll
-                for (int k = 0; k < R; ++k) tl.my[lds_pad(base + k * Ns)] = v[i][k];
+                for (int k = 0; k < R; ++k) dst[k * Ns] = v[i][k];
             }
         }
     }
@@ -533,9 +510,7 @@ __device__ __forceinline__ void tile_body(const PassArgs &a, Tile<T> &tl, cpx<T>
                 }
             }
             constexpr int CH = (KIND & K_EXT) ? ext_chunk<T>() : KMAX;
-            // padded LDS index of idx + k*step is linear in k when step % 16 == 0
-            const bool lin = (step & 15) == 0;
-            const int pidx = lds_pad(idx), pstep = step + (step >> 4);
+            // the last stage's layout is unpadded
 #pragma unroll
             for (int k0 = 0; k0 < KMAX; k0 += CH) {
                 // the last chunk may run past KMAX: those elements lie past
@@ -544,8 +519,7 @@ __device__ __forceinline__ void tile_body(const PassArgs &a, Tile<T> &tl, cpx<T>
 #pragma unroll
                 for (int q = 0; q < CH; ++q) {
                     const int kk = idx + (k0 + q) * step;
-                    const int pk = lin ? pidx + (k0 + q) * pstep : lds_pad(kk);
-                    y[q] = kk < n ? src[pk] : cpx<T>{T(0), T(0)};
+                    y[q] = kk < n ? src[kk] : cpx<T>{T(0), T(0)};
                     if (tw) {
                         if constexpr (sizeof(T) == 8) {
                             if (kk < n) y[q] = mul_d(y[q], tw4_root(a, (int64_t)kk * cs));

@@ -8,12 +8,15 @@
 // Padding lines of a partial last tile (line index >= the vector length) take
 // an in-range line's tables in both kernels; the check also reports how many
 // passes would overrun a table if they did not (the lines the clamp protects).
+// The generic kernel's LDS layouts between stages are simulated per pass:
+// every read finds the element the previous step wrote there, inside the line.
 //
 // Usage:
 //   plan_host_check bounds <prec> <n_lo> <n_hi> <batch> <primes|all|composite>
 //     plans every 1-D length in [n_lo, n_hi] of that class, batch transforms
 //     out of place, and checks them; prints one line per violation and a
-//     summary "checked plans=P passes=S partial=Q guarded=G violations=V".
+//     summary "checked plans=P passes=S partial=Q guarded=G lds=L violations=V"
+//     (L: passes whose LDS layouts were simulated).
 //   plan_host_check plan <prec> <n> <batch>
 //     prints the plan's pass list (as the library describes it).
 //   plan_host_check cands <prec> <n_lo> <n_hi> <batch> [print]
@@ -122,7 +125,7 @@ static int host_plan(PlanImpl *p, int prec, int64_t n, int64_t batch)
 struct Checker {
     const PlanImpl *p;
     std::string name;
-    int violations = 0, guarded = 0;
+    int violations = 0, guarded = 0, lds_checked = 0;
 
     // bytes from ptr to the end of the table that holds it (-1: none)
     int64_t avail(const void *ptr) const
@@ -158,9 +161,56 @@ struct Checker {
         }
     }
 
+    // The generic kernel's LDS layouts of one pass (every pass has them: a
+    // batch may run any pass in that kernel): each stage's butterfly b reads,
+    // at b + (q >> rd_shift) + k*rd_stride, exactly the element b + k*nb the
+    // tile load or the previous stage left there, writes element
+    // q*Ns*R + j + k*Ns to a slot no other write of the stage takes, and every
+    // slot lies inside the line's lds_stride; the last layout is unpadded (the
+    // LDS store phase and a following transform read element i at i).
+    void check_lds(const Pass &ps)
+    {
+        const PassArgs &a = ps.a;
+        const int n = a.n, S = a.lds_stride;
+        if (a.nst < 1 || n < 2) return;
+        auto bad = [&](const char *what, int s, int b, int k) {
+            std::printf("VIOLATION %s: LDS %s, stage %d butterfly %d element %d (%s)\n",
+                        name.c_str(), what, s, b, k, ps.desc.c_str());
+            ++violations;
+        };
+        if (n > S) return bad("line longer than its slots", -1, 0, 0);
+        std::vector<int> cur(S, -1), nxt(S);
+        for (int i = 0; i < n; ++i) cur[i] = i;   // the tile load: unpadded
+        for (int s = 0; s < a.nst; ++s) {
+            const StageDesc &sd = a.st[s];
+            const int R = sd.R, Ns = sd.Ns, nb = n / R;
+            if (sd.nb != nb || sd.rd_shift < 0 || sd.rd_shift > 31 || sd.wr_shift < 0 ||
+                sd.wr_shift > 31)
+                return bad("descriptor", s, 0, 0);
+            std::fill(nxt.begin(), nxt.end(), -1);
+            for (int b = 0; b < nb; ++b) {
+                const int q = b / Ns, j = b - q * Ns;
+                const int qd = (int)((((uint64_t)b * sd.magic >> 32) + (uint64_t)b) >> sd.shift);
+                if (qd != q) return bad("quotient", s, b, 0);
+                for (int k = 0; k < R; ++k) {
+                    const int64_t ra = (int64_t)b + (q >> sd.rd_shift) + (int64_t)k * sd.rd_stride;
+                    if (ra < 0 || ra >= S || cur[ra] != b + k * nb) return bad("read", s, b, k);
+                    const int64_t wa = (int64_t)q * Ns * R + j + (q >> sd.wr_shift) + (int64_t)k * Ns;
+                    if (wa < 0 || wa >= S || nxt[wa] != -1) return bad("write", s, b, k);
+                    nxt[wa] = q * Ns * R + j + k * Ns;
+                }
+            }
+            cur.swap(nxt);
+        }
+        for (int i = 0; i < n; ++i)
+            if (cur[i] != i) return bad("last layout", a.nst, i, 0);
+        ++lds_checked;
+    }
+
     void check_pass(const Pass &ps)
     {
         if (ps.kind != 0) return;
+        check_lds(ps);
         const PassArgs &a = ps.a;
         const int eb = ps.prec ? 16 : 8;
         const int64_t n = a.n;
@@ -299,7 +349,7 @@ int main(int argc, char **argv)
         const int prec = std::atoi(argv[2]);
         const int64_t lo = std::atoll(argv[3]), hi = std::atoll(argv[4]), batch = std::atoll(argv[5]);
         const std::string cls = argv[6];
-        int plans = 0, passes = 0, partial = 0, guarded = 0, violations = 0, failed = 0;
+        int plans = 0, passes = 0, partial = 0, guarded = 0, violations = 0, failed = 0, lds = 0;
         for (int64_t n = lo; n <= hi; ++n) {
             const bool pr = is_prime(n);
             if (cls == "primes" && !pr) continue;
@@ -322,10 +372,11 @@ int main(int argc, char **argv)
             }
             violations += ck.violations;
             guarded += ck.guarded;
+            lds += ck.lds_checked;
             ++plans;
         }
-        std::printf("checked plans=%d passes=%d partial=%d guarded=%d violations=%d failed=%d\n",
-                    plans, passes, partial, guarded, violations, failed);
+        std::printf("checked plans=%d passes=%d partial=%d guarded=%d lds=%d violations=%d failed=%d\n",
+                    plans, passes, partial, guarded, lds, violations, failed);
         return violations || failed ? 1 : 0;
     }
     if (argc >= 5 && !std::strcmp(argv[1], "plan")) {
