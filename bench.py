@@ -52,7 +52,8 @@ DEFAULT = "c2c_1d_n4096_b16384_c32"
 # power-of-two workloads): a counter summary applies while their hash matches
 LEAF_SOURCES = ["paper_2602_23525_amd/csrc/leaf.h", "paper_2602_23525_amd/csrc/k_leaf.hip",
                 "paper_2602_23525_amd/csrc/butterfly.h", "paper_2602_23525_amd/csrc/internal.h",
-                "paper_2602_23525_amd/csrc/twiddle4.h", "paper_2602_23525_amd/csrc/leaf_shape.h"]
+                "paper_2602_23525_amd/csrc/twiddle4.h", "paper_2602_23525_amd/csrc/leaf_shape.h",
+                "paper_2602_23525_amd/csrc/gmem.h"]
 
 
 def kernel_source_hash() -> str:

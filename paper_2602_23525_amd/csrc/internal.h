@@ -45,6 +45,7 @@ enum : uint32_t {
     PF_R2C = 1u << 14,       // leaf kernel: split the packed real transform on store (n+1 out)
     PF_C2R = 1u << 15,       // leaf kernel: combine a half spectrum on load (n+1 in)
     PF_NT_IN = 1u << 16,     // generic kernel: non-temporal element loads
+    PF_NT_OUT = 1u << 17,    // generic kernel: non-temporal element stores (plain stores)
     PF_LEAF_COL = 1u << 18,  // leaf kernel: tile of adjacent lines with strided elements
     PF_LEAF_CR = 1u << 19,   // leaf kernel: adjacent lines in, unit-stride lines out
     PF_LEAF_RC = 1u << 20,   // leaf kernel: unit-stride lines in, adjacent lines out

@@ -16,6 +16,7 @@
 // thread do not depend on the tile and are loaded into registers once.
 #pragma once
 #include "butterfly.h"
+#include "gmem.h"
 #include "internal.h"
 #include "leaf_shape.h"
 #include "twiddle4.h"
@@ -40,7 +41,7 @@ struct StageTw {
 };
 
 template <typename T, int N, int TPT, int NS, int R>
-__device__ __forceinline__ void load_stage_tw(StageTw<T, R> &tw, const cpx<T> *table, int t)
+__device__ __forceinline__ void load_stage_tw(StageTw<T, R> &tw, gptr<const cpx<T>> table, int t)
 {
     constexpr int NB = 16 / R;
 #pragma unroll
@@ -127,7 +128,7 @@ template <typename T, int N, int TPT, int NS, int R, int... Rest>
 struct StageChain {
     StageTw<T, R> tw;
     StageChain<T, N, TPT, NS * R, Rest...> next;
-    __device__ __forceinline__ void load(const cpx<T> *table, int off, int t)
+    __device__ __forceinline__ void load(gptr<const cpx<T>> table, int off, int t)
     {
         if constexpr (NS > 1) load_stage_tw<T, N, TPT, NS, R>(tw, table + off, t);
         next.load(table, off + NS * R, t);
@@ -146,7 +147,7 @@ struct StageChain {
 template <typename T, int N, int TPT, int NS, int R>
 struct StageChain<T, N, TPT, NS, R> {
     StageTw<T, R> tw;
-    __device__ __forceinline__ void load(const cpx<T> *table, int off, int t)
+    __device__ __forceinline__ void load(gptr<const cpx<T>> table, int off, int t)
     {
         if constexpr (NS > 1) load_stage_tw<T, N, TPT, NS, R>(tw, table + off, t);
     }
@@ -159,7 +160,7 @@ struct StageChain<T, N, TPT, NS, R> {
 // Global loads and stores of one element, non-temporal when the pass does
 // not reuse what it reads (NT bit 1) or writes (NT bit 0).
 template <int NT, typename T>
-__device__ __forceinline__ cpx<T> ld_elem(const cpx<T> *p)
+__device__ __forceinline__ cpx<T> ld_elem(gptr<const cpx<T>> p)
 {
     if constexpr (NT & 2) {
         return {__builtin_nontemporal_load(&p->re), __builtin_nontemporal_load(&p->im)};
@@ -169,7 +170,7 @@ __device__ __forceinline__ cpx<T> ld_elem(const cpx<T> *p)
 }
 
 template <int NT, typename T>
-__device__ __forceinline__ void st_elem(cpx<T> *p, cpx<T> v)
+__device__ __forceinline__ void st_elem(gptr<cpx<T>> p, cpx<T> v)
 {
     if constexpr (NT & 1) {
         __builtin_nontemporal_store(v.re, &p->re);
@@ -232,7 +233,7 @@ __device__ __forceinline__ void leaf_body(const PassArgs &a, cpx<T> *lds, int64_
     const bool cin = (a.flags & PF_CONJ_IN) != 0, cout = (a.flags & PF_CONJ_OUT) != 0;
 
     StageChain<T, N, TPT, 1, Rs...> chain;
-    chain.load((const cpx<T> *)a.tw_leaf, 0, t);
+    chain.load(glob((const cpx<T> *)a.tw_leaf), 0, t);
 
     // column tiles: inner index of the lane's store line (for the twiddle);
     // Bluestein modes: index of the lane's load line clamped to the vector
@@ -263,16 +264,16 @@ __device__ __forceinline__ void leaf_body(const PassArgs &a, cpx<T> *lds, int64_
         *obs = bo + cs * a.vos;
     };
     auto load_line = [&](cpx<T>(&x)[16], int64_t ib) {
-        const cpx<T> *src = (const cpx<T> *)a.in + ib + t * eis;
+        const gptr<const cpx<T>> src = glob((const cpx<T> *)a.in) + ib + t * eis;
         if constexpr (pre) {
             // elements past li_lim read element 0 of the line (in range) and
             // become zero
-            const cpx<T> *pm = (const cpx<T> *)a.pre;
+            const gptr<const cpx<T>> pm = glob((const cpx<T> *)a.pre);
             const int64_t j0 = lc * a.li_c + (int64_t)t * a.li_l, js = (int64_t)TPT * a.li_l;
 #pragma unroll
             for (int e = 0; e < 16; ++e)
                 x[e] = ld_elem<NT>(j0 + e * js < a.li_lim ? &src[e * TPT * eis]
-                                                          : (const cpx<T> *)a.in + ib);
+                                                          : glob((const cpx<T> *)a.in) + ib);
 #pragma unroll
             for (int e = 0; e < 16; ++e) {
                 const int64_t j = j0 + e * js;
@@ -293,7 +294,7 @@ __device__ __forceinline__ void leaf_body(const PassArgs &a, cpx<T> *lds, int64_
     // n+1 outputs on store (both as the elementwise real-data steps, through
     // LDS since the partners k and n-k sit in different lanes).
     constexpr bool r2c = RD == 1, c2r = RD == 2;
-    const cpx<T> *rtw = (const cpx<T> *)a.post;   // w_2n^k, k <= n/2
+    const gptr<const cpx<T>> rtw = glob((const cpx<T> *)a.post);   // w_2n^k, k <= n/2
     // half spectrum X (n+1 values from ib) -> packed Z' in LDS, lane t taking
     // the pairs (k, n-k), k = t + j*TPT <= n/2 (j <= 8); the loads of a group
     // of JC pairs (all nine in FP32, two groups in FP64 to bound registers)
@@ -301,7 +302,7 @@ __device__ __forceinline__ void leaf_body(const PassArgs &a, cpx<T> *lds, int64_
     constexpr int J = N / 2 / TPT + 1;
     constexpr int JC = sizeof(T) == 4 ? J : (J + 1) / 2;
     auto combine_half_spectrum = [&](int64_t ib) {
-        const cpx<T> *X = (const cpx<T> *)a.in + ib;
+        const gptr<const cpx<T>> X = glob((const cpx<T> *)a.in) + ib;
         // an opaque copy of the lane index keeps the compiler from hoisting
         // the J table and line addresses out of the tile loop
         int tq = t;
@@ -341,7 +342,7 @@ __device__ __forceinline__ void leaf_body(const PassArgs &a, cpx<T> *lds, int64_
         for (int e = 0; e < 16; ++e) *lds_slot<TPT>(line, t, e) = z[e];
         __syncthreads();
         if (ok) {
-            cpx<T> *X = (cpx<T> *)a.out + ob;
+            const gptr<cpx<T>> X = glob((cpx<T> *)a.out) + ob;
             const T half = T(0.5);
             int tq = t;   // opaque, as in the combine
             __asm__ volatile("" : "+v"(tq));
@@ -397,7 +398,7 @@ __device__ __forceinline__ void leaf_body(const PassArgs &a, cpx<T> *lds, int64_
         if constexpr (conv) {
             // every LDS read of the first transform came before its last
             // barrier, so the second may start at once
-            const cpx<T> *cv = (const cpx<T> *)a.conv + lc * a.conv_c + (int64_t)t * a.conv_k;
+            const gptr<const cpx<T>> cv = glob((const cpx<T> *)a.conv) + lc * a.conv_c + (int64_t)t * a.conv_k;
             const int64_t cks = (int64_t)TPT * a.conv_k;
 #pragma unroll
             for (int e = 0; e < 16; ++e) x[e] = conj(cmul(x[e], cv[e * cks]));
@@ -443,8 +444,8 @@ __device__ __forceinline__ void leaf_body(const PassArgs &a, cpx<T> *lds, int64_
                 // load line, in range when ok)
                 const int64_t sc = xpose ? cst : lc;
                 const int sr = xpose ? ts : t;
-                cpx<T> *dst = (cpx<T> *)a.out + ob + sr * eos;
-                const cpx<T> *pm = (const cpx<T> *)a.post;
+                const gptr<cpx<T>> dst = glob((cpx<T> *)a.out) + ob + sr * eos;
+                const gptr<const cpx<T>> pm = glob((const cpx<T> *)a.post);
                 const bool ca = (a.flags & PF_CONJ_A) != 0;
                 const int64_t g0 = sc * a.lo_c + (int64_t)sr * a.lo_k, gs = (int64_t)TPT * a.lo_k;
 #pragma unroll
@@ -459,7 +460,7 @@ __device__ __forceinline__ void leaf_body(const PassArgs &a, cpx<T> *lds, int64_
         } else if constexpr (r2c) {
             split_to_half_spectrum(x, ob, ok);
         } else if (ok) {
-            cpx<T> *dst = (cpx<T> *)a.out + ob + (xpose ? ts : t) * eos;
+            const gptr<cpx<T>> dst = glob((cpx<T> *)a.out) + ob + (xpose ? ts : t) * eos;
 #pragma unroll
             for (int e = 0; e < 16; ++e)
                 st_elem<NT>(&dst[e * TPT * eos], cout ? conj(x[e]) : x[e]);

@@ -17,8 +17,9 @@
 
 #include <cstdint>
 
-#include "radix.h"
+#include "gmem.h"
 #include "internal.h"
+#include "radix.h"
 #include "twiddle4.h"
 
 namespace mfft {
@@ -49,7 +50,7 @@ struct Tile {
 
 // Element load that marks the data as not reused (PF_NT_IN).
 template <typename T>
-__device__ __forceinline__ cpx<T> ld_nt(const cpx<T> *p)
+__device__ __forceinline__ cpx<T> ld_nt(gptr<const cpx<T>> p)
 {
     return {__builtin_nontemporal_load(&p->re), __builtin_nontemporal_load(&p->im)};
 }
@@ -69,13 +70,13 @@ __device__ __forceinline__ void issue_plain(const PassArgs &a, const Tile<T> &tl
     constexpr int KMAX = EMAX + 2;
     const int n = a.n, step = a.tpt;
     const int64_t c = tl.c0 + line;
-    const cpx<T> *p0 = (const cpx<T> *)a.in + tl.ob_in + (c < a.vn ? c : tl.c0) * a.vis +
-                       (int64_t)idx0 * a.is;
+    const gptr<const cpx<T>> p0 = glob((const cpx<T> *)a.in) + tl.ob_in +
+                                  (c < a.vn ? c : tl.c0) * a.vis + (int64_t)idx0 * a.is;
     const int64_t pst = (int64_t)step * a.is;
     // slots past ceil(n / step) hold no element of any lane: skipped by a
     // uniform branch rather than loaded from p0
     const int kn = (n + step - 1) / step;
-    const cpx<T> *p = p0;
+    gptr<const cpx<T>> p = p0;
     if (a.flags & PF_NT_IN) {
 #pragma unroll
         for (int k = 0; k < KMAX; ++k) {
@@ -118,7 +119,7 @@ __device__ __forceinline__ void load_line(const PassArgs &a, const Tile<T> &tl, 
     const int n = a.n, step = a.tpt;
     const int64_t c = tl.c0 + line;
     const bool okc = c < a.vn;
-    const cpx<T> *in = (const cpx<T> *)a.in + tl.ob_in + (okc ? c : tl.c0) * a.vis;
+    const gptr<const cpx<T>> in = glob((const cpx<T> *)a.in) + tl.ob_in + (okc ? c : tl.c0) * a.vis;
     cpx<T> *dst = lds + line * a.lds_stride;
     const bool cj = (a.flags & PF_CONJ_IN) != 0;
     cpx<T> r[KMAX];
@@ -145,7 +146,7 @@ __device__ __forceinline__ void load_line(const PassArgs &a, const Tile<T> &tl, 
             }
             if (f & PF_GATHER) {
 #pragma unroll
-                for (int q = 0; q < CH; ++q) e[q] = a.gather[li[q]];
+                for (int q = 0; q < CH; ++q) e[q] = glob(a.gather)[li[q]];
             }
             if (f & PF_NT_IN) {
 #pragma unroll
@@ -156,7 +157,7 @@ __device__ __forceinline__ void load_line(const PassArgs &a, const Tile<T> &tl, 
             }
             if (f & PF_PRE_MUL) {
 #pragma unroll
-                for (int q = 0; q < CH; ++q) pm[q] = ((const cpx<T> *)a.pre)[li[q]];
+                for (int q = 0; q < CH; ++q) pm[q] = glob((const cpx<T> *)a.pre)[li[q]];
             }
 #pragma unroll
             for (int q = 0; q < CH; ++q) {
@@ -182,7 +183,7 @@ template <typename T, int M, int KIND, bool CHECK>
 __device__ __forceinline__ void store_run(const PassArgs &a, const Tile<T> &tl, int64_t c, bool okc,
                                           int64_t base, int k0, int ks, const cpx<T> (&y)[M])
 {
-    cpx<T> *out = (cpx<T> *)a.out + base;
+    const gptr<cpx<T>> out = glob((cpx<T> *)a.out) + base;
     const uint32_t f = a.flags;
     const int n = a.n;
     if constexpr (KIND & K_EXT) {
@@ -203,11 +204,11 @@ __device__ __forceinline__ void store_run(const PassArgs &a, const Tile<T> &tl, 
             }
             if (f & PF_SCATTER) {
 #pragma unroll
-                for (int q = 0; q < CH; ++q) e[q] = a.scatter[lo[q]];
+                for (int q = 0; q < CH; ++q) e[q] = glob(a.scatter)[lo[q]];
             }
             if (f & PF_POST_MUL) {
 #pragma unroll
-                for (int q = 0; q < CH; ++q) pm[q] = ((const cpx<T> *)a.post)[lo[q]];
+                for (int q = 0; q < CH; ++q) pm[q] = glob((const cpx<T> *)a.post)[lo[q]];
             }
 #pragma unroll
             for (int q = 0; q < CH; ++q) {
@@ -215,7 +216,7 @@ __device__ __forceinline__ void store_run(const PassArgs &a, const Tile<T> &tl, 
                 cpx<T> v = y[m0 + q < M ? m0 + q : M - 1];
                 if (f & PF_CONJ_A) v = conj(v);
                 if ((f & PF_AUX_A0) && !(f & PF_CONV) && lo[q] == 0)
-                    ((cpx<T> *)a.aux)[2 * tl.o + 1] = v;
+                    glob((cpx<T> *)a.aux)[2 * tl.o + 1] = v;
                 if (f & PF_POST_MUL) v = cmul(v, pm[q]);
                 if (f & (PF_RADER | PF_AUX_ADD)) v = cadd(v, tl.x0);
                 if (f & PF_CONJ_OUT) v = conj(v);
@@ -231,11 +232,23 @@ __device__ __forceinline__ void store_run(const PassArgs &a, const Tile<T> &tl, 
         if (okc) {
             const bool cj = (f & PF_CONJ_OUT) != 0;
             const int64_t pst = (int64_t)ks * a.os;
-            cpx<T> *p = out + (int64_t)k0 * a.os;
+            gptr<cpx<T>> p = out + (int64_t)k0 * a.os;
+            if (f & PF_NT_OUT) {
 #pragma unroll
-            for (int m = 0; m < M; ++m) {
-                if (!CHECK || k0 + m * ks < n) *p = cj ? conj(y[m]) : y[m];
-                p += pst;
+                for (int m = 0; m < M; ++m) {
+                    if (!CHECK || k0 + m * ks < n) {
+                        const cpx<T> v = cj ? conj(y[m]) : y[m];
+                        __builtin_nontemporal_store(v.re, &p->re);
+                        __builtin_nontemporal_store(v.im, &p->im);
+                    }
+                    p += pst;
+                }
+            } else {
+#pragma unroll
+                for (int m = 0; m < M; ++m) {
+                    if (!CHECK || k0 + m * ks < n) *p = cj ? conj(y[m]) : y[m];
+                    p += pst;
+                }
             }
         }
     }
@@ -257,7 +270,13 @@ __device__ __forceinline__ void stage(const PassArgs &a, const StageDesc &sd, Ti
     // nb comes from the stage descriptor (not n / R) so that LDS addresses are
     // computed inside the stage rather than hoisted for every radix up front
     const int nb = sd.nb, tpt = a.tpt, Ns = sd.Ns;
-    const int64_t c = tl.c0 + tl.tr;
+    // opaque copies of the lane's thread and line indices: keep the compiler
+    // from hoisting each radix's address arithmetic out of the stage loop
+    // (registers held for the whole kernel; FP32 plain kind 102 -> 79 VGPRs)
+    int t = tl.t, tr = tl.tr;
+    __asm__ volatile("" : "+v"(t), "+v"(tr));
+    cpx<T> *const my = tl.lds + tr * a.lds_stride;
+    const int64_t c = tl.c0 + tr;
     const bool ok = c < a.vn;
     // lines past the vector loop (the last tile's padding) compute on an
     // in-range line's tables and store nothing: table reads stay in bounds
@@ -273,10 +292,10 @@ __device__ __forceinline__ void stage(const PassArgs &a, const StageDesc &sd, Ti
     // (one address per butterfly, the k-th element rd_stride further)
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
-        const int b = tl.t + i * tpt;
+        const int b = t + i * tpt;
         qv[i] = fast_div(b, sd.magic, sd.shift);
         if (b < nbl) {
-            const cpx<T> *src = tl.my + b + (qv[i] >> sd.rd_shift);
+            const cpx<T> *src = my + b + (qv[i] >> sd.rd_shift);
 #pragma unroll
             for (int k = 0; k < R; ++k) v[i][k] = src[k * sd.rd_stride];
         }
@@ -287,9 +306,10 @@ __device__ __forceinline__ void stage(const PassArgs &a, const StageDesc &sd, Ti
             // entry conv[c*conv_c + idx*conv_k], conjugated (inverse by conjugation)
 #pragma unroll
             for (int i = 0; i < NB; ++i) {
-                const int b = tl.t + i * tpt;
+                const int b = t + i * tpt;
                 if (b < nbl) {
-                    const cpx<T> *cv = (const cpx<T> *)a.conv + cs * a.conv_c + (int64_t)b * a.conv_k;
+                    const gptr<const cpx<T>> cv =
+                        glob((const cpx<T> *)a.conv) + cs * a.conv_c + (int64_t)b * a.conv_k;
                     const int64_t cst = (int64_t)nb * a.conv_k;
 #pragma unroll
                     for (int k = 0; k < R; ++k) v[i][k] = conj(cmul(v[i][k], cv[k * cst]));
@@ -299,10 +319,10 @@ __device__ __forceinline__ void stage(const PassArgs &a, const StageDesc &sd, Ti
     }
     __syncthreads();
 
-    const cpx<T> *tw = (const cpx<T> *)a.tw + sd.tw_off;
+    const gptr<const cpx<T>> tw = glob((const cpx<T> *)a.tw) + sd.tw_off;
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
-        const int b = tl.t + i * tpt;
+        const int b = t + i * tpt;
         if (b < nbl) {
             const int q = qv[i];
             const int j = b - q * Ns;
@@ -310,7 +330,7 @@ __device__ __forceinline__ void stage(const PassArgs &a, const StageDesc &sd, Ti
                 if constexpr (sizeof(T) == 4) {
                     // FP32: j-major table, the butterfly's R-1 twiddles are
                     // consecutive (one address, immediate offsets, 16-byte loads)
-                    const cpx<T> *w = tw + (uint32_t)j * (uint32_t)(R - 1);
+                    const gptr<const cpx<T>> w = tw + (uint32_t)j * (uint32_t)(R - 1);
                     cpx<T> wk[R - 1];
 #pragma unroll
                     for (int k = 1; k < R; ++k) wk[k - 1] = w[k - 1];
@@ -320,7 +340,7 @@ __device__ __forceinline__ void stage(const PassArgs &a, const StageDesc &sd, Ti
                     // FP64: k-major table, lanes with consecutive j read
                     // consecutive entries (16-byte elements: wide rows of the
                     // j-major form spread a wave's load over too many lines)
-                    const cpx<T> *w = tw + j;
+                    const gptr<const cpx<T>> w = tw + j;
 #pragma unroll
                     for (int k = 1; k < R; ++k) v[i][k] = cmul(v[i][k], w[k * Ns]);
                 }
@@ -350,7 +370,7 @@ __device__ __forceinline__ void stage(const PassArgs &a, const StageDesc &sd, Ti
                 }
                 store_run<T, R, KIND, false>(a, tl, c, ok, out_base, base, Ns, v[i]);
             } else {
-                cpx<T> *dst = tl.my + base + (q >> sd.wr_shift);
+                cpx<T> *dst = my + base + (q >> sd.wr_shift);
 #pragma unroll
                 for (int k = 0; k < R; ++k) dst[k * Ns] = v[i][k];
             }
@@ -469,7 +489,7 @@ __device__ __forceinline__ void tile_body(const PassArgs &a, Tile<T> &tl, cpx<T>
             }
         }
         if ((f & PF_AUX_A0) && tl.act && tl.t == 0 && tl.c0 + tl.tr == 0)
-            ((cpx<T> *)a.aux)[2 * tl.o + 1] = tl.my[0];   // zero frequency of line 0
+            glob((cpx<T> *)a.aux)[2 * tl.o + 1] = tl.my[0];   // zero frequency of line 0
         run_fft<T, EMAX, KIND>(a, tl, F_LDS_CONV, last_emit);
     } else {
         run_fft<T, EMAX, KIND>(a, tl, first_fetch, last_emit);
@@ -550,15 +570,15 @@ __device__ __forceinline__ void run_tile(const PassArgs &a, int64_t tile, cpx<T>
                 const int64_t c = tl.c0 + tl.tr;
                 cpx<T> x0 = {T(0), T(0)};
                 if (c < a.vn) {
-                    x0 = ((const cpx<T> *)a.in)[tl.ob_in + c * a.vis];
+                    x0 = glob((const cpx<T> *)a.in)[tl.ob_in + c * a.vis];
                     if (f & PF_CONJ_IN) x0 = conj(x0);
                 }
                 slots[2 * tl.tr] = x0;
-                if ((f & PF_AUX_X0) && c == 0) ((cpx<T> *)a.aux)[2 * tl.o] = x0;
+                if ((f & PF_AUX_X0) && c == 0) glob((cpx<T> *)a.aux)[2 * tl.o] = x0;
             }
         }
         if (f & PF_AUX_ADD) {
-            const cpx<T> *aux = (const cpx<T> *)a.aux;
+            const gptr<const cpx<T>> aux = glob((const cpx<T> *)a.aux);
             tl.x0 = aux[2 * tl.o];
             tl.a0 = aux[2 * tl.o + 1];
         }

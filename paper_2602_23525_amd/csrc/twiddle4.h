@@ -3,6 +3,7 @@
 // shared by the generic tile kernel and the leaf kernel's transposing tiles.
 #pragma once
 #include "butterfly.h"
+#include "gmem.h"
 #include "internal.h"
 
 namespace mfft {
@@ -11,8 +12,8 @@ __device__ __forceinline__ double2 tw4_root(const PassArgs &a, int64_t e)
 {
     // w_N^e = hi[e >> s] * lo[e & mask], both factors and the product in FP64
     // (the two-table scheme of Section 6)
-    const double2 h = ((const double2 *)a.tw4_hi)[e >> a.tw4_shift];
-    const double2 l = ((const double2 *)a.tw4_lo)[e & a.tw4_mask];
+    const double2 h = glob((const double2 *)a.tw4_hi)[e >> a.tw4_shift];
+    const double2 l = glob((const double2 *)a.tw4_lo)[e & a.tw4_mask];
     return make_double2(h.x * l.x - h.y * l.y, h.x * l.y + h.y * l.x);
 }
 
