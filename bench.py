@@ -127,7 +127,7 @@ def run_uneven(args, emit=True):
     """Uneven batch: `items` 1-D FP32 transforms of log-uniform sizes 64..65536
     (60% powers of two, 30% 7-smooth, 10% primes), batch 1..32 each, packed at
     256-byte aligned offsets of one input and one output buffer, executed
-    (a) as one batch (persistent launches, HIP graph) and (b) one plan per
+    (a) as one batch (batched launches, HIP graph) and (b) one plan per
     launch on one stream."""
     import numpy as np
     import torch
@@ -682,7 +682,7 @@ def main():
     plan.destroy()
     if extras and not args.no_extras:
         # the rest of the metric on the same GPU: the uneven batch (one graph of
-        # persistent launches vs one plan per launch) and a bounded serving
+        # batched launches vs one plan per launch) and a bounded serving
         # replay (p50/p99 at rho = 0.8 of the sequential capacity)
         del xt, yt
         torch.cuda.empty_cache()

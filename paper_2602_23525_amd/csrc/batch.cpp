@@ -1,15 +1,16 @@
 // Batches across plans: the passes of many planned transforms run as a few
-// persistent launches (the vector-loop rule of Section 4.2, applied across
-// problems instead of within one).
+// launches (the vector-loop rule of Section 4.2, applied across problems
+// instead of within one).
 //
 // Pass k of every plan forms phase k; within a phase, passes that share a
 // kernel family (precision, feature kind, workgroup-size class) become one
-// launch of the persistent tile kernel over a device descriptor list.  Tiles
-// are numbered item by item, items ordered by line length, largest first, and
-// workgroups pop tile indices from a counter (and find the tile's item in a
-// tile-to-item table), so long lines start early and short ones fill the tail.  Phases run in order on the stream, so pass k+1 of
-// a plan always sees pass k complete.  Counters are cleared by a kernel (not a
-// memset) so that the whole sequence can be captured in a HIP graph.
+// launch of the tile kernel over a device descriptor list, one workgroup per
+// tile.  Tiles are numbered item by item, items ordered by line length,
+// largest first, and each workgroup finds its tile's item in a tile-to-item
+// table, so long lines start early and short ones fill the tail.  Phases run
+// in order on the stream, so pass k+1 of a plan always sees pass k complete.
+// The sequence holds kernel launches only, so it can be captured in a HIP
+// graph.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -22,7 +23,6 @@
 
 namespace mfft {
 
-extern int g_num_cus;
 extern size_t g_lds_budget;
 
 // Retile a pass for a workgroup-size class: 256, 512 or 1024 threads, with
@@ -130,7 +130,7 @@ int build_batch_layout(const std::vector<BatchItem> &items, BatchLayout *L)
         }
     }
     std::vector<std::pair<Key, std::vector<Item>>> order(fam.begin(), fam.end());
-    size_t bytes = 512 + sizeof(unsigned long long) * order.size();
+    size_t bytes = 512;
     for (auto &kv : order) {
         std::stable_sort(kv.second.begin(), kv.second.end(),
                          [](const Item &x, const Item &y) { return x.n > y.n; });
@@ -156,8 +156,6 @@ int build_batch_layout(const std::vector<BatchItem> &items, BatchLayout *L)
         off = o + n;
         return o;
     };
-    L->counters_off = take(sizeof(unsigned long long) * std::max<size_t>(1, order.size()));
-    L->ncounters = (int)order.size();
     L->groups.clear();
     L->steps.clear();
     L->tiles = 0;
@@ -166,7 +164,6 @@ int build_batch_layout(const std::vector<BatchItem> &items, BatchLayout *L)
         BatchGroup g;
         g.items_off = take(kv.second.size() * sizeof(PassArgs));
         g.prefix_off = take((kv.second.size() + 1) * sizeof(int64_t));
-        g.counter_off = L->counters_off + gi * sizeof(unsigned long long);
         PassArgs *dst = (PassArgs *)(L->host.data() + g.items_off);
         int64_t *prefix = (int64_t *)(L->host.data() + g.prefix_off);
         prefix[0] = 0;
@@ -185,9 +182,7 @@ int build_batch_layout(const std::vector<BatchItem> &items, BatchLayout *L)
         for (int j = 0; j < g.nitems; ++j)
             for (int64_t t = prefix[j]; t < prefix[j + 1]; ++t) owner[t] = j;
         L->tiles += g.tiles;
-        const int64_t resident =
-            (int64_t)batch_blocks_per_cu(g.prec, g.kind, g.block, g.lds) * g_num_cus;
-        g.grid = (int)std::max<int64_t>(1, std::min<int64_t>(g.tiles, resident));
+        g.grid = (int)g.tiles;
         L->groups.push_back(g);
     }
     std::map<int, std::vector<int>> leaf_groups;   // phase -> group indices
@@ -261,10 +256,6 @@ int build_batch_layout(const std::vector<BatchItem> &items, BatchLayout *L)
 
 int enqueue_batch_layout(const BatchLayout &L, char *dev, hipStream_t s)
 {
-    if (L.ncounters > 0) {
-        hipError_t e = launch_zero_u64((unsigned long long *)(dev + L.counters_off), L.ncounters, s);
-        if (e != hipSuccess) return fail(MFFT_EHIP, std::string("batch launch: ") + hipGetErrorString(e));
-    }
     for (const BatchStep &st : L.steps) {
         hipError_t e;
         if (st.copy) {
@@ -287,9 +278,8 @@ int enqueue_batch_layout(const BatchLayout &L, char *dev, hipStream_t s)
             const BatchGroup &g = L.groups[st.group];
             e = launch_batch((const PassArgs *)(dev + g.items_off),
                              (const int64_t *)(dev + g.prefix_off),
-                             (const int32_t *)(dev + g.owner_off), g.tiles,
-                             (unsigned long long *)(dev + g.counter_off), g.prec, g.kind, g.block,
-                             g.grid, g.lds, s);
+                             (const int32_t *)(dev + g.owner_off), g.tiles, g.prec, g.kind,
+                             g.block, g.lds, s);
             if (e != hipSuccess)
                 return fail(MFFT_EHIP, std::string("batch launch (block ") + std::to_string(g.block) +
                                            ", lds " + std::to_string(g.lds) + ", grid " +
@@ -302,7 +292,7 @@ int enqueue_batch_layout(const BatchLayout &L, char *dev, hipStream_t s)
 
 int batch_launch_count(const BatchLayout &L)
 {
-    return (int)L.steps.size() + (L.ncounters > 0 ? 1 : 0);
+    return (int)L.steps.size();
 }
 
 }  // namespace mfft

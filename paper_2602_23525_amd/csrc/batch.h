@@ -1,5 +1,6 @@
 // Batch layout shared by mfft_batch_* and the request server: the host image
-// of the descriptor lists, prefix sums and counters, and the launch sequence.
+// of the descriptor lists, prefix sums and tile-to-item tables, and the launch
+// sequence.
 #pragma once
 #include <vector>
 
@@ -21,7 +22,7 @@ struct BatchGroup {
     int grid = 0;
     int nitems = 0;
     int64_t tiles = 0;
-    size_t items_off = 0, prefix_off = 0, counter_off = 0;   // offsets in the image
+    size_t items_off = 0, prefix_off = 0;   // offsets in the image
     size_t owner_off = 0;   // the item of each tile (int32)
 };
 
@@ -44,8 +45,6 @@ struct BatchStep {   // one launch: a group, a copy pass, a real-data step or a 
 struct BatchLayout {
     std::vector<unsigned char> host;   // device image (upload `bytes` of it)
     size_t bytes = 0;
-    size_t counters_off = 0;
-    int ncounters = 0;
     std::vector<BatchGroup> groups;
     std::vector<BatchStep> steps;
     int64_t tiles = 0;

@@ -49,14 +49,16 @@ hipError_t launch_real(const RealArgs &a, int prec, hipStream_t s);
 hipError_t launch_gen_roots(void *out, int prec, int64_t count, int64_t N, hipStream_t s);
 
 hipError_t launch_pass(const PassArgs &a, int prec, int emax, size_t lds_bytes, hipStream_t s);
+// Batched generic-kernel launch: one workgroup of `block` threads per tile of
+// the concatenated tile list (items, prefix sums and tile owners in device
+// memory).
 hipError_t launch_batch(const PassArgs *items_dev, const int64_t *prefix_dev,
-                        const int32_t *owner_dev, int64_t total, unsigned long long *counter,
-                        int prec, int kind, int block, int grid, size_t lds_bytes, hipStream_t s);
+                        const int32_t *owner_dev, int64_t total, int prec, int kind, int block,
+                        size_t lds_bytes, hipStream_t s);
 int pass_kind(uint32_t flags);
 // Batched-launch family of the variants with 24 elements per thread (lines
 // with radices 17, 19, 23): kWideKind + pass_kind, for kinds 0 and 1.
 constexpr int kWideKind = 16;
-int batch_blocks_per_cu(int prec, int kind, int block, size_t lds);
 hipError_t launch_copy(const CopyArgs &a, hipStream_t s);
 
 // In-place transpose of q x q blocks (the last step of an in-place two-pass
@@ -101,7 +103,6 @@ hipError_t launch_gen_rader(int32_t *gather, int32_t *scatter, void *b, int64_t 
                             hipStream_t s);
 hipError_t launch_convert_scale(void *out, int prec, const void *in, int64_t count, double scale,
                                 hipStream_t s);
-hipError_t launch_zero_u64(unsigned long long *p, int count, hipStream_t s);
 
 }  // namespace mfft
 

@@ -267,10 +267,8 @@ static inline unsigned blocks_for(int64_t count, int threads)
 #define MFFT_VARIANT(P, K)                                                                   \
     hipError_t launch_pass_##P##_k##K(const PassArgs &a, size_t lds, hipStream_t s);          \
     hipError_t launch_batch_##P##_k##K(const PassArgs *items, const int64_t *prefix,         \
-                                       const int32_t *owner, int64_t total,                   \
-                                       unsigned long long *counter, int block, int grid,      \
-                                       size_t lds, hipStream_t s);                            \
-    int batch_blocks_per_cu_##P##_k##K(int block, size_t lds);
+                                       const int32_t *owner, int64_t total, int block,        \
+                                       size_t lds, hipStream_t s);
 MFFT_VARIANT(c32, 0)
 MFFT_VARIANT(c32, 1)
 MFFT_VARIANT(c32, 5)
@@ -321,32 +319,13 @@ hipError_t launch_pass(const PassArgs &a, int prec, int emax, size_t lds_bytes, 
     return launch_pass_c64_k7(a, lds_bytes, s);
 }
 
-int batch_blocks_per_cu(int prec, int kind, int block, size_t lds)
-{
-    if (kind == kWideKind || kind == kWideKind + 1) {
-        if (prec == 0)
-            return kind == kWideKind ? batch_blocks_per_cu_c32_k0_e24(block, lds)
-                                     : batch_blocks_per_cu_c32_k1_e24(block, lds);
-        return kind == kWideKind ? batch_blocks_per_cu_c64_k0_e24(block, lds)
-                                 : batch_blocks_per_cu_c64_k1_e24(block, lds);
-    }
-    if (prec == 0) {
-        if (kind == 0) return batch_blocks_per_cu_c32_k0(block, lds);
-        if (kind == 1) return batch_blocks_per_cu_c32_k1(block, lds);
-        if (kind == 5) return batch_blocks_per_cu_c32_k5(block, lds);
-        return batch_blocks_per_cu_c32_k7(block, lds);
-    }
-    if (kind == 0) return batch_blocks_per_cu_c64_k0(block, lds);
-    if (kind == 1) return batch_blocks_per_cu_c64_k1(block, lds);
-    if (kind == 5) return batch_blocks_per_cu_c64_k5(block, lds);
-    return batch_blocks_per_cu_c64_k7(block, lds);
-}
-
 hipError_t launch_batch(const PassArgs *items_dev, const int64_t *prefix_dev,
-                        const int32_t *owner_dev, int64_t total, unsigned long long *counter,
-                        int prec, int kind, int block, int grid, size_t lds_bytes, hipStream_t s)
+                        const int32_t *owner_dev, int64_t total, int prec, int kind, int block,
+                        size_t lds_bytes, hipStream_t s)
 {
-#define MFFT_BATCH_ARGS items_dev, prefix_dev, owner_dev, total, counter, block, grid, lds_bytes, s
+    if (total <= 0) return hipSuccess;
+    if (total > 0x7fffffffLL) return hipErrorInvalidValue;
+#define MFFT_BATCH_ARGS items_dev, prefix_dev, owner_dev, total, block, lds_bytes, s
     if (kind == kWideKind || kind == kWideKind + 1) {
         if (prec == 0)
             return kind == kWideKind ? launch_batch_c32_k0_e24(MFFT_BATCH_ARGS)
@@ -621,19 +600,6 @@ hipError_t launch_convert_scale(void *out, int prec, const void *in, int64_t cou
     else
         hipLaunchKernelGGL(convert_scale<double>, dim3(blocks_for(count, 256)), dim3(256), 0, s,
                            (cpx<double> *)out, (const double2 *)in, count, scale);
-    return hipGetLastError();
-}
-
-// Clears a counter array with a kernel (graph-capture friendly).
-__global__ void zero_u64(unsigned long long *p, int count)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < count) p[i] = 0ull;
-}
-
-hipError_t launch_zero_u64(unsigned long long *p, int count, hipStream_t s)
-{
-    hipLaunchKernelGGL(zero_u64, dim3(blocks_for(count, 256)), dim3(256), 0, s, p, count);
     return hipGetLastError();
 }
 

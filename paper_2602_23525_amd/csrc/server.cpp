@@ -452,7 +452,7 @@ static void server_loop(mfft_server_s *S)
             }
             const PlanImpl *p = &q->plan->impl;
             // descriptor image bound: per pass one descriptor, a prefix entry and
-            // (at worst) its own group's alignment padding and counter
+            // (at worst) its own group's alignment padding
             const size_t dneed = p->passes.size() * (sizeof(PassArgs) + 8 + 520) + 64;
             if (desc_need + dneed > S->descs.size() - S->descs.used()) {
                 if (tick.empty() && S->inflight.empty()) {

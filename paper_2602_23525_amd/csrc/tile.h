@@ -618,39 +618,22 @@ __global__ __launch_bounds__(max_block<T>(EMAX)) void pass_kernel(PassArgs a)
     run_tile<T, EMAX, KIND>(*ap, tile, lds);
 }
 
-// Persistent batched kernel: workgroups pop tiles from a shared counter until
-// the list is exhausted.  items[i] covers tiles [prefix[i], prefix[i+1]);
-// owner[t] is the item of tile t, total the number of tiles.
+// Batched kernel over the passes of many plans, one tile per workgroup:
+// workgroup g runs tile g of the concatenated tile list (items[i] covers tiles
+// [prefix[i], prefix[i+1]), owner[g] is the item of tile g).  The hardware
+// dispatcher starts each next workgroup where one finishes, as in a
+// single-pass launch (measured on MI355X against a persistent grid popping
+// tiles from a counter: the 7-smooth class of the uneven batch 5.10 -> 4.70 ms).
 template <typename T, int EMAX, int KIND>
 __global__ __launch_bounds__(max_block<T>(EMAX)) void batch_kernel(const PassArgs *__restrict__ items,
                                                      const int64_t *__restrict__ prefix,
-                                                     const int32_t *__restrict__ owner,
-                                                     int64_t total, unsigned long long *counter)
+                                                     const int32_t *__restrict__ owner)
 {
     extern __shared__ unsigned char smem[];
     cpx<T> *lds = (cpx<T> *)smem;
-    __shared__ long long next;
-    if (threadIdx.x == 0) next = (long long)atomicAdd(counter, 1ull);
-    __syncthreads();
-    for (;;) {
-        // the popped index is the same for the whole workgroup: make it a
-        // scalar so the descriptor reads below are scalar loads
-        const uint64_t gv = (uint64_t)next;
-        const int64_t g = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane(
-                                         (int)(gv >> 32)) << 32) |
-                                    (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)gv));
-        if (g >= total) break;
-        // pop the following tile now: the atomic's round trip overlaps this
-        // tile's loads instead of preceding the next tile's (past the end of
-        // the batch it pops an index no tile has; the counter is reset per launch)
-        unsigned long long popped = 0;
-        if (threadIdx.x == 0) popped = atomicAdd(counter, 1ull);
-        // the item holding tile g, from the tile-to-item table
-        const int i = owner[g];
-        run_tile<T, EMAX, KIND>(items[i], g - prefix[i], lds);   // ends with a barrier
-        if (threadIdx.x == 0) next = (long long)popped;
-        __syncthreads();
-    }
+    const int64_t g = blockIdx.x;
+    const int i = owner[g];
+    run_tile<T, EMAX, KIND>(items[i], g - prefix[i], lds);
 }
 
 }  // namespace mfft

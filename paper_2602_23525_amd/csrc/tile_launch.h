@@ -1,6 +1,5 @@
 // Launchers of one variant (element type, kernel kind, elements per thread)
-// of the generic tile kernel: the single-pass launch, the persistent batched
-// launch and its occupancy query.  Each variant is instantiated by a
+// of the generic tile kernel: the single-pass launch and the batched launch.  Each variant is instantiated by a
 // translation unit of its own (k_c{32,64}_k{0,1,5,7}.hip, and
 // k_c{32,64}_k{0,1}_e24.hip for lines with radices 17, 19, 23) so that the
 // variants compile in parallel.
@@ -42,50 +41,33 @@ struct TileLaunch {
         return hipGetLastError();
     }
 
+    // batched launch: one workgroup per tile of the concatenated list
     static hipError_t batch(const PassArgs *items, const int64_t *prefix, const int32_t *owner,
-                            int64_t total, unsigned long long *counter, int block, int grid,
-                            size_t lds, hipStream_t s)
+                            int64_t total, int block, size_t lds, hipStream_t s)
     {
         static size_t granted = 65536;
         hipError_t e = allow_dynamic_lds((const void *)batch_kernel<T, EMAX, KIND>, lds, &granted, &mu());
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((batch_kernel<T, EMAX, KIND>), dim3(grid), dim3(block), lds, s, items,
-                           prefix, owner, total, counter);
+        hipLaunchKernelGGL((batch_kernel<T, EMAX, KIND>), dim3((unsigned)total), dim3(block), lds, s,
+                           items, prefix, owner);
         return hipGetLastError();
-    }
-
-    static int blocks_per_cu(int block, size_t lds)
-    {
-        int b = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, batch_kernel<T, EMAX, KIND>, block, lds) !=
-            hipSuccess) {
-            (void)hipGetLastError();
-            return 1;
-        }
-        return b > 0 ? b : 1;
     }
 };
 
 }  // namespace mfft
 
-// The three entry points of variant NAME (kernels.hip dispatches to them).
+// The two entry points of variant NAME (kernels.hip dispatches to them).
 #define MFFT_TILE_LAUNCHERS(T, NAME, KIND) MFFT_TILE_LAUNCHERS_E(T, NAME, KIND, 16)
 #define MFFT_TILE_LAUNCHERS_E(T, NAME, KIND, EMAX)                                                \
     namespace mfft {                                                                              \
     hipError_t launch_pass_##NAME(const PassArgs &a, size_t lds, hipStream_t s)                   \
     {                                                                                             \
-        return TileLaunch<T, KIND, EMAX>::pass(a, lds, s);                                              \
+        return TileLaunch<T, KIND, EMAX>::pass(a, lds, s);                                        \
     }                                                                                             \
     hipError_t launch_batch_##NAME(const PassArgs *items, const int64_t *prefix,                  \
-                                   const int32_t *owner, int64_t total,                           \
-                                   unsigned long long *counter, int block, int grid, size_t lds,  \
+                                   const int32_t *owner, int64_t total, int block, size_t lds,    \
                                    hipStream_t s)                                                 \
     {                                                                                             \
-        return TileLaunch<T, KIND, EMAX>::batch(items, prefix, owner, total, counter, block, grid, lds, \
-                                          s);                                                     \
-    }                                                                                             \
-    int batch_blocks_per_cu_##NAME(int block, size_t lds)                                         \
-    {                                                                                             \
-        return TileLaunch<T, KIND, EMAX>::blocks_per_cu(block, lds);                                    \
+        return TileLaunch<T, KIND, EMAX>::batch(items, prefix, owner, total, block, lds, s);      \
     }                                                                                             \
     }

@@ -1,4 +1,4 @@
-"""GPU tests of batches across plans: uneven sizes in persistent launches (with
+"""GPU tests of batches across plans: uneven sizes in batched launches (with
 and without a HIP graph) give, item by item, the transform of the oracle, and
 the same result as each plan executed alone (within the precision's bound)."""
 import numpy as np
