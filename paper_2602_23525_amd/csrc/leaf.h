@@ -210,10 +210,23 @@ constexpr int leaf_lds_stride() { return (lds_pad(N - 1) + 1) | 1; }
 
 // The leaf pass from tile `tile` on, every G-th tile, with the tile's LDS at
 // lds (BT lines of leaf_lds_stride<N>() elements).
+// The compile-time radix list Rs... is the one the planner lays the stage
+// twiddle table out for (leaf_radix_at).
+template <int N, int... Rs>
+constexpr bool leaf_radices_match()
+{
+    constexpr int r[] = {Rs...};
+    if ((int)sizeof...(Rs) != leaf_radix_count(N)) return false;
+    for (int i = 0; i < (int)sizeof...(Rs); ++i)
+        if (r[i] != leaf_radix_at(N, i)) return false;
+    return true;
+}
+
 template <typename T, int N, int BT, bool PF, int NT, int RD, int... Rs>
 __device__ __forceinline__ void leaf_body(const PassArgs &a, cpx<T> *lds, int64_t tile,
                                           const int64_t G)
 {
+    static_assert(leaf_radices_match<N, Rs...>(), "radix list differs from the planner's table layout");
     constexpr int TPT = N / 16;
     constexpr int STRIDE = leaf_lds_stride<N>();
     constexpr bool cols_in = RD == 3 || RD == 4 || RD == 6 || RD == 8;

@@ -31,6 +31,14 @@ constexpr bool leaf_supported(int prec, int64_t n)
 }
 inline int leaf_lines_per_tile(int prec, int n) { return leaf_row_lines(prec, n); }
 
+// Radix sequence of the leaf kernel for a supported length n = 2^e, in
+// execution order: e/4 stages of radix 16, then one of radix 2^(e mod 4)
+// when that is above 1.  The kernel's stage twiddle table is laid out for
+// this sequence, whatever sequence a generic-kernel plan of n would use.
+constexpr int leaf_log2(int64_t n) { return n > 1 ? 1 + leaf_log2(n / 2) : 0; }
+constexpr int leaf_radix_count(int64_t n) { return leaf_log2(n) / 4 + (leaf_log2(n) % 4 ? 1 : 0); }
+constexpr int leaf_radix_at(int64_t n, int i) { return i < leaf_log2(n) / 4 ? 16 : 1 << (leaf_log2(n) % 4); }
+
 // Column tiles: 64-2048 points; transposing ones (columns in, rows out or the
 // reverse) from 256, so that a row run is at least 16 lanes
 constexpr bool leaf_col_supported(int prec, int64_t n, bool transposing)

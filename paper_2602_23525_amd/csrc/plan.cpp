@@ -393,7 +393,14 @@ static int fill_leaf(PlanImpl *p, const Leaf &L, PassArgs *a,
     }
     lds_layouts(L.n, a->nst, L.tpt, L.lds_stride, L.emax, (int)elem_bytes(p->prob.prec), a->st);
     int rc = stage_table(p, L, jmajor, cache, &a->tw);
-    if (rc == MFFT_OK && leaf_kernel) rc = stage_table(p, L, false, cache, &a->tw_leaf);
+    if (rc == MFFT_OK && leaf_kernel) {
+        // the leaf kernel's own radix sequence (its table layout), which a
+        // measured or imported structure for this length does not change
+        Leaf Lk = L;
+        Lk.rad.clear();
+        for (int i = 0; i < leaf_radix_count(L.n); ++i) Lk.rad.push_back(leaf_radix_at(L.n, i));
+        rc = stage_table(p, Lk, false, cache, &a->tw_leaf);
+    }
     return rc;
 }
 

@@ -23,6 +23,9 @@
 //     every structural candidate measure mode would time for each length
 //     (radix sequences, lines per tile, splits, Rader / Bluestein lengths),
 //     planned with that choice and checked like the estimate's plan.
+//   plan_host_check forced <prec> <n> <choice> <batch>
+//     plans n with a structure choice forced on it ("r=16.8.8.8:b=2", the
+//     wisdom grammar) and checks the plan.
 //   plan_host_check steps <n> <R.R...>
 //     plans one n-point transform with the radix sequence forced (Stockham
 //     stages in execution order) and prints its stage descriptors, then the
@@ -259,8 +262,18 @@ struct Checker {
                      sd.tw_off + (int64_t)(ps.prec ? sd.R : sd.R - 1) * sd.Ns - 1, eb, 0);
         }
         if (leaf) {
-            int64_t total = 0;
-            for (int s = 0; s < a.nst; ++s) total += (int64_t)a.st[s].Ns * a.st[s].R;
+            // laid out for the leaf kernel's own radix sequence (the one its
+            // instantiations compile), whatever a.st holds
+            int64_t total = 0, Ns = 1;
+            for (int s = 0; s < leaf_radix_count(a.n); ++s) {
+                total += Ns * leaf_radix_at(a.n, s);
+                Ns *= leaf_radix_at(a.n, s);
+            }
+            if (Ns != a.n) {
+                std::printf("VIOLATION %s: leaf radices do not multiply to n (%s)\n", name.c_str(),
+                            ps.desc.c_str());
+                ++violations;
+            }
             need(ps, "stage (leaf layout)", a.tw_leaf, total - 1, eb, 0);
         }
         if (!leaf) {
@@ -435,6 +448,30 @@ int main(int argc, char **argv)
         std::printf("checked lengths=%d candidates=%d planned=%d violations=%d failed=%d\n", lengths,
                     cands, planned, violations, failed);
         return violations || failed ? 1 : 0;
+    }
+    if (argc >= 6 && !std::strcmp(argv[1], "forced")) {
+        // one length planned with a structure text forced on it (as wisdom
+        // would), then checked like any plan
+        const int prec = std::atoi(argv[2]);
+        const int64_t n = std::atoll(argv[3]), batch = std::atoll(argv[5]);
+        mfft_plan_s pl;
+        PlanImpl *p = &pl.impl;
+        int64_t n2 = 0;
+        StructChoice c;
+        if (!parse_choice("n=" + std::to_string(n) + ":" + argv[4], &n2, &c)) return 2;
+        p->overrides[n] = c;
+        if (host_plan(p, prec, n, batch)) {
+            std::printf("PLAN FAILED\n");
+            return 1;
+        }
+        Checker ck{p, "n=" + std::to_string(n) + " forced " + argv[4]};
+        for (const Pass &ps : p->passes) {
+            ck.check_pass(ps);
+            std::printf("%s kernel=%d\n", ps.desc.c_str(), ps.kernel);
+        }
+        std::printf("checked passes=%d lds=%d violations=%d\n", (int)p->passes.size(), ck.lds_checked,
+                    ck.violations);
+        return ck.violations ? 1 : 0;
     }
     if (argc >= 4 && !std::strcmp(argv[1], "steps")) {
         const int64_t n = std::atoll(argv[2]);

@@ -98,6 +98,23 @@ def test_measure_candidates_plan_and_stay_inside_their_tables(checker, prec, lo,
     assert s["violations"] == 0 and s["failed"] == 0 and s["candidates"] > s["lengths"]
 
 
+@pytest.mark.parametrize("prec,n,rad", [(0, 8192, "16.8.8.8"), (0, 16384, "4.16.16.16"),
+                                         (1, 8192, "8.8.8.16"), (0, 1024, "4.4.4.4.4"),
+                                         (0, 2048, "2.16.4.16")])
+def test_forced_radices_keep_the_leaf_kernels_table(checker, prec, n, rad):
+    """A power-of-two length runs in the specialized leaf kernel, whose stage
+    twiddle table is laid out for its own radix sequence (radix-16 stages,
+    then 2^(e mod 4)).  A structure imported as wisdom that names another
+    sequence for the length changes the generic shape only: the leaf kernel's
+    table still covers what the kernel reads (a table laid out for 16.8.8.8
+    holds 9360 entries where the kernel reads up to index 12559)."""
+    r = subprocess.run([checker, "forced", str(prec), str(n), "r=" + rad, "4"],
+                       capture_output=True, text=True)
+    print(r.stdout[-2000:])
+    assert r.returncode == 0 and "VIOLATION" not in r.stdout, r.stdout + r.stderr
+    assert "kernel=1" in r.stdout   # the specialized leaf kernel runs it
+
+
 def test_fig3_plan_of_30_with_radices_3_2_5(checker):
     """Fig. 3 (Section 4.2, "Discussion"): n = 30 planned by DIT steps of radix
     3, then 2, then 5.  Here the steps are Stockham stages, executed innermost
