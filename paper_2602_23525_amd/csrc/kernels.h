@@ -56,6 +56,9 @@ hipError_t launch_batch(const PassArgs *items_dev, const int64_t *prefix_dev,
                         const int32_t *owner_dev, int64_t total, int prec, int kind, int block,
                         size_t lds_bytes, hipStream_t s);
 int pass_kind(uint32_t flags);
+// Resident workgroups per CU of the single-pass generic kernel for a pass of
+// kind `kind` (pass_kind) with `emax` elements per thread.
+int pass_blocks_per_cu(int prec, int kind, int emax, int block, size_t lds);
 // Batched-launch family of the variants with 24 elements per thread (lines
 // with radices 17, 19, 23): kWideKind + pass_kind, for kinds 0 and 1.
 constexpr int kWideKind = 16;

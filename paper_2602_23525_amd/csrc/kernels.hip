@@ -268,7 +268,8 @@ static inline unsigned blocks_for(int64_t count, int threads)
     hipError_t launch_pass_##P##_k##K(const PassArgs &a, size_t lds, hipStream_t s);          \
     hipError_t launch_batch_##P##_k##K(const PassArgs *items, const int64_t *prefix,         \
                                        const int32_t *owner, int64_t total, int block,        \
-                                       size_t lds, hipStream_t s);
+                                       size_t lds, hipStream_t s);                            \
+    int pass_blocks_per_cu_##P##_k##K(int block, size_t lds);
 MFFT_VARIANT(c32, 0)
 MFFT_VARIANT(c32, 1)
 MFFT_VARIANT(c32, 5)
@@ -317,6 +318,25 @@ hipError_t launch_pass(const PassArgs &a, int prec, int emax, size_t lds_bytes, 
     if (k == 1) return launch_pass_c64_k1(a, lds_bytes, s);
     if (k == 5) return launch_pass_c64_k5(a, lds_bytes, s);
     return launch_pass_c64_k7(a, lds_bytes, s);
+}
+
+int pass_blocks_per_cu(int prec, int kind, int emax, int block, size_t lds)
+{
+    if (emax > 16) {
+        if (kind > 1) return 1;
+        if (prec == 0) return kind ? pass_blocks_per_cu_c32_k1_e24(block, lds) : pass_blocks_per_cu_c32_k0_e24(block, lds);
+        return kind ? pass_blocks_per_cu_c64_k1_e24(block, lds) : pass_blocks_per_cu_c64_k0_e24(block, lds);
+    }
+    if (prec == 0) {
+        if (kind == 0) return pass_blocks_per_cu_c32_k0(block, lds);
+        if (kind == 1) return pass_blocks_per_cu_c32_k1(block, lds);
+        if (kind == 5) return pass_blocks_per_cu_c32_k5(block, lds);
+        return pass_blocks_per_cu_c32_k7(block, lds);
+    }
+    if (kind == 0) return pass_blocks_per_cu_c64_k0(block, lds);
+    if (kind == 1) return pass_blocks_per_cu_c64_k1(block, lds);
+    if (kind == 5) return pass_blocks_per_cu_c64_k5(block, lds);
+    return pass_blocks_per_cu_c64_k7(block, lds);
 }
 
 hipError_t launch_batch(const PassArgs *items_dev, const int64_t *prefix_dev,

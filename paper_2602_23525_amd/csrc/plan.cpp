@@ -99,6 +99,17 @@ static int stage_threads(int64_t n, int R, int emax)
 // that need a radix 17, 19 or 23 (the kernel variant that holds them).
 static int leaf_emax(int64_t n) { return is_smooth(n) ? 16 : 24; }
 
+// Shortest LDS padding period of a generic leaf: 16 elements, or 64 for lines
+// above 4096 points with 24 elements per thread (one line per tile: the
+// saving lets two tiles share a CU, e.g. 10000 FP32 points in 81 KB rather
+// than 85 KB).  Lines of 16 per thread keep 16: with 64, 12000 x 2048 FP32
+// ran 178 -> 207 us from the bank conflicts of radix-16 stages.
+static int pad_period_min(int64_t n, int emax) { return emax > 16 && n > 4096 ? 64 : 16; }
+
+// 7-smooth lengths a generic leaf may also run with 24 elements per thread
+// (plain and twiddled unit-stride lines; 512 threads hold them).
+static bool wide_range(int64_t n) { return is_smooth(n) && n > 4096 && n <= 10240; }
+
 // Radix sequence of a leaf of length n (smooth): the fewest stages over the
 // radices the tile kernel compiles whose thread need fits max_tpt (each stage
 // is one LDS exchange); among those, the smallest thread count, then larger
@@ -183,18 +194,18 @@ static bool radices_for(int64_t n, int emax, int max_tpt, std::vector<int> *r)
     return true;
 }
 
-static int line_lds_stride(int n)
+static int line_lds_stride(int n, int emax)
 {
-    int s = lds_pad(n - 1) + 1;
+    int s = n + (n - 1) / pad_period_min(n, emax) + 1;
     return s | 1;
 }
 
 // Dynamic LDS requested by scattering passes: at most two workgroups per CU.
 constexpr size_t kScatterLdsBytes = 64 * 1024;
 
-static size_t tile_lds_bytes(int n, int bt, int prec)
+static size_t tile_lds_bytes(int n, int bt, int prec, int emax = 16)
 {
-    return ((size_t)bt * line_lds_stride(n) + 2 * (size_t)bt) * elem_bytes(prec);
+    return ((size_t)bt * line_lds_stride(n, emax) + 2 * (size_t)bt) * elem_bytes(prec);
 }
 
 static bool leaf_shape_from(int64_t n, int emax, int max_tpt, const std::vector<int> &rad, Leaf *L);
@@ -230,8 +241,40 @@ static bool leaf_shape_from(int64_t n, int emax, int max_tpt, const std::vector<
     L->rad = rad;
     L->emax = emax;
     L->tpt = tpt;
-    L->lds_stride = line_lds_stride((int)n);
+    L->lds_stride = line_lds_stride((int)n, emax);
     return true;
+}
+
+// A plain unit-stride line of length n fits a leaf pass with 24 elements per
+// thread.
+static bool wide_leaf_fits(int64_t n, int prec)
+{
+    Leaf L;
+    return wide_range(n) && make_leaf_shape(n, 24, max_threads(prec, 24), &L) &&
+           tile_lds_bytes((int)n, 1, prec, 24) <= g_lds_budget;
+}
+
+// Estimate-mode choice of 24 elements per thread for a plain unit-stride
+// line in wide_range: when 16 per thread has no one-pass shape, when 24 needs
+// fewer stages (FP64 lines of 512 threads otherwise fall to radix 3), or when
+// its half-size workgroups let more tiles share a CU without fewer resident
+// threads (a 10000-point FP32 line: one 1000-thread workgroup per CU, or two
+// of 500).  Measured on MI355X, 16 -> 24: 10000 x 2048 FP32 127 -> 103 us,
+// 8000 x 2048 107 -> 95 us, 6561 x 2048 FP64 228 -> 161 us, 8000 x 1024 FP64
+// 164 -> 98 us (two passes -> one); 6561 x 4096 FP32 139 -> 158 us (two
+// workgroups of 729 threads per CU against two of 365) keeps 16.
+static bool prefer_wide(int64_t n, int prec, int kind)
+{
+    if (!wide_leaf_fits(n, prec)) return false;
+    Leaf a, w;
+    make_leaf_shape(n, 24, max_threads(prec, 24), &w);
+    if (!make_leaf_shape(n, 16, max_threads(prec, 16), &a) ||
+        tile_lds_bytes((int)n, 1, prec) > g_lds_budget)
+        return true;
+    if (w.rad.size() < a.rad.size()) return true;
+    const int o16 = pass_blocks_per_cu(prec, kind, 16, a.tpt, tile_lds_bytes((int)n, 1, prec));
+    const int o24 = pass_blocks_per_cu(prec, kind, 24, w.tpt, tile_lds_bytes((int)n, 1, prec, 24));
+    return o24 > o16 && (int64_t)o24 * w.tpt >= (int64_t)o16 * a.tpt;
 }
 
 // A line of length n fits a leaf pass with at least `bt` lines per tile.
@@ -240,7 +283,7 @@ static bool leaf_fits(int64_t n, int prec, int bt)
     Leaf L;
     const int mt = max_threads(prec, leaf_emax(n));
     if (!make_leaf_shape(n, leaf_emax(n), mt / bt, &L)) return false;
-    return tile_lds_bytes((int)n, bt, prec) <= g_lds_budget && bt * L.tpt <= mt;
+    return tile_lds_bytes((int)n, bt, prec, L.emax) <= g_lds_budget && bt * L.tpt <= mt;
 }
 
 // Stage twiddle tables of a leaf: stage s holds w_(Ns*R)^(j*k) for j < Ns.
@@ -315,13 +358,15 @@ static int lds_access_cycles(const int (&addr)[64], int eb)
 
 // LDS layouts of a generic leaf's stages (StageDesc::rd_stride, rd_shift,
 // wr_shift): for each stage boundary, the padding period G*2^sh (G = Ns*R of
-// the writing stage) or none, among those of at least 16 elements (a line
-// then never needs more than lds_pad(n - 1) + 1 slots) that divide the next
+// the writing stage) or none, among those of at least pad_period_min(n, emax)
+// elements (a line then never needs more than line_lds_stride(n, emax) slots) that
+// divide the next
 // stage's butterfly count (its reads stay affine), with the fewest modeled
 // bank-conflict cycles over the first wave's writes and the next stage's
 // reads; ties go to no padding, then to the longer period.
 void lds_layouts(int n, int nst, int tpt, int lds_stride, int emax, int eb, StageDesc *st)
 {
+    const int pmin = pad_period_min(n, emax);
     constexpr int kNone = 31;
     auto lane_cost = [&](int s, int sh, bool write) {
         const StageDesc &sd = st[s];
@@ -355,7 +400,7 @@ void lds_layouts(int n, int nst, int tpt, int lds_stride, int emax, int eb, Stag
             int rstride = nbn;
             if (sh != kNone) {
                 const int64_t per = (int64_t)G << sh;
-                if (per < 16 || per > nbn || nbn % per != 0) continue;
+                if (per < pmin || per > nbn || nbn % per != 0) continue;
                 rstride = nbn + (int)(nbn / per);
             }
             nx.rd_stride = rstride;
@@ -544,15 +589,15 @@ static bool leaf_col_fits(const LineSpec &ls, const PassArgs &a, const Dim &in_d
 // the vector loop has.  Among the classes, the best filled; ties go to the
 // smaller.  (Powers of two alone left up to a quarter of the lanes idle, e.g.
 // 200 of 256 threads for 1000-point lines.)
-int row_lines_per_tile(int n, int tpt, int prec, int64_t lines)
+int row_lines_per_tile(int n, int tpt, int prec, int64_t lines, int emax)
 {
-    const int mt = max_threads(prec, leaf_emax(n));
+    const int mt = max_threads(prec, emax ? emax : leaf_emax(n));
     int best = 1;
     double best_fill = -1;
     for (int cls = 256; cls <= mt; cls *= 2) {
         int bt = std::max(1, cls / tpt);
-        while (bt > 1 && tile_lds_bytes(n, bt, prec) > 65536) --bt;
-        while (bt > 1 && tile_lds_bytes(n, bt, prec) > g_lds_budget) --bt;
+        while (bt > 1 && tile_lds_bytes(n, bt, prec, emax ? emax : leaf_emax(n)) > 65536) --bt;
+        while (bt > 1 && tile_lds_bytes(n, bt, prec, emax ? emax : leaf_emax(n)) > g_lds_budget) --bt;
         if (lines > 0) bt = (int)std::max<int64_t>(1, std::min<int64_t>(bt, lines));
         int block = 256;
         while (block < bt * tpt) block *= 2;
@@ -628,11 +673,22 @@ static int add_line_pass(Builder &b, const LineSpec &ls)
     // 256-thread workgroups.  Both bounded by the LDS budget.
     const bool col = a.load_mode == kModeCol || a.store_mode == kModeCol;
     const int bt_floor = col ? (prec ? 4 : 8) : 1;
-    const int emax = leaf_emax(n);
+    // elements per thread: 24 for radices 17, 19, 23; for plain and twiddled
+    // unit-stride row lines in wide_range as measured or estimated; else 16
+    const bool plain_tw = !(ls.flags & ~(PF_CONJ_IN | PF_CONJ_OUT | PF_TW4 | PF_XCD));
+    int emax = leaf_emax(n);
+    if (emax > 16 && !plain_tw)
+        return fail(MFFT_ENOTSUP, "radices above 16 only in plain or twiddled lines");
+    if (emax == 16 && plain_tw && !col && ls.line.is == 1 && ls.line.os == 1 && wide_range(n)) {
+        const int kind = (ls.flags & PF_TW4) ? 1 : 0;
+        if (ch && ch->emax) {
+            if (ch->emax == 24 && wide_leaf_fits(n, prec)) emax = 24;
+        } else if (prefer_wide(n, prec, kind)) {
+            emax = 24;
+        }
+    }
     const int mt = max_threads(prec, emax);
     Leaf L;
-    if (emax > 16 && (ls.flags & ~(PF_CONJ_IN | PF_CONJ_OUT | PF_TW4 | PF_XCD)))
-        return fail(MFFT_ENOTSUP, "radices above 16 only in plain or twiddled lines");
     if (!make_leaf_shape(n, emax, mt / bt_floor, &L) && !make_leaf_shape(n, emax, mt, &L))
         return fail(MFFT_ENOTSUP, "no leaf shape for n");
     if (ch && !ch->rad.empty()) {
@@ -648,22 +704,22 @@ static int add_line_pass(Builder &b, const LineSpec &ls)
     int bt;
     if (col) {
         bt = prec ? 8 : 16;
-        while (bt > bt_floor && (tile_lds_bytes(L.n, bt, prec) > 65536 || bt * L.tpt > mt)) bt >>= 1;
-        while (bt > 1 && (tile_lds_bytes(L.n, bt, prec) > g_lds_budget || bt * L.tpt > mt)) bt >>= 1;
+        while (bt > bt_floor && (tile_lds_bytes(L.n, bt, prec, L.emax) > 65536 || bt * L.tpt > mt)) bt >>= 1;
+        while (bt > 1 && (tile_lds_bytes(L.n, bt, prec, L.emax) > g_lds_budget || bt * L.tpt > mt)) bt >>= 1;
         while (bt > 1 && bt / 2 >= in_dim.n) bt >>= 1;   // no wider than the loop
     } else {
-        bt = row_lines_per_tile(L.n, L.tpt, prec, in_dim.n);
+        bt = row_lines_per_tile(L.n, L.tpt, prec, in_dim.n, L.emax);
         if (ch && ch->bt > 0 && ch->bt * L.tpt <= mt &&
-            tile_lds_bytes(L.n, ch->bt, prec) <= g_lds_budget)
+            tile_lds_bytes(L.n, ch->bt, prec, L.emax) <= g_lds_budget)
             bt = (int)std::max<int64_t>(1, std::min<int64_t>(ch->bt, in_dim.n));
     }
-    if (tile_lds_bytes(L.n, bt, prec) > g_lds_budget || bt * L.tpt > mt)
+    if (tile_lds_bytes(L.n, bt, prec, L.emax) > g_lds_budget || bt * L.tpt > mt)
         return fail(MFFT_ENOTSUP, "leaf does not fit the LDS budget");
     a.bt = bt;
     a.bt_log2 = ilog2(bt);
     a.ntiles_inner = (a.vn + bt - 1) / bt;
     a.ntiles = a.ntiles_inner * nouter_total;
-    ps.lds_bytes = tile_lds_bytes(L.n, bt, prec);
+    ps.lds_bytes = tile_lds_bytes(L.n, bt, prec, L.emax);
     if ((ls.flags & PF_SCATTER) && (ls.flags & PF_XCD)) {
         // A scattering pass fills each cache line of its output from many
         // tiles; lines written back before they are full cost a partial
@@ -1494,7 +1550,8 @@ static int plan_line(Builder &b, Dim d, std::vector<Dim> V, int src, int dst, in
                          (leaf_fits(n, prec, 1) || split_for(b.p, n, prec, &wsp));
     if (is_smooth(n) || wide_ok) {
         const bool strided = std::llabs(d.is) != 1 || std::llabs(d.os) != 1;
-        if (leaf_fits(n, prec, strided ? (prec ? 4 : 8) : 1) || leaf_fits(n, prec, 1)) {
+        if (leaf_fits(n, prec, strided ? (prec ? 4 : 8) : 1) || leaf_fits(n, prec, 1) ||
+            (!strided && wide_leaf_fits(n, prec) && !(choice_for(b.p, n) && choice_for(b.p, n)->split))) {
             const bool inplace = src == dst && src_off == dst_off;
             if (!inplace || d.is == d.os)
                 return plan_leaf(b, d, V, src, dst, src_off, dst_off, conj_in, conj_out);
@@ -1724,12 +1781,15 @@ static StructChoice estimate_choice(const PlanImpl *p, int64_t n)
         return c;
     }
     if (!is_smooth23(n)) return c;
-    if (leaf_fits(n, prec, 1)) {
+    if (leaf_fits(n, prec, 1) || wide_leaf_fits(n, prec)) {
         if (leaf_supported(prec, n)) return c;
+        // (a unit-stride line of a batch: the estimate's elements per thread)
+        const int emax = wide_range(n) && prefer_wide(n, prec, 0) ? 24 : leaf_emax(n);
         Leaf L;
-        if (make_leaf_shape(n, leaf_emax(n), max_threads(prec, leaf_emax(n)), &L)) {
+        if (make_leaf_shape(n, emax, max_threads(prec, emax), &L)) {
             c.rad = L.rad;
-            c.bt = row_lines_per_tile(L.n, L.tpt, prec, 0);
+            c.bt = row_lines_per_tile(L.n, L.tpt, prec, 0, emax);
+            if (wide_range(n)) c.emax = emax;
         }
         return c;
     }
@@ -1778,6 +1838,17 @@ std::vector<StructChoice> structure_candidates(const PlanImpl *p, int64_t n)
         return out;
     }
     if (!is_smooth23(n)) return out;
+    if (wide_leaf_fits(n, prec)) {
+        // one pass with 24 or 16 elements per thread (radices and lines per
+        // tile as the estimate shapes them), and the two-pass splits below
+        for (int e : {24, 16}) {
+            Leaf L;
+            if (!make_leaf_shape(n, e, max_threads(prec, e), &L)) continue;
+            StructChoice c;
+            c.emax = e;
+            out.push_back(c);
+        }
+    }
     if (leaf_fits(n, prec, 1)) {
         // one pass; powers of two run in the specialized leaf kernel (fixed
         // radices), the rest in the generic kernel
@@ -1797,7 +1868,7 @@ std::vector<StructChoice> structure_candidates(const PlanImpl *p, int64_t n)
             const int bt = row_lines_per_tile(L.n, L.tpt, prec, 0);
             for (int b2 : {bt / 2, bt * 2}) {
                 if (b2 < 1 || b2 == bt || b2 * L.tpt > mt ||
-                    tile_lds_bytes(L.n, b2, prec) > g_lds_budget)
+                    tile_lds_bytes(L.n, b2, prec, L.emax) > g_lds_budget)
                     continue;
                 StructChoice cb = c;
                 cb.bt = b2;
@@ -1823,7 +1894,7 @@ std::vector<StructChoice> structure_candidates(const PlanImpl *p, int64_t n)
     return out;
 }
 
-// "n=<length>[:r=<R>.<R>...][:b=<lines>][:s=<split>][:a=R|B][:M=<length>]"
+// "n=<length>[:r=<R>.<R>...][:b=<lines>][:s=<split>][:a=R|B][:M=<length>][:e=16|24]"
 std::string choice_text(int64_t n, const StructChoice &c)
 {
     std::ostringstream s;
@@ -1836,6 +1907,7 @@ std::string choice_text(int64_t n, const StructChoice &c)
     if (c.split) s << ":s=" << c.split;
     if (c.prime) s << ":a=" << (c.prime == 1 ? "R" : "B");
     if (c.M) s << ":M=" << c.M;
+    if (c.emax) s << ":e=" << c.emax;
     return s.str();
 }
 
@@ -1873,6 +1945,10 @@ bool parse_choice(const std::string &text, int64_t *n, StructChoice *c)
             else return false;
             break;
         case 'M': c->M = std::strtoll(v.c_str(), &end, 10); break;
+        case 'e':
+            c->emax = (int)std::strtol(v.c_str(), &end, 10);
+            if (c->emax != 16 && c->emax != 24) return false;
+            break;
         default: return false;
         }
         if (end && *end) return false;
@@ -2297,7 +2373,7 @@ PermuteArgs resolve_permute(const PlanImpl *p, const Pass &ps, const void *in, v
 
 size_t generic_lds_bytes(const Pass &ps)
 {
-    return tile_lds_bytes(ps.a.n, ps.a.bt, ps.prec);
+    return tile_lds_bytes(ps.a.n, ps.a.bt, ps.prec, ps.emax);
 }
 
 int run_plan(const PlanImpl *p, const void *in, void *out, void *scratch, hipStream_t s)

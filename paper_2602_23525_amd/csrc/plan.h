@@ -84,7 +84,8 @@ struct StructChoice {
     int64_t split = 0;      // two-pass Cooley-Tukey: length of the first pass's lines
     int prime = 0;          // prime length: 1 Rader, 2 Bluestein
     int64_t M = 0;          // Bluestein's convolution length
-    bool empty() const { return rad.empty() && !bt && !split && !prime && !M; }
+    int emax = 0;           // elements per thread of a generic leaf (16 or 24)
+    bool empty() const { return rad.empty() && !bt && !split && !prime && !M && !emax; }
 };
 
 struct DeviceAlloc {
@@ -155,7 +156,7 @@ TransposeArgs resolve_transpose(const PlanImpl *p, const Pass &ps, const void *i
 PermuteArgs resolve_permute(const PlanImpl *p, const Pass &ps, const void *in, void *out,
                             void *scratch);
 // Lines per tile of a generic-kernel row tile (see plan.cpp).
-int row_lines_per_tile(int n, int tpt, int prec, int64_t lines);
+int row_lines_per_tile(int n, int tpt, int prec, int64_t lines, int emax = 0);
 // LDS layouts of the generic kernel's stage boundaries (StageDesc rd_stride,
 // rd_shift, wr_shift) for a leaf of nst stages st[0..nst) with R, Ns, nb set.
 void lds_layouts(int n, int nst, int tpt, int lds_stride, int emax, int eb, StageDesc *st);

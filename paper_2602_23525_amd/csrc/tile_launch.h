@@ -41,6 +41,23 @@ struct TileLaunch {
         return hipGetLastError();
     }
 
+    // resident workgroups per CU of the single-pass kernel
+    static int pass_blocks_per_cu(int block, size_t lds)
+    {
+        static size_t granted = 65536;
+        if (allow_dynamic_lds((const void *)pass_kernel<T, EMAX, KIND>, lds, &granted, &mu()) != hipSuccess) {
+            (void)hipGetLastError();
+            return 1;
+        }
+        int b = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, pass_kernel<T, EMAX, KIND>, block, lds) !=
+            hipSuccess) {
+            (void)hipGetLastError();
+            return 1;
+        }
+        return b > 0 ? b : 1;
+    }
+
     // batched launch: one workgroup per tile of the concatenated list
     static hipError_t batch(const PassArgs *items, const int64_t *prefix, const int32_t *owner,
                             int64_t total, int block, size_t lds, hipStream_t s)
@@ -56,7 +73,7 @@ struct TileLaunch {
 
 }  // namespace mfft
 
-// The two entry points of variant NAME (kernels.hip dispatches to them).
+// The entry points of variant NAME (kernels.hip dispatches to them).
 #define MFFT_TILE_LAUNCHERS(T, NAME, KIND) MFFT_TILE_LAUNCHERS_E(T, NAME, KIND, 16)
 #define MFFT_TILE_LAUNCHERS_E(T, NAME, KIND, EMAX)                                                \
     namespace mfft {                                                                              \
@@ -69,5 +86,9 @@ struct TileLaunch {
                                    hipStream_t s)                                                 \
     {                                                                                             \
         return TileLaunch<T, KIND, EMAX>::batch(items, prefix, owner, total, block, lds, s);      \
+    }                                                                                             \
+    int pass_blocks_per_cu_##NAME(int block, size_t lds)                                          \
+    {                                                                                             \
+        return TileLaunch<T, KIND, EMAX>::pass_blocks_per_cu(block, lds);                         \
     }                                                                                             \
     }

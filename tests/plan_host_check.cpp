@@ -79,6 +79,18 @@ hipError_t launch_convert_scale(void *, int, const void *, int64_t, double, hipS
 hipError_t launch_leaf(const PassArgs &, int, int, int, int, hipStream_t) { return hipSuccess; }
 // occupancy of the leaf kernel (only sizes persistent grids): one workgroup per CU
 int leaf_blocks_per_cu(int, int, int) { return 1; }
+// The device's answer modeled from the register use of the generic kernel
+// variants (waves per SIMD: FP32 6, or 5 with twiddles; FP64 3, or 2; with 24
+// elements per thread FP32 4, FP64 2), the LDS and 2048 threads per CU.
+int pass_blocks_per_cu(int prec, int kind, int emax, int block, size_t lds)
+{
+    const int wps = emax > 16 ? (prec ? 2 : 4) : (prec ? (kind ? 2 : 3) : (kind ? 5 : 6));
+    const int waves = (block + 63) / 64;
+    int b = 4 * wps / waves;
+    if (lds) b = std::min<int>(b, (int)((163840 - 256) / lds));
+    b = std::min(b, 2048 / block);
+    return b > 0 ? b : 1;
+}
 
 // The FP64 sub-plans that compute Rader and Bluestein spectra: no tables are
 // computed on the host, so they plan nothing.

@@ -66,6 +66,28 @@ def test_wide_radices_strided_and_in_place():
     run_case([(1088, 1, 1)], [(7, 1088, 1088)], inplace=True, seed=73, name="wide in place")
 
 
+def _one_pass_24_per_thread(tpt):
+    def check(info):
+        d = info["desc"]
+        assert info["n_passes"] == 1 and f"tpt={tpt} " in d, d
+    return check
+
+
+# 7-smooth lines of 4097..10240 points that may run with 24 elements per
+# thread (512-thread workgroups): FP64 lengths whose 16-per-thread shape needs
+# radix 3 (6561) or has no one-pass form (8000) take it always; FP32 lengths
+# as the occupancy estimate decides (both forms are checked)
+@pytest.mark.parametrize("n,prec,tpt", [(6561, 1, 365), (8000, 1, 400), (5000, 1, 250),
+                                        (10000, 0, None), (8000, 0, None), (9000, 0, None),
+                                        (4608, 0, None), (10240, 0, None), (6561, 0, None)])
+def test_long_smooth_lines(n, prec, tpt):
+    b = 4
+    chk = _one_pass_24_per_thread(tpt) if tpt else None
+    run_case([(n, 1, 1)], [(b, n, n)], sign=-1, prec=prec, seed=n + 11, name=f"long {n}",
+             check_info=chk)
+    run_case([(n, 1, 1)], [(b, n, n)], sign=1, prec=prec, seed=n + 12, name=f"long {n} inv")
+
+
 @pytest.mark.parametrize("n", [8192, 14175, 16384, 65536, 100000])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_cooley_tukey_two_pass(n, prec):

@@ -220,3 +220,24 @@ def test_forced_radices_of_fig3_compute_the_dft():
     assert oracle.rel_rms(y.reshape(b, n), ref) <= 1e-13
     p.destroy()
     mfft.mfft_wisdom_forget()
+
+
+@pytest.mark.parametrize("emax,tpt", [(16, 1000), (24, 500)])
+def test_forced_elements_per_thread_compute_the_dft(emax, tpt):
+    """10000-point FP32 lines with 16 or 24 elements per thread (a structural
+    choice stored as wisdom, ":e=16" / ":e=24") both compute the DFT."""
+    import paper_2602_23525_amd as mfft
+    n, b = 10000, 4
+    x = uniform_complex(n * b, seed=77, dtype=np.complex64)
+    ref = oracle.fft(x.astype(np.complex128).reshape(b, n))
+    mfft.mfft_wisdom_forget()
+    mfft.Plan([(n, 1, 1)], [(b, n, n)], flags=mfft.MEASURE).destroy()
+    key = [k for k in _wisdom_lines() if k.startswith(f"line c32 n={n} ")][0]
+    mfft.mfft_wisdom_forget()
+    mfft.mfft_wisdom_import(f"mfft-wisdom 1 {mfft.mfft_version()}\n{key} => n={n}:e={emax}\n")
+    p = mfft.Plan([(n, 1, 1)], [(b, n, n)], flags=mfft.WISDOM_ONLY)
+    assert f"tpt={tpt} " in p.info()["desc"], p.info()["desc"]
+    y = _run(p, x)
+    assert oracle.rel_rms(y.reshape(b, n), ref) <= 2e-6
+    p.destroy()
+    mfft.mfft_wisdom_forget()
