@@ -259,7 +259,10 @@ __device__ __forceinline__ int fast_div(int b, uint32_t magic, int shift)
     return (int)((__umulhi((uint32_t)b, magic) + (uint32_t)b) >> shift);
 }
 
-enum { F_LDS = 0, F_LDS_CONV = 2 };
+// Where a stage's inputs come from: LDS; LDS times the convolution spectrum;
+// the pass's input in global memory (the first stage of a row tile: element
+// b + k*nb of the line, so the lanes of a wave read consecutive elements)
+enum { F_LDS = 0, F_GLOBAL = 1, F_LDS_CONV = 2 };
 enum { E_LDS = 0, E_GLOBAL = 1 };
 
 template <typename T, int R, int EMAX, int KIND>
@@ -288,16 +291,43 @@ __device__ __forceinline__ void stage(const PassArgs &a, const StageDesc &sd, Ti
     cpx<T> v[NB][R];
     int qv[NB];
 
-    // butterfly b = q*Ns + j reads element b + k*nb of the previous layout
-    // (one address per butterfly, the k-th element rd_stride further)
 #pragma unroll
-    for (int i = 0; i < NB; ++i) {
-        const int b = t + i * tpt;
-        qv[i] = fast_div(b, sd.magic, sd.shift);
-        if (b < nbl) {
-            const cpx<T> *src = my + b + (qv[i] >> sd.rd_shift);
+    for (int i = 0; i < NB; ++i) qv[i] = fast_div(t + i * tpt, sd.magic, sd.shift);
+    if (fetch == F_GLOBAL) {
+        // straight from the input: line c (padding lines read line c0),
+        // element b + k*nb, every load of the lane issued before the first use
+        const gptr<const cpx<T>> src =
+            glob((const cpx<T> *)a.in) + tl.ob_in + (ok ? c : tl.c0) * a.vis;
+        const bool nt = (a.flags & PF_NT_IN) != 0, cj = (a.flags & PF_CONJ_IN) != 0;
 #pragma unroll
-            for (int k = 0; k < R; ++k) v[i][k] = src[k * sd.rd_stride];
+        for (int i = 0; i < NB; ++i) {
+            const int b = t + i * tpt;
+            if (b < nbl) {
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    const gptr<const cpx<T>> e = src + (int64_t)(b + k * nb) * a.is;
+                    if (nt) v[i][k] = ld_nt(e);
+                    else v[i][k] = *e;
+                }
+            }
+        }
+        if (cj) {
+#pragma unroll
+            for (int i = 0; i < NB; ++i)
+#pragma unroll
+                for (int k = 0; k < R; ++k) v[i][k] = conj(v[i][k]);
+        }
+    } else {
+        // butterfly b = q*Ns + j reads element b + k*nb of the previous layout
+        // (one address per butterfly, the k-th element rd_stride further)
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            const int b = t + i * tpt;
+            if (b < nbl) {
+                const cpx<T> *src = my + b + (qv[i] >> sd.rd_shift);
+#pragma unroll
+                for (int k = 0; k < R; ++k) v[i][k] = src[k * sd.rd_stride];
+            }
         }
     }
     if constexpr (KIND & K_CONV) {
@@ -317,7 +347,10 @@ __device__ __forceinline__ void stage(const PassArgs &a, const StageDesc &sd, Ti
             }
         }
     }
-    __syncthreads();
+    // every read of the previous layout done before it is overwritten (a
+    // stage that read the input has nothing to wait for: the tile's LDS was
+    // released by the barrier that ended the previous tile)
+    if (fetch != F_GLOBAL) __syncthreads();
 
     const gptr<const cpx<T>> tw = glob((const cpx<T> *)a.tw) + sd.tw_off;
 #pragma unroll
@@ -467,12 +500,12 @@ __device__ __forceinline__ void load_lane(const PassArgs &a, const Tile<T> &tl, 
 // spectrum product for an in-kernel convolution) and the store.  Ends with a
 // barrier, so the workgroup may load its next tile into LDS.
 template <typename T, int EMAX, int KIND>
-__device__ __forceinline__ void tile_body(const PassArgs &a, Tile<T> &tl, cpx<T> *lds)
+__device__ __forceinline__ void tile_body(const PassArgs &a, Tile<T> &tl, cpx<T> *lds,
+                                          int first_fetch)
 {
     const int n = a.n, bt = a.bt;
     const uint32_t f = a.flags;
     cpx<T> *slots = lds + a.bt * a.lds_stride;   // 2 per line: x0, a0
-    const int first_fetch = F_LDS;
     const int last_emit = a.store_mode == kModeCol ? E_LDS : E_GLOBAL;
 
     bool conv = false;
@@ -557,7 +590,11 @@ __device__ __forceinline__ void tile_body(const PassArgs &a, Tile<T> &tl, cpx<T>
 }
 
 
-template <typename T, int EMAX, int KIND>
+// DIRECT: the single-pass kernel lets wide row tiles read the input in their
+// first stage; the batched kernel keeps the LDS load (the direct path costs
+// it 7 VGPRs, one wave per SIMD: the uneven batch's 7-smooth class ran 4.70
+// -> 4.90 ms with it).
+template <typename T, int EMAX, int KIND, bool DIRECT>
 __device__ __forceinline__ void run_tile(const PassArgs &a, int64_t tile, cpx<T> *lds)
 {
     Tile<T> tl = tile_setup<T>(a, tile, lds);
@@ -584,13 +621,25 @@ __device__ __forceinline__ void run_tile(const PassArgs &a, int64_t tile, cpx<T>
         }
     }
 
+    // plain and twiddled row tiles of lines at least a wave wide: the first
+    // stage reads the input itself (no LDS round trip and barrier for the
+    // load).  Measured on MI355X against the LDS load: 1000 x 16384 FP32
+    // 66.5 -> 64.7 us, 3000 x 8192 110 -> 105, 6561 x 4096 142 -> 136, 6561 x
+    // 2048 FP64 161 -> 153; lines of fewer lanes lost (60 x 131072 42 -> 47,
+    // 200 x 32768 34.8 -> 36.7 us) and keep the LDS load.
+    if constexpr (DIRECT && !(KIND & (K_EXT | K_CONV))) {
+        if (a.load_mode == kModeRow && a.tpt >= 64) {
+            tile_body<T, EMAX, KIND>(a, tl, lds, F_GLOBAL);
+            return;
+        }
+    }
     if (tl.act) {
         int line, idx0;
         load_lane(a, tl, &line, &idx0);
         load_line<T, EMAX, KIND>(a, tl, lds, line, idx0);
     }
     __syncthreads();
-    tile_body<T, EMAX, KIND>(a, tl, lds);
+    tile_body<T, EMAX, KIND>(a, tl, lds, F_LDS);
 }
 
 // Largest workgroup of the generic kernels: FP64 lines, and FP32 lines with 24
@@ -615,7 +664,7 @@ __global__ __launch_bounds__(max_block<T>(EMAX)) void pass_kernel(PassArgs a)
         tile = (int64_t)(blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
         if (tile >= ap->ntiles) return;   // whole workgroup leaves together
     }
-    run_tile<T, EMAX, KIND>(*ap, tile, lds);
+    run_tile<T, EMAX, KIND, true>(*ap, tile, lds);
 }
 
 // Batched kernel over the passes of many plans, one tile per workgroup:
@@ -633,7 +682,7 @@ __global__ __launch_bounds__(max_block<T>(EMAX)) void batch_kernel(const PassArg
     cpx<T> *lds = (cpx<T> *)smem;
     const int64_t g = blockIdx.x;
     const int i = owner[g];
-    run_tile<T, EMAX, KIND>(items[i], g - prefix[i], lds);
+    run_tile<T, EMAX, KIND, false>(items[i], g - prefix[i], lds);
 }
 
 }  // namespace mfft
