@@ -688,7 +688,12 @@ def main():
         torch.cuda.empty_cache()
         ua = argparse.Namespace(**vars(args))
         ua.items, ua.steps, ua.warmup = 10000, 5, 1
+        # the workload's plans are autotuned and kept as wisdom: measure mode
+        # once per distinct length, then every item from wisdom alone
+        ua.plan = "measure"
         u = run_uneven(ua, emit=False)
+        import paper_2602_23525_amd as mfft
+        mfft.mfft_wisdom_forget()   # the serving replay plans on its own
         out["uneven_batch"] = {
             "workload": u["config"]["workload"], "gflops": u["value"],
             "ms_per_step": u["ms_per_step"], "hbm_frac": u["roofline"]["frac"],
@@ -697,6 +702,7 @@ def main():
             "launches_per_step": u["config"]["launches_per_step"],
             "plan_source": u["config"]["plan_source"],
             "plan_seconds": u["config"]["plan_seconds"],
+            "measure_seconds": u["config"].get("measure_seconds"),
             "sampled_relrms_max": u["config"]["sampled_relrms_max"],
             "sampled_maxerr_max": u["config"]["sampled_maxerr_max"]}
         sa = argparse.Namespace(**vars(args))
