@@ -88,6 +88,26 @@ def test_long_smooth_lines(n, prec, tpt):
     run_case([(n, 1, 1)], [(b, n, n)], sign=1, prec=prec, seed=n + 12, name=f"long {n} inv")
 
 
+def _smooth_in(lo, hi, count, seed):
+    def smooth(v):
+        for p in (2, 3, 5, 7):
+            while v % p == 0:
+                v //= p
+        return v == 1
+    pool = [v for v in range(lo, hi + 1) if smooth(v) and v & (v - 1)]
+    rng = np.random.default_rng(seed)
+    return sorted(int(v) for v in rng.choice(pool, count, replace=False))
+
+
+# a seeded sample of the 7-smooth lengths in 4097..10240 (24 or 16 elements per
+# thread as the planner decides, LDS padded once per 64 elements with 24)
+@pytest.mark.parametrize("n", _smooth_in(4097, 10240, 12, 5))
+@pytest.mark.parametrize("prec", [0, 1])
+def test_long_smooth_sample(n, prec):
+    run_case([(n, 1, 1)], [(3, n, n)], sign=-1 if n % 2 else 1, prec=prec, seed=n + 13,
+             name=f"long sample {n}")
+
+
 @pytest.mark.parametrize("n", [8192, 14175, 16384, 65536, 100000])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_cooley_tukey_two_pass(n, prec):
