@@ -111,6 +111,15 @@ typedef struct {
     size_t scratch_bytes;     /* device scratch owned by the plan              */
     size_t table_bytes;       /* device twiddle / chirp / index tables         */
     char desc[1024];          /* human-readable pass list                      */
+    /* The radices each pass executes (its Stockham stages in order, Section 2;
+     * one transform of the product per line), the passes in launch order and
+     * each list closed by a 0; a pass that transforms nothing (a copy, a
+     * transpose, a real-data step) contributes the 0 alone.  At most
+     * MFFT_INFO_RADICES entries; n_radices counts those filled (a longer list
+     * is cut there). */
+#define MFFT_INFO_RADICES 64
+    int n_radices;
+    int radices[MFFT_INFO_RADICES];
 } mfft_plan_info_t;
 
 /*

@@ -51,7 +51,8 @@ class PlanInfo(ctypes.Structure):
                 ("howmany", ctypes.c_int64), ("flops", ctypes.c_double),
                 ("bytes_compulsory", ctypes.c_double), ("bytes_passes", ctypes.c_double),
                 ("scratch_bytes", ctypes.c_size_t), ("table_bytes", ctypes.c_size_t),
-                ("desc", ctypes.c_char * 1024)]
+                ("desc", ctypes.c_char * 1024), ("n_radices", ctypes.c_int),
+                ("radices", ctypes.c_int * 64)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
@@ -240,8 +241,17 @@ STATIC_SCRATCH_BYTES = 64 << 20
 def mfft_plan_info(plan: int) -> dict:
     info = PlanInfo()
     _check(lib().mfft_plan_info(plan, ctypes.byref(info)), "mfft_plan_info")
-    d = {k: getattr(info, k) for k, _ in PlanInfo._fields_ if k != "desc"}
+    d = {k: getattr(info, k) for k, _ in PlanInfo._fields_ if k not in ("desc", "radices")}
     d["desc"] = info.desc.decode(errors="replace")
+    # radices per pass (a pass without a transform: an empty list)
+    passes, cur = [], []
+    for r in info.radices[: info.n_radices]:
+        if r == 0:
+            passes.append(cur)
+            cur = []
+        else:
+            cur.append(r)
+    d["radices"] = passes
     return d
 
 

@@ -402,6 +402,20 @@ int mfft_plan_info(mfft_plan plan, mfft_plan_info_t *info)
     info->scratch_bytes = p->scratch_bytes;
     info->table_bytes = p->table_bytes;
     std::strncpy(info->desc, p->desc.c_str(), sizeof(info->desc) - 1);
+    auto put = [&](int r) {
+        if (info->n_radices < MFFT_INFO_RADICES) info->radices[info->n_radices++] = r;
+    };
+    for (const Pass &ps : p->passes) {
+        if (ps.kind == 0) {
+            if (ps.kernel == 1) {
+                // the specialized leaf kernel runs its own sequence
+                for (int s = 0; s < leaf_radix_count(ps.a.n); ++s) put(leaf_radix_at(ps.a.n, s));
+            } else {
+                for (int s = 0; s < ps.a.nst; ++s) put(ps.a.st[s].R);
+            }
+        }
+        put(0);
+    }
     return MFFT_OK;
 }
 

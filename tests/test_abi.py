@@ -157,3 +157,28 @@ def test_aliasing_check_is_exact_on_random_layouts():
         seen_ok += want == OK
         seen_bad += want == EINVAL
     assert seen_ok > 100 and seen_bad > 100
+
+
+def test_plan_info_struct_matches_header(tmp_path):
+    """The binding's PlanInfo has the header's mfft_plan_info_t layout: size and
+    the offsets of the last fields, from a C program built against the header."""
+    import ctypes
+    import os
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no gcc")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    src = tmp_path / "info.c"
+    src.write_text(
+        "#include <stddef.h>\n#include <stdio.h>\n#include \"mfft.h\"\n"
+        "int main(void){printf(\"%zu %zu %zu %zu\\n\", sizeof(mfft_plan_info_t),"
+        " offsetof(mfft_plan_info_t, desc), offsetof(mfft_plan_info_t, n_radices),"
+        " offsetof(mfft_plan_info_t, radices));return 0;}\n")
+    exe = str(tmp_path / "info")
+    subprocess.run(["gcc", "-I", os.path.join(root, "include"), str(src), "-o", exe], check=True)
+    size, desc, nrad, rad = map(int, subprocess.run([exe], capture_output=True, text=True,
+                                                    check=True).stdout.split())
+    P = mfft.PlanInfo
+    assert (ctypes.sizeof(P), P.desc.offset, P.n_radices.offset, P.radices.offset) == \
+        (size, desc, nrad, rad)

@@ -241,3 +241,26 @@ def test_forced_elements_per_thread_compute_the_dft(emax, tpt):
     assert oracle.rel_rms(y.reshape(b, n), ref) <= 2e-6
     p.destroy()
     mfft.mfft_wisdom_forget()
+
+
+def test_plan_info_lists_each_pass_radices():
+    """mfft_plan_info reports the radices each pass executes (Stockham stages in
+    order; the leaf kernel's own sequence for its passes), one list per pass."""
+    import paper_2602_23525_amd as mfft
+    cases = [([(4096, 1, 1)], [(16, 4096, 4096)], 0, [[16, 16, 16]]),
+             ([(8192, 1, 1)], [(4, 8192, 8192)], 0, [[16, 16, 16, 2]]),
+             ([(1000, 1, 1)], [(8, 1000, 1000)], 0, [[10, 10, 10]]),
+             ([(65536, 1, 1)], [(4, 65536, 65536)], 0, None)]
+    for dims, hd, prec, want in cases:
+        p = mfft.Plan(dims, hd, prec=prec)
+        info = p.info()
+        rad = info["radices"]
+        assert len(rad) == info["n_passes"], (rad, info["desc"])
+        for r in rad:
+            assert r and all(x in (2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17, 19, 23)
+                             for x in r), rad
+        # the passes' radices multiply to the transform length
+        assert int(np.prod([int(np.prod(r)) for r in rad])) == dims[0][0], rad
+        if want is not None:
+            assert rad == want, (rad, info["desc"])
+        p.destroy()
