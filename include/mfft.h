@@ -236,19 +236,23 @@ int mfft_plan_destroy(mfft_plan plan);
 /*
  * Many planned transforms executed as one workload (the vector-loop rule of
  * Section 4.2 extended across plans): pass k of every plan runs in one
- * persistent launch per kernel family, whose workgroups pop tiles from a shared
- * list ordered largest line first, so uneven sizes balance across the GPU;
- * passes of the specialized power-of-two leaf kernel run in one launch per
- * length and tile kind, with the same results as the plans alone.  Column
- * passes move 128-byte runs: items whose data start on a 128-byte boundary
- * run them about twice as fast as misaligned ones.
+ * launch per kernel family, one workgroup per tile of a list ordered largest
+ * line first, so uneven sizes balance across the GPU; passes of the
+ * specialized power-of-two leaf kernel run in one launch per length and tile
+ * kind, with the same results as the plans alone.  The launches of one pass
+ * index are independent and run on up to four concurrent lanes (the caller's
+ * stream and three of the batch's own, forked from and joined back to it;
+ * parallel branches of the graph).  Column passes move 128-byte runs: items
+ * whose data start on a 128-byte boundary run them about twice as fast as
+ * misaligned ones.
  *   count, plans, ins, outs: plan i runs on ins[i] -> outs[i] (device
  *       pointers with the plan's in-place rule); plans must outlive the batch;
  *       a plan that owns scratch may appear at most once.
  *   flags: MFFT_BATCH_GRAPH captures the launches in a HIP graph at creation;
  *       execute then launches the graph.
- * Execution is asynchronous on hip_stream and allocates nothing.  Errors:
- * EINVAL (bad arguments, shared scratch), ENOMEM, EHIP.
+ * Execution is asynchronous on hip_stream and allocates nothing; executions
+ * of one batch must not overlap (they share its lanes).  Errors: EINVAL (bad
+ * arguments, shared scratch), ENOMEM, EHIP.
  */
 typedef struct mfft_batch_s *mfft_batch;
 #define MFFT_BATCH_GRAPH 1u

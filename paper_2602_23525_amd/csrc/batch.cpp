@@ -251,41 +251,124 @@ int build_batch_layout(const std::vector<BatchItem> &items, BatchLayout *L)
                 L->steps.push_back(st);
             }
     }
+    // phases, costs and lanes: within a phase the steps are balanced over
+    // kBatchLanes lanes by the elements they move, largest first
+    {
+        size_t i = 0;
+        for (int k = 0; k < nphase; ++k) {
+            const size_t n_k = copies[k].size() + leaves[k].size() + reals[k].size() +
+                               transposes[k].size() + permutes[k].size() + leaf_groups[k].size();
+            size_t n_g = 0;
+            for (size_t gi = 0; gi < order.size(); ++gi) n_g += std::get<0>(order[gi].first) == k;
+            const size_t end = i + n_k + n_g;
+            std::vector<size_t> idx;
+            for (size_t j = i; j < end; ++j) {
+                BatchStep &st = L->steps[j];
+                st.phase = k;
+                double c = 1.0;
+                auto pass_cost = [](const PassArgs &a) {
+                    return (double)a.ntiles * (double)a.bt * (double)a.n;
+                };
+                if (st.group >= 0) {
+                    const BatchGroup &g = L->groups[st.group];
+                    const PassArgs *it = (const PassArgs *)(L->host.data() + g.items_off);
+                    c = 0;
+                    for (int m = 0; m < g.nitems; ++m) c += pass_cost(it[m]);
+                } else if (st.leaf) {
+                    c = pass_cost(st.a);
+                } else if (st.copy) {
+                    c = (double)st.c.total;
+                }
+                st.cost = c;
+                idx.push_back(j);
+            }
+            std::stable_sort(idx.begin(), idx.end(), [&](size_t x, size_t y) {
+                return L->steps[x].cost > L->steps[y].cost;
+            });
+            double load[kBatchLanes] = {};
+            for (size_t j : idx) {
+                int best = 0;
+                for (int l = 1; l < kBatchLanes; ++l)
+                    if (load[l] < load[best]) best = l;
+                L->steps[j].lane = best;
+                load[best] += L->steps[j].cost;
+            }
+            i = end;
+        }
+    }
     return MFFT_OK;
 }
 
-int enqueue_batch_layout(const BatchLayout &L, char *dev, hipStream_t s)
+int enqueue_batch_layout(const BatchLayout &L, char *dev, hipStream_t s, const hipStream_t *aux,
+                         hipEvent_t *ev)
 {
+    const bool lanes = aux && ev;
+    int phase = -1;
+    bool used[kBatchLanes] = {};
+    auto join = [&]() -> hipError_t {
+        // s waits for the lanes that ran in the phase
+        for (int l = 1; l < kBatchLanes; ++l) {
+            if (!used[l]) continue;
+            hipError_t e = hipEventRecord(ev[l], aux[l - 1]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(s, ev[l], 0);
+            if (e != hipSuccess) return e;
+            used[l] = false;
+        }
+        return hipSuccess;
+    };
     for (const BatchStep &st : L.steps) {
         hipError_t e;
+        hipStream_t q = s;
+        if (lanes) {
+            if (st.phase != phase) {
+                e = join();
+                if (e == hipSuccess) e = hipEventRecord(ev[0], s);   // the phase starts
+                if (e != hipSuccess)
+                    return fail(MFFT_EHIP, std::string("batch lanes: ") + hipGetErrorString(e));
+                phase = st.phase;
+            }
+            if (st.lane > 0) {
+                q = aux[st.lane - 1];
+                if (!used[st.lane]) {
+                    e = hipStreamWaitEvent(q, ev[0], 0);
+                    if (e != hipSuccess)
+                        return fail(MFFT_EHIP, std::string("batch lanes: ") + hipGetErrorString(e));
+                    used[st.lane] = true;
+                }
+            }
+        }
         if (st.copy) {
-            e = launch_copy(st.c, s);
+            e = launch_copy(st.c, q);
         } else if (st.real) {
-            e = launch_real(st.r, st.prec, s);
+            e = launch_real(st.r, st.prec, q);
         } else if (st.transpose) {
-            e = launch_transpose_sq(st.t, s);
+            e = launch_transpose_sq(st.t, q);
         } else if (st.permute) {
-            e = launch_permute_items(st.pm, s);
+            e = launch_permute_items(st.pm, q);
         } else if (st.leaf) {
-            e = launch_leaf(st.a, st.prec, st.a.n, st.leaf_variant, st.leaf_grid, s);
+            e = launch_leaf(st.a, st.prec, st.a.n, st.leaf_variant, st.leaf_grid, q);
         } else if (L.groups[st.group].leaf_n > 0) {
             const BatchGroup &g = L.groups[st.group];
             e = launch_leaf_batch((const PassArgs *)(dev + g.items_off),
                                   (const int64_t *)(dev + g.prefix_off),
                                   (const int32_t *)(dev + g.owner_off), g.tiles, g.prec, g.leaf_n,
-                                  g.leaf_mode, s);
+                                  g.leaf_mode, q);
         } else {
             const BatchGroup &g = L.groups[st.group];
             e = launch_batch((const PassArgs *)(dev + g.items_off),
                              (const int64_t *)(dev + g.prefix_off),
                              (const int32_t *)(dev + g.owner_off), g.tiles, g.prec, g.kind,
-                             g.block, g.lds, s);
+                             g.block, g.lds, q);
             if (e != hipSuccess)
                 return fail(MFFT_EHIP, std::string("batch launch (block ") + std::to_string(g.block) +
                                            ", lds " + std::to_string(g.lds) + ", grid " +
                                            std::to_string(g.grid) + "): " + hipGetErrorString(e));
         }
         if (e != hipSuccess) return fail(MFFT_EHIP, std::string("batch launch: ") + hipGetErrorString(e));
+    }
+    if (lanes) {
+        hipError_t e = join();
+        if (e != hipSuccess) return fail(MFFT_EHIP, std::string("batch lanes: ") + hipGetErrorString(e));
     }
     return MFFT_OK;
 }
@@ -303,6 +386,10 @@ struct mfft_batch_s {
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    // the concurrent lanes of a phase (default priority, non-blocking)
+    hipStream_t aux[mfft::kBatchLanes - 1] = {};
+    hipEvent_t ev[mfft::kBatchLanes] = {};
+    bool lanes = false;
 };
 
 namespace mfft {
@@ -312,6 +399,10 @@ static void batch_free(mfft_batch_s *b)
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    for (hipStream_t q : b->aux)
+        if (q) (void)hipStreamDestroy(q);
+    for (hipEvent_t e : b->ev)
+        if (e) (void)hipEventDestroy(e);
     if (b->dev_mem) (void)hipFree(b->dev_mem);
     delete b;
 }
@@ -361,10 +452,23 @@ int mfft_batch_create(mfft_batch *out, int count, const mfft_plan *plans, const 
         return fail(MFFT_EHIP, "batch descriptor upload failed");
     }
     (void)hip_stream;
+    {
+        hipError_t e = hipSuccess;
+        for (hipStream_t &q : b->aux)
+            if (e == hipSuccess) e = hipStreamCreateWithFlags(&q, hipStreamNonBlocking);
+        for (hipEvent_t &ev : b->ev)
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            batch_free(b);
+            return fail(MFFT_EHIP, std::string("batch lanes: ") + hipGetErrorString(e));
+        }
+        b->lanes = true;
+    }
     if (flags & MFFT_BATCH_GRAPH) {
         hipError_t e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeRelaxed);
-        rc = e == hipSuccess ? enqueue_batch_layout(b->layout, (char *)b->dev_mem, b->cap_stream)
+        rc = e == hipSuccess ? enqueue_batch_layout(b->layout, (char *)b->dev_mem, b->cap_stream,
+                                                    b->aux, b->ev)
                              : MFFT_EHIP;
         if (e == hipSuccess) {
             hipError_t e2 = hipStreamEndCapture(b->cap_stream, &b->graph);
@@ -390,7 +494,7 @@ int mfft_batch_execute(mfft_batch batch, void *hip_stream)
         if (e != hipSuccess) return fail(MFFT_EHIP, std::string("graph launch: ") + hipGetErrorString(e));
         return MFFT_OK;
     }
-    return enqueue_batch_layout(batch->layout, (char *)batch->dev_mem, s);
+    return enqueue_batch_layout(batch->layout, (char *)batch->dev_mem, s, batch->aux, batch->ev);
 }
 
 int mfft_batch_info(mfft_batch batch, int *launches, int64_t *tiles)

@@ -40,6 +40,9 @@ struct BatchStep {   // one launch: a group, a copy pass, a real-data step or a 
     int leaf_variant = 0, leaf_grid = 0;
     int prec = 0;
     int group = -1;
+    int phase = 0;       // pass index of the plans: phases run in order
+    int lane = 0;        // concurrent lane of the phase (0: the caller's stream)
+    double cost = 0;     // complex elements the launch moves (lane balancing)
 };
 
 struct BatchLayout {
@@ -50,9 +53,17 @@ struct BatchLayout {
     int64_t tiles = 0;
 };
 
+// Lanes per phase that build_batch_layout balances the steps over.
+constexpr int kBatchLanes = 4;
+
 int build_batch_layout(const std::vector<BatchItem> &items, BatchLayout *L);
-// Launch the sequence with the image resident at `dev`.
-int enqueue_batch_layout(const BatchLayout &L, char *dev, hipStream_t s);
+// Launch the sequence with the image resident at `dev`.  With `aux`
+// (kBatchLanes - 1 streams) and `ev` (kBatchLanes events), the steps of a
+// phase, which touch different plans' buffers, run as concurrent lanes: the
+// auxiliary streams wait for the phase's start on s, and s waits for their
+// ends before the next phase (under graph capture: parallel branches).
+int enqueue_batch_layout(const BatchLayout &L, char *dev, hipStream_t s,
+                         const hipStream_t *aux = nullptr, hipEvent_t *ev = nullptr);
 int batch_launch_count(const BatchLayout &L);
 
 }  // namespace mfft
