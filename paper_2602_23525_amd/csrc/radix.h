@@ -1,6 +1,7 @@
 // Butterflies of the generic tile kernel: the radices of butterfly.h, the
-// composites 6, 9, 10, 12, 14 and 15, each one step of eq. ct with constant
-// twiddles (fewer LDS exchanges for sizes with factors 3, 5 and 7), and the
+// composites 6, 9, 10, 12, 14 and 15 (fewer LDS exchanges for sizes with
+// factors 3, 5 and 7: 9 as one step of eq. ct with constant twiddles, the
+// others of coprime factors by the prime-factor map, without twiddles), and the
 // primes 11, 13, 17, 19 and 23 by the definition with paired terms (17 to 23
 // only in the kernel variant that holds 24 elements per thread).
 #pragma once
@@ -105,6 +106,44 @@ __device__ __forceinline__ void dft_ab(cpx<T> *v)
     }
 }
 
+// Inverse of b modulo m (gcd(b, m) = 1), at compile time.
+constexpr int inv_mod(int b, int m)
+{
+    for (int x = 1; x < m; ++x)
+        if ((b * x) % m == 1) return x;
+    return 1;   // m = 1
+}
+
+// R = A * B with gcd(A, B) = 1 by the prime-factor (Good-Thomas) algorithm,
+// which Section 2 names beside Cooley-Tukey and Section 5 uses for hard-coded
+// codelets: input x[(B n1 + A n2) mod R] as a B x A array, DFT-A over n1,
+// DFT-B over n2, output index k with k = k1 (mod A) and k = k2 (mod B), i.e.
+// (B bA k1 + A aB k2) mod R with bA = B^-1 mod A, aB = A^-1 mod B.  The
+// exponent of w_R splits into w_A^(n1 k1) w_B^(n2 k2) exactly, so no twiddle
+// factors sit between the two sets of DFTs (a plain register permutation).
+template <typename T, int A, int B>
+__device__ __forceinline__ void dft_pfa(cpx<T> *v)
+{
+    constexpr int R = A * B;
+    constexpr int bA = inv_mod(B % A, A), aB = inv_mod(A % B, B);
+    cpx<T> z[B][A];
+#pragma unroll
+    for (int n2 = 0; n2 < B; ++n2) {
+#pragma unroll
+        for (int n1 = 0; n1 < A; ++n1) z[n2][n1] = v[(B * n1 + A * n2) % R];
+        dftx<T, A>(z[n2]);
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < A; ++k1) {
+        cpx<T> w[B];
+#pragma unroll
+        for (int n2 = 0; n2 < B; ++n2) w[n2] = z[n2][k1];
+        dftx<T, B>(w);
+#pragma unroll
+        for (int k2 = 0; k2 < B; ++k2) v[(B * bA * k1 + A * aB * k2) % R] = w[k2];
+    }
+}
+
 // Odd prime R by the definition with paired terms: for k = 1 .. (R-1)/2,
 //   a_k = v0 + sum_j cos(2 pi jk/R) (v_j + v_(R-j)),
 //   b_k = sum_j sin(2 pi jk/R) (v_j - v_(R-j)),
@@ -142,12 +181,12 @@ __device__ __forceinline__ void dft_odd_prime(cpx<T> *v)
 template <typename T, int R>
 __device__ __forceinline__ void dftx(cpx<T> *v)
 {
-    if constexpr (R == 6) dft_ab<T, 3, 2>(v);
+    if constexpr (R == 6) dft_pfa<T, 3, 2>(v);
     else if constexpr (R == 9) dft_ab<T, 3, 3>(v);
-    else if constexpr (R == 10) dft_ab<T, 5, 2>(v);
-    else if constexpr (R == 12) dft_ab<T, 4, 3>(v);
-    else if constexpr (R == 14) dft_ab<T, 7, 2>(v);
-    else if constexpr (R == 15) dft_ab<T, 5, 3>(v);
+    else if constexpr (R == 10) dft_pfa<T, 5, 2>(v);
+    else if constexpr (R == 12) dft_pfa<T, 4, 3>(v);
+    else if constexpr (R == 14) dft_pfa<T, 7, 2>(v);
+    else if constexpr (R == 15) dft_pfa<T, 5, 3>(v);
     else if constexpr (R == 11 || R == 13 || R == 17 || R == 19 || R == 23) dft_odd_prime<T, R>(v);
     else dft<T, R>(v);
 }
