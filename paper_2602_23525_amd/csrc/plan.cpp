@@ -583,27 +583,33 @@ static bool leaf_col_fits(const LineSpec &ls, const PassArgs &a, const Dim &in_d
 }
 
 // Lines per tile of a row tile (lanes along the lines, so any count works):
-// the workgroup of bt * tpt threads should fill its waves and the 256-, 512-
-// or 1024-thread class that batched launches round it up to, with a tile of
-// at most 64 KB of LDS (two or more workgroups per CU) and no more lines than
-// the vector loop has.  Among the classes, the best filled; ties go to the
-// smaller.  (Powers of two alone left up to a quarter of the lanes idle, e.g.
-// 200 of 256 threads for 1000-point lines.)
+// the workgroup of bt * tpt threads rounds up to the 256-, 512- or 1024-thread
+// class that batched launches use, with a tile of at most 64 KB of LDS (two or
+// more workgroups per CU) and no more lines than the vector loop has.  Among
+// the classes, the one that keeps the most working lanes resident on a CU (bt
+// * tpt times the workgroups per CU that registers and LDS allow); ties go to
+// the smaller.  Filling the class alone chose 73 lines of 98 points (511 of
+// 512 threads, 62 KB, two workgroups per CU) where 36 lines (252 of 256, five
+// per CU) run 98 x 65536 FP32 in 31 rather than 33 us (MI355X); powers of two
+// alone left up to a quarter of the lanes idle (200 of 256 threads for
+// 1000-point lines).
 int row_lines_per_tile(int n, int tpt, int prec, int64_t lines, int emax)
 {
-    const int mt = max_threads(prec, emax ? emax : leaf_emax(n));
+    const int e = emax ? emax : leaf_emax(n);
+    const int mt = max_threads(prec, e);
     int best = 1;
-    double best_fill = -1;
+    int64_t best_live = -1;
     for (int cls = 256; cls <= mt; cls *= 2) {
         int bt = std::max(1, cls / tpt);
-        while (bt > 1 && tile_lds_bytes(n, bt, prec, emax ? emax : leaf_emax(n)) > 65536) --bt;
-        while (bt > 1 && tile_lds_bytes(n, bt, prec, emax ? emax : leaf_emax(n)) > g_lds_budget) --bt;
+        while (bt > 1 && tile_lds_bytes(n, bt, prec, e) > 65536) --bt;
+        while (bt > 1 && tile_lds_bytes(n, bt, prec, e) > g_lds_budget) --bt;
         if (lines > 0) bt = (int)std::max<int64_t>(1, std::min<int64_t>(bt, lines));
         int block = 256;
         while (block < bt * tpt) block *= 2;
-        const double fill = (double)(bt * tpt) / block;
-        if (fill > best_fill + 1e-9) {
-            best_fill = fill;
+        const int64_t live =
+            (int64_t)bt * tpt * pass_blocks_per_cu(prec, 0, e, block, tile_lds_bytes(n, bt, prec, e));
+        if (live > best_live) {
+            best_live = live;
             best = bt;
         }
     }
