@@ -5,6 +5,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 #include "butterfly.h"
 #include "internal.h"
@@ -320,7 +323,7 @@ hipError_t launch_pass(const PassArgs &a, int prec, int emax, size_t lds_bytes, 
     return launch_pass_c64_k7(a, lds_bytes, s);
 }
 
-int pass_blocks_per_cu(int prec, int kind, int emax, int block, size_t lds)
+static int query_blocks_per_cu(int prec, int kind, int emax, int block, size_t lds)
 {
     if (emax > 16) {
         if (kind > 1) return 1;
@@ -337,6 +340,30 @@ int pass_blocks_per_cu(int prec, int kind, int emax, int block, size_t lds)
     if (kind == 1) return pass_blocks_per_cu_c64_k1(block, lds);
     if (kind == 5) return pass_blocks_per_cu_c64_k5(block, lds);
     return pass_blocks_per_cu_c64_k7(block, lds);
+}
+
+// The occupancy answers, kept per device and question: the planner asks for
+// every size class of every line length it plans (10,000 plans of a batch
+// repeat a few hundred questions).
+int pass_blocks_per_cu(int prec, int kind, int emax, int block, size_t lds)
+{
+    static std::mutex mu;
+    static std::map<std::tuple<int, int, int, int, int, size_t>, int> seen;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return query_blocks_per_cu(prec, kind, emax, block, lds);
+    }
+    const auto key = std::make_tuple(dev, prec, kind, emax, block, lds);
+    {
+        std::lock_guard<std::mutex> g(mu);
+        const auto it = seen.find(key);
+        if (it != seen.end()) return it->second;
+    }
+    const int b = query_blocks_per_cu(prec, kind, emax, block, lds);
+    std::lock_guard<std::mutex> g(mu);
+    seen[key] = b;
+    return b;
 }
 
 hipError_t launch_batch(const PassArgs *items_dev, const int64_t *prefix_dev,
