@@ -115,6 +115,24 @@ def test_forced_radices_keep_the_leaf_kernels_table(checker, prec, n, rad):
     assert "kernel=1" in r.stdout   # the specialized leaf kernel runs it
 
 
+@pytest.mark.parametrize("prec,n,batch,bt", [(0, 98, 65536, 36), (0, 1000, 16384, 5),
+                                              (0, 60, 131072, 64), (0, 144, 65536, 21),
+                                              (1, 1000, 8192, 2)])
+def test_lines_per_row_tile_keep_most_lanes_resident(checker, prec, n, batch, bt):
+    """Lines per row tile come from the 256/512/1024-thread class that keeps the
+    most working lanes resident per CU (lines x threads x workgroups per CU;
+    here the checker's model of the occupancy query: registers of the plain
+    FP32 kernel allow 6 waves per SIMD, FP64 3, and 160 KB of LDS per CU).
+    98 points: 36 lines (252 of 256 threads, five per CU) rather than 73 (511
+    of 512, two per CU); 1000 points FP32: 5 lines of 100 threads (512-thread
+    class, three per CU) rather than 2 or 10."""
+    r = subprocess.run([checker, "plan", str(prec), str(n), str(batch)],
+                       capture_output=True, text=True)
+    print(r.stdout)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert f" bt={bt} " in r.stdout, r.stdout
+
+
 def test_fig3_plan_of_30_with_radices_3_2_5(checker):
     """Fig. 3 (Section 4.2, "Discussion"): n = 30 planned by DIT steps of radix
     3, then 2, then 5.  Here the steps are Stockham stages, executed innermost
