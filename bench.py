@@ -113,14 +113,22 @@ def cpu_baseline(x, dims, hdims, sign, n_total, howmany, budget_s=30.0):
     x64 = x[: sample * n_total].astype(np.complex128)
     out = np.empty_like(x64)
     vd = [(sample, n_total, n_total)] if sample > 1 else []
-    t0 = time.perf_counter()
-    oracle.dft(x64, out, dims, vd, sign=sign)
-    t = time.perf_counter() - t0
-    flops = 5.0 * n_total * math.log2(n_total) * sample
+    # the whole workload, when it takes less than a third of the budget, is
+    # run again until about a third of the budget has passed (at most 64 runs)
+    reps, t = 0, 0.0
+    while True:
+        t0 = time.perf_counter()
+        oracle.dft(x64, out, dims, vd, sign=sign)
+        t += time.perf_counter() - t0
+        reps += 1
+        if sample < n_items or t >= budget_s / 3 or reps >= 64:
+            break
+    flops = 5.0 * n_total * math.log2(n_total) * sample * reps
+    runs = f", {reps} runs" if reps > 1 else ""
     return {"value": round(flops / t / 1e9, 3), "unit": "GFLOP/s", "cores": cores,
             "kind": "oracle", "cpu_model": cpu_model(),
             "sample": f"{sample} of {n_items} transforms of n={n_total}, FP64 oracle "
-                      f"(mixed-radix recursion), {t:.2f} s"}
+                      f"(mixed-radix recursion){runs}, {t:.2f} s"}
 
 
 def run_uneven(args, emit=True):
